@@ -1,0 +1,228 @@
+"""ctypes front end of the serial FP64 reference solver ("oracle").
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``. The product package never imports it.
+
+A case is described by a plain mapping with the keys ``n`` (3 interior extents,
+1 = inactive axis), ``nh`` (halo width), ``lo``/``hi`` (box), ``gamma``, ``mu``,
+``prandtl``, ``cfl``, ``bc`` (6 boundary codes, 0 periodic, 1 zero gradient,
+order x-, x+, y-, y+, z-, z+) and ``flags`` (1 inviscid, 2 viscous, 4 heat).
+States are float64 numpy arrays of shape (5, Z, Y, X) with halos (x fastest).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class OracleCfg(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3),
+        ("nh", C.c_int32),
+        ("lo", C.c_double * 3),
+        ("hi", C.c_double * 3),
+        ("gamma", C.c_double),
+        ("mu", C.c_double),
+        ("prandtl", C.c_double),
+        ("cfl", C.c_double),
+        ("bc", C.c_int32 * 6),
+        ("flags", C.c_uint32),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b  # noqa: F401  (build on first use)
+        _b.build()
+    lib = C.CDLL(_LIB_PATH)
+    P = C.POINTER
+    d = C.c_double
+    dp = P(d)
+    cfgp = P(OracleCfg)
+    lib.oracle_state_numel.argtypes = [cfgp]
+    lib.oracle_state_numel.restype = C.c_long
+    lib.oracle_state_init.argtypes = [cfgp, dp, dp]
+    lib.oracle_fill_halo.argtypes = [cfgp, dp]
+    lib.oracle_rhs.argtypes = [cfgp, dp, dp]
+    lib.oracle_dt.argtypes = [cfgp, dp, d, d]
+    lib.oracle_dt.restype = d
+    lib.oracle_rk3_step.argtypes = [cfgp, dp, d, dp]
+    lib.oracle_advance.argtypes = [cfgp, dp, C.c_int, d, d, dp]
+    lib.oracle_weno5.argtypes = [d, d, d, d, d]
+    lib.oracle_weno5.restype = d
+    lib.oracle_hllc.argtypes = [d, dp, dp, C.c_int, dp]
+    lib.oracle_hllc.restype = None
+    lib.oracle_opcount.argtypes = [cfgp, dp, dp]
+    lib.oracle_vjp_rhs.argtypes = [cfgp, dp, dp, dp]
+    lib.oracle_vjp_rk3_step.argtypes = [cfgp, dp, d, dp, dp]
+    lib.oracle_grad_ke.argtypes = [cfgp, dp, C.c_int, d, dp, dp]
+    _lib = lib
+    return lib
+
+
+def make_cfg(case) -> OracleCfg:
+    c = OracleCfg()
+    for i in range(3):
+        c.n[i] = int(case["n"][i])
+        c.lo[i] = float(case["lo"][i])
+        c.hi[i] = float(case["hi"][i])
+    c.nh = int(case.get("nh", 3))
+    c.gamma = float(case["gamma"])
+    c.mu = float(case.get("mu", 0.0))
+    c.prandtl = float(case.get("prandtl", 0.72))
+    c.cfl = float(case.get("cfl", 0.5))
+    for i in range(6):
+        c.bc[i] = int(case["bc"][i])
+    c.flags = int(case["flags"])
+    return c
+
+
+def padded_shape(case):
+    nh = int(case.get("nh", 3))
+    ext = []
+    for d in range(3):
+        n = int(case["n"][d])
+        ext.append(n + 2 * nh if n > 1 else n)
+    return (5, ext[2], ext[1], ext[0])
+
+
+def interior(case, U):
+    """View of the interior cells of a padded state (5, nz, ny, nx)."""
+    nh = int(case.get("nh", 3))
+    sl = []
+    for d in (2, 1, 0):
+        n = int(case["n"][d])
+        sl.append(slice(nh, nh + n) if n > 1 else slice(0, 1))
+    return U[(slice(None),) + tuple(sl)]
+
+
+def _ptr(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ok(rc):
+    if rc != 0:
+        raise ValueError("oracle rejected the configuration")
+
+
+def state_init(case, W):
+    """Padded conservative state from interior primitive point values W (5, nz, ny, nx)."""
+    lib = _load()
+    cfg = make_cfg(case)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    U = np.zeros(padded_shape(case))
+    _ok(lib.oracle_state_init(C.byref(cfg), _ptr(W), _ptr(U)))
+    return U
+
+
+def fill_halo(case, U):
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    _ok(lib.oracle_fill_halo(C.byref(cfg), _ptr(U)))
+    return U
+
+
+def rhs(case, U):
+    """Right-hand side R(U) (padded, halo entries zero)."""
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    R = np.zeros_like(U)
+    _ok(lib.oracle_rhs(C.byref(cfg), _ptr(U), _ptr(R)))
+    return R
+
+
+def cfl_dt(case, U, t=0.0, t_end=0.0):
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return float(lib.oracle_dt(C.byref(cfg), _ptr(U), float(t), float(t_end)))
+
+
+def rk3_step(case, U, dt=0.0):
+    """One TVD-RK3 step (dt <= 0: CFL step). Returns (U_new, dt_used)."""
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    dtu = C.c_double(0.0)
+    _ok(lib.oracle_rk3_step(C.byref(cfg), _ptr(U), float(dt), C.byref(dtu)))
+    return U, dtu.value
+
+
+def advance(case, U, n_steps, t_end=0.0, fixed_dt=0.0, t=0.0):
+    """Up to n_steps steps, stopping at t_end (> 0). Returns (U, t, steps_taken)."""
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64).copy()
+    tt = C.c_double(float(t))
+    n = lib.oracle_advance(C.byref(cfg), _ptr(U), int(n_steps), float(t_end), float(fixed_dt),
+                           C.byref(tt))
+    if n < 0:
+        raise ValueError("oracle rejected the configuration")
+    return U, tt.value, int(n)
+
+
+def weno5(a, b, c, d, e):
+    return float(_load().oracle_weno5(float(a), float(b), float(c), float(d), float(e)))
+
+
+def hllc(gamma, WL, WR, axis):
+    lib = _load()
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    F = np.zeros(5)
+    lib.oracle_hllc(float(gamma), _ptr(WL), _ptr(WR), int(axis), _ptr(F))
+    return F
+
+
+def opcount(case, U):
+    """Operation counts of one right-hand side: dict add/mul/div/sqrt/cmp."""
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.zeros(5)
+    _ok(lib.oracle_opcount(C.byref(cfg), _ptr(U), _ptr(out)))
+    return dict(zip(("add", "mul", "div", "sqrt", "cmp"), out.tolist()))
+
+
+def vjp_rhs(case, U, Rbar):
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    Rbar = np.ascontiguousarray(Rbar, dtype=np.float64)
+    Ubar = np.zeros_like(U)
+    _ok(lib.oracle_vjp_rhs(C.byref(cfg), _ptr(U), _ptr(Rbar), _ptr(Ubar)))
+    return Ubar
+
+
+def vjp_rk3_step(case, Un, dt, Ubar_np1):
+    lib = _load()
+    cfg = make_cfg(case)
+    Un = np.ascontiguousarray(Un, dtype=np.float64)
+    Ubar_np1 = np.ascontiguousarray(Ubar_np1, dtype=np.float64)
+    Ubar_n = np.zeros_like(Un)
+    _ok(lib.oracle_vjp_rk3_step(C.byref(cfg), _ptr(Un), float(dt), _ptr(Ubar_np1), _ptr(Ubar_n)))
+    return Ubar_n
+
+
+def grad_kinetic_energy(case, W0, n_steps, dt):
+    """Loss = total kinetic energy after n_steps fixed-dt steps from primitive W0,
+    and its gradient with respect to the initial (u, v, w). Returns (L, grad(3, nz, ny, nx))."""
+    lib = _load()
+    cfg = make_cfg(case)
+    W0 = np.ascontiguousarray(W0, dtype=np.float64)
+    g = np.zeros((3,) + W0.shape[1:])
+    L = C.c_double(0.0)
+    _ok(lib.oracle_grad_ke(C.byref(cfg), _ptr(W0), int(n_steps), float(dt), C.byref(L), _ptr(g)))
+    return L.value, g

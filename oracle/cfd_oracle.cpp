@@ -1,0 +1,702 @@
+// Serial FP64 reference solver ("oracle") for the finite-volume right-hand
+// side of the compressible Navier-Stokes equations in Bezgin, Buhendwa &
+// Adams, "JAX-FLUIDS: A fully-differentiable high-order computational fluid
+// dynamics solver for compressible two-phase flows" (arXiv:2203.13760).
+//
+// TEST INFRASTRUCTURE ONLY. The test suite, the smoke check and the
+// CPU-baseline leg of the benchmark are its only users; the product library
+// never includes, links or calls it, and it shares no code with it.
+//
+// It is deliberately plain: one loop per face, per axis, per variable, in the
+// order the method defines the operation, with no blocking or fusion. Each
+// step cites the passage of the paper (or of the method the paper cites) that
+// defines it. Where the paper does not print a formula, the standard published
+// form of the cited method is written out and the reading is named.
+//
+// Data layout at the C interface: a state is 5 contiguous variables
+// (rho, rho*u, rho*v, rho*w, E), each a padded block [Z][Y][X] with x fastest.
+// An active axis with n cells carries nh halo cells on each side; an inactive
+// axis (n == 1) carries none (§4.1: inactive axes have extent one).
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "scalar.hpp"
+
+extern "C" {
+typedef struct {
+  int32_t n[3];        // interior cells per axis; 1 marks an inactive axis
+  int32_t nh;          // halo width on active axes (>= 3)
+  double lo[3], hi[3]; // domain box
+  double gamma;        // ratio of specific heats (> 1)
+  double mu;           // dynamic viscosity (>= 0)
+  double prandtl;      // Prandtl number (> 0)
+  double cfl;          // CFL number
+  int32_t bc[6];       // x-, x+, y-, y+, z-, z+ : 0 periodic, 1 zero gradient
+  uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux
+} oracle_cfg;
+}
+
+namespace oracle {
+
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
+enum : uint32_t { F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u };
+
+// --------------------------------------------------------------------------
+// Grid: cell (i,j,k), interior indices 0..n-1, halo indices -nh..-1, n..n+nh-1.
+// Cell sizes dx_d = (hi_d - lo_d)/n_d (§3.1: cuboid cells on a Cartesian grid).
+struct Grid {
+  int n[3], h[3], N[3];
+  bool act[3];
+  double dx[3];
+  long ncell;
+  explicit Grid(const oracle_cfg& c) {
+    for (int d = 0; d < 3; ++d) {
+      n[d] = c.n[d];
+      act[d] = c.n[d] > 1;
+      h[d] = act[d] ? c.nh : 0;
+      N[d] = n[d] + 2 * h[d];
+      dx[d] = (c.hi[d] - c.lo[d]) / n[d];
+    }
+    ncell = (long)N[0] * N[1] * N[2];
+  }
+  long at(int i, int j, int k) const {
+    return ((long)(k + h[2]) * N[1] + (j + h[1])) * N[0] + (i + h[0]);
+  }
+  // Index of the cell displaced by s along axis d from cell (i,j,k).
+  long shift(int d, int i, int j, int k, int s) const {
+    int q[3] = {i, j, k};
+    q[d] += s;
+    return at(q[0], q[1], q[2]);
+  }
+};
+
+// --------------------------------------------------------------------------
+// Boundary conditions (§3.7 and Table of numerical methods: periodic and zero
+// gradient; the setup file of Appendix A calls zero gradient "neumann" without
+// a value). Halo layers are filled axis by axis, x then y then z; each later
+// axis sweeps the full extent of the earlier axes including their halos, so
+// edge and corner halo cells are filled consistently.
+template <class R>
+void fill_halo(const oracle_cfg& c, const Grid& g, std::vector<R>& U) {
+  for (int d = 0; d < 3; ++d) {
+    if (!g.act[d]) continue;
+    const int n = g.n[d];
+    // ranges of the two other axes: interior for later axes, padded for earlier
+    int lo[3], hi[3];
+    for (int e = 0; e < 3; ++e) {
+      if (e < d) { lo[e] = -g.h[e]; hi[e] = g.n[e] + g.h[e]; }
+      else       { lo[e] = 0;       hi[e] = g.n[e]; }
+    }
+    lo[d] = 0; hi[d] = 1;  // the axis itself is looped below
+    for (int k = lo[2]; k < hi[2]; ++k)
+      for (int j = lo[1]; j < hi[1]; ++j)
+        for (int i = lo[0]; i < hi[0]; ++i) {
+          for (int m = 1; m <= g.h[d]; ++m) {
+            // low side: halo cell -m; high side: halo cell n-1+m
+            const int src_lo = (c.bc[2 * d] == BC_PERIODIC) ? n - m : 0;
+            const int src_hi = (c.bc[2 * d + 1] == BC_PERIODIC) ? m - 1 : n - 1;
+            int q[3] = {i, j, k};
+            q[d] = 0;
+            for (int v = 0; v < 5; ++v) {
+              R* Uv = U.data() + (long)v * g.ncell;
+              Uv[g.shift(d, q[0], q[1], q[2], -m)] = Uv[g.shift(d, q[0], q[1], q[2], src_lo)];
+              Uv[g.shift(d, q[0], q[1], q[2], n - 1 + m)] = Uv[g.shift(d, q[0], q[1], q[2], src_hi)];
+            }
+          }
+        }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Primitive variables W = (rho, u, v, w, p) from U = (rho, rho u, rho v, rho w, E)
+// (§2: E = rho e + 1/2 rho u.u; stiffened-gas law p = (gamma-1) rho e - gamma B
+// with B = 0, the ideal gas used throughout §5). Also T~ = p/rho, which is the
+// temperature times the gas constant; the heat flux below needs only T~.
+template <class R>
+struct Prims {
+  std::vector<R> rho, u[3], p, T;
+};
+
+template <class R>
+void primitives(const oracle_cfg& c, const Grid& g, const std::vector<R>& U, Prims<R>& W) {
+  W.rho.assign(g.ncell, R(0.0));
+  for (int d = 0; d < 3; ++d) W.u[d].assign(g.ncell, R(0.0));
+  W.p.assign(g.ncell, R(0.0));
+  W.T.assign(g.ncell, R(0.0));
+  for (long q = 0; q < g.ncell; ++q) {
+    const R rho = U[q];
+    const R ux = U[1 * g.ncell + q] / rho;
+    const R uy = U[2 * g.ncell + q] / rho;
+    const R uz = U[3 * g.ncell + q] / rho;
+    const R E = U[4 * g.ncell + q];
+    const R kin = 0.5 * (U[1 * g.ncell + q] * ux + U[2 * g.ncell + q] * uy + U[3 * g.ncell + q] * uz);
+    const R p = (c.gamma - 1.0) * (E - kin);
+    W.rho[q] = rho;
+    W.u[0][q] = ux;
+    W.u[1][q] = uy;
+    W.u[2][q] = uz;
+    W.p[q] = p;
+    W.T[q] = p / rho;
+  }
+}
+
+// --------------------------------------------------------------------------
+// WENO5-JS (Jiang & Shu 1996; the paper's HLLC setup of §5 uses it on the
+// primitive variables). Value at the right face of the centre cell c of the
+// five-cell stencil (a, b, c, d, e) = (q_{i-2}, ..., q_{i+2}):
+// three third-order candidates p_k, smoothness indicators beta_k, linear
+// weights (0.1, 0.6, 0.3), nonlinear weights alpha_k = d_k/(eps + beta_k)^2
+// with eps = 1e-6, normalised.
+template <class R>
+R weno5_js(R a, R b, R c, R d, R e) {
+  const double eps = 1.0e-6;
+  const R beta0 = (13.0 / 12.0) * sq(a - 2.0 * b + c) + 0.25 * sq(a - 4.0 * b + 3.0 * c);
+  const R beta1 = (13.0 / 12.0) * sq(b - 2.0 * c + d) + 0.25 * sq(b - d);
+  const R beta2 = (13.0 / 12.0) * sq(c - 2.0 * d + e) + 0.25 * sq(3.0 * c - 4.0 * d + e);
+  const R p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  const R p1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  const R p2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  const R alpha0 = 0.1 / sq(eps + beta0);
+  const R alpha1 = 0.6 / sq(eps + beta1);
+  const R alpha2 = 0.3 / sq(eps + beta2);
+  return (alpha0 * p0 + alpha1 * p1 + alpha2 * p2) / (alpha0 + alpha1 + alpha2);
+}
+
+// --------------------------------------------------------------------------
+// HLLC approximate Riemann solver (Toro, Spruce & Speares 1994; §3.3 step 3)
+// with the Einfeldt (1988) signal-speed estimate (the setup file of Appendix A
+// selects "HLLC" with "EINFELDT"). Inputs are the reconstructed primitive
+// states left (L) and right (R) of a face normal to axis d, in physical slot
+// order (rho, u, v, w, p). The output F is in physical slot order as well.
+template <class R>
+void hllc_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]) {
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  // normal-first ordering of the state (§3.3: dimension-by-dimension)
+  const R rL = WL[0], uL = WL[1 + d], aL = WL[1 + t1], bL = WL[1 + t2], pL = WL[4];
+  const R rR = WR[0], uR = WR[1 + d], aR = WR[1 + t1], bR = WR[1 + t2], pR = WR[4];
+  // step 2 of §3.3: primitive -> conservative face states, and the physical
+  // fluxes of §2 (convective flux F, G, H rotated to the face normal)
+  const R EL = pL / (gamma - 1.0) + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+  const R ER = pR / (gamma - 1.0) + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+  const R cL = sqrt_(gamma * pL / rL);
+  const R cR = sqrt_(gamma * pR / rR);
+  const R UL[5] = {rL, rL * uL, rL * aL, rL * bL, EL};
+  const R UR[5] = {rR, rR * uR, rR * aR, rR * bR, ER};
+  const R FL[5] = {rL * uL, rL * uL * uL + pL, rL * uL * aL, rL * uL * bL, uL * (EL + pL)};
+  const R FR[5] = {rR * uR, rR * uR * uR + pR, rR * uR * aR, rR * uR * bR, uR * (ER + pR)};
+  // Einfeldt: Roe-averaged normal velocity and sound-speed bound
+  const R sL = sqrt_(rL), sR = sqrt_(rR);
+  const R ubar = (sL * uL + sR * uR) / (sL + sR);
+  const R eta2 = 0.5 * sL * sR / sq(sL + sR);
+  const R dbar2 = (sL * cL * cL + sR * cR * cR) / (sL + sR) + eta2 * sq(uR - uL);
+  const R dbar = sqrt_(dbar2);
+  const R SL = min_(uL - cL, ubar - dbar);
+  const R SR = max_(uR + cR, ubar + dbar);
+  // contact wave speed
+  const R Sstar = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
+                  (rL * (SL - uL) - rR * (SR - uR));
+  R Fn[5];
+  if (0.0 <= val(SL)) {
+    for (int v = 0; v < 5; ++v) Fn[v] = FL[v];
+  } else if (val(SL) < 0.0 && 0.0 <= val(Sstar)) {
+    const R f = rL * (SL - uL) / (SL - Sstar);
+    const R Us[5] = {f, f * Sstar, f * aL, f * bL,
+                     f * (EL / rL + (Sstar - uL) * (Sstar + pL / (rL * (SL - uL))))};
+    for (int v = 0; v < 5; ++v) Fn[v] = FL[v] + SL * (Us[v] - UL[v]);
+  } else if (val(Sstar) < 0.0 && 0.0 < val(SR)) {
+    const R f = rR * (SR - uR) / (SR - Sstar);
+    const R Us[5] = {f, f * Sstar, f * aR, f * bR,
+                     f * (ER / rR + (Sstar - uR) * (Sstar + pR / (rR * (SR - uR))))};
+    for (int v = 0; v < 5; ++v) Fn[v] = FR[v] + SR * (Us[v] - UR[v]);
+  } else {
+    for (int v = 0; v < 5; ++v) Fn[v] = FR[v];
+  }
+  // back to physical slot order
+  F[0] = Fn[0];
+  F[1 + d] = Fn[1];
+  F[1 + t1] = Fn[2];
+  F[1 + t2] = Fn[3];
+  F[4] = Fn[4];
+}
+
+// --------------------------------------------------------------------------
+// Dissipative flux at the face between cells i and i+1 along axis d
+// (§2: stresses tau with the Stokes hypothesis, Fourier heat flux q = -lambda
+// grad T; §3.4: fourth-order central differences).
+//  * derivative along the face normal, directly at the face:
+//        (psi_{i-1} - 27 psi_i + 27 psi_{i+1} - psi_{i+2}) / (24 dx)
+//  * derivative along a tangential axis t: first at the cell centres
+//        (psi_{c-2} - 8 psi_{c-1} + 8 psi_{c+1} - psi_{c+2}) / (12 dx_t),
+//    for the four cells c = i-1 .. i+2 along d, then interpolated to the face
+//    with the fourth-order central interpolation (-D_{i-1} + 9 D_i + 9 D_{i+1} - D_{i+2})/16
+//    (reading: the paper's interpolation indices are shifted by one cell; the
+//    face i+1/2 sits between cells i and i+1);
+//  * face velocities for the work term: the same fourth-order interpolation.
+// lambda grad T = gamma mu / ((gamma-1) Pr) grad(p/rho), because
+// lambda = mu c_p / Pr and c_p = gamma R/(gamma-1): the gas constant cancels.
+template <class R>
+void dissipative_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d,
+                      int i, int j, int k, bool viscous, bool heat, R F[5]) {
+  const int ii[3] = {i, j, k};
+  auto cell = [&](int s) {  // cell displaced by s along d from (i,j,k)
+    int q[3] = {ii[0], ii[1], ii[2]};
+    q[d] += s;
+    return g.at(q[0], q[1], q[2]);
+  };
+  // normal derivative at the face
+  auto dnormal = [&](const std::vector<R>& psi) {
+    return (psi[cell(-1)] - 27.0 * psi[cell(0)] + 27.0 * psi[cell(1)] - psi[cell(2)]) / (24.0 * g.dx[d]);
+  };
+  // tangential derivative along t at the face
+  auto dtangent = [&](const std::vector<R>& psi, int t) {
+    if (!g.act[t]) return R(0.0);
+    R D[4];
+    for (int s = -1; s <= 2; ++s) {
+      int q[3] = {ii[0], ii[1], ii[2]};
+      q[d] += s;
+      auto at_t = [&](int o) {
+        int r[3] = {q[0], q[1], q[2]};
+        r[t] += o;
+        return g.at(r[0], r[1], r[2]);
+      };
+      D[s + 1] = (psi[at_t(-2)] - 8.0 * psi[at_t(-1)] + 8.0 * psi[at_t(1)] - psi[at_t(2)]) / (12.0 * g.dx[t]);
+    }
+    return (-D[0] + 9.0 * D[1] + 9.0 * D[2] - D[3]) / 16.0;
+  };
+  auto interp = [&](const std::vector<R>& psi) {
+    return (-psi[cell(-1)] + 9.0 * psi[cell(0)] + 9.0 * psi[cell(1)] - psi[cell(2)]) / 16.0;
+  };
+
+  for (int v = 0; v < 5; ++v) F[v] = R(0.0);
+  if (viscous) {
+    // velocity gradient at the face: grad[a][b] = d u_a / d x_b
+    R grad[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        grad[a][b] = (b == d) ? dnormal(W.u[a]) : dtangent(W.u[a], b);
+    const R div = grad[0][0] + grad[1][1] + grad[2][2];
+    R tau[3];  // tau^{d,b}
+    for (int b = 0; b < 3; ++b) {
+      tau[b] = c.mu * (grad[d][b] + grad[b][d]);
+      if (b == d) tau[b] = tau[b] - (2.0 / 3.0) * c.mu * div;
+    }
+    R uf[3];
+    for (int a = 0; a < 3; ++a) uf[a] = interp(W.u[a]);
+    F[1] = tau[0];
+    F[2] = tau[1];
+    F[3] = tau[2];
+    F[4] = uf[0] * tau[0] + uf[1] * tau[1] + uf[2] * tau[2];
+  }
+  if (heat) {
+    const double kappa = c.gamma * c.mu / ((c.gamma - 1.0) * c.prandtl);
+    // -q_d = lambda dT/dx_d
+    F[4] = F[4] + kappa * dnormal(W.T);
+  }
+}
+
+// --------------------------------------------------------------------------
+// Right-hand side of the semi-discrete finite-volume scheme (§3.1, Eq. FVD):
+//   dU_i/dt = - sum_d (G_{i+1/2} - G_{i-1/2}) / dx_d,   G = F - F^d,
+// where F is the convective numerical flux of the high-order Godunov approach
+// (§3.3: reconstruct W with WENO5-JS, convert, HLLC) and F^d the dissipative
+// flux. Axes are treated one after the other (dimension by dimension, §3.1).
+// Each face flux is computed once and used by both neighbouring cells.
+// U is the padded state; its halos are refreshed here (Algorithm 2 refills
+// boundaries before every right-hand-side evaluation). R is padded; its halo
+// entries are zero.
+template <class R>
+void rhs(const oracle_cfg& c, const Grid& g, std::vector<R>& U, std::vector<R>& Rhs) {
+  fill_halo(c, g, U);
+  Prims<R> W;
+  primitives(c, g, U, W);
+  Rhs.assign(5 * g.ncell, R(0.0));
+  const bool inviscid = c.flags & F_INVISCID;
+  const bool viscous = (c.flags & F_VISCOUS) && c.mu > 0.0;
+  const bool heat = (c.flags & F_HEAT) && c.mu > 0.0;
+  const std::vector<R>* q[5] = {&W.rho, &W.u[0], &W.u[1], &W.u[2], &W.p};
+  for (int d = 0; d < 3; ++d) {
+    if (!g.act[d]) continue;
+    const int n = g.n[d];
+    int ext[3] = {g.n[0], g.n[1], g.n[2]};
+    ext[d] = 1;
+    std::vector<R> G((size_t)(n + 1) * 5);
+    for (int k = 0; k < ext[2]; ++k)
+      for (int j = 0; j < ext[1]; ++j)
+        for (int i = 0; i < ext[0]; ++i) {
+          // faces f = -1 .. n-1, face f between cells f and f+1 of this line
+          for (int f = -1; f < n; ++f) {
+            int a[3] = {i, j, k};
+            a[d] = f;
+            R Fc[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
+            if (inviscid) {
+              R WL[5], WR[5];
+              for (int v = 0; v < 5; ++v) {
+                const std::vector<R>& s = *q[v];
+                auto at = [&](int o) { return s[g.shift(d, a[0], a[1], a[2], o)]; };
+                WL[v] = weno5_js(at(-2), at(-1), at(0), at(1), at(2));
+                WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
+              }
+              hllc_flux(c.gamma, WL, WR, d, Fc);
+            }
+            R Fd[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
+            if (viscous || heat) dissipative_flux(c, g, W, d, a[0], a[1], a[2], viscous, heat, Fd);
+            for (int v = 0; v < 5; ++v) G[(size_t)(f + 1) * 5 + v] = Fc[v] - Fd[v];
+          }
+          for (int m = 0; m < n; ++m) {
+            int a[3] = {i, j, k};
+            a[d] = m;
+            const long cidx = g.at(a[0], a[1], a[2]);
+            for (int v = 0; v < 5; ++v) {
+              const R diff = (G[(size_t)(m + 1) * 5 + v] - G[(size_t)m * 5 + v]) / g.dx[d];
+              Rhs[(long)v * g.ncell + cidx] = Rhs[(long)v * g.ncell + cidx] - diff;
+            }
+          }
+        }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Time step from the CFL criterion (§3.2 cites Hoppe et al. 2022; the formula
+// is not printed, reading):
+//   convective: s_c = max over interior cells of sum_d (|u_d| + c)/dx_d
+//   viscous   : s_v = max over interior cells of 2 (mu/rho) max(4/3, gamma/Pr) sum_d dx_d^-2
+//   dt = CFL / max(s_c, s_v), then clipped so that t + dt <= t_end.
+inline double cfl_dt(const oracle_cfg& c, const Grid& g, const std::vector<double>& U,
+                     double t, double t_end) {
+  double sc = 0.0, sv = 0.0;
+  const bool visc = ((c.flags & (F_VISCOUS | F_HEAT)) != 0) && c.mu > 0.0;
+  double inv2 = 0.0;
+  for (int d = 0; d < 3; ++d)
+    if (g.act[d]) inv2 += 1.0 / (g.dx[d] * g.dx[d]);
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        const long q = g.at(i, j, k);
+        const double rho = U[q];
+        double u[3];
+        for (int d = 0; d < 3; ++d) u[d] = U[(1 + d) * g.ncell + q] / rho;
+        const double kin = 0.5 * (U[1 * g.ncell + q] * u[0] + U[2 * g.ncell + q] * u[1] +
+                                  U[3 * g.ncell + q] * u[2]);
+        const double p = (c.gamma - 1.0) * (U[4 * g.ncell + q] - kin);
+        const double cs = std::sqrt(c.gamma * p / rho);
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d)
+          if (g.act[d]) s += (std::fabs(u[d]) + cs) / g.dx[d];
+        sc = std::max(sc, s);
+        if (visc) {
+          const double r = std::max(4.0 / 3.0, c.gamma / c.prandtl);
+          sv = std::max(sv, 2.0 * (c.mu / rho) * r * inv2);
+        }
+      }
+  double dt = c.cfl / std::max(sc, sv);
+  if (t_end > 0.0) dt = std::min(dt, t_end - t);
+  return dt;
+}
+
+// --------------------------------------------------------------------------
+// Third-order TVD Runge-Kutta (Gottlieb & Shu 1998; §3.2), in exactly this form:
+//   U1   = Un + dt R(Un)
+//   U2   = 3/4 Un + 1/4 (U1 + dt R(U1))
+//   Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2))
+// dt stays fixed over the three stages. Only interior cells are updated; the
+// halos of the result are refreshed afterwards.
+template <class R>
+void rk3_step(const oracle_cfg& c, const Grid& g, std::vector<R>& U, double dt) {
+  std::vector<R> Un = U, U1 = U, U2 = U, Rh;
+  auto interior = [&](auto&& body) {
+    for (int v = 0; v < 5; ++v)
+      for (int k = 0; k < g.n[2]; ++k)
+        for (int j = 0; j < g.n[1]; ++j)
+          for (int i = 0; i < g.n[0]; ++i) body((long)v * g.ncell + g.at(i, j, k));
+  };
+  rhs(c, g, Un, Rh);
+  interior([&](long q) { U1[q] = Un[q] + dt * Rh[q]; });
+  rhs(c, g, U1, Rh);
+  interior([&](long q) { U2[q] = 0.75 * Un[q] + 0.25 * (U1[q] + dt * Rh[q]); });
+  rhs(c, g, U2, Rh);
+  interior([&](long q) { U[q] = (1.0 / 3.0) * Un[q] + (2.0 / 3.0) * (U2[q] + dt * Rh[q]); });
+  fill_halo(c, g, U);
+}
+
+// Conservative state from primitive point values, interior cells only (§2).
+template <class R>
+void state_init(const oracle_cfg& c, const Grid& g, const R* W, std::vector<R>& U) {
+  U.assign(5 * g.ncell, R(0.0));
+  const long ni = (long)g.n[0] * g.n[1] * g.n[2];
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        const long s = ((long)k * g.n[1] + j) * g.n[0] + i;
+        const long q = g.at(i, j, k);
+        const R rho = W[s], u = W[ni + s], v = W[2 * ni + s], w = W[3 * ni + s], p = W[4 * ni + s];
+        U[q] = rho;
+        U[g.ncell + q] = rho * u;
+        U[2 * g.ncell + q] = rho * v;
+        U[3 * g.ncell + q] = rho * w;
+        U[4 * g.ncell + q] = p / (c.gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+      }
+  fill_halo(c, g, U);
+}
+
+}  // namespace oracle
+
+// ============================================================================
+// C interface for the test suite (ctypes). All arrays are host memory owned by
+// the caller; padded arrays have 5 * prod(n_d + 2 h_d) entries. Return 0 on
+// success, -1 on an invalid configuration.
+using namespace oracle;
+
+static int check_cfg(const oracle_cfg* c) {
+  if (!c) return -1;
+  for (int d = 0; d < 3; ++d) {
+    if (c->n[d] < 1) return -1;
+    if (c->n[d] > 1 && c->n[d] < c->nh) return -1;  // periodic images need n >= nh
+    if (!(c->hi[d] > c->lo[d])) return -1;
+    if (c->n[d] > 1 && ((c->bc[2 * d] == BC_PERIODIC) != (c->bc[2 * d + 1] == BC_PERIODIC))) return -1;
+  }
+  if (c->nh < 3 || !(c->gamma > 1.0) || !(c->mu >= 0.0) || !(c->prandtl > 0.0)) return -1;
+  return 0;
+}
+
+extern "C" {
+
+long oracle_state_numel(const oracle_cfg* c) {
+  if (check_cfg(c)) return -1;
+  return 5 * Grid(*c).ncell;
+}
+
+int oracle_state_init(const oracle_cfg* c, const double* W, double* U) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  std::vector<double> u;
+  state_init(*c, g, W, u);
+  std::memcpy(U, u.data(), sizeof(double) * u.size());
+  return 0;
+}
+
+int oracle_fill_halo(const oracle_cfg* c, double* U) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  std::vector<double> u(U, U + 5 * g.ncell);
+  fill_halo(*c, g, u);
+  std::memcpy(U, u.data(), sizeof(double) * u.size());
+  return 0;
+}
+
+// R = rhs(U); U's halos are refreshed in place.
+int oracle_rhs(const oracle_cfg* c, double* U, double* R) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  std::vector<double> u(U, U + 5 * g.ncell), r;
+  rhs(*c, g, u, r);
+  std::memcpy(U, u.data(), sizeof(double) * u.size());
+  std::memcpy(R, r.data(), sizeof(double) * r.size());
+  return 0;
+}
+
+double oracle_dt(const oracle_cfg* c, const double* U, double t, double t_end) {
+  if (check_cfg(c)) return -1.0;
+  Grid g(*c);
+  std::vector<double> u(U, U + 5 * g.ncell);
+  return cfl_dt(*c, g, u, t, t_end);
+}
+
+// One TVD-RK3 step; dt <= 0 selects the CFL time step. Writes the dt used.
+int oracle_rk3_step(const oracle_cfg* c, double* U, double dt, double* dt_used) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  std::vector<double> u(U, U + 5 * g.ncell);
+  fill_halo(*c, g, u);
+  if (dt <= 0.0) dt = cfl_dt(*c, g, u, 0.0, 0.0);
+  rk3_step(*c, g, u, dt);
+  std::memcpy(U, u.data(), sizeof(double) * u.size());
+  if (dt_used) *dt_used = dt;
+  return 0;
+}
+
+// n_steps CFL steps, stopping at t_end (> 0) with a clipped last step.
+// fixed_dt > 0 replaces the CFL step. *t is read and updated. Returns the
+// number of steps taken.
+int oracle_advance(const oracle_cfg* c, double* U, int n_steps, double t_end, double fixed_dt,
+                   double* t) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  std::vector<double> u(U, U + 5 * g.ncell);
+  fill_halo(*c, g, u);
+  double time = t ? *t : 0.0;
+  int taken = 0;
+  for (int s = 0; s < n_steps; ++s) {
+    if (t_end > 0.0 && time >= t_end) break;
+    double dt = fixed_dt > 0.0 ? fixed_dt : cfl_dt(*c, g, u, time, t_end);
+    if (fixed_dt > 0.0 && t_end > 0.0) dt = std::min(dt, t_end - time);
+    rk3_step(*c, g, u, dt);
+    time += dt;
+    ++taken;
+  }
+  std::memcpy(U, u.data(), sizeof(double) * u.size());
+  if (t) *t = time;
+  return taken;
+}
+
+// Single-face building blocks, for unit tests of the method's pieces.
+double oracle_weno5(double a, double b, double c, double d, double e) {
+  return weno5_js(a, b, c, d, e);
+}
+void oracle_hllc(double gamma, const double* WL, const double* WR, int d, double* F) {
+  hllc_flux(gamma, WL, WR, d, F);
+}
+
+// Operation counts of one right-hand-side evaluation of state U:
+// out = {add, mul, div, sqrt, cmp}.
+int oracle_opcount(const oracle_cfg* c, const double* U, double* out) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  std::vector<OpCount> u(5 * g.ncell), r;
+  for (long q = 0; q < 5 * g.ncell; ++q) u[q] = OpCount(U[q]);
+  tally() = OpTally();
+  rhs(*c, g, u, r);
+  const OpTally t = tally();
+  out[0] = t.add; out[1] = t.mul; out[2] = t.div; out[3] = t.sqrt; out[4] = t.cmp;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse-mode derivatives from the tape (independent of any hand-derived
+// adjoint). Each records the forward computation with TVar and reverses it.
+
+// Ubar = (dR/dU)^T Rbar for R = rhs(U). Halo entries of Ubar receive nothing:
+// the halo fill overwrites them before they are read.
+int oracle_vjp_rhs(const oracle_cfg* c, const double* U, const double* Rbar, double* Ubar) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  Tape tape;
+  active_tape() = &tape;
+  std::vector<TVar> u(5 * g.ncell), r;
+  for (long q = 0; q < 5 * g.ncell; ++q) u[q] = TVar::leaf(U[q]);
+  std::vector<int32_t> leaf(5 * g.ncell);
+  for (long q = 0; q < 5 * g.ncell; ++q) leaf[q] = u[q].id;
+  rhs(*c, g, u, r);
+  std::vector<double> adj(tape.nodes.size(), 0.0);
+  for (long q = 0; q < 5 * g.ncell; ++q)
+    if (r[q].id >= 0) adj[r[q].id] += Rbar[q];
+  tape.reverse(adj);
+  for (long q = 0; q < 5 * g.ncell; ++q) Ubar[q] = adj[leaf[q]];
+  active_tape() = nullptr;
+  return 0;
+}
+
+// Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1 for one TVD-RK3 step with fixed dt.
+int oracle_vjp_rk3_step(const oracle_cfg* c, const double* Un, double dt, const double* Ubar_np1,
+                        double* Ubar_n) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  Tape tape;
+  active_tape() = &tape;
+  std::vector<TVar> u(5 * g.ncell);
+  std::vector<int32_t> leaf(5 * g.ncell);
+  for (long q = 0; q < 5 * g.ncell; ++q) { u[q] = TVar::leaf(Un[q]); leaf[q] = u[q].id; }
+  rk3_step(*c, g, u, dt);
+  std::vector<double> adj(tape.nodes.size(), 0.0);
+  // the result's halo cells are copies of interior cells: seed interior only
+  for (int v = 0; v < 5; ++v)
+    for (int k = 0; k < g.n[2]; ++k)
+      for (int j = 0; j < g.n[1]; ++j)
+        for (int i = 0; i < g.n[0]; ++i) {
+          const long q = (long)v * g.ncell + g.at(i, j, k);
+          if (u[q].id >= 0) adj[u[q].id] += Ubar_np1[q];
+        }
+  tape.reverse(adj);
+  for (long q = 0; q < 5 * g.ncell; ++q) Ubar_n[q] = adj[leaf[q]];
+  active_tape() = nullptr;
+  return 0;
+}
+
+// Loss L = sum over interior cells of 1/2 |rho u|^2 / rho * dV after n_steps
+// fixed-dt TVD-RK3 steps from the primitive initial state W0 (5 x interior),
+// and its gradient with respect to the initial velocities (3 x interior).
+// Forward states are stored; the backward pass tapes one step at a time.
+int oracle_grad_ke(const oracle_cfg* c, const double* W0, int n_steps, double dt, double* loss,
+                   double* grad_uvw) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  const long ni = (long)g.n[0] * g.n[1] * g.n[2];
+  const double dV = g.dx[0] * g.dx[1] * g.dx[2];
+  // forward, keeping every state
+  std::vector<std::vector<double>> states;
+  {
+    std::vector<double> u;
+    state_init(*c, g, W0, u);
+    states.push_back(u);
+    for (int s = 0; s < n_steps; ++s) {
+      rk3_step(*c, g, u, dt);
+      states.push_back(u);
+    }
+  }
+  // loss and its adjoint at the final state
+  std::vector<double> ubar(5 * g.ncell, 0.0);
+  {
+    Tape tape;
+    active_tape() = &tape;
+    const std::vector<double>& uN = states.back();
+    std::vector<TVar> u(5 * g.ncell);
+    std::vector<int32_t> leaf(5 * g.ncell);
+    for (long q = 0; q < 5 * g.ncell; ++q) { u[q] = TVar::leaf(uN[q]); leaf[q] = u[q].id; }
+    TVar L(0.0);
+    for (int k = 0; k < g.n[2]; ++k)
+      for (int j = 0; j < g.n[1]; ++j)
+        for (int i = 0; i < g.n[0]; ++i) {
+          const long q = g.at(i, j, k);
+          const TVar m2 = u[g.ncell + q] * u[g.ncell + q] + u[2 * g.ncell + q] * u[2 * g.ncell + q] +
+                          u[3 * g.ncell + q] * u[3 * g.ncell + q];
+          L = L + 0.5 * m2 / u[q] * dV;
+        }
+    *loss = L.v;
+    std::vector<double> adj(tape.nodes.size(), 0.0);
+    adj[L.id] = 1.0;
+    tape.reverse(adj);
+    for (long q = 0; q < 5 * g.ncell; ++q) ubar[q] = adj[leaf[q]];
+    active_tape() = nullptr;
+  }
+  // backward through the steps
+  for (int s = n_steps - 1; s >= 0; --s) {
+    std::vector<double> prev(5 * g.ncell);
+    oracle_vjp_rk3_step(c, states[s].data(), dt, ubar.data(), prev.data());
+    ubar.swap(prev);
+  }
+  // through the primitive -> conservative map of the initial state, with rho
+  // and p held fixed
+  {
+    Tape tape;
+    active_tape() = &tape;
+    std::vector<double> Wd(W0, W0 + 5 * ni);
+    std::vector<TVar> W(5 * ni);
+    std::vector<int32_t> leaf(3 * ni);
+    for (long s = 0; s < ni; ++s) {
+      W[s] = TVar(Wd[s]);
+      W[4 * ni + s] = TVar(Wd[4 * ni + s]);
+      for (int a = 0; a < 3; ++a) {
+        W[(1 + a) * ni + s] = TVar::leaf(Wd[(1 + a) * ni + s]);
+        leaf[a * ni + s] = W[(1 + a) * ni + s].id;
+      }
+    }
+    std::vector<TVar> u;
+    state_init(*c, g, W.data(), u);
+    std::vector<double> adj(tape.nodes.size(), 0.0);
+    for (int v = 0; v < 5; ++v)
+      for (int k = 0; k < g.n[2]; ++k)
+        for (int j = 0; j < g.n[1]; ++j)
+          for (int i = 0; i < g.n[0]; ++i) {
+            const long q = (long)v * g.ncell + g.at(i, j, k);
+            if (u[q].id >= 0) adj[u[q].id] += ubar[q];
+          }
+    tape.reverse(adj);
+    for (long s = 0; s < 3 * ni; ++s) grad_uvw[s] = adj[leaf[s]];
+    active_tape() = nullptr;
+  }
+  return 0;
+}
+
+}  // extern "C"
