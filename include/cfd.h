@@ -1,0 +1,145 @@
+/*
+ * libcfd - FP64 finite-volume right-hand side of the compressible
+ * Navier-Stokes equations on a structured Cartesian grid, hand-written HIP
+ * for gfx950 (MI355X). C ABI, C99 header.
+ *
+ * The method is the "HLLC" setup of Bezgin, Buhendwa & Adams, JAX-FLUIDS
+ * (arXiv:2203.13760): WENO5-JS reconstruction of the primitive variables,
+ * HLLC Riemann flux with Einfeldt signal speeds per axis (§3.3), fourth-order
+ * central viscous and heat fluxes (§3.4), the finite-volume flux divergence
+ * (§3.1, Eq. FVD), and TVD-RK3 time integration with a CFL time step (§3.2).
+ *
+ * Conventions shared by every entry point
+ *  - State layout (§2, §4.1): a state U holds the conservative variables
+ *    (rho, rho*u, rho*v, rho*w, E) as 5 contiguous FP64 blocks; each block is
+ *    [Z][Y][X] with x fastest, where an active axis of n cells is padded with
+ *    nh halo cells on each side and an inactive axis (n == 1) has extent 1.
+ *    cfd_state_numel() gives the element count. Interior cell (i,j,k) of
+ *    variable v lives at v*Nz*Ny*Nx + (k+hz)*Ny*Nx + (j+hy)*Nx + (i+hx).
+ *  - Memory: every array argument is device memory owned by the caller,
+ *    FP64 and contiguous unless stated. The solver owns only its scratch.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream). Every call only enqueues work on that stream and returns; none
+ *    synchronises except cfd_create, cfd_destroy and cfd_check. A solver
+ *    handle must be used from one stream at a time.
+ *  - Errors: every function returns cfd_status and never throws; on failure
+ *    cfd_last_error() returns a message (thread-local).
+ */
+#ifndef LIBCFD_CFD_H
+#define LIBCFD_CFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CFD_OK = 0,
+  CFD_EINVAL = -1,      /* invalid argument or configuration */
+  CFD_ENOMEM = -2,      /* device allocation failed */
+  CFD_EHIP = -3,        /* a HIP runtime call failed */
+  CFD_ENONFINITE = -4,  /* reserved: reported through cfd_check */
+  CFD_EUNSUPPORTED = -5 /* valid request that this build does not implement */
+} cfd_status;
+
+/* Boundary types (§3.7): periodic (in pairs) and zero gradient, the paper's
+ * "neumann" without a value. */
+typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1 } cfd_bc;
+
+/* Physics switches, after the paper's is_inviscid_flux / is_viscous_flux /
+ * is_heat_flux (Appendix A). */
+enum { CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u };
+
+typedef struct {
+  int32_t n[3];      /* interior cells (x,y,z); n[d] == 1 marks an inactive axis */
+  int32_t nh;        /* halo width on active axes; >= 3 (WENO5 and the C4 stencils) */
+  double lo[3];      /* box lower corner */
+  double hi[3];      /* box upper corner; dx_d = (hi_d - lo_d)/n_d */
+  double gamma;      /* ratio of specific heats, > 1 (ideal gas, §2 with B = 0) */
+  double mu;         /* dynamic viscosity, >= 0, constant (§2) */
+  double prandtl;    /* > 0; heat conductivity = mu c_p / Pr */
+  double cfl;        /* CFL number in (0, 1] (§3.2) */
+  int32_t bc[6];     /* x-, x+, y-, y+, z-, z+ (cfd_bc); periodic only in pairs */
+  uint32_t flags;    /* CFD_F_* */
+} cfd_config;
+
+typedef struct cfd_solver cfd_solver; /* opaque; owns the stage buffers and scratch */
+
+/* Validate `cfg` and allocate the solver on the current HIP device: two stage
+ * states, the primitive and velocity-gradient scratch, a right-hand-side
+ * accumulator and a small device control block. Active axes need n >= nh.
+ * Returns CFD_EINVAL (bad config), CFD_ENOMEM or CFD_EHIP. Synchronises. */
+cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out);
+
+/* Free everything the solver owns. NULL is accepted. Synchronises. */
+void cfd_destroy(cfd_solver* s);
+
+/* Number of FP64 elements of one padded state (5 * Nz * Ny * Nx), or -1. */
+int64_t cfd_state_numel(const cfd_solver* s);
+
+/* Conservative state from primitive point values (§2): W holds
+ * (rho, u, v, w, p) as 5 blocks of interior cells [nz][ny][nx] (no halo);
+ * U receives the padded conservative state with its halos filled. */
+cfd_status cfd_state_init(cfd_solver* s, const double* W, double* U, void* stream);
+
+/* Refresh the halo cells of U in place from its interior, per the boundary
+ * types (§3.7): periodic images or zero-gradient copies, x then y then z. */
+cfd_status cfd_fill_halo(cfd_solver* s, double* U, void* stream);
+
+/* Right-hand side of the semi-discrete scheme (§3.1, Eq. FVD):
+ *   R_i = - sum_d (G_{i+1/2} - G_{i-1/2}) / dx_d,  G = F - F^d,
+ * F the WENO5-JS/HLLC convective flux (§3.3) and F^d the viscous and heat
+ * flux (§3.4), per the physics flags. U's halos are refreshed in place. R is
+ * a padded state; its halo entries are set to zero. */
+cfd_status cfd_rhs(cfd_solver* s, double* U, double* R, void* stream);
+
+/* CFL time step of state U (§3.2): dt = cfl / max over interior cells of
+ * max(sum_d (|u_d| + c)/dx_d, 2 (mu/rho) max(4/3, gamma/Pr) sum_d dx_d^-2).
+ * Writes one double to dt_dev (device memory). */
+cfd_status cfd_compute_dt(cfd_solver* s, const double* U, double* dt_dev, void* stream);
+
+/* One TVD-RK3 step (§3.2, Gottlieb & Shu):
+ *   U1 = Un + dt R(Un);  U2 = 3/4 Un + 1/4 (U1 + dt R(U1));
+ *   Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2)),
+ * in place on U (halos refreshed on return). dt > 0 fixes the step; dt <= 0
+ * uses the CFL step of Un. dt_used_dev (device, nullable) receives the step. */
+cfd_status cfd_rk3_step(cfd_solver* s, double* U, double dt, double* dt_used_dev, void* stream);
+
+/* n_steps CFL steps (Algorithm 1's time loop) on U in place, with the time
+ * kept on the device in *t_dev (device memory, read and updated). With
+ * t_end > 0 the last step is clipped to end exactly at t_end, and steps
+ * after that are device-side no-ops, so no host synchronisation is needed.
+ * The step sequence is replayed from a captured HIP graph. */
+cfd_status cfd_advance(cfd_solver* s, double* U, int32_t n_steps, double t_end, double* t_dev,
+                       void* stream);
+
+/* n_steps steps with a fixed dt (the paper's fixed-step rollout used for
+ * differentiation, §4.5), graph-replayed like cfd_advance. */
+cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double dt, void* stream);
+
+/* Discrete adjoint of cfd_rhs: Ubar += (dR/dU)^T Rbar, evaluated at U
+ * (interior cells of Rbar are read; its halo is ignored). The transposed halo
+ * fill folds halo contributions back into their source cells, so the halo
+ * entries of Ubar are left unchanged. U is not modified. */
+cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar,
+                           void* stream);
+
+/* Discrete adjoint of one fixed-dt TVD-RK3 step: with U^{n+1} = S(U^n),
+ * Ubar_n = (dS/dU^n)^T Ubar_np1 (interior cells; Ubar_n's halo is zeroed).
+ * The stage states are recomputed from Un. Ubar_n must not alias the others. */
+cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
+                                double* Ubar_n, void* stream);
+
+/* Synchronise the solver's last stream use and report its health word:
+ * bit 0 a non-finite conservative value, bit 1 rho <= 0, bit 2 p <= 0, seen
+ * at the start of any step since the previous cfd_check (which clears it). */
+cfd_status cfd_check(cfd_solver* s, int32_t* status_out);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* cfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBCFD_CFD_H */

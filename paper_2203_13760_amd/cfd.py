@@ -1,0 +1,189 @@
+"""ctypes binding of libcfd (include/cfd.h), with the C ABI's names.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libcfd.so. Arrays are torch tensors on the GPU (float64,
+contiguous); streams default to torch's current stream. If libcfd.so is
+missing or cannot be loaded, every entry point raises - there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcfd.so")
+
+CFD_OK, CFD_EINVAL, CFD_ENOMEM, CFD_EHIP, CFD_ENONFINITE, CFD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CFD_BC_PERIODIC, CFD_BC_ZERO_GRADIENT = 0, 1
+CFD_F_INVISCID, CFD_F_VISCOUS, CFD_F_HEAT = 1, 2, 4
+
+
+class CfdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libcfd error {code}: {msg}")
+        self.code = code
+
+
+class cfd_config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32 * 3),
+        ("nh", C.c_int32),
+        ("lo", C.c_double * 3),
+        ("hi", C.c_double * 3),
+        ("gamma", C.c_double),
+        ("mu", C.c_double),
+        ("prandtl", C.c_double),
+        ("cfl", C.c_double),
+        ("bc", C.c_int32 * 6),
+        ("flags", C.c_uint32),
+    ]
+
+
+EXPORTS = (
+    "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_fill_halo", "cfd_rhs",
+    "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
+    "cfd_rk3_step_adjoint", "cfd_check", "cfd_last_error",
+)
+
+_lib = None
+
+
+def load():
+    """Load libcfd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_2203_13760_amd/build.py "
+                           "(or __graft_entry__.build()) first; there is no fallback path")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp = C.c_void_p, C.c_void_p
+    cfgp = C.POINTER(cfd_config)
+    st = C.c_int
+    sig = {
+        "cfd_create": ([cfgp, C.POINTER(C.c_void_p)], st),
+        "cfd_destroy": ([vp], None),
+        "cfd_state_numel": ([vp], C.c_int64),
+        "cfd_state_init": ([vp, dp, dp, vp], st),
+        "cfd_fill_halo": ([vp, dp, vp], st),
+        "cfd_rhs": ([vp, dp, dp, vp], st),
+        "cfd_compute_dt": ([vp, dp, dp, vp], st),
+        "cfd_rk3_step": ([vp, dp, C.c_double, dp, vp], st),
+        "cfd_advance": ([vp, dp, C.c_int32, C.c_double, dp, vp], st),
+        "cfd_advance_fixed": ([vp, dp, C.c_int32, C.c_double, vp], st),
+        "cfd_rhs_adjoint": ([vp, dp, dp, dp, vp], st),
+        "cfd_rk3_step_adjoint": ([vp, dp, C.c_double, dp, dp, vp], st),
+        "cfd_check": ([vp, C.POINTER(C.c_int32)], st),
+        "cfd_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != CFD_OK:
+        raise CfdError(rc, load().cfd_last_error().decode())
+
+
+def make_config(case) -> cfd_config:
+    c = cfd_config()
+    for i in range(3):
+        c.n[i] = int(case["n"][i])
+        c.lo[i] = float(case["lo"][i])
+        c.hi[i] = float(case["hi"][i])
+    c.nh = int(case.get("nh", 3))
+    c.gamma = float(case["gamma"])
+    c.mu = float(case.get("mu", 0.0))
+    c.prandtl = float(case.get("prandtl", 0.72))
+    c.cfl = float(case.get("cfl", 0.5))
+    for i in range(6):
+        c.bc[i] = int(case["bc"][i])
+    c.flags = int(case["flags"])
+    return c
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return C.c_void_p(0)
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), \
+        "expected a contiguous float64 CUDA tensor"
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- entry points
+def cfd_create(case):
+    h = C.c_void_p()
+    cfg = make_config(case)
+    _check(load().cfd_create(C.byref(cfg), C.byref(h)))
+    return h
+
+
+def cfd_destroy(h):
+    if h:
+        load().cfd_destroy(h)
+
+
+def cfd_state_numel(h):
+    return int(load().cfd_state_numel(h))
+
+
+def cfd_state_init(h, W, U, stream=None):
+    _check(load().cfd_state_init(h, _ptr(W), _ptr(U), _stream(stream)))
+
+
+def cfd_fill_halo(h, U, stream=None):
+    _check(load().cfd_fill_halo(h, _ptr(U), _stream(stream)))
+
+
+def cfd_rhs(h, U, R, stream=None):
+    _check(load().cfd_rhs(h, _ptr(U), _ptr(R), _stream(stream)))
+
+
+def cfd_compute_dt(h, U, dt_dev, stream=None):
+    _check(load().cfd_compute_dt(h, _ptr(U), _ptr(dt_dev), _stream(stream)))
+
+
+def cfd_rk3_step(h, U, dt=0.0, dt_used_dev=None, stream=None):
+    _check(load().cfd_rk3_step(h, _ptr(U), float(dt), _ptr(dt_used_dev), _stream(stream)))
+
+
+def cfd_advance(h, U, n_steps, t_end, t_dev, stream=None):
+    _check(load().cfd_advance(h, _ptr(U), int(n_steps), float(t_end), _ptr(t_dev), _stream(stream)))
+
+
+def cfd_advance_fixed(h, U, n_steps, dt, stream=None):
+    _check(load().cfd_advance_fixed(h, _ptr(U), int(n_steps), float(dt), _stream(stream)))
+
+
+def cfd_rhs_adjoint(h, U, Rbar, Ubar, stream=None):
+    _check(load().cfd_rhs_adjoint(h, _ptr(U), _ptr(Rbar), _ptr(Ubar), _stream(stream)))
+
+
+def cfd_rk3_step_adjoint(h, Un, dt, Ubar_np1, Ubar_n, stream=None):
+    _check(load().cfd_rk3_step_adjoint(h, _ptr(Un), float(dt), _ptr(Ubar_np1), _ptr(Ubar_n),
+                                       _stream(stream)))
+
+
+def cfd_check(h):
+    v = C.c_int32(0)
+    _check(load().cfd_check(h, C.byref(v)))
+    return int(v.value)
+
+
+def cfd_last_error():
+    return load().cfd_last_error().decode()

@@ -1,0 +1,406 @@
+// libcfd host side: the C ABI of include/cfd.h over the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/cfd.h"
+#include "kernels_fwd.hpp"
+
+using namespace cfd;
+
+namespace {
+
+thread_local std::string g_err;
+
+cfd_status fail(cfd_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define CFD_HIP(call)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess) return fail(CFD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CFD_LAUNCHED()                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = hipGetLastError();                                                   \
+    if (e_ != hipSuccess) return fail(CFD_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+unsigned grid_for(long long n, long long cap = 1 << 20) {
+  long long b = (n + kBlock - 1) / kBlock;
+  return (unsigned)std::max(1LL, std::min(b, cap));
+}
+
+}  // namespace
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const void* key[3] = {nullptr, nullptr, nullptr};
+  double kd[2] = {0.0, 0.0};
+  int mode = -1;
+};
+
+struct cfd_solver {
+  cfd_config cfg;
+  Geom g;
+  long long ncell = 0;  // padded cells
+  long long nint = 0;   // interior cells
+  double* U1 = nullptr;
+  double* U2 = nullptr;
+  double* P = nullptr;    // 6 x padded
+  double* Gv = nullptr;   // 9 x padded (viscous runs)
+  double* Racc = nullptr; // 5 x padded
+  double* A1 = nullptr;   // adjoint scratch (allocated on first adjoint call)
+  double* A2 = nullptr;
+  double* A3 = nullptr;
+  double* Wbar = nullptr;
+  DevCtl* ctl = nullptr;
+  hipStream_t cap = nullptr;
+  GraphCache graph;
+};
+
+static cfd_status validate(const cfd_config* c) {
+  if (!c) return fail(CFD_EINVAL, "config is NULL");
+  if (c->nh < 3) return fail(CFD_EINVAL, "nh must be >= 3");
+  for (int d = 0; d < 3; ++d) {
+    if (c->n[d] < 1) return fail(CFD_EINVAL, "n must be >= 1 on every axis");
+    if (c->n[d] > 1 && c->n[d] < c->nh) return fail(CFD_EINVAL, "active axes need n >= nh");
+    if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d]))
+      return fail(CFD_EINVAL, "box must satisfy lo < hi");
+    for (int s = 0; s < 2; ++s)
+      if (c->bc[2 * d + s] != CFD_BC_PERIODIC && c->bc[2 * d + s] != CFD_BC_ZERO_GRADIENT)
+        return fail(CFD_EINVAL, "unknown boundary type");
+    if (c->n[d] > 1 && ((c->bc[2 * d] == CFD_BC_PERIODIC) != (c->bc[2 * d + 1] == CFD_BC_PERIODIC)))
+      return fail(CFD_EINVAL, "periodic boundaries come in pairs");
+  }
+  if (c->n[0] == 1 && c->n[1] == 1 && c->n[2] == 1) return fail(CFD_EINVAL, "no active axis");
+  if (!(c->gamma > 1.0)) return fail(CFD_EINVAL, "gamma must be > 1");
+  if (!(c->mu >= 0.0)) return fail(CFD_EINVAL, "mu must be >= 0");
+  if (!(c->prandtl > 0.0)) return fail(CFD_EINVAL, "prandtl must be > 0");
+  if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return fail(CFD_EINVAL, "cfl must lie in (0, 1]");
+  if (c->flags & ~7u) return fail(CFD_EINVAL, "unknown physics flag");
+  return CFD_OK;
+}
+
+static void make_geom(const cfd_config& c, Geom& g) {
+  std::memset(&g, 0, sizeof(g));
+  double inv2 = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = c.n[d];
+    g.act[d] = c.n[d] > 1;
+    g.h[d] = g.act[d] ? c.nh : 0;
+    g.N[d] = g.n[d] + 2 * g.h[d];
+    g.dx[d] = (c.hi[d] - c.lo[d]) / c.n[d];
+    g.idx[d] = 1.0 / g.dx[d];
+    if (g.act[d]) inv2 += 1.0 / (g.dx[d] * g.dx[d]);
+  }
+  for (int s = 0; s < 6; ++s) g.bc[s] = c.bc[s];
+  g.s[0] = 1;
+  g.s[1] = g.N[0];
+  g.s[2] = (long long)g.N[0] * g.N[1];
+  g.vs = (long long)g.N[0] * g.N[1] * g.N[2];
+  g.gamma = c.gamma;
+  g.mu = c.mu;
+  g.kappa = c.gamma * c.mu / ((c.gamma - 1.0) * c.prandtl);
+  g.cfl = c.cfl;
+  g.visc_rate = 2.0 * std::max(4.0 / 3.0, c.gamma / c.prandtl) * inv2;
+  g.inviscid = (c.flags & CFD_F_INVISCID) ? 1 : 0;
+  g.viscous = ((c.flags & CFD_F_VISCOUS) && c.mu > 0.0) ? 1 : 0;
+  g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Enqueue the primitive pass of stage input Uk; `what` selects the CFL max
+// and the health check (PRIM_* bits).
+static cfd_status enqueue_prim(cfd_solver* s, const double* Uk, int what, const double* dtp,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_prim, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, Uk, s->P, s->g, s->ctl,
+                     what, dtp);
+  CFD_LAUNCHED();
+  return CFD_OK;
+}
+
+template <int D>
+static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t st) {
+  const Geom& g = s->g;
+  if (D == 0) {
+    const long long faces = (long long)(g.n[0] + 1) * g.n[1] * g.n[2];
+    const long long waves = (faces + 64 * kXIters - 2) / (64 * kXIters - 1);
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    switch (mode) {
+      case MODE_WRITE: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL(k_sweep_x<MODE_ACC>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL(k_sweep_x<MODE_ACC_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      default: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+    }
+  } else {
+    constexpr int AX = D == 0 ? 1 : D;
+    const int ot = AX == 1 ? 2 : 1;
+    const long long nseg = (g.n[AX] + kSeg - 1) / kSeg;
+    dim3 grid((g.n[0] + 63) / 64, (unsigned)(((long long)g.n[ot] * nseg + 3) / 4));
+    switch (mode) {
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+    }
+  }
+}
+
+// Enqueue the gradient pass and the per-axis sweeps after a primitive pass.
+// With rk set, the last active axis applies the stage update into io.Uout;
+// otherwise io.R receives the full right-hand side.
+static cfd_status enqueue_fluxes(cfd_solver* s, const StageIO& io, bool rk, hipStream_t st) {
+  const Geom& g = s->g;
+  if (g.viscous) {
+    hipLaunchKernelGGL(k_grad, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g,
+                       io.dtp);
+    CFD_LAUNCHED();
+  }
+  int first = -1, last = -1;
+  for (int d = 0; d < 3; ++d)
+    if (g.act[d]) {
+      if (first < 0) first = d;
+      last = d;
+    }
+  for (int d = 0; d < 3; ++d) {
+    if (!g.act[d]) continue;
+    int mode;
+    if (d == last && rk) mode = d == first ? MODE_WRITE_RK : MODE_ACC_RK;
+    else mode = d == first ? MODE_WRITE : MODE_ACC;
+    if (d == 0) launch_sweep<0>(s, mode, io, st);
+    else if (d == 1) launch_sweep<1>(s, mode, io, st);
+    else launch_sweep<2>(s, mode, io, st);
+    CFD_LAUNCHED();
+  }
+  return CFD_OK;
+}
+
+// Enqueue one TVD-RK3 step on U in place. fixed_dt > 0 fixes the step;
+// otherwise the CFL step of Un, clipped against *t_dev and t_end when t_dev
+// is given. dt_out (nullable) receives the step.
+static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double t_end, double* t_dev,
+                               double* dt_out, hipStream_t st) {
+  const double* dtp = &s->ctl->dt;
+  const bool cfl = !(fixed_dt > 0.0);
+  StageIO io{};
+  io.R = s->Racc;
+  io.Un = U;
+  io.dtp = dtp;
+  cfd_status rc;
+  // stage 1: U1 = Un + dt R(Un); the prim pass runs before dt is known
+  if ((rc = enqueue_prim(s, U, PRIM_HEALTH | (cfl ? PRIM_CFL : 0), nullptr, st))) return rc;
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out);
+  CFD_LAUNCHED();
+  io.Uk = U;
+  io.Uout = s->U1;
+  io.a = 0.0;
+  io.b = 1.0;
+  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt R(U1))
+  if ((rc = enqueue_prim(s, s->U1, 0, dtp, st))) return rc;
+  io.Uk = s->U1;
+  io.Uout = s->U2;
+  io.a = 0.75;
+  io.b = 0.25;
+  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2)), in place on U
+  if ((rc = enqueue_prim(s, s->U2, 0, dtp, st))) return rc;
+  io.Uk = s->U2;
+  io.Uout = U;
+  io.a = 1.0 / 3.0;
+  io.b = 2.0 / 3.0;
+  return enqueue_fluxes(s, io, true, st);
+}
+
+static cfd_status enqueue_fill_halo(cfd_solver* s, double* U, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_halo, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, U, s->g);
+  CFD_LAUNCHED();
+  return CFD_OK;
+}
+
+// Replay `n` copies of a captured single-step graph on stream st. The graph
+// is re-captured when its key (pointers and scalars) changes.
+static cfd_status run_graph(cfd_solver* s, double* U, int mode, double fixed_dt, double t_end, double* t_dev,
+                            int n, hipStream_t st) {
+  GraphCache& gc = s->graph;
+  const bool hit = gc.exec && gc.mode == mode && gc.key[0] == U && gc.key[1] == t_dev &&
+                   gc.kd[0] == fixed_dt && gc.kd[1] == t_end;
+  if (!hit) {
+    if (gc.exec) {
+      CFD_HIP(hipGraphExecDestroy(gc.exec));
+      gc.exec = nullptr;
+    }
+    hipGraph_t graph;
+    CFD_HIP(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
+    cfd_status rc = enqueue_step(s, U, fixed_dt, t_end, t_dev, nullptr, s->cap);
+    hipError_t ec = hipStreamEndCapture(s->cap, &graph);
+    if (rc) return rc;
+    if (ec != hipSuccess) return fail(CFD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    hipError_t ei = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      gc.exec = nullptr;
+      return fail(CFD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    gc.mode = mode;
+    gc.key[0] = U;
+    gc.key[1] = t_dev;
+    gc.kd[0] = fixed_dt;
+    gc.kd[1] = t_end;
+  }
+  for (int i = 0; i < n; ++i) CFD_HIP(hipGraphLaunch(gc.exec, st));
+  return CFD_OK;
+}
+
+// ===========================================================================
+extern "C" {
+
+const char* cfd_last_error(void) { return g_err.c_str(); }
+
+cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
+  if (!out) return fail(CFD_EINVAL, "out is NULL");
+  *out = nullptr;
+  cfd_status rc = validate(cfg);
+  if (rc) return rc;
+  cfd_solver* s = new (std::nothrow) cfd_solver();
+  if (!s) return fail(CFD_ENOMEM, "host allocation failed");
+  s->cfg = *cfg;
+  make_geom(*cfg, s->g);
+  s->ncell = s->g.vs;
+  s->nint = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
+  bool ok = hipMalloc(&s->U1, st) == hipSuccess && hipMalloc(&s->U2, st) == hipSuccess &&
+            hipMalloc(&s->Racc, st) == hipSuccess &&
+            hipMalloc(&s->P, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
+            hipMalloc(&s->ctl, sizeof(DevCtl)) == hipSuccess;
+  if (ok && s->g.viscous) ok = hipMalloc(&s->Gv, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    cfd_destroy(s);
+    return fail(CFD_ENOMEM, "device allocation failed");
+  }
+  if (hipMemset(s->ctl, 0, sizeof(DevCtl)) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    cfd_destroy(s);
+    return fail(CFD_EHIP, "solver initialisation failed");
+  }
+  *out = s;
+  return CFD_OK;
+}
+
+void cfd_destroy(cfd_solver* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
+  if (s->cap) (void)hipStreamDestroy(s->cap);
+  double* bufs[] = {s->U1, s->U2, s->P, s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar};
+  for (double* b : bufs)
+    if (b) (void)hipFree(b);
+  if (s->ctl) (void)hipFree(s->ctl);
+  delete s;
+}
+
+int64_t cfd_state_numel(const cfd_solver* s) { return s ? 5 * (int64_t)s->ncell : -1; }
+
+cfd_status cfd_state_init(cfd_solver* s, const double* W, double* U, void* stream) {
+  if (!s || !W || !U) return fail(CFD_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_state_init, dim3(grid_for(s->nint)), dim3(kBlock), 0, st, W, U, s->g);
+  CFD_LAUNCHED();
+  return enqueue_fill_halo(s, U, st);
+}
+
+cfd_status cfd_fill_halo(cfd_solver* s, double* U, void* stream) {
+  if (!s || !U) return fail(CFD_EINVAL, "NULL argument");
+  return enqueue_fill_halo(s, U, (hipStream_t)stream);
+}
+
+cfd_status cfd_rhs(cfd_solver* s, double* U, double* R, void* stream) {
+  if (!s || !U || !R) return fail(CFD_EINVAL, "NULL argument");
+  if (U == R) return fail(CFD_EINVAL, "U and R must not alias");
+  hipStream_t st = (hipStream_t)stream;
+  cfd_status rc;
+  if ((rc = enqueue_fill_halo(s, U, st))) return rc;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(5 * s->ncell)), dim3(kBlock), 0, st, R, 5 * s->ncell);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_prim(s, U, 0, nullptr, st))) return rc;
+  StageIO io{};
+  io.R = R;
+  io.dtp = nullptr;
+  return enqueue_fluxes(s, io, false, st);
+}
+
+cfd_status cfd_compute_dt(cfd_solver* s, const double* U, double* dt_dev, void* stream) {
+  if (!s || !U || !dt_dev) return fail(CFD_EINVAL, "NULL argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_cfl, dim3(grid_for(s->nint)), dim3(kBlock), 0, st, U, s->g, s->ctl);
+  CFD_LAUNCHED();
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, s->ctl, s->g.cfl, 0.0, 0.0, (double*)nullptr, dt_dev);
+  CFD_LAUNCHED();
+  return CFD_OK;
+}
+
+cfd_status cfd_rk3_step(cfd_solver* s, double* U, double dt, double* dt_used_dev, void* stream) {
+  if (!s || !U) return fail(CFD_EINVAL, "NULL argument");
+  if (!std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be finite");
+  hipStream_t st = (hipStream_t)stream;
+  cfd_status rc = enqueue_step(s, U, dt > 0.0 ? dt : 0.0, 0.0, nullptr, dt_used_dev, st);
+  if (rc) return rc;
+  return enqueue_fill_halo(s, U, st);
+}
+
+cfd_status cfd_advance(cfd_solver* s, double* U, int32_t n_steps, double t_end, double* t_dev,
+                       void* stream) {
+  if (!s || !U || !t_dev) return fail(CFD_EINVAL, "NULL argument");
+  if (n_steps < 0) return fail(CFD_EINVAL, "n_steps must be >= 0");
+  if (n_steps == 0) return CFD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  cfd_status rc = run_graph(s, U, 1, 0.0, t_end > 0.0 ? t_end : 0.0, t_dev, n_steps, st);
+  if (rc) return rc;
+  return enqueue_fill_halo(s, U, st);
+}
+
+cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double dt, void* stream) {
+  if (!s || !U) return fail(CFD_EINVAL, "NULL argument");
+  if (n_steps < 0 || !(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "need n_steps >= 0 and dt > 0");
+  if (n_steps == 0) return CFD_OK;
+  hipStream_t st = (hipStream_t)stream;
+  cfd_status rc = run_graph(s, U, 2, dt, 0.0, nullptr, n_steps, st);
+  if (rc) return rc;
+  return enqueue_fill_halo(s, U, st);
+}
+
+cfd_status cfd_check(cfd_solver* s, int32_t* status_out) {
+  if (!s || !status_out) return fail(CFD_EINVAL, "NULL argument");
+  CFD_HIP(hipDeviceSynchronize());
+  int v = 0;
+  CFD_HIP(hipMemcpy(&v, &s->ctl->status, sizeof(int), hipMemcpyDeviceToHost));
+  const int zero = 0;
+  CFD_HIP(hipMemcpy(&s->ctl->status, &zero, sizeof(int), hipMemcpyHostToDevice));
+  *status_out = v;
+  return CFD_OK;
+}
+
+cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
+  (void)U; (void)Rbar; (void)Ubar; (void)stream;
+  if (!s) return fail(CFD_EINVAL, "NULL argument");
+  return fail(CFD_EUNSUPPORTED, "rhs adjoint not built yet");
+}
+
+cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
+                                double* Ubar_n, void* stream) {
+  (void)Un; (void)dt; (void)Ubar_np1; (void)Ubar_n; (void)stream;
+  if (!s) return fail(CFD_EINVAL, "NULL argument");
+  return fail(CFD_EUNSUPPORTED, "step adjoint not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,190 @@
+// Device building blocks of the finite-volume right-hand side (gfx950).
+//
+// Face-local arithmetic only: WENO5-JS reconstruction, HLLC flux with Einfeldt
+// signal speeds, the fourth-order dissipative flux, and the cell-local
+// primitive conversion. The sweep kernels feed these from registers; face
+// fluxes never leave the register file.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cfd {
+
+// Grid geometry and physics constants, passed to every kernel by value.
+struct Geom {
+  int n[3];        // interior cells
+  int h[3];        // halo width per axis (0 on inactive axes)
+  int N[3];        // padded extents
+  long long s[3];  // element strides of the padded block: 1, Nx, Nx*Ny
+  long long vs;    // stride between variables: Nx*Ny*Nz
+  double dx[3];
+  double idx[3];   // 1/dx
+  int act[3];      // axis active (n > 1)
+  int bc[6];       // boundary types, x-, x+, y-, y+, z-, z+
+  double gamma;
+  double mu;
+  double kappa;    // gamma mu / ((gamma - 1) Pr): lambda grad T = kappa grad(p/rho)
+  double cfl;
+  double visc_rate;  // 2 max(4/3, gamma/Pr) sum_d dx_d^-2 (times mu/rho gives the diffusive rate)
+  int inviscid, viscous, heat;
+};
+
+__device__ __forceinline__ double sq(double x) { return x * x; }
+
+// Cell index of interior-relative coordinates (i,j,k) (halo cells negative).
+__device__ __forceinline__ long long cell_at(const Geom& g, int i, int j, int k) {
+  return (long long)(k + g.h[2]) * g.s[2] + (long long)(j + g.h[1]) * g.s[1] + (i + g.h[0]);
+}
+
+// Interior source coordinate of a (possibly halo) coordinate c on an axis with
+// n cells: periodic image or zero-gradient clamp (§3.7). Applying it per axis
+// reproduces the axis-by-axis halo fill, corners included.
+__device__ __forceinline__ int bc_source(int c, int n, int bc_lo, int bc_hi) {
+  if (c < 0) return bc_lo == 0 ? c + n : 0;
+  if (c >= n) return bc_hi == 0 ? c - n : n - 1;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// WENO5-JS (Jiang & Shu 1996) value at the right face of the centre cell c of
+// the stencil (a,b,c,d,e); smoothness indicators beta_k, candidates p_k,
+// linear weights (0.1, 0.6, 0.3), alpha_k = d_k/(1e-6 + beta_k)^2.
+__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
+  constexpr double k13 = 13.0 / 12.0;
+  constexpr double eps = 1.0e-6;
+  const double b0 = k13 * sq(a - 2.0 * b + c) + 0.25 * sq(a - 4.0 * b + 3.0 * c);
+  const double b1 = k13 * sq(b - 2.0 * c + d) + 0.25 * sq(b - d);
+  const double b2 = k13 * sq(c - 2.0 * d + e) + 0.25 * sq(3.0 * c - 4.0 * d + e);
+  const double p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  const double p1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  const double p2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  const double a0 = 0.1 / sq(eps + b0);
+  const double a1 = 0.6 / sq(eps + b1);
+  const double a2 = 0.3 / sq(eps + b2);
+  return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+// ---------------------------------------------------------------------------
+// HLLC flux (Toro, Spruce & Speares 1994) with Einfeldt (1988) speeds across a
+// face normal to axis D. Inputs: reconstructed primitive states (rho, u, v, w, p)
+// left/right. Output in physical slot order. The four-way choice
+// (0 <= S_L | S_L < 0 <= S* | S* < 0 < S_R | S_R <= 0) is a select, so
+// lanes never diverge; unselected star states may be non-finite and are
+// discarded by the select.
+template <int D>
+__device__ __forceinline__ void hllc(double gamma, const double* WL, const double* WR, double* F) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const double rL = WL[0], uL = WL[1 + D], aL = WL[1 + T1], bL = WL[1 + T2], pL = WL[4];
+  const double rR = WR[0], uR = WR[1 + D], aR = WR[1 + T1], bR = WR[1 + T2], pR = WR[4];
+  const double gm1i = 1.0 / (gamma - 1.0);
+  const double EL = pL * gm1i + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+  const double ER = pR * gm1i + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+  const double cL = sqrt(gamma * pL / rL);
+  const double cR = sqrt(gamma * pR / rR);
+  const double sL = sqrt(rL), sR = sqrt(rR);
+  const double isum = 1.0 / (sL + sR);
+  const double ubar = (sL * uL + sR * uR) * isum;
+  const double eta2 = 0.5 * sL * sR * isum * isum;
+  const double dbar = sqrt((sL * cL * cL + sR * cR * cR) * isum + eta2 * sq(uR - uL));
+  const double SL = fmin(uL - cL, ubar - dbar);
+  const double SR = fmax(uR + cR, ubar + dbar);
+  const double mL = rL * (SL - uL), mR = rR * (SR - uR);  // mass fluxes relative to the waves
+  const double Ss = (pR - pL + uL * mL - uR * mR) / (mL - mR);
+  // star states
+  const double fL = mL / (SL - Ss);
+  const double fR = mR / (SR - Ss);
+  const double eL = EL / rL + (Ss - uL) * (Ss + pL / mL);
+  const double eR = ER / rR + (Ss - uR) * (Ss + pR / mR);
+  // physical fluxes
+  const double FL0 = rL * uL, FR0 = rR * uR;
+  const double FL[5] = {FL0, FL0 * uL + pL, FL0 * aL, FL0 * bL, uL * (EL + pL)};
+  const double FR[5] = {FR0, FR0 * uR + pR, FR0 * aR, FR0 * bR, uR * (ER + pR)};
+  const double UL[5] = {rL, rL * uL, rL * aL, rL * bL, EL};
+  const double UR[5] = {rR, rR * uR, rR * aR, rR * bR, ER};
+  const double UsL[5] = {fL, fL * Ss, fL * aL, fL * bL, fL * eL};
+  const double UsR[5] = {fR, fR * Ss, fR * aR, fR * bR, fR * eR};
+  const bool useL = 0.0 <= SL;
+  const bool useSL = !useL && 0.0 <= Ss;
+  const bool useSR = !useL && !useSL && 0.0 < SR;
+  double Fn[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double fsl = FL[v] + SL * (UsL[v] - UL[v]);
+    const double fsr = FR[v] + SR * (UsR[v] - UR[v]);
+    Fn[v] = useL ? FL[v] : (useSL ? fsl : (useSR ? fsr : FR[v]));
+  }
+  F[0] = Fn[0];
+  F[1 + D] = Fn[1];
+  F[1 + T1] = Fn[2];
+  F[1 + T2] = Fn[3];
+  F[4] = Fn[4];
+}
+
+// ---------------------------------------------------------------------------
+// Stencil window of one face between window cells 2 and 3 (cells f-2 .. f+3
+// along the face normal): primitive values q[c][v] (rho,u,v,w,p) and, for the
+// four cells f-1 .. f+2, T~ = p/rho and the four tangential velocity
+// derivatives the face needs (cell-centred, fourth order):
+//   tg[c][0] = d u_D / d x_T1,  tg[c][1] = d u_T1 / d x_T1,
+//   tg[c][2] = d u_D / d x_T2,  tg[c][3] = d u_T2 / d x_T2.
+struct FaceWindow {
+  double q[6][5];
+  double T[4];
+  double tg[4][4];
+};
+
+// Numerical flux G = F - F^d across the face (§3.3, §3.4); the dissipative
+// part uses the fourth-order face derivative along the normal, the centred
+// derivatives interpolated with the fourth-order central interpolation along
+// the normal, and face velocities from the same interpolation.
+template <int D>
+__device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (g.inviscid) {
+    double WL[5], WR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      WL[v] = weno5(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
+      WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
+    }
+    hllc<D>(g.gamma, WL, WR, F);
+  }
+  if (g.viscous || g.heat) {
+    const double i24 = g.idx[D] / 24.0;
+    auto dn = [&](double a, double b, double c, double d) { return (a - 27.0 * b + 27.0 * c - d) * i24; };
+    auto rc4 = [&](double a, double b, double c, double d) { return (-a + 9.0 * b + 9.0 * c - d) / 16.0; };
+    double Fd1 = 0.0, Fd2 = 0.0, Fd3 = 0.0, Fd4 = 0.0;  // slots D, T1, T2 momentum; energy
+    if (g.viscous) {
+      // normal derivatives of the three velocity components
+      const double dD = dn(w.q[1][1 + D], w.q[2][1 + D], w.q[3][1 + D], w.q[4][1 + D]);
+      const double d1 = dn(w.q[1][1 + T1], w.q[2][1 + T1], w.q[3][1 + T1], w.q[4][1 + T1]);
+      const double d2 = dn(w.q[1][1 + T2], w.q[2][1 + T2], w.q[3][1 + T2], w.q[4][1 + T2]);
+      const double uD_t1 = rc4(w.tg[0][0], w.tg[1][0], w.tg[2][0], w.tg[3][0]);
+      const double u1_t1 = rc4(w.tg[0][1], w.tg[1][1], w.tg[2][1], w.tg[3][1]);
+      const double uD_t2 = rc4(w.tg[0][2], w.tg[1][2], w.tg[2][2], w.tg[3][2]);
+      const double u2_t2 = rc4(w.tg[0][3], w.tg[1][3], w.tg[2][3], w.tg[3][3]);
+      const double div = dD + u1_t1 + u2_t2;
+      const double tDD = g.mu * (dD + dD) - (2.0 / 3.0) * g.mu * div;
+      const double tD1 = g.mu * (uD_t1 + d1);
+      const double tD2 = g.mu * (uD_t2 + d2);
+      const double ufD = rc4(w.q[1][1 + D], w.q[2][1 + D], w.q[3][1 + D], w.q[4][1 + D]);
+      const double uf1 = rc4(w.q[1][1 + T1], w.q[2][1 + T1], w.q[3][1 + T1], w.q[4][1 + T1]);
+      const double uf2 = rc4(w.q[1][1 + T2], w.q[2][1 + T2], w.q[3][1 + T2], w.q[4][1 + T2]);
+      Fd1 = tDD;
+      Fd2 = tD1;
+      Fd3 = tD2;
+      Fd4 = ufD * tDD + uf1 * tD1 + uf2 * tD2;
+    }
+    if (g.heat) Fd4 += g.kappa * dn(w.T[0], w.T[1], w.T[2], w.T[3]);
+    F[1 + D] -= Fd1;
+    F[1 + T1] -= Fd2;
+    F[1 + T2] -= Fd3;
+    F[4] -= Fd4;
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) G[v] = F[v];
+}
+
+}  // namespace cfd
