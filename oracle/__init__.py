@@ -226,3 +226,36 @@ def grad_kinetic_energy(case, W0, n_steps, dt):
     L = C.c_double(0.0)
     _ok(lib.oracle_grad_ke(C.byref(cfg), _ptr(W0), int(n_steps), float(dt), C.byref(L), _ptr(g)))
     return L.value, g
+
+
+def rhs_rounding_bound(case, U, k=16.0):
+    """Per-variable absolute tolerance for comparing two evaluations of the
+    right-hand side that differ only in rounding (operation order, fused
+    multiply-adds). R_i is a difference of face fluxes whose magnitude is
+    bounded by |F_d| + (|u_d| + c)|U| (physical flux plus the Riemann solver's
+    dissipation), so rounding errors of relative size eps in those fluxes give
+    errors up to about eps * sum_d 2 (|F_d| + (|u_d| + c)|U|)/dx_d in R_i,
+    however small R_i itself is. Returns k * eps * max_i of that scale, per
+    conservative variable (k covers the few roundings per flux)."""
+    Ui = interior(case, np.asarray(U, dtype=np.float64))
+    g = float(case["gamma"])
+    rho = Ui[0]
+    u = Ui[1:4] / rho
+    E = Ui[4]
+    p = (g - 1.0) * (E - 0.5 * (Ui[1] * u[0] + Ui[2] * u[1] + Ui[3] * u[2]))
+    c = np.sqrt(np.abs(g * p / rho))
+    cons = [rho, Ui[1], Ui[2], Ui[3], E]
+    scale = np.zeros(5)
+    acc = [np.zeros_like(rho) for _ in range(5)]
+    for d in range(3):
+        if int(case["n"][d]) <= 1:
+            continue
+        dx = (case["hi"][d] - case["lo"][d]) / case["n"][d]
+        ud = u[d]
+        F = [rho * ud, Ui[1] * ud, Ui[2] * ud, Ui[3] * ud, ud * (E + p)]
+        F[1 + d] = F[1 + d] + p
+        for v in range(5):
+            acc[v] += 2.0 * (np.abs(F[v]) + (np.abs(ud) + c) * np.abs(cons[v])) / dx
+    for v in range(5):
+        scale[v] = float(acc[v].max())
+    return k * np.finfo(np.float64).eps * scale

@@ -75,9 +75,13 @@ def test_rhs_matches_oracle(Solver, name):
     Uo = oracle.state_init(case, W)
     Ro = oracle.rhs(case, Uo)
     assert normwise(U.cpu().numpy(), Uo) <= 1e-15
-    e = normwise(R, Ro)
     s.close()
-    assert e <= TOL_ONE, (name, e)
+    # normwise 1e-12, or the rounding bound of the flux differences where the
+    # right-hand side is small next to the fluxes it is the difference of
+    bound = oracle.rhs_rounding_bound(case, Uo)
+    for v in range(5):
+        err = float(np.max(np.abs(R[v] - Ro[v])))
+        assert err <= max(TOL_ONE * float(np.max(np.abs(Ro[v]))), bound[v]), (name, v, err, bound[v])
 
 
 @pytest.mark.parametrize("name", ["tgv_ragged", "shocky3d", "smooth_mixed_bc", "kh64x48", "sod200"])
