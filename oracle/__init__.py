@@ -62,6 +62,7 @@ def _load():
     lib.oracle_hllc.argtypes = [d, dp, dp, C.c_int, dp]
     lib.oracle_hllc.restype = None
     lib.oracle_opcount.argtypes = [cfgp, dp, dp]
+    lib.oracle_opcount_parts.argtypes = [cfgp, dp, dp]
     lib.oracle_vjp_rhs.argtypes = [cfgp, dp, dp, dp]
     lib.oracle_vjp_rk3_step.argtypes = [cfgp, dp, d, dp, dp]
     lib.oracle_grad_ke.argtypes = [cfgp, dp, C.c_int, d, dp, dp]
@@ -194,6 +195,17 @@ def opcount(case, U):
     out = np.zeros(5)
     _ok(lib.oracle_opcount(C.byref(cfg), _ptr(U), _ptr(out)))
     return dict(zip(("add", "mul", "div", "sqrt", "cmp"), out.tolist()))
+
+
+def opcount_parts(case, U):
+    """Flops (add+mul+div+sqrt) of the parts of one right-hand side:
+    {"prim_per_cell", "face": [x, y, z]} (one face flux each)."""
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.zeros(4)
+    _ok(lib.oracle_opcount_parts(C.byref(cfg), _ptr(U), _ptr(out)))
+    return {"prim_per_cell": float(out[0]), "face": [float(x) for x in out[1:]]}
 
 
 def vjp_rhs(case, U, Rbar):

@@ -298,11 +298,34 @@ void dissipative_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int
 }
 
 // --------------------------------------------------------------------------
+// Numerical flux G = F - F^d across the face between cells (a) and (a)+1
+// along axis d: F is the convective flux of the high-order Godunov approach
+// (§3.3: reconstruct W with WENO5-JS left and right of the face, convert,
+// HLLC), F^d the dissipative flux.
+template <class R>
+void face_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d, const int a[3],
+               bool inviscid, bool viscous, bool heat, R G[5]) {
+  const std::vector<R>* q[5] = {&W.rho, &W.u[0], &W.u[1], &W.u[2], &W.p};
+  R Fc[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
+  if (inviscid) {
+    R WL[5], WR[5];
+    for (int v = 0; v < 5; ++v) {
+      const std::vector<R>& s = *q[v];
+      auto at = [&](int o) { return s[g.shift(d, a[0], a[1], a[2], o)]; };
+      WL[v] = weno5_js(at(-2), at(-1), at(0), at(1), at(2));
+      WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
+    }
+    hllc_flux(c.gamma, WL, WR, d, Fc);
+  }
+  R Fd[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
+  if (viscous || heat) dissipative_flux(c, g, W, d, a[0], a[1], a[2], viscous, heat, Fd);
+  for (int v = 0; v < 5; ++v) G[v] = Fc[v] - Fd[v];
+}
+
+// --------------------------------------------------------------------------
 // Right-hand side of the semi-discrete finite-volume scheme (§3.1, Eq. FVD):
-//   dU_i/dt = - sum_d (G_{i+1/2} - G_{i-1/2}) / dx_d,   G = F - F^d,
-// where F is the convective numerical flux of the high-order Godunov approach
-// (§3.3: reconstruct W with WENO5-JS, convert, HLLC) and F^d the dissipative
-// flux. Axes are treated one after the other (dimension by dimension, §3.1).
+//   dU_i/dt = - sum_d (G_{i+1/2} - G_{i-1/2}) / dx_d,   G = F - F^d.
+// Axes are treated one after the other (dimension by dimension, §3.1).
 // Each face flux is computed once and used by both neighbouring cells.
 // U is the padded state; its halos are refreshed here (Algorithm 2 refills
 // boundaries before every right-hand-side evaluation). R is padded; its halo
@@ -316,7 +339,6 @@ void rhs(const oracle_cfg& c, const Grid& g, std::vector<R>& U, std::vector<R>& 
   const bool inviscid = c.flags & F_INVISCID;
   const bool viscous = (c.flags & F_VISCOUS) && c.mu > 0.0;
   const bool heat = (c.flags & F_HEAT) && c.mu > 0.0;
-  const std::vector<R>* q[5] = {&W.rho, &W.u[0], &W.u[1], &W.u[2], &W.p};
   for (int d = 0; d < 3; ++d) {
     if (!g.act[d]) continue;
     const int n = g.n[d];
@@ -330,20 +352,7 @@ void rhs(const oracle_cfg& c, const Grid& g, std::vector<R>& U, std::vector<R>& 
           for (int f = -1; f < n; ++f) {
             int a[3] = {i, j, k};
             a[d] = f;
-            R Fc[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
-            if (inviscid) {
-              R WL[5], WR[5];
-              for (int v = 0; v < 5; ++v) {
-                const std::vector<R>& s = *q[v];
-                auto at = [&](int o) { return s[g.shift(d, a[0], a[1], a[2], o)]; };
-                WL[v] = weno5_js(at(-2), at(-1), at(0), at(1), at(2));
-                WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
-              }
-              hllc_flux(c.gamma, WL, WR, d, Fc);
-            }
-            R Fd[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
-            if (viscous || heat) dissipative_flux(c, g, W, d, a[0], a[1], a[2], viscous, heat, Fd);
-            for (int v = 0; v < 5; ++v) G[(size_t)(f + 1) * 5 + v] = Fc[v] - Fd[v];
+            face_flux(c, g, W, d, a, inviscid, viscous, heat, &G[(size_t)(f + 1) * 5]);
           }
           for (int m = 0; m < n; ++m) {
             int a[3] = {i, j, k};
@@ -560,6 +569,35 @@ int oracle_opcount(const oracle_cfg* c, const double* U, double* out) {
   rhs(*c, g, u, r);
   const OpTally t = tally();
   out[0] = t.add; out[1] = t.mul; out[2] = t.div; out[3] = t.sqrt; out[4] = t.cmp;
+  return 0;
+}
+
+// Operation counts (add+mul+div+sqrt) of the parts of one right-hand side,
+// evaluated on state U: out[0] primitive conversion per cell, out[1..3] one
+// face flux G normal to x, y, z at an interior face (0 for inactive axes).
+int oracle_opcount_parts(const oracle_cfg* c, const double* U, double* out) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  std::vector<OpCount> u(5 * g.ncell);
+  for (long q = 0; q < 5 * g.ncell; ++q) u[q] = OpCount(U[q]);
+  fill_halo(*c, g, u);
+  auto flops = [](const OpTally& t) { return t.add + t.mul + t.div + t.sqrt; };
+  tally() = OpTally();
+  Prims<OpCount> W;
+  primitives(*c, g, u, W);
+  out[0] = flops(tally()) / (double)g.ncell;
+  const bool inviscid = c->flags & F_INVISCID;
+  const bool viscous = (c->flags & F_VISCOUS) && c->mu > 0.0;
+  const bool heat = (c->flags & F_HEAT) && c->mu > 0.0;
+  for (int d = 0; d < 3; ++d) {
+    out[1 + d] = 0.0;
+    if (!g.act[d]) continue;
+    int a[3] = {g.n[0] / 2, g.n[1] / 2, g.n[2] / 2};
+    OpCount G[5];
+    tally() = OpTally();
+    face_flux(*c, g, W, d, a, inviscid, viscous, heat, G);
+    out[1 + d] = flops(tally());
+  }
   return 0;
 }
 

@@ -43,7 +43,7 @@ class cfd_config(C.Structure):
 EXPORTS = (
     "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_fill_halo", "cfd_rhs",
     "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
-    "cfd_rk3_step_adjoint", "cfd_check", "cfd_last_error",
+    "cfd_rk3_step_adjoint", "cfd_profile_stage", "cfd_check", "cfd_last_error",
 )
 
 _lib = None
@@ -74,6 +74,7 @@ def load():
         "cfd_advance_fixed": ([vp, dp, C.c_int32, C.c_double, vp], st),
         "cfd_rhs_adjoint": ([vp, dp, dp, dp, vp], st),
         "cfd_rk3_step_adjoint": ([vp, dp, C.c_double, dp, dp, vp], st),
+        "cfd_profile_stage": ([vp, dp, C.c_int32, C.POINTER(C.c_double), vp], st),
         "cfd_check": ([vp, C.POINTER(C.c_int32)], st),
         "cfd_last_error": ([], C.c_char_p),
     }
@@ -177,6 +178,13 @@ def cfd_rhs_adjoint(h, U, Rbar, Ubar, stream=None):
 def cfd_rk3_step_adjoint(h, Un, dt, Ubar_np1, Ubar_n, stream=None):
     _check(load().cfd_rk3_step_adjoint(h, _ptr(Un), float(dt), _ptr(Ubar_np1), _ptr(Ubar_n),
                                        _stream(stream)))
+
+
+def cfd_profile_stage(h, U, reps=5, stream=None):
+    """Average ms of the stage kernels [prim, grad, sweep_x, sweep_y, sweep_z]."""
+    out = (C.c_double * 5)()
+    _check(load().cfd_profile_stage(h, _ptr(U), int(reps), out, _stream(stream)))
+    return list(out)
 
 
 def cfd_check(h):

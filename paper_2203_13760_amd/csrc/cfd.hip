@@ -390,6 +390,65 @@ cfd_status cfd_check(cfd_solver* s, int32_t* status_out) {
   return CFD_OK;
 }
 
+cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, double* ms_out, void* stream) {
+  if (!s || !U || !ms_out || reps < 1) return fail(CFD_EINVAL, "bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  const Geom& g = s->g;
+  // a fixed nonzero step so that the stage kernels do their work
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, s->ctl, g.cfl, 1e-12, 0.0, (double*)nullptr,
+                     (double*)nullptr);
+  CFD_LAUNCHED();
+  StageIO io{};
+  io.R = s->Racc;
+  io.Un = U;
+  io.Uk = U;
+  io.Uout = s->U2;
+  io.a = 0.75;
+  io.b = 0.25;
+  io.dtp = &s->ctl->dt;
+  int first = -1, last = -1;
+  for (int d = 0; d < 3; ++d)
+    if (g.act[d]) {
+      if (first < 0) first = d;
+      last = d;
+    }
+  hipEvent_t ev[6];
+  for (int e = 0; e < 6; ++e) CFD_HIP(hipEventCreate(&ev[e]));
+  double acc[5] = {0, 0, 0, 0, 0};
+  cfd_status rc = CFD_OK;
+  for (int r = 0; r < reps && rc == CFD_OK; ++r) {
+    (void)hipEventRecord(ev[0], st);
+    hipLaunchKernelGGL(k_prim, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0,
+                       io.dtp);
+    (void)hipEventRecord(ev[1], st);
+    if (g.viscous)
+      hipLaunchKernelGGL(k_grad, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, (const double*)s->P, s->Gv,
+                         g, io.dtp);
+    (void)hipEventRecord(ev[2], st);
+    for (int d = 0; d < 3; ++d) {
+      if (g.act[d]) {
+        int mode = d == last ? (d == first ? MODE_WRITE_RK : MODE_ACC_RK) : (d == first ? MODE_WRITE : MODE_ACC);
+        if (d == 0) launch_sweep<0>(s, mode, io, st);
+        else if (d == 1) launch_sweep<1>(s, mode, io, st);
+        else launch_sweep<2>(s, mode, io, st);
+      }
+      (void)hipEventRecord(ev[3 + d], st);
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+      rc = fail(CFD_EHIP, "profiled stage failed");
+      break;
+    }
+    for (int k = 0; k < 5; ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      acc[k] += ms;
+    }
+  }
+  for (int e = 0; e < 6; ++e) (void)hipEventDestroy(ev[e]);
+  for (int k = 0; k < 5; ++k) ms_out[k] = acc[k] / reps;
+  return rc;
+}
+
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
   (void)U; (void)Rbar; (void)Ubar; (void)stream;
   if (!s) return fail(CFD_EINVAL, "NULL argument");

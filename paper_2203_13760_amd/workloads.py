@@ -130,13 +130,13 @@ def isotropic_turbulence(n, seed=2203, k0=4.0, mach_t=0.3, re_lambda=100.0, gamm
     E = kmag ** 4 * np.exp(-2.0 * k2 / (k0 * k0))
     amp = np.where(k2 == 0, 0.0, np.sqrt(E / (4.0 * np.pi * k2s)))
     uh = [a * amp for a in uh]
-    vel = [np.fft.irfftn(a, s=(n, n, n)) for a in uh]
+    vel = [np.fft.irfftn(a, s=(n, n, n), axes=(0, 1, 2)) for a in uh]
     urms = math.sqrt(sum(float(np.mean(f * f)) for f in vel) / 3.0)
     vel = [f / urms for f in vel]
     uh = [a / urms for a in uh]
     uprime = 1.0
     # Taylor microscale from the spectral derivative du/dx
-    dudx = np.fft.irfftn(1j * KX * uh[0], s=(n, n, n))
+    dudx = np.fft.irfftn(1j * KX * uh[0], s=(n, n, n), axes=(0, 1, 2))
     lam = uprime / math.sqrt(float(np.mean(dudx * dudx)))
     rho0 = 1.0
     c = math.sqrt(3.0) * uprime / mach_t
