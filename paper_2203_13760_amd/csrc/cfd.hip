@@ -38,6 +38,11 @@ unsigned grid_for(long long n, long long cap = 1 << 20) {
   return (unsigned)std::max(1LL, std::min(b, cap));
 }
 
+// Plane-indexed launch over the padded grid (see PlaneIdx).
+dim3 plane_grid(const Geom& g) {
+  return dim3((unsigned)(((long long)g.N[0] * g.N[1] + kBlock - 1) / kBlock), (unsigned)g.N[2]);
+}
+
 }  // namespace
 
 struct GraphCache {
@@ -61,6 +66,8 @@ struct cfd_solver {
   double* A2 = nullptr;
   double* A3 = nullptr;
   double* Wbar = nullptr;
+  double* partial = nullptr;  // CFL rate maxima, one per block of a plane-indexed launch
+  int npart = 0;
   DevCtl* ctl = nullptr;
   hipStream_t cap = nullptr;
   GraphCache graph;
@@ -86,6 +93,15 @@ static cfd_status validate(const cfd_config* c) {
   if (!(c->prandtl > 0.0)) return fail(CFD_EINVAL, "prandtl must be > 0");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return fail(CFD_EINVAL, "cfl must lie in (0, 1]");
   if (c->flags & ~7u) return fail(CFD_EINVAL, "unknown physics flag");
+  // index ranges of the kernels: faces per axis and padded planes in 32 bits,
+  // padded z extent within the launch grid's y limit
+  long long N[3];
+  for (int d = 0; d < 3; ++d) N[d] = c->n[d] > 1 ? c->n[d] + 2LL * c->nh : 1;
+  for (int d = 0; d < 3; ++d) {
+    long long faces = (long long)c->n[0] * c->n[1] * c->n[2] / c->n[d] * (c->n[d] + 1);
+    if (faces >= (1LL << 31)) return fail(CFD_EINVAL, "grid too large: faces per axis must fit in 31 bits");
+  }
+  if (N[0] * N[1] >= (1LL << 31) || N[2] > 65535) return fail(CFD_EINVAL, "grid too large for the launch shape");
   return CFD_OK;
 }
 
@@ -107,6 +123,7 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.s[2] = (long long)g.N[0] * g.N[1];
   g.vs = (long long)g.N[0] * g.N[1] * g.N[2];
   g.gamma = c.gamma;
+  g.gm1i = 1.0 / (c.gamma - 1.0);
   g.mu = c.mu;
   g.kappa = c.gamma * c.mu / ((c.gamma - 1.0) * c.prandtl);
   g.cfl = c.cfl;
@@ -121,8 +138,8 @@ static void make_geom(const cfd_config& c, Geom& g) {
 // and the health check (PRIM_* bits).
 static cfd_status enqueue_prim(cfd_solver* s, const double* Uk, int what, const double* dtp,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_prim, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, Uk, s->P, s->g, s->ctl,
-                     what, dtp);
+  hipLaunchKernelGGL(k_prim, plane_grid(s->g), dim3(kBlock), 0, st, Uk, s->P, s->g, s->ctl, what, dtp,
+                     s->partial);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -160,8 +177,7 @@ static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t
 static cfd_status enqueue_fluxes(cfd_solver* s, const StageIO& io, bool rk, hipStream_t st) {
   const Geom& g = s->g;
   if (g.viscous) {
-    hipLaunchKernelGGL(k_grad, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g,
-                       io.dtp);
+    hipLaunchKernelGGL(k_grad, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
     CFD_LAUNCHED();
   }
   int first = -1, last = -1;
@@ -197,7 +213,8 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   cfd_status rc;
   // stage 1: U1 = Un + dt R(Un); the prim pass runs before dt is known
   if ((rc = enqueue_prim(s, U, PRIM_HEALTH | (cfl ? PRIM_CFL : 0), nullptr, st))) return rc;
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out);
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out,
+                     (const double*)s->partial, s->npart);
   CFD_LAUNCHED();
   io.Uk = U;
   io.Uout = s->U1;
@@ -221,7 +238,7 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
 }
 
 static cfd_status enqueue_fill_halo(cfd_solver* s, double* U, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_halo, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, U, s->g);
+  hipLaunchKernelGGL(k_fill_halo, plane_grid(s->g), dim3(kBlock), 0, st, U, s->g);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -281,6 +298,11 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
             hipMalloc(&s->Racc, st) == hipSuccess &&
             hipMalloc(&s->P, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
             hipMalloc(&s->ctl, sizeof(DevCtl)) == hipSuccess;
+  {
+    const dim3 pg = plane_grid(s->g);
+    s->npart = (int)(pg.x * pg.y);
+    ok = ok && hipMalloc(&s->partial, sizeof(double) * (size_t)s->npart) == hipSuccess;
+  }
   if (ok && s->g.viscous) ok = hipMalloc(&s->Gv, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -302,7 +324,7 @@ void cfd_destroy(cfd_solver* s) {
   (void)hipDeviceSynchronize();
   if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
-  double* bufs[] = {s->U1, s->U2, s->P, s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar};
+  double* bufs[] = {s->U1, s->U2, s->P, s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->partial};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (s->ctl) (void)hipFree(s->ctl);
@@ -314,7 +336,7 @@ int64_t cfd_state_numel(const cfd_solver* s) { return s ? 5 * (int64_t)s->ncell 
 cfd_status cfd_state_init(cfd_solver* s, const double* W, double* U, void* stream) {
   if (!s || !W || !U) return fail(CFD_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_state_init, dim3(grid_for(s->nint)), dim3(kBlock), 0, st, W, U, s->g);
+  hipLaunchKernelGGL(k_state_init, plane_grid(s->g), dim3(kBlock), 0, st, W, U, s->g);
   CFD_LAUNCHED();
   return enqueue_fill_halo(s, U, st);
 }
@@ -342,9 +364,10 @@ cfd_status cfd_rhs(cfd_solver* s, double* U, double* R, void* stream) {
 cfd_status cfd_compute_dt(cfd_solver* s, const double* U, double* dt_dev, void* stream) {
   if (!s || !U || !dt_dev) return fail(CFD_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_cfl, dim3(grid_for(s->nint)), dim3(kBlock), 0, st, U, s->g, s->ctl);
+  hipLaunchKernelGGL(k_cfl, plane_grid(s->g), dim3(kBlock), 0, st, U, s->g, s->partial);
   CFD_LAUNCHED();
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, s->ctl, s->g.cfl, 0.0, 0.0, (double*)nullptr, dt_dev);
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, 0.0, 0.0, (double*)nullptr, dt_dev,
+                     (const double*)s->partial, s->npart);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -395,8 +418,8 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
   hipStream_t st = (hipStream_t)stream;
   const Geom& g = s->g;
   // a fixed nonzero step so that the stage kernels do their work
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, st, s->ctl, g.cfl, 1e-12, 0.0, (double*)nullptr,
-                     (double*)nullptr);
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, 1e-12, 0.0, (double*)nullptr,
+                     (double*)nullptr, (const double*)s->partial, s->npart);
   CFD_LAUNCHED();
   StageIO io{};
   io.R = s->Racc;
@@ -418,12 +441,11 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
   cfd_status rc = CFD_OK;
   for (int r = 0; r < reps && rc == CFD_OK; ++r) {
     (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_prim, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0,
-                       io.dtp);
+    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0, io.dtp,
+                       s->partial);
     (void)hipEventRecord(ev[1], st);
     if (g.viscous)
-      hipLaunchKernelGGL(k_grad, dim3(grid_for(s->ncell)), dim3(kBlock), 0, st, (const double*)s->P, s->Gv,
-                         g, io.dtp);
+      hipLaunchKernelGGL(k_grad, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
     (void)hipEventRecord(ev[2], st);
     for (int d = 0; d < 3; ++d) {
       if (g.act[d]) {

@@ -17,9 +17,8 @@ namespace cfd {
 
 // Device control block of a solver.
 struct DevCtl {
-  unsigned long long smax;  // max CFL rate of the current step, as the bits of a non-negative double
-  double dt;                // step of the current step (0: step disabled, t_end reached)
-  int status;               // health bits, see cfd_check
+  double dt;   // step of the current step (0: step disabled, t_end reached)
+  int status;  // health bits, see cfd_check
   int pad;
 };
 
@@ -39,47 +38,93 @@ struct StageIO {
 
 __device__ __forceinline__ bool step_disabled(const double* dtp) { return dtp != nullptr && *dtp == 0.0; }
 
-// ----------------------------------------------------------------------------
-// Halo refresh of a padded state (in place). Threads over the padded grid;
-// halo cells copy their interior source cell, interior cells do nothing.
-__global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) {
-  const long long total = (long long)g.N[0] * g.N[1] * g.N[2];
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < total;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(c % g.N[0]) - g.h[0];
-    const int j = (int)((c / g.N[0]) % g.N[1]) - g.h[1];
-    const int k = (int)(c / ((long long)g.N[0] * g.N[1])) - g.h[2];
-    const int si = bc_source(i, g.n[0], g.bc[0], g.bc[1]);
-    const int sj = bc_source(j, g.n[1], g.bc[2], g.bc[3]);
-    const int sk = bc_source(k, g.n[2], g.bc[4], g.bc[5]);
-    if (si == i && sj == j && sk == k) continue;
-    const long long s = cell_at(g, si, sj, sk);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) U[v * g.vs + c] = U[v * g.vs + s];
+// Kernels over the padded grid use a plane-indexed launch: blockIdx.y is the
+// padded z index, and threads cover the x-y plane with a 32-bit in-plane index.
+struct PlaneIdx {
+  int i, j, k;      // interior-relative coordinates (halo cells negative)
+  long long c;      // padded cell index
+  bool in;          // inside the padded grid
+};
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2). The XCD-major order gives each XCD one contiguous range of logical
+// blocks - consecutive planes - so the neighbour planes a stencil re-reads stay
+// in that XCD's L2. XCD x receives the hardware blocks b = x, x+8, x+16, ...;
+// the first nb % 8 XCDs get one block more, and the map is a permutation.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_major_block(int b, int nb) {
+  const int x = b % kXcds, local = b / kXcds;
+  const int q = nb / kXcds, r = nb % kXcds;
+  return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+__device__ __forceinline__ PlaneIdx plane_index(const Geom& g, bool xcd_major = false) {
+  PlaneIdx p;
+  const int plane = g.N[0] * g.N[1];
+  int bx = blockIdx.x, bz = blockIdx.y;
+  if (xcd_major) {
+    const int logical = xcd_major_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+    bz = logical / gridDim.x;
+    bx = logical - bz * gridDim.x;
   }
+  const int t = bx * blockDim.x + threadIdx.x;
+  p.in = t < plane;
+  const int jj = t / g.N[0];
+  const int ii = t - jj * g.N[0];
+  p.i = ii - g.h[0];
+  p.j = jj - g.h[1];
+  p.k = bz - g.h[2];
+  p.c = (long long)bz * plane + t;
+  return p;
+}
+
+// ----------------------------------------------------------------------------
+// Halo refresh of a padded state (in place): halo cells copy their interior
+// source cell, interior cells do nothing.
+__global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) {
+  const PlaneIdx p = plane_index(g);
+  if (!p.in) return;
+  const int si = bc_source(p.i, g.n[0], g.bc[0], g.bc[1]);
+  const int sj = bc_source(p.j, g.n[1], g.bc[2], g.bc[3]);
+  const int sk = bc_source(p.k, g.n[2], g.bc[4], g.bc[5]);
+  if (si == p.i && sj == p.j && sk == p.k) return;
+  const long long s = cell_at(g, si, sj, sk);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) U[v * g.vs + p.c] = U[v * g.vs + s];
 }
 
 // Conservative interior state from primitive point values W (5 x interior, no halo).
 __global__ void __launch_bounds__(kBlock) k_state_init(const double* W, double* U, Geom g) {
+  const PlaneIdx p = plane_index(g);
+  if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
   const long long ni = (long long)g.n[0] * g.n[1] * g.n[2];
-  for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < ni;
-       s += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(s % g.n[0]);
-    const int j = (int)((s / g.n[0]) % g.n[1]);
-    const int k = (int)(s / ((long long)g.n[0] * g.n[1]));
-    const long long c = cell_at(g, i, j, k);
-    const double rho = W[s], u = W[ni + s], v = W[2 * ni + s], w = W[3 * ni + s], p = W[4 * ni + s];
-    U[c] = rho;
-    U[g.vs + c] = rho * u;
-    U[2 * g.vs + c] = rho * v;
-    U[3 * g.vs + c] = rho * w;
-    U[4 * g.vs + c] = p / (g.gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
-  }
+  const long long s = ((long long)p.k * g.n[1] + p.j) * g.n[0] + p.i;
+  const double rho = W[s], u = W[ni + s], v = W[2 * ni + s], w = W[3 * ni + s], pr = W[4 * ni + s];
+  U[p.c] = rho;
+  U[g.vs + p.c] = rho * u;
+  U[2 * g.vs + p.c] = rho * v;
+  U[3 * g.vs + p.c] = rho * w;
+  U[4 * g.vs + p.c] = pr / (g.gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
 }
 
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Block maximum (wavefront shuffles, then across the block's wavefronts via
+// LDS); the result is valid in thread 0.
+__device__ __forceinline__ double block_max(double x) {
+  __shared__ double part[kBlock / 64];
+  x = wave_max(x);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) part[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) x = fmax(x, part[i]);
+  }
   return x;
 }
 
@@ -94,29 +139,23 @@ __device__ __forceinline__ double cfl_rate(const Geom& g, double rho, const doub
   return s;
 }
 
-__device__ __forceinline__ void publish_max(DevCtl* ctl, double s) {
-  s = wave_max(s);
-  if ((threadIdx.x & 63) == 0 && s > 0.0) atomicMax(&ctl->smax, (unsigned long long)__double_as_longlong(s));
-}
-
 // Primitive variables on the padded grid, gathered through the boundary map.
-// Over interior cells, `what` bit 0 adds the CFL rate max and bit 1 the health bits.
+// Over interior cells, `what` bit 0 adds the CFL rate (block maxima written
+// to partial[], one per block) and bit 1 the health bits.
 constexpr int PRIM_CFL = 1, PRIM_HEALTH = 2;
 
 __global__ void __launch_bounds__(kBlock) k_prim(const double* __restrict__ U, double* __restrict__ P,
-                                                 Geom g, DevCtl* ctl, int what, const double* dtp) {
+                                                 Geom g, DevCtl* ctl, int what, const double* dtp,
+                                                 double* __restrict__ partial) {
   if (step_disabled(dtp)) return;
-  const long long total = (long long)g.N[0] * g.N[1] * g.N[2];
+  const PlaneIdx q = plane_index(g);
   double smax = 0.0;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < total;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(c % g.N[0]) - g.h[0];
-    const int j = (int)((c / g.N[0]) % g.N[1]) - g.h[1];
-    const int k = (int)(c / ((long long)g.N[0] * g.N[1])) - g.h[2];
-    const int si = bc_source(i, g.n[0], g.bc[0], g.bc[1]);
-    const int sj = bc_source(j, g.n[1], g.bc[2], g.bc[3]);
-    const int sk = bc_source(k, g.n[2], g.bc[4], g.bc[5]);
+  if (q.in) {
+    const int si = bc_source(q.i, g.n[0], g.bc[0], g.bc[1]);
+    const int sj = bc_source(q.j, g.n[1], g.bc[2], g.bc[3]);
+    const int sk = bc_source(q.k, g.n[2], g.bc[4], g.bc[5]);
     const long long s = cell_at(g, si, sj, sk);
+    const long long c = q.c;
     const double rho = U[s];
     const double m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];
     const double u[3] = {m0 / rho, m1 / rho, m2 / rho};
@@ -128,7 +167,7 @@ __global__ void __launch_bounds__(kBlock) k_prim(const double* __restrict__ U, d
     P[4 * g.vs + c] = p;
     P[5 * g.vs + c] = p / rho;
     if (what && s == c) {
-      if (what & PRIM_CFL) smax = fmax(smax, cfl_rate(g, rho, u, p));
+      if (what & PRIM_CFL) smax = cfl_rate(g, rho, u, p);
       if (what & PRIM_HEALTH) {
         int bad = 0;
         if (!isfinite(rho) || !isfinite(m0) || !isfinite(m1) || !isfinite(m2) || !isfinite(E)) bad |= 1;
@@ -138,35 +177,43 @@ __global__ void __launch_bounds__(kBlock) k_prim(const double* __restrict__ U, d
       }
     }
   }
-  if (what & PRIM_CFL) publish_max(ctl, smax);
+  if (what & PRIM_CFL) {
+    smax = block_max(smax);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = smax;
+  }
 }
 
-// CFL rate max of a state (interior cells only), for cfd_compute_dt.
-__global__ void __launch_bounds__(kBlock) k_cfl(const double* __restrict__ U, Geom g, DevCtl* ctl) {
-  const long long ni = (long long)g.n[0] * g.n[1] * g.n[2];
+// CFL rate maxima of a state (interior cells only), for cfd_compute_dt.
+__global__ void __launch_bounds__(kBlock) k_cfl(const double* __restrict__ U, Geom g,
+                                                double* __restrict__ partial) {
+  const PlaneIdx q = plane_index(g);
   double smax = 0.0;
-  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < ni;
-       q += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(q % g.n[0]);
-    const int j = (int)((q / g.n[0]) % g.n[1]);
-    const int k = (int)(q / ((long long)g.n[0] * g.n[1]));
-    const long long s = cell_at(g, i, j, k);
+  if (q.in && q.i >= 0 && q.i < g.n[0] && q.j >= 0 && q.j < g.n[1] && q.k >= 0 && q.k < g.n[2]) {
+    const long long s = q.c;
     const double rho = U[s];
     const double m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];
     const double u[3] = {m0 / rho, m1 / rho, m2 / rho};
     const double p = (g.gamma - 1.0) * (E - 0.5 * (m0 * u[0] + m1 * u[1] + m2 * u[2]));
-    smax = fmax(smax, cfl_rate(g, rho, u, p));
+    smax = cfl_rate(g, rho, u, p);
   }
-  publish_max(ctl, smax);
+  smax = block_max(smax);
+  if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = smax;
 }
 
-// Step size of the current step: fixed, or cfl / max rate; clipped to t_end
-// (> 0) and zero once t_end is reached. Advances *t, resets the max slot.
-__global__ void k_dt(DevCtl* ctl, double cfl, double fixed_dt, double t_end, double* t,
-                     double* dt_out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double dt = fixed_dt > 0.0 ? fixed_dt : cfl / __longlong_as_double((long long)ctl->smax);
-  ctl->smax = 0ull;
+// Step size of the current step: fixed, or cfl / (max of the npart CFL rate
+// partials); clipped to t_end (> 0) and zero once t_end is reached. Advances
+// *t. One block of kBlock threads.
+__global__ void __launch_bounds__(kBlock) k_dt(DevCtl* ctl, double cfl, double fixed_dt, double t_end,
+                                               double* t, double* dt_out, const double* __restrict__ partial,
+                                               int npart) {
+  double dt = fixed_dt;
+  if (!(fixed_dt > 0.0)) {
+    double m = 0.0;
+    for (int i = threadIdx.x; i < npart; i += blockDim.x) m = fmax(m, partial[i]);
+    m = block_max(m);
+    dt = cfl / m;
+  }
+  if (threadIdx.x != 0) return;
   if (t != nullptr && t_end > 0.0) {
     const double rem = t_end - *t;
     dt = rem > 0.0 ? fmin(dt, rem) : 0.0;
@@ -183,21 +230,19 @@ __global__ void k_dt(DevCtl* ctl, double cfl, double fixed_dt, double t_end, dou
 __global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ P, double* __restrict__ Gv,
                                                  Geom g, const double* dtp) {
   if (step_disabled(dtp)) return;
-  const long long total = (long long)g.N[0] * g.N[1] * g.N[2];
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < total;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int q[3] = {(int)(c % g.N[0]) - g.h[0], (int)((c / g.N[0]) % g.N[1]) - g.h[1],
-                      (int)(c / ((long long)g.N[0] * g.N[1])) - g.h[2]};
+  const PlaneIdx p = plane_index(g, true);
+  if (!p.in) return;
+  const int q[3] = {p.i, p.j, p.k};
+  const long long c = p.c;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      if (!g.act[b] || q[b] < 0 || q[b] >= g.n[b]) continue;
-      const long long st = g.s[b];
-      const double i12 = g.idx[b] / 12.0;
+  for (int b = 0; b < 3; ++b) {
+    if (!g.act[b] || q[b] < 0 || q[b] >= g.n[b]) continue;
+    const long long st = g.s[b];
+    const double i12 = g.idx[b] / 12.0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double* u = P + (1 + a) * g.vs + c;
-        Gv[(a * 3 + b) * g.vs + c] = (u[-2 * st] - 8.0 * u[-st] + 8.0 * u[st] - u[2 * st]) * i12;
-      }
+    for (int a = 0; a < 3; ++a) {
+      const double* u = P + (1 + a) * g.vs + c;
+      Gv[(a * 3 + b) * g.vs + c] = (u[-2 * st] - 8.0 * u[-st] + 8.0 * u[st] - u[2 * st]) * i12;
     }
   }
 }
@@ -259,25 +304,26 @@ template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P,
                                                     const double* __restrict__ Gv, StageIO io, Geom g) {
   if (step_disabled(io.dtp)) return;
+  // face numbering fits in 32 bits (checked when the solver is created)
   const int lane = threadIdx.x & 63;
-  const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int F = g.n[0] + 1;
-  const long long total = (long long)F * g.n[1] * g.n[2];
-  constexpr long long Q = 64 * kXIters - 1;
-  const long long first = wave * Q;
+  const int total = F * g.n[1] * g.n[2];
+  constexpr int Q = 64 * kXIters - 1;
+  const int first = wave * Q;
   if (first >= total) return;  // whole wavefront exits together
   double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int it = 0; it < kXIters; ++it) {
-    const long long gf = first - 1 + it * 64 + lane;
+    const int gf = first - 1 + it * 64 + lane;
     const bool valid = gf >= 0 && gf < total;
     double G[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    long long row = 0;
+    int row = 0;
     int f = 0;
     if (valid) {
       row = gf / F;
-      f = (int)(gf - row * F);
-      const int j = (int)(row % g.n[1]);
-      const int k = (int)(row / g.n[1]);
+      f = gf - row * F;
+      const int k = row / g.n[1];
+      const int j = row - k * g.n[1];
       FaceWindow w;
       const long long c0 = cell_at(g, f - 3, j, k);
 #pragma unroll
@@ -299,8 +345,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P
       carry[v] = __shfl(G[v], 63, 64);
     }
     if (valid && gf >= first && f >= 1) {
-      const int j = (int)(row % g.n[1]);
-      const int k = (int)(row / g.n[1]);
+      const int k = row / g.n[1];
+      const int j = row - k * g.n[1];
       double D[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[0];
@@ -347,6 +393,17 @@ __global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict
   }
   double Gm[5];
   for (int f = s0 - 1; f < s1; ++f) {
+    // issue the loads of the cell entering the window at the next face before
+    // this face's arithmetic, so their latency overlaps it
+    const bool more = f + 1 < s1;
+    double nq[5], nT = 0.0, ntg[4] = {0.0, 0.0, 0.0, 0.0};
+    if (more) {
+      load_prims(P, g.vs, c + 6 * st, nq);
+      if (dis) {
+        nT = P[5 * g.vs + c + 5 * st];
+        if (g.viscous) load_tangential<AX>(g, Gv, c + 5 * st, ntg);
+      }
+    }
     double G[5];
     face_flux<AX>(g, w, G);
     if (f >= s0) {
@@ -357,14 +414,15 @@ __global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) Gm[v] = G[v];
-    if (f + 1 < s1) {
+    if (more) {
       // shift the window by one cell along the axis
 #pragma unroll
       for (int m = 0; m < 5; ++m)
 #pragma unroll
         for (int v = 0; v < 5; ++v) w.q[m][v] = w.q[m + 1][v];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) w.q[5][v] = nq[v];
       c += st;
-      load_prims(P, g.vs, c + 5 * st, w.q[5]);
       if (dis) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
@@ -372,8 +430,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict
 #pragma unroll
           for (int v = 0; v < 4; ++v) w.tg[m][v] = w.tg[m + 1][v];
         }
-        w.T[3] = P[5 * g.vs + c + 4 * st];
-        if (g.viscous) load_tangential<AX>(g, Gv, c + 4 * st, w.tg[3]);
+        w.T[3] = nT;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w.tg[3][v] = ntg[v];
       }
     }
   }

@@ -23,6 +23,7 @@ struct Geom {
   int act[3];      // axis active (n > 1)
   int bc[6];       // boundary types, x-, x+, y-, y+, z-, z+
   double gamma;
+  double gm1i;     // 1/(gamma - 1)
   double mu;
   double kappa;    // gamma mu / ((gamma - 1) Pr): lambda grad T = kappa grad(p/rho)
   double cfl;
@@ -48,62 +49,68 @@ __device__ __forceinline__ int bc_source(int c, int n, int bc_lo, int bc_hi) {
 
 // ---------------------------------------------------------------------------
 // WENO5-JS (Jiang & Shu 1996) value at the right face of the centre cell c of
-// the stencil (a,b,c,d,e); smoothness indicators beta_k, candidates p_k,
-// linear weights (0.1, 0.6, 0.3), alpha_k = d_k/(1e-6 + beta_k)^2.
+// the stencil (a,b,c,d,e): smoothness indicators beta_k, candidates p_k,
+// linear weights (0.1, 0.6, 0.3), alpha_k = d_k/(1e-6 + beta_k)^2, normalised.
+// Evaluated with a single division: with s_k = (1e-6 + beta_k)^2 the weights
+// are proportional to d_k * prod_{j != k} s_j, and the 1/6 of the candidate
+// stencils is applied to the normaliser. The products stay within FP64 range
+// for |beta_k| up to ~1e100.
 __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
   constexpr double k13 = 13.0 / 12.0;
   constexpr double eps = 1.0e-6;
-  const double b0 = k13 * sq(a - 2.0 * b + c) + 0.25 * sq(a - 4.0 * b + 3.0 * c);
-  const double b1 = k13 * sq(b - 2.0 * c + d) + 0.25 * sq(b - d);
-  const double b2 = k13 * sq(c - 2.0 * d + e) + 0.25 * sq(3.0 * c - 4.0 * d + e);
-  const double p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
-  const double p1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
-  const double p2 = (2.0 * c + 5.0 * d - e) / 6.0;
-  const double a0 = 0.1 / sq(eps + b0);
-  const double a1 = 0.6 / sq(eps + b1);
-  const double a2 = 0.3 / sq(eps + b2);
-  return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+  const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+  const double t1 = b - 2.0 * c + d, u1 = b - d;
+  const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+  const double s0 = sq(eps + (k13 * t0 * t0 + 0.25 * u0 * u0));
+  const double s1 = sq(eps + (k13 * t1 * t1 + 0.25 * u1 * u1));
+  const double s2 = sq(eps + (k13 * t2 * t2 + 0.25 * u2 * u2));
+  const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
+  const double P0 = 2.0 * a - 7.0 * b + 11.0 * c;
+  const double P1 = -b + 5.0 * c + 2.0 * d;
+  const double P2 = 2.0 * c + 5.0 * d - e;
+  return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
 }
 
 // ---------------------------------------------------------------------------
 // HLLC flux (Toro, Spruce & Speares 1994) with Einfeldt (1988) speeds across a
-// face normal to axis D. Inputs: reconstructed primitive states (rho, u, v, w, p)
+// face normal to axis D (six divisions, five square roots). Inputs: reconstructed primitive states (rho, u, v, w, p)
 // left/right. Output in physical slot order. The four-way choice
 // (0 <= S_L | S_L < 0 <= S* | S* < 0 < S_R | S_R <= 0) is a select, so
 // lanes never diverge; unselected star states may be non-finite and are
 // discarded by the select.
 template <int D>
-__device__ __forceinline__ void hllc(double gamma, const double* WL, const double* WR, double* F) {
+__device__ __forceinline__ void hllc(double gamma, double gm1i, const double* WL, const double* WR, double* F) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const double rL = WL[0], uL = WL[1 + D], aL = WL[1 + T1], bL = WL[1 + T2], pL = WL[4];
   const double rR = WR[0], uR = WR[1 + D], aR = WR[1 + T1], bR = WR[1 + T2], pR = WR[4];
-  const double gm1i = 1.0 / (gamma - 1.0);
   const double EL = pL * gm1i + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
   const double ER = pR * gm1i + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
-  const double cL = sqrt(gamma * pL / rL);
-  const double cR = sqrt(gamma * pR / rR);
+  const double c2L = gamma * pL / rL, c2R = gamma * pR / rR;
+  const double cL = sqrt(c2L), cR = sqrt(c2R);
+  // Einfeldt: Roe-averaged normal velocity and sound-speed bound
   const double sL = sqrt(rL), sR = sqrt(rR);
   const double isum = 1.0 / (sL + sR);
   const double ubar = (sL * uL + sR * uR) * isum;
   const double eta2 = 0.5 * sL * sR * isum * isum;
-  const double dbar = sqrt((sL * cL * cL + sR * cR * cR) * isum + eta2 * sq(uR - uL));
+  const double dbar = sqrt((sL * c2L + sR * c2R) * isum + eta2 * sq(uR - uL));
   const double SL = fmin(uL - cL, ubar - dbar);
   const double SR = fmax(uR + cR, ubar + dbar);
   const double mL = rL * (SL - uL), mR = rR * (SR - uR);  // mass fluxes relative to the waves
   const double Ss = (pR - pL + uL * mL - uR * mR) / (mL - mR);
-  // star states
-  const double fL = mL / (SL - Ss);
-  const double fR = mR / (SR - Ss);
-  const double eL = EL / rL + (Ss - uL) * (Ss + pL / mL);
-  const double eR = ER / rR + (Ss - uR) * (Ss + pR / mR);
+  // star states U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S*, t1, t2, E_K/rho_K + (S*-u_K)(S* + p_K/(rho_K (S_K-u_K))));
+  // the energy slot is rearranged so that no division by rho_K or m_K remains
+  const double iL = 1.0 / (SL - Ss), iR = 1.0 / (SR - Ss);
+  const double fL = mL * iL, fR = mR * iR;
+  const double eL = (SL - uL) * iL * EL + (Ss - uL) * (fL * Ss + pL * iL);
+  const double eR = (SR - uR) * iR * ER + (Ss - uR) * (fR * Ss + pR * iR);
   // physical fluxes
   const double FL0 = rL * uL, FR0 = rR * uR;
   const double FL[5] = {FL0, FL0 * uL + pL, FL0 * aL, FL0 * bL, uL * (EL + pL)};
   const double FR[5] = {FR0, FR0 * uR + pR, FR0 * aR, FR0 * bR, uR * (ER + pR)};
   const double UL[5] = {rL, rL * uL, rL * aL, rL * bL, EL};
   const double UR[5] = {rR, rR * uR, rR * aR, rR * bR, ER};
-  const double UsL[5] = {fL, fL * Ss, fL * aL, fL * bL, fL * eL};
-  const double UsR[5] = {fR, fR * Ss, fR * aR, fR * bR, fR * eR};
+  const double UsL[5] = {fL, fL * Ss, fL * aL, fL * bL, eL};
+  const double UsR[5] = {fR, fR * Ss, fR * aR, fR * bR, eR};
   const bool useL = 0.0 <= SL;
   const bool useSL = !useL && 0.0 <= Ss;
   const bool useSR = !useL && !useSL && 0.0 < SR;
@@ -149,7 +156,7 @@ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, do
       WL[v] = weno5(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
       WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
     }
-    hllc<D>(g.gamma, WL, WR, F);
+    hllc<D>(g.gamma, g.gm1i, WL, WR, F);
   }
   if (g.viscous || g.heat) {
     const double i24 = g.idx[D] / 24.0;
