@@ -1,0 +1,87 @@
+"""Differentiable fixed-step TVD-RK3 rollouts (the paper's fixed-dt,
+differentiable `feed_forward` rollout, §4.5) backed by the hand-written
+discrete adjoint of libcfd.
+
+RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every) returns U_N; its
+backward pass walks the rollout in reverse segment by segment: the segment's
+states are recomputed from its checkpoint (kept every `ckpt_every` steps in the
+forward pass), then cfd_rk3_step_adjoint maps the adjoint back one step at a
+time (each step adjoint recomputes its two inner stages). Memory: the
+checkpoints plus one segment of states. Gradients flow to the interior cells of
+U0; halo entries of the returned gradient are zero.
+"""
+from __future__ import annotations
+
+import torch
+
+from .solver import Solver, interior
+
+
+class RK3Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, solver: Solver, dt: float, n_steps: int, ckpt_every: int = 20):
+        if n_steps < 0 or ckpt_every < 1:
+            raise ValueError("need n_steps >= 0 and ckpt_every >= 1")
+        U = U0.detach().clone().contiguous()
+        solver.fill_halo(U)
+        ckpts = []
+        done = 0
+        while done < n_steps:
+            ckpts.append((done, U.clone()))
+            k = min(ckpt_every, n_steps - done)
+            solver.advance_fixed(U, k, dt)
+            done += k
+        ctx.solver = solver
+        ctx.dt = float(dt)
+        ctx.n_steps = int(n_steps)
+        ctx.ckpt_every = int(ckpt_every)
+        ctx.ckpts = ckpts
+        return U
+
+    @staticmethod
+    def backward(ctx, Ubar):
+        solver, dt = ctx.solver, ctx.dt
+        Ub = torch.zeros_like(Ubar)
+        interior(solver.case, Ub).copy_(interior(solver.case, Ubar))
+        scratch = torch.empty_like(Ub)
+        for start, ck in reversed(ctx.ckpts):
+            k = min(ctx.ckpt_every, ctx.n_steps - start)
+            states = [ck]
+            U = ck.clone()
+            for _ in range(k - 1):
+                solver.advance_fixed(U, 1, dt)
+                states.append(U.clone())
+            for s in reversed(range(k)):
+                solver.step_adjoint(states[s], dt, Ub, scratch)
+                Ub, scratch = scratch, Ub
+        ctx.ckpts = None
+        return Ub, None, None, None, None
+
+
+def rollout(U0, solver: Solver, dt: float, n_steps: int, ckpt_every: int = 20):
+    return RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every)
+
+
+def conservative_from_primitive(solver: Solver, W):
+    """Differentiable torch map from interior primitives W (5, nz, ny, nx) to a
+    padded conservative state (halos zero; the rollout refreshes them)."""
+    g = solver.case["gamma"]
+    rho, u, v, w, p = W[0], W[1], W[2], W[3], W[4]
+    Ui = torch.stack([rho, rho * u, rho * v, rho * w, p / (g - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
+    U = torch.zeros(solver.shape, dtype=W.dtype, device=W.device)
+    nh = solver.case.get("nh", 3)
+    sl = []
+    for d in (2, 1, 0):
+        n = solver.case["n"][d]
+        sl.append(slice(nh, nh + n) if n > 1 else slice(0, 1))
+    U[(slice(None),) + tuple(sl)] = Ui
+    return U
+
+
+def kinetic_energy(solver: Solver, U):
+    """Total kinetic energy sum 1/2 |rho u|^2 / rho dV over interior cells."""
+    Ui = interior(solver.case, U)
+    dV = 1.0
+    for d in range(3):
+        dV *= (solver.case["hi"][d] - solver.case["lo"][d]) / solver.case["n"][d]
+    return (0.5 * (Ui[1] ** 2 + Ui[2] ** 2 + Ui[3] ** 2) / Ui[0]).sum() * dV

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "../../include/cfd.h"
+#include "kernels_adj.hpp"
 #include "kernels_fwd.hpp"
 
 using namespace cfd;
@@ -62,10 +63,11 @@ struct cfd_solver {
   double* P = nullptr;    // 6 x padded
   double* Gv = nullptr;   // 9 x padded (viscous runs)
   double* Racc = nullptr; // 5 x padded
-  double* A1 = nullptr;   // adjoint scratch (allocated on first adjoint call)
+  double* A1 = nullptr;   // adjoint scratch (allocated on the first adjoint call)
   double* A2 = nullptr;
   double* A3 = nullptr;
-  double* Wbar = nullptr;
+  double* Wbar = nullptr; // 6 x padded
+  double* Dbar = nullptr; // 9 x padded (viscous runs)
   double* partial = nullptr;  // CFL rate maxima, one per block of a plane-indexed launch
   int npart = 0;
   DevCtl* ctl = nullptr;
@@ -277,6 +279,62 @@ static cfd_status run_graph(cfd_solver* s, double* U, int mode, double fixed_dt,
   return CFD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint scratch: two adjoint states, the primitive-adjoint and the
+// derivative-adjoint accumulators. Allocated on the first adjoint call.
+static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
+  if (s->A1) return CFD_OK;
+  const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
+  bool ok = hipMalloc(&s->A1, st) == hipSuccess && hipMalloc(&s->A2, st) == hipSuccess &&
+            hipMalloc(&s->Wbar, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess;
+  if (ok && s->g.viscous) ok = hipMalloc(&s->Dbar, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar};
+    for (double* x : b)
+      if (x) (void)hipFree(x);
+    s->A1 = s->A2 = s->Wbar = s->Dbar = nullptr;
+    return fail(CFD_ENOMEM, "adjoint scratch allocation failed");
+  }
+  return CFD_OK;
+}
+
+template <int D>
+static void launch_face_adj(cfd_solver* s, const double* Rbar, double rscale, hipStream_t st) {
+  const Geom& g = s->g;
+  long long faces = (long long)g.n[0] * g.n[1] * g.n[2] / g.n[D] * (g.n[D] + 1);
+  hipLaunchKernelGGL(k_face_adj<D>, dim3(grid_for(faces, 1LL << 31)), dim3(kBlock), 0, st, (const double*)s->P,
+                     (const double*)s->Gv, Rbar, rscale, s->Wbar, s->Dbar, g);
+}
+
+// Ubar += (dR/dU(U))^T (rscale Rbar), interior cells.
+static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double rscale,
+                                      double* Ubar, hipStream_t st) {
+  const Geom& g = s->g;
+  cfd_status rc;
+  if ((rc = enqueue_prim(s, U, 0, nullptr, st))) return rc;
+  if (g.viscous) {
+    hipLaunchKernelGGL(k_grad, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g,
+                       (const double*)nullptr);
+    CFD_LAUNCHED();
+  }
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * s->ncell)), dim3(kBlock), 0, st, s->Wbar, 6 * s->ncell);
+  CFD_LAUNCHED();
+  if (g.viscous) {
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(kGradComps * s->ncell)), dim3(kBlock), 0, st, s->Dbar,
+                       kGradComps * s->ncell);
+    CFD_LAUNCHED();
+  }
+  if (g.act[0]) launch_face_adj<0>(s, Rbar, rscale, st);
+  if (g.act[1]) launch_face_adj<1>(s, Rbar, rscale, st);
+  if (g.act[2]) launch_face_adj<2>(s, Rbar, rscale, st);
+  CFD_LAUNCHED();
+  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, U, (const double*)s->Wbar,
+                     (const double*)s->Dbar, Ubar, g);
+  CFD_LAUNCHED();
+  return CFD_OK;
+}
+
 // ===========================================================================
 extern "C" {
 
@@ -324,7 +382,7 @@ void cfd_destroy(cfd_solver* s) {
   (void)hipDeviceSynchronize();
   if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
-  double* bufs[] = {s->U1, s->U2, s->P, s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->partial};
+  double* bufs[] = {s->U1, s->U2, s->P, s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->Dbar, s->partial};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (s->ctl) (void)hipFree(s->ctl);
@@ -472,16 +530,60 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
 }
 
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
-  (void)U; (void)Rbar; (void)Ubar; (void)stream;
-  if (!s) return fail(CFD_EINVAL, "NULL argument");
-  return fail(CFD_EUNSUPPORTED, "rhs adjoint not built yet");
+  if (!s || !U || !Rbar || !Ubar) return fail(CFD_EINVAL, "NULL argument");
+  if (Ubar == U || Ubar == Rbar) return fail(CFD_EINVAL, "Ubar must not alias U or Rbar");
+  cfd_status rc = ensure_adjoint_scratch(s);
+  if (rc) return rc;
+  return enqueue_rhs_adjoint(s, U, Rbar, 1.0, Ubar, (hipStream_t)stream);
 }
 
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream) {
-  (void)Un; (void)dt; (void)Ubar_np1; (void)Ubar_n; (void)stream;
-  if (!s) return fail(CFD_EINVAL, "NULL argument");
-  return fail(CFD_EUNSUPPORTED, "step adjoint not built yet");
+  if (!s || !Un || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
+  if (Ubar_n == Un || Ubar_n == Ubar_np1) return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
+  cfd_status rc = ensure_adjoint_scratch(s);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Geom& g = s->g;
+  // forward recompute of the stage states U1, U2 with the fixed step
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, dt, 0.0, (double*)nullptr,
+                     (double*)nullptr, (const double*)s->partial, s->npart);
+  CFD_LAUNCHED();
+  const double* dtp = &s->ctl->dt;
+  StageIO io{};
+  io.R = s->Racc;
+  io.Un = Un;
+  io.dtp = dtp;
+  io.Uk = Un;
+  io.Uout = s->U1;
+  io.a = 0.0;
+  io.b = 1.0;
+  if ((rc = enqueue_prim(s, Un, 0, dtp, st))) return rc;
+  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  io.Uk = s->U1;
+  io.Uout = s->U2;
+  io.a = 0.75;
+  io.b = 0.25;
+  if ((rc = enqueue_prim(s, s->U1, 0, dtp, st))) return rc;
+  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  // reverse:  U3 = 1/3 Un + 2/3 (U2 + dt R(U2)),  U2 = 3/4 Un + 1/4 (U1 + dt R(U1)),
+  //           U1 = Un + dt R(Un)
+  // A2 = Ubar_2 = 2/3 Ubar_3 + (dR/dU(U2))^T (2/3 dt Ubar_3)
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
+                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_rhs_adjoint(s, s->U2, Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
+  // A1 = Ubar_1 = 1/4 Ubar_2 + (dR/dU(U1))^T (1/4 dt Ubar_2)
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
+                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_rhs_adjoint(s, s->U1, s->A2, 0.25 * dt, s->A1, st))) return rc;
+  // Ubar_n = 1/3 Ubar_3 + 3/4 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
+                     (const double*)s->A2, 1.0, (const double*)s->A1, g);
+  CFD_LAUNCHED();
+  return enqueue_rhs_adjoint(s, Un, s->A1, dt, Ubar_n, st);
 }
 
 }  // extern "C"

@@ -1,0 +1,218 @@
+// Discrete adjoint of the right-hand side (gfx950).
+//
+//   1. forward recompute of the primitives P and the centred velocity
+//      gradient at the state (the forward kernels);
+//   2. k_face_adj<D>: one thread per face normal to D. The face flux adjoint
+//      follows from Rbar (R_i = -(G_{i+1/2} - G_{i-1/2})/dx gives
+//      Gbar_{i+1/2} = (Rbar_{i+1} - Rbar_i)/dx), the face recomputes its
+//      forward flux and reverses it (physics_adj.hpp), and its contributions
+//      are added with hardware FP64 atomics into Wbar (rho,u,v,w,p,T~ of the
+//      stencil cells) and Dbar (the adjoints of the centred derivatives);
+//   3. k_adj_fold: per interior cell, the transposed halo fill (every padded
+//      cell that the boundary map sends to it), the transposed centred
+//      differences of Dbar, and the transposed primitive map at U give Ubar.
+// The atomics make the summation order, and so the last bits, vary between
+// runs; everything else is deterministic.
+#pragma once
+#include "kernels_fwd.hpp"
+#include "physics_adj.hpp"
+
+namespace cfd {
+
+__device__ __forceinline__ void atomic_add(double* p, double v) {
+  if (v != 0.0) unsafeAtomicAdd(p, v);
+}
+
+// Face numbering for axis D: face f in [0, n_D] lies between cells f-1 and f.
+// D = 0: f runs fastest (faces of a row are consecutive); D = 1, 2: x runs
+// fastest so that lanes load consecutive cells.
+template <int D>
+__device__ __forceinline__ bool face_coords(const Geom& g, int t, int& i, int& j, int& k, int& f) {
+  if (D == 0) {
+    const int F = g.n[0] + 1;
+    const int row = t / F;
+    f = t - row * F;
+    k = row / g.n[1];
+    j = row - k * g.n[1];
+    i = f;
+    return k < g.n[2];
+  } else if (D == 1) {
+    const int F = g.n[1] + 1;
+    const int r = t / g.n[0];
+    i = t - r * g.n[0];
+    k = r / F;
+    f = r - k * F;
+    j = f;
+    return k < g.n[2];
+  } else {
+    const int r = t / g.n[0];
+    i = t - r * g.n[0];
+    f = r / g.n[1];
+    j = r - f * g.n[1];
+    k = f;
+    return f <= g.n[2];
+  }
+}
+
+// Rbar is read as rscale * Rbar (interior cells only).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_adj(const double* __restrict__ P, const double* __restrict__ Gv,
+                                                     const double* __restrict__ Rbar, double rscale,
+                                                     double* __restrict__ Wbar, double* __restrict__ Dbar, Geom g) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k, f;
+  if (!face_coords<D>(g, t, i, j, k, f)) return;
+  const long long st = g.s[D];
+  // cell f of the face's line; the face lies between f-1 and f
+  const long long cf = cell_at(g, i, j, k);
+  double Gb[5];
+  const bool hasL = f >= 1, hasR = f < g.n[D];
+  double any = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double rl = hasL ? Rbar[v * g.vs + cf - st] : 0.0;
+    const double rr = hasR ? Rbar[v * g.vs + cf] : 0.0;
+    Gb[v] = rscale * (rr - rl) * g.idx[D];
+    any += fabs(Gb[v]);
+  }
+  if (any == 0.0) return;
+  FaceWindow w;
+  const long long c0 = cf - 3 * st;  // window cell 0 = cell f-3
+#pragma unroll
+  for (int m = 0; m < 6; ++m) load_prims(P, g.vs, c0 + m * st, w.q[m]);
+  if (g.viscous || g.heat) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      w.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
+      if (g.viscous) load_tangential<D>(g, Gv, c0 + (1 + m) * st, w.tg[m]);
+    }
+  }
+  // contributions go straight to the accumulators as the reverse produces them
+  struct AtomicSink {
+    double* Wbar;
+    double* Dbar;
+    long long c0, st, vs;
+    int comp[4];
+    bool act[4];
+    __device__ void q(int m, int v, double x) { atomic_add(&Wbar[v * vs + c0 + m * st], x); }
+    __device__ void tg(int m, int k, double x) {
+      if (act[k]) atomic_add(&Dbar[comp[k] * vs + c0 + m * st], x);
+    }
+  } sink{Wbar, Dbar, c0, st, g.vs,
+         {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2},
+         {g.viscous && g.act[T1], g.viscous && g.act[T1], g.viscous && g.act[T2], g.viscous && g.act[T2]}};
+  face_flux_rev<D>(g, w, Gb, sink);
+}
+
+// Padded coordinates of axis d that the boundary map sends to interior
+// coordinate x (the halo images of x plus x itself).
+__device__ __forceinline__ int images(const Geom& g, int d, int x, int* out) {
+  const int n = g.n[d], h = g.h[d];
+  if (!g.act[d]) {
+    out[0] = 0;
+    return 1;
+  }
+  int cnt = 0;
+  const bool plo = g.bc[2 * d] == 0, phi = g.bc[2 * d + 1] == 0;
+  if (plo || phi) {  // periodic (pairs): images x - n and x + n when inside the padding
+    if (x - n >= -h) out[cnt++] = x - n;
+    out[cnt++] = x;
+    if (x + n < n + h) out[cnt++] = x + n;
+    return cnt;
+  }
+  if (x == 0)
+    for (int y = -h; y < 0; ++y) out[cnt++] = y;
+  out[cnt++] = x;
+  if (x == n - 1)
+    for (int y = n; y < n + h; ++y) out[cnt++] = y;
+  return cnt;
+}
+
+// Per interior cell s: gather the adjoints of all its images, apply the
+// transposed centred differences of Dbar, then the transposed primitive map
+// at U[s]; Ubar[s] += result. Halo entries of Ubar are not touched.
+__global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ U, const double* __restrict__ Wbar,
+                                                     const double* __restrict__ Dbar, double* __restrict__ Ubar,
+                                                     Geom g) {
+  const PlaneIdx p = plane_index(g);
+  if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
+  int ix[8], iy[8], iz[8];
+  const int nx = images(g, 0, p.i, ix), ny = images(g, 1, p.j, iy), nz = images(g, 2, p.k, iz);
+  double wb[6] = {0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < nz; ++c)
+    for (int b = 0; b < ny; ++b)
+      for (int a = 0; a < nx; ++a) {
+        const int q[3] = {ix[a], iy[b], iz[c]};
+        const long long cc = cell_at(g, q[0], q[1], q[2]);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) wb[v] += Wbar[v * g.vs + cc];
+        if (g.viscous) {
+          // phi_bar(m) += (Dbar(m+2) - 8 Dbar(m+1) + 8 Dbar(m-1) - Dbar(m-2)) / (12 dx_t)
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            if (!g.act[t]) continue;
+            const long long st = g.s[t];
+            const int lo = -g.h[t], hi = g.n[t] + g.h[t];
+            const int y = q[t];
+            const double i12 = g.idx[t] / 12.0;
+#pragma unroll
+            for (int comp = 0; comp < 3; ++comp) {
+              const double* Db = Dbar + (comp * 3 + t) * g.vs + cc;
+              double acc = 0.0;
+              if (y + 2 < hi) acc += Db[2 * st];
+              if (y + 1 < hi) acc -= 8.0 * Db[st];
+              if (y - 1 >= lo) acc += 8.0 * Db[-st];
+              if (y - 2 >= lo) acc -= Db[-2 * st];
+              wb[1 + comp] += acc * i12;
+            }
+          }
+        }
+      }
+  // transposed primitive map at U[s]
+  const long long s = p.c;
+  const double rho = U[s], m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];
+  const double ir = 1.0 / rho;
+  const double u[3] = {m0 * ir, m1 * ir, m2 * ir};
+  const double gm1 = g.gamma - 1.0;
+  const double pr = gm1 * (E - 0.5 * (m0 * u[0] + m1 * u[1] + m2 * u[2]));
+  // T~ = p / rho
+  const double pb = wb[4] + wb[5] * ir;
+  double rb = wb[0] - wb[5] * pr * ir * ir;
+  // p = (gamma-1)(E - |m|^2 / (2 rho)), u_a = m_a / rho
+  const double q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  rb += pb * gm1 * 0.5 * q2;
+  double mb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mb[a] = wb[1 + a] * ir - pb * gm1 * u[a];
+    rb -= wb[1 + a] * u[a] * ir;
+  }
+  Ubar[s] += rb;
+  Ubar[g.vs + s] += mb[0];
+  Ubar[2 * g.vs + s] += mb[1];
+  Ubar[3 * g.vs + s] += mb[2];
+  Ubar[4 * g.vs + s] += pb * gm1;
+}
+
+// out = a X + b Y + c Z over interior cells (null terms are skipped); the halo
+// of out is set to zero.
+__global__ void __launch_bounds__(kBlock) k_lincomb(double* __restrict__ out, double a, const double* X, double b,
+                                                    const double* Y, double c, const double* Z, Geom g) {
+  const PlaneIdx p = plane_index(g);
+  if (!p.in) return;
+  const bool in = p.i >= 0 && p.i < g.n[0] && p.j >= 0 && p.j < g.n[1] && p.k >= 0 && p.k < g.n[2];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long e = v * g.vs + p.c;
+    double r = 0.0;
+    if (in) {
+      if (X) r += a * X[e];
+      if (Y) r += b * Y[e];
+      if (Z) r += c * Z[e];
+    }
+    out[e] = r;
+  }
+}
+
+}  // namespace cfd

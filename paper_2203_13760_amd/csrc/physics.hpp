@@ -31,7 +31,7 @@ struct Geom {
   int inviscid, viscous, heat;
 };
 
-__device__ __forceinline__ double sq(double x) { return x * x; }
+__host__ __device__ __forceinline__ double sq(double x) { return x * x; }
 
 // Cell index of interior-relative coordinates (i,j,k) (halo cells negative).
 __device__ __forceinline__ long long cell_at(const Geom& g, int i, int j, int k) {
@@ -55,7 +55,7 @@ __device__ __forceinline__ int bc_source(int c, int n, int bc_lo, int bc_hi) {
 // are proportional to d_k * prod_{j != k} s_j, and the 1/6 of the candidate
 // stencils is applied to the normaliser. The products stay within FP64 range
 // for |beta_k| up to ~1e100.
-__device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
+__host__ __device__ __forceinline__ double weno5(double a, double b, double c, double d, double e) {
   constexpr double k13 = 13.0 / 12.0;
   constexpr double eps = 1.0e-6;
   const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
@@ -79,7 +79,7 @@ __device__ __forceinline__ double weno5(double a, double b, double c, double d, 
 // lanes never diverge; unselected star states may be non-finite and are
 // discarded by the select.
 template <int D>
-__device__ __forceinline__ void hllc(double gamma, double gm1i, const double* WL, const double* WR, double* F) {
+__host__ __device__ __forceinline__ void hllc(double gamma, double gm1i, const double* WL, const double* WR, double* F) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const double rL = WL[0], uL = WL[1 + D], aL = WL[1 + T1], bL = WL[1 + T2], pL = WL[4];
   const double rR = WR[0], uR = WR[1 + D], aR = WR[1 + T1], bR = WR[1 + T2], pR = WR[4];
@@ -146,7 +146,7 @@ struct FaceWindow {
 // derivatives interpolated with the fourth-order central interpolation along
 // the normal, and face velocities from the same interpolation.
 template <int D>
-__device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
+__host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (g.inviscid) {

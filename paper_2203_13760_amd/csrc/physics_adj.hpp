@@ -1,0 +1,349 @@
+// Reverse (adjoint) building blocks of the face flux, hand-derived from the
+// forward code in physics.hpp: each routine recomputes the forward
+// intermediates of one face and propagates output adjoints back to its inputs
+// in reverse order. Branches (the HLLC wave pattern, the Einfeldt min/max)
+// follow the decisions of the forward evaluation at the same state.
+#pragma once
+#include "physics.hpp"
+
+namespace cfd {
+
+// q = weno5(a,b,c,d,e); g[0..4] += (dq/d(a..e)) * qbar.
+__host__ __device__ __forceinline__ void weno5_rev(double a, double b, double c, double d, double e,
+                                                    double qbar, double* g) {
+  constexpr double k13 = 13.0 / 12.0;
+  constexpr double eps = 1.0e-6;
+  const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+  const double t1 = b - 2.0 * c + d, u1 = b - d;
+  const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+  const double e0 = eps + (k13 * t0 * t0 + 0.25 * u0 * u0);
+  const double e1 = eps + (k13 * t1 * t1 + 0.25 * u1 * u1);
+  const double e2 = eps + (k13 * t2 * t2 + 0.25 * u2 * u2);
+  const double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
+  const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
+  const double P0 = 2.0 * a - 7.0 * b + 11.0 * c;
+  const double P1 = -b + 5.0 * c + 2.0 * d;
+  const double P2 = 2.0 * c + 5.0 * d - e;
+  const double Dn = 6.0 * (w0 + w1 + w2);
+  const double iD = 1.0 / Dn;
+  const double q = (w0 * P0 + w1 * P1 + w2 * P2) * iD;
+  // reverse
+  const double Nb = qbar * iD;
+  const double Db = -qbar * q * iD;
+  const double w0b = Nb * P0 + 6.0 * Db, w1b = Nb * P1 + 6.0 * Db, w2b = Nb * P2 + 6.0 * Db;
+  const double P0b = Nb * w0, P1b = Nb * w1, P2b = Nb * w2;
+  const double s0b = 0.6 * s2 * w1b + 0.3 * s1 * w2b;
+  const double s1b = 0.1 * s2 * w0b + 0.3 * s0 * w2b;
+  const double s2b = 0.1 * s1 * w0b + 0.6 * s0 * w1b;
+  const double b0b = 2.0 * e0 * s0b, b1b = 2.0 * e1 * s1b, b2b = 2.0 * e2 * s2b;
+  const double t0b = 2.0 * k13 * t0 * b0b, u0b = 0.5 * u0 * b0b;
+  const double t1b = 2.0 * k13 * t1 * b1b, u1b = 0.5 * u1 * b1b;
+  const double t2b = 2.0 * k13 * t2 * b2b, u2b = 0.5 * u2 * b2b;
+  g[0] += t0b + u0b + 2.0 * P0b;
+  g[1] += -2.0 * t0b - 4.0 * u0b - 7.0 * P0b + t1b + u1b - P1b;
+  g[2] += t0b + 3.0 * u0b + 11.0 * P0b - 2.0 * t1b + 5.0 * P1b + t2b + 3.0 * u2b + 2.0 * P2b;
+  g[3] += t1b - u1b + 2.0 * P1b - 2.0 * t2b - 4.0 * u2b + 5.0 * P2b;
+  g[4] += t2b + u2b - P2b;
+}
+
+// Reverse of hllc<D>: given Fbar (physical slot order) accumulate WLb, WRb
+// (physical slot order).
+template <int D>
+__host__ __device__ __forceinline__ void hllc_rev(double gamma, double gm1i, const double* WL, const double* WR,
+                                                   const double* Fbar, double* WLb, double* WRb) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  // ---- forward recompute (same expressions as hllc<D>)
+  const double rL = WL[0], uL = WL[1 + D], aL = WL[1 + T1], bL = WL[1 + T2], pL = WL[4];
+  const double rR = WR[0], uR = WR[1 + D], aR = WR[1 + T1], bR = WR[1 + T2], pR = WR[4];
+  const double EL = pL * gm1i + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+  const double ER = pR * gm1i + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+  const double c2L = gamma * pL / rL, c2R = gamma * pR / rR;
+  const double cL = sqrt(c2L), cR = sqrt(c2R);
+  const double sL = sqrt(rL), sR = sqrt(rR);
+  const double isum = 1.0 / (sL + sR);
+  const double ubar = (sL * uL + sR * uR) * isum;
+  const double eta2 = 0.5 * sL * sR * isum * isum;
+  const double Hs = sL * c2L + sR * c2R;
+  const double du = uR - uL;
+  const double dbar = sqrt(Hs * isum + eta2 * du * du);
+  const double candL1 = uL - cL, candL2 = ubar - dbar;
+  const double candR1 = uR + cR, candR2 = ubar + dbar;
+  const bool firstL = !(candL2 < candL1);  // fmin keeps the first on ties
+  const bool firstR = !(candR2 > candR1);
+  const double SL = firstL ? candL1 : candL2;
+  const double SR = firstR ? candR1 : candR2;
+  const double mL = rL * (SL - uL), mR = rR * (SR - uR);
+  const double den = mL - mR;
+  const double Ss = (pR - pL + uL * mL - uR * mR) / den;
+  const bool useL = 0.0 <= SL;
+  const bool useSL = !useL && 0.0 <= Ss;
+  const bool useSR = !useL && !useSL && 0.0 < SR;
+  const bool useR = !useL && !useSL && !useSR;
+
+  const double Fb[5] = {Fbar[0], Fbar[1 + D], Fbar[1 + T1], Fbar[1 + T2], Fbar[4]};
+  // adjoints of the normal-first primitives and intermediates
+  double rLb = 0, uLb = 0, aLb = 0, bLb = 0, pLb = 0, ELb = 0;
+  double rRb = 0, uRb = 0, aRb = 0, bRb = 0, pRb = 0, ERb = 0;
+  double SLb = 0, SRb = 0, Ssb = 0, mLb = 0, mRb = 0;
+  double FLb[5] = {0, 0, 0, 0, 0}, FRb[5] = {0, 0, 0, 0, 0};
+
+  if (useL) {
+    for (int v = 0; v < 5; ++v) FLb[v] = Fb[v];
+  } else if (useR) {
+    for (int v = 0; v < 5; ++v) FRb[v] = Fb[v];
+  } else if (useSL) {
+    // F = FL + SL (UsL - UL)
+    const double iL = 1.0 / (SL - Ss);
+    const double fL = mL * iL;
+    const double A = SL - uL, C = Ss - uL, B = fL * Ss + pL * iL;
+    const double eL = A * iL * EL + C * B;
+    const double UsL[5] = {fL, fL * Ss, fL * aL, fL * bL, eL};
+    const double UL[5] = {rL, rL * uL, rL * aL, rL * bL, EL};
+    double Usb[5], Ulb[5];
+    for (int v = 0; v < 5; ++v) {
+      FLb[v] = Fb[v];
+      SLb += Fb[v] * (UsL[v] - UL[v]);
+      Usb[v] = SL * Fb[v];
+      Ulb[v] = -SL * Fb[v];
+    }
+    double fLb = Usb[0] + Usb[1] * Ss + Usb[2] * aL + Usb[3] * bL;
+    Ssb += Usb[1] * fL;
+    aLb += Usb[2] * fL;
+    bLb += Usb[3] * fL;
+    const double eLb = Usb[4];
+    const double Ab = eLb * iL * EL;
+    double iLb = eLb * A * EL;
+    ELb += eLb * A * iL;
+    const double Cb = eLb * B, Bb = eLb * C;
+    fLb += Bb * Ss;
+    Ssb += Bb * fL;
+    pLb += Bb * iL;
+    iLb += Bb * pL;
+    SLb += Ab;
+    uLb -= Ab;
+    Ssb += Cb;
+    uLb -= Cb;
+    rLb += Ulb[0] + Ulb[1] * uL + Ulb[2] * aL + Ulb[3] * bL;
+    uLb += Ulb[1] * rL;
+    aLb += Ulb[2] * rL;
+    bLb += Ulb[3] * rL;
+    ELb += Ulb[4];
+    mLb += fLb * iL;
+    iLb += fLb * mL;
+    SLb -= iLb * iL * iL;
+    Ssb += iLb * iL * iL;
+  } else {
+    // useSR: F = FR + SR (UsR - UR)
+    const double iR = 1.0 / (SR - Ss);
+    const double fR = mR * iR;
+    const double A = SR - uR, C = Ss - uR, B = fR * Ss + pR * iR;
+    const double eR = A * iR * ER + C * B;
+    const double UsR[5] = {fR, fR * Ss, fR * aR, fR * bR, eR};
+    const double UR[5] = {rR, rR * uR, rR * aR, rR * bR, ER};
+    double Usb[5], Urb[5];
+    for (int v = 0; v < 5; ++v) {
+      FRb[v] = Fb[v];
+      SRb += Fb[v] * (UsR[v] - UR[v]);
+      Usb[v] = SR * Fb[v];
+      Urb[v] = -SR * Fb[v];
+    }
+    double fRb = Usb[0] + Usb[1] * Ss + Usb[2] * aR + Usb[3] * bR;
+    Ssb += Usb[1] * fR;
+    aRb += Usb[2] * fR;
+    bRb += Usb[3] * fR;
+    const double eRb = Usb[4];
+    const double Ab = eRb * iR * ER;
+    double iRb = eRb * A * ER;
+    ERb += eRb * A * iR;
+    const double Cb = eRb * B, Bb = eRb * C;
+    fRb += Bb * Ss;
+    Ssb += Bb * fR;
+    pRb += Bb * iR;
+    iRb += Bb * pR;
+    SRb += Ab;
+    uRb -= Ab;
+    Ssb += Cb;
+    uRb -= Cb;
+    rRb += Urb[0] + Urb[1] * uR + Urb[2] * aR + Urb[3] * bR;
+    uRb += Urb[1] * rR;
+    aRb += Urb[2] * rR;
+    bRb += Urb[3] * rR;
+    ERb += Urb[4];
+    mRb += fRb * iR;
+    iRb += fRb * mR;
+    SRb -= iRb * iR * iR;
+    Ssb += iRb * iR * iR;
+  }
+  // physical fluxes FL, FR
+  {
+    const double F0 = rL * uL;
+    const double F0b = FLb[0] + FLb[1] * uL + FLb[2] * aL + FLb[3] * bL;
+    uLb += FLb[1] * F0 + FLb[4] * (EL + pL);
+    aLb += FLb[2] * F0;
+    bLb += FLb[3] * F0;
+    pLb += FLb[1] + FLb[4] * uL;
+    ELb += FLb[4] * uL;
+    rLb += F0b * uL;
+    uLb += F0b * rL;
+  }
+  {
+    const double F0 = rR * uR;
+    const double F0b = FRb[0] + FRb[1] * uR + FRb[2] * aR + FRb[3] * bR;
+    uRb += FRb[1] * F0 + FRb[4] * (ER + pR);
+    aRb += FRb[2] * F0;
+    bRb += FRb[3] * F0;
+    pRb += FRb[1] + FRb[4] * uR;
+    ERb += FRb[4] * uR;
+    rRb += F0b * uR;
+    uRb += F0b * rR;
+  }
+  if (!useL && !useR) {
+    // contact speed S* = num / den
+    const double numb = Ssb / den;
+    const double denb = -Ssb * Ss / den;
+    pRb += numb;
+    pLb -= numb;
+    uLb += numb * mL;
+    mLb += numb * uL + denb;
+    uRb -= numb * mR;
+    mRb += -numb * uR - denb;
+    // m_K = rho_K (S_K - u_K)
+    rLb += mLb * (SL - uL);
+    SLb += mLb * rL;
+    uLb -= mLb * rL;
+    rRb += mRb * (SR - uR);
+    SRb += mRb * rR;
+    uRb -= mRb * rR;
+    // Einfeldt speeds
+    double cLb = 0, cRb = 0, ubarb = 0, dbarb = 0;
+    if (firstL) { uLb += SLb; cLb -= SLb; } else { ubarb += SLb; dbarb -= SLb; }
+    if (firstR) { uRb += SRb; cRb += SRb; } else { ubarb += SRb; dbarb += SRb; }
+    const double dbar2b = dbarb * 0.5 / dbar;
+    const double Hsb = dbar2b * isum;
+    double isumb = dbar2b * Hs;
+    const double eta2b = dbar2b * du * du;
+    const double dub = dbar2b * eta2 * 2.0 * du;
+    double sLb = Hsb * c2L, sRb = Hsb * c2R;
+    double c2Lb = Hsb * sL, c2Rb = Hsb * sR;
+    uRb += dub;
+    uLb -= dub;
+    sLb += eta2b * 0.5 * sR * isum * isum;
+    sRb += eta2b * 0.5 * sL * isum * isum;
+    isumb += eta2b * sL * sR * isum;
+    const double Nu = sL * uL + sR * uR;
+    const double Nub = ubarb * isum;
+    isumb += ubarb * Nu;
+    sLb += Nub * uL;
+    uLb += Nub * sL;
+    sRb += Nub * uR;
+    uRb += Nub * sR;
+    const double sumb = -isumb * isum * isum;
+    sLb += sumb;
+    sRb += sumb;
+    rLb += sLb * 0.5 / sL;
+    rRb += sRb * 0.5 / sR;
+    c2Lb += cLb * 0.5 / cL;
+    c2Rb += cRb * 0.5 / cR;
+    pLb += c2Lb * gamma / rL;
+    rLb -= c2Lb * c2L / rL;
+    pRb += c2Rb * gamma / rR;
+    rRb -= c2Rb * c2R / rR;
+  }
+  // total energies
+  pLb += ELb * gm1i;
+  rLb += ELb * 0.5 * (uL * uL + aL * aL + bL * bL);
+  uLb += ELb * rL * uL;
+  aLb += ELb * rL * aL;
+  bLb += ELb * rL * bL;
+  pRb += ERb * gm1i;
+  rRb += ERb * 0.5 * (uR * uR + aR * aR + bR * bR);
+  uRb += ERb * rR * uR;
+  aRb += ERb * rR * aR;
+  bRb += ERb * rR * bR;
+  WLb[0] += rLb;
+  WLb[1 + D] += uLb;
+  WLb[1 + T1] += aLb;
+  WLb[1 + T2] += bLb;
+  WLb[4] += pLb;
+  WRb[0] += rRb;
+  WRb[1 + D] += uRb;
+  WRb[1 + T1] += aRb;
+  WRb[1 + T2] += bRb;
+  WRb[4] += pRb;
+}
+
+// Adjoint of the face window, accumulated in arrays (used by host checks):
+// qb[6][6] holds (rho,u,v,w,p,T~) of the six window cells, tgb[4][4] the
+// tangential-derivative inputs of window cells 1..4.
+struct FaceWindowAdj {
+  double qb[6][6];
+  double tgb[4][4];
+  __host__ __device__ void q(int m, int v, double x) { qb[m][v] += x; }
+  __host__ __device__ void tg(int m, int k, double x) { tgb[m][k] += x; }
+};
+
+// Reverse of face_flux<D>: given Gbar (physical slot order) hand the adjoints
+// of the window inputs to the sink as they become final:
+// sink.q(cell m, variable v, value) with v in 0..5 = (rho,u,v,w,p,T~), and
+// sink.tg(cell m in 1..4, input k, value).
+template <int D, class Sink>
+__host__ __device__ __forceinline__ void face_flux_rev(const Geom& g, const FaceWindow& w, const double* Gbar,
+                                                        Sink& sink) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  if (g.inviscid) {
+    double WL[5], WR[5];
+    for (int v = 0; v < 5; ++v) {
+      WL[v] = weno5(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
+      WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
+    }
+    double WLb[5] = {0, 0, 0, 0, 0}, WRb[5] = {0, 0, 0, 0, 0};
+    hllc_rev<D>(g.gamma, g.gm1i, WL, WR, Gbar, WLb, WRb);
+    for (int v = 0; v < 5; ++v) {
+      double gs[6] = {0, 0, 0, 0, 0, 0};
+      weno5_rev(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v], WLb[v], gs);
+      double gr[5] = {0, 0, 0, 0, 0};
+      weno5_rev(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v], WRb[v], gr);
+      for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
+      for (int m = 0; m < 6; ++m) sink.q(m, v, gs[m]);
+    }
+  }
+  if (g.viscous || g.heat) {
+    const double i24 = g.idx[D] / 24.0;
+    const double cdn[4] = {i24, -27.0 * i24, 27.0 * i24, -i24};                   // normal derivative weights
+    const double crc[4] = {-1.0 / 16.0, 9.0 / 16.0, 9.0 / 16.0, -1.0 / 16.0};  // face interpolation weights
+    // G slots carry -F^d
+    const double Fd1b = -Gbar[1 + D], Fd2b = -Gbar[1 + T1], Fd3b = -Gbar[1 + T2], Fd4b = -Gbar[4];
+    if (g.heat)
+      for (int m = 0; m < 4; ++m) sink.q(1 + m, 5, g.kappa * Fd4b * cdn[m]);
+    if (g.viscous) {
+      auto dn = [&](int v) {
+        return cdn[0] * w.q[1][v] + cdn[1] * w.q[2][v] + cdn[2] * w.q[3][v] + cdn[3] * w.q[4][v];
+      };
+      auto rc = [&](int v) { return crc[0] * w.q[1][v] + crc[1] * w.q[2][v] + crc[2] * w.q[3][v] + crc[3] * w.q[4][v]; };
+      auto rct = [&](int k) { return crc[0] * w.tg[0][k] + crc[1] * w.tg[1][k] + crc[2] * w.tg[2][k] + crc[3] * w.tg[3][k]; };
+      const double dD = dn(1 + D), d1 = dn(1 + T1), d2 = dn(1 + T2);
+      const double uD_t1 = rct(0), u1_t1 = rct(1), uD_t2 = rct(2), u2_t2 = rct(3);
+      const double div = dD + u1_t1 + u2_t2;
+      const double tDD = g.mu * (dD + dD) - (2.0 / 3.0) * g.mu * div;
+      const double tD1 = g.mu * (uD_t1 + d1);
+      const double tD2 = g.mu * (uD_t2 + d2);
+      const double ufD = rc(1 + D), uf1 = rc(1 + T1), uf2 = rc(1 + T2);
+      const double tDDb = Fd1b + Fd4b * ufD;
+      const double tD1b = Fd2b + Fd4b * uf1;
+      const double tD2b = Fd3b + Fd4b * uf2;
+      const double ufDb = Fd4b * tDD, uf1b = Fd4b * tD1, uf2b = Fd4b * tD2;
+      const double divb = -(2.0 / 3.0) * g.mu * tDDb;
+      const double dDb = 2.0 * g.mu * tDDb + divb;
+      const double d1b = g.mu * tD1b, d2b = g.mu * tD2b;
+      const double tgb[4] = {g.mu * tD1b, divb, g.mu * tD2b, divb};
+      for (int m = 0; m < 4; ++m) {
+        sink.q(1 + m, 1 + D, cdn[m] * dDb + crc[m] * ufDb);
+        sink.q(1 + m, 1 + T1, cdn[m] * d1b + crc[m] * uf1b);
+        sink.q(1 + m, 1 + T2, cdn[m] * d2b + crc[m] * uf2b);
+        for (int k = 0; k < 4; ++k) sink.tg(1 + m, k, crc[m] * tgb[k]);
+      }
+    }
+  }
+}
+
+}  // namespace cfd
