@@ -43,6 +43,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=24, help="z-planes of the oracle's timed slab")
     ap.add_argument("--copy-bytes", type=int, default=0)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation measurement")
+    ap.add_argument("--adj-n", type=int, default=128)
+    ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving benchmark (batched vs one at a time) instead")
+    ap.add_argument("--serving-requests", type=int, default=400)
+    ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--serving-steps", type=int, default=200)
+    ap.add_argument("--serving-sweep", type=str, default="",
+                    help="comma-separated extra arrival rates for a load sweep (batched only)")
     return ap.parse_args()
 
 
@@ -80,6 +90,88 @@ def cpu_baseline(case, W, nz):
                       f"of the same field ({cells} cell-updates, {sec:.1f} s)"}
 
 
+def differentiation(n, nsteps, ckpt_every=20, reps=5):
+    """Cost of the discrete adjoint on the Taylor-Green vortex with seeded noise
+    (sigma 1e-3) at n^3: one fixed-dt TVD-RK3 step vs one step adjoint (which
+    recomputes its two inner stages), each timed with torch events on the
+    stream the library launches on, and the full gradient of the final kinetic
+    energy through an n_steps rollout with checkpoints every ckpt_every steps."""
+    import torch
+    from paper_2203_13760_amd import workloads as wl
+    from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
+    from paper_2203_13760_amd.solver import Solver
+    case, W = wl.taylor_green_noisy(n, sigma=1e-3, seed=4)
+    s = Solver(case)
+    U = s.init(W)
+    dt = float(s.compute_dt(U).item())
+    Ub = torch.ones_like(U)
+    out = torch.empty_like(U)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    s.step(U, dt)
+    s.step_adjoint(U, dt, Ub, out)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        s.step(U, dt)
+    ev[1].record()
+    for _ in range(reps):
+        s.step_adjoint(U, dt, Ub, out)
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) / reps
+    adj = ev[1].elapsed_time(ev[2]) / reps
+    Wt = torch.from_numpy(W).cuda().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = kinetic_energy(s, rollout(conservative_from_primitive(s, Wt), s, dt, nsteps, ckpt_every))
+    L.backward()
+    torch.cuda.synchronize()
+    tgrad = time.perf_counter() - t0
+    gnorm = float(Wt.grad[1:4].norm().item())
+    s.close()
+    return {"workload": f"Taylor-Green vortex {n}^3 + Gaussian noise 1e-3 (seed 4), fixed dt {dt:.4g}",
+            "step_ms": fwd, "step_adjoint_ms": adj, "adjoint_over_step": adj / fwd,
+            "gradient_steps": nsteps, "checkpoint_every": ckpt_every, "gradient_s": tgrad,
+            "loss": float(L.item()), "grad_norm": gnorm}
+
+
+def serving_bench(args):
+    """Continuous-batching serving of mixed 2D Kelvin-Helmholtz / 3D Taylor-Green
+    solves (seeded Poisson arrivals): batched persistent launches vs the same
+    kernels and graph with one resident solve, p50/p99 time to solution."""
+    import torch
+    from paper_2203_13760_amd import serving
+    torch.cuda.set_device(0)
+    srv = serving.BatchServer(max_grids=256, arena_bytes=96 << 30)
+    # warm-up: a handful of small requests through both paths
+    srv.run(serving.mixed_workload(8, 1000.0, seed=99, steps=3, kh_range=(64, 96), tgv_range=(32, 40)))
+    mk = lambda rate: serving.mixed_workload(args.serving_requests, rate, seed=3, steps=args.serving_steps)
+    log = lambda m: print(m, flush=True)
+    batched = srv.run(mk(args.serving_rate), log=log)
+    print(f"serving: batched {batched}", flush=True)
+    single = srv.run(mk(args.serving_rate), max_resident=1, log=log)
+    print(f"serving: one at a time {single}", flush=True)
+    sweep = []
+    for r in [float(x) for x in args.serving_sweep.split(",") if x]:
+        res = srv.run(mk(r), log=log)
+        res["rate"] = r
+        sweep.append(res)
+        print(f"serving: rate {r} {res}", flush=True)
+    srv.close()
+    out = {
+        "metric": "p99 solve latency (s), serving, mixed 2D KH / 3D TGV FP64 solves",
+        "value": batched["p99_s"], "unit": "s", "higher_is_better": False, "n_gpus": 1,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.serving_requests} requests, Poisson {args.serving_rate}/s (seed 3), "
+                               f"60% KH 2D n in [64,1024], 40% TGV 3D n in [32,128], "
+                               f"{args.serving_steps} TVD-RK3 CFL steps each"},
+        "batched": batched, "one_at_a_time": single,
+        "throughput_ratio": batched["throughput_req_s"] / single["throughput_req_s"],
+        "load_sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -91,6 +183,9 @@ def main():
 
     if args.copy_bytes:
         copy_calibration(args.copy_bytes)
+        return
+    if args.serving:
+        serving_bench(args)
         return
     from paper_2203_13760_amd import cfd
     from paper_2203_13760_amd import workloads as wl
@@ -144,6 +239,13 @@ def main():
     del U
     torch.cuda.empty_cache()
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = differentiation(args.adj_n, args.adj_steps)
+        print(f"bench: adjoint step / step = {adjoint['adjoint_over_step']:.3f} at {args.adj_n}^3, "
+              f"gradient through {args.adj_steps} steps in {adjoint['gradient_s']:.2f} s", flush=True)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case, W, args.cpu_slab)
@@ -171,6 +273,7 @@ def main():
         "step_tflops": step_flops * cells * args.steps / sec / 1e12,
         "fused_min_traffic_GBps": 320.0 * value * 1e6 / 1e9,
         "cpu_baseline": cpu,
+        "differentiation": adjoint,
         "paper_context": {"value": 1000.0 / 92.76, "unit": "Mcell-updates/s",
                           "workload": "Taylor-Green vortex 256^3, HLLC float64, JAX on one RTX A6000"},
         "health": health,

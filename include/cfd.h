@@ -147,6 +147,54 @@ cfd_status cfd_check(cfd_solver* s, int32_t* status_out);
 /* Message of the last failure on this thread ("" if none). */
 const char* cfd_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Serving batch: many independent solves (mixed sizes, 2D and 3D, different
+ * physics) resident on the device at once, advanced together. Each TVD-RK3
+ * step is one replay of a captured HIP graph whose launches are persistent
+ * kernels, one per phase of each stage (primitives, CFL step, velocity
+ * gradient, x/y/z sweeps), each covering the work of every resident grid
+ * through a device descriptor table. Every grid keeps its own state, scratch
+ * and CFL step, so its result does not depend on the other grids in the batch.
+ * A batch is used from one stream at a time. */
+typedef struct cfd_batch cfd_batch; /* opaque */
+
+/* Create a batch for up to max_grids resident grids (<= 512) whose buffers are
+ * carved from one device arena of arena_bytes. Synchronises. */
+cfd_status cfd_batch_create(int32_t max_grids, int64_t arena_bytes, cfd_batch** out);
+
+/* Free the batch and its arena. NULL is accepted. Synchronises. */
+void cfd_batch_destroy(cfd_batch* b);
+
+/* Arena bytes one grid of this configuration occupies (its admission cost). */
+cfd_status cfd_batch_footprint(const cfd_config* cfg, int64_t* bytes);
+
+/* Admit a grid: validate cfg, take a slot and arena space, and enqueue the
+ * conservative initial state from W (device, 5 x interior primitives, as for
+ * cfd_state_init). Returns CFD_ENOMEM, with nothing changed, when no slot or
+ * arena space is free; the caller retries after removing finished grids. */
+cfd_status cfd_batch_add(cfd_batch* b, const cfd_config* cfg, const double* W, int32_t* slot_out, void* stream);
+
+/* Retire a grid and free its slot and arena space. The caller must have
+ * synchronised the stream after the last step that used the grid. */
+cfd_status cfd_batch_remove(cfd_batch* b, int32_t slot);
+
+/* Device pointer to a resident grid's padded state and its element count. */
+cfd_status cfd_batch_state(cfd_batch* b, int32_t slot, double** U_out, int64_t* numel);
+
+/* One CFL TVD-RK3 step of every resident grid (uploads the descriptor table
+ * first when grids were added or removed since the last step). */
+cfd_status cfd_batch_step(cfd_batch* b, void* stream);
+
+/* Refresh the halo cells of a resident grid's state (for read-out). */
+cfd_status cfd_batch_finish(cfd_batch* b, int32_t slot, void* stream);
+
+/* Enqueue a device-to-device copy of a resident grid's padded state into dst
+ * (caller-owned device memory of cfd_batch_state's element count). */
+cfd_status cfd_batch_copy_state(cfd_batch* b, int32_t slot, double* dst, void* stream);
+
+/* Number of resident grids, or -1 for NULL. */
+int32_t cfd_batch_count(const cfd_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

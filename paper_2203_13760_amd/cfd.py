@@ -44,6 +44,8 @@ EXPORTS = (
     "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_fill_halo", "cfd_rhs",
     "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
     "cfd_rk3_step_adjoint", "cfd_profile_stage", "cfd_check", "cfd_last_error",
+    "cfd_batch_create", "cfd_batch_destroy", "cfd_batch_footprint", "cfd_batch_add", "cfd_batch_remove",
+    "cfd_batch_state", "cfd_batch_step", "cfd_batch_finish", "cfd_batch_copy_state", "cfd_batch_count",
 )
 
 _lib = None
@@ -77,6 +79,16 @@ def load():
         "cfd_profile_stage": ([vp, dp, C.c_int32, C.POINTER(C.c_double), vp], st),
         "cfd_check": ([vp, C.POINTER(C.c_int32)], st),
         "cfd_last_error": ([], C.c_char_p),
+        "cfd_batch_create": ([C.c_int32, C.c_int64, C.POINTER(C.c_void_p)], st),
+        "cfd_batch_destroy": ([vp], None),
+        "cfd_batch_footprint": ([cfgp, C.POINTER(C.c_int64)], st),
+        "cfd_batch_add": ([vp, cfgp, dp, C.POINTER(C.c_int32), vp], st),
+        "cfd_batch_remove": ([vp, C.c_int32], st),
+        "cfd_batch_state": ([vp, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)], st),
+        "cfd_batch_step": ([vp, vp], st),
+        "cfd_batch_finish": ([vp, C.c_int32, vp], st),
+        "cfd_batch_copy_state": ([vp, C.c_int32, dp, vp], st),
+        "cfd_batch_count": ([vp], C.c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -195,3 +207,61 @@ def cfd_check(h):
 
 def cfd_last_error():
     return load().cfd_last_error().decode()
+
+
+# ---------------------------------------------------------------- serving batch
+def cfd_batch_create(max_grids, arena_bytes):
+    h = C.c_void_p()
+    _check(load().cfd_batch_create(int(max_grids), int(arena_bytes), C.byref(h)))
+    return h
+
+
+def cfd_batch_destroy(b):
+    if b:
+        load().cfd_batch_destroy(b)
+
+
+def cfd_batch_footprint(case):
+    n = C.c_int64(0)
+    cfg = make_config(case)
+    _check(load().cfd_batch_footprint(C.byref(cfg), C.byref(n)))
+    return int(n.value)
+
+
+def cfd_batch_add(b, case, W, stream=None):
+    """Admit a grid; returns its slot, or None when the batch is full (CFD_ENOMEM)."""
+    slot = C.c_int32(-1)
+    cfg = make_config(case)
+    rc = load().cfd_batch_add(b, C.byref(cfg), _ptr(W), C.byref(slot), _stream(stream))
+    if rc == CFD_ENOMEM:
+        return None
+    _check(rc)
+    return int(slot.value)
+
+
+def cfd_batch_remove(b, slot):
+    _check(load().cfd_batch_remove(b, int(slot)))
+
+
+def cfd_batch_state(b, slot):
+    """(device pointer, element count) of a resident grid's padded state."""
+    p = C.c_void_p()
+    n = C.c_int64(0)
+    _check(load().cfd_batch_state(b, int(slot), C.byref(p), C.byref(n)))
+    return int(p.value), int(n.value)
+
+
+def cfd_batch_step(b, stream=None):
+    _check(load().cfd_batch_step(b, _stream(stream)))
+
+
+def cfd_batch_finish(b, slot, stream=None):
+    _check(load().cfd_batch_finish(b, int(slot), _stream(stream)))
+
+
+def cfd_batch_copy_state(b, slot, dst, stream=None):
+    _check(load().cfd_batch_copy_state(b, int(slot), _ptr(dst), _stream(stream)))
+
+
+def cfd_batch_count(b):
+    return int(load().cfd_batch_count(b))

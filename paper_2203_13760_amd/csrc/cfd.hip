@@ -150,9 +150,7 @@ template <int D>
 static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t st) {
   const Geom& g = s->g;
   if (D == 0) {
-    const long long faces = (long long)(g.n[0] + 1) * g.n[1] * g.n[2];
-    const long long waves = (faces + 64 * kXIters - 2) / (64 * kXIters - 1);
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const unsigned blocks = (unsigned)sweep_x_blocks(g);
     switch (mode) {
       case MODE_WRITE: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
       case MODE_ACC: hipLaunchKernelGGL(k_sweep_x<MODE_ACC>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
@@ -161,9 +159,9 @@ static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t
     }
   } else {
     constexpr int AX = D == 0 ? 1 : D;
-    const int ot = AX == 1 ? 2 : 1;
-    const long long nseg = (g.n[AX] + kSeg - 1) / kSeg;
-    dim3 grid((g.n[0] + 63) / 64, (unsigned)(((long long)g.n[ot] * nseg + 3) / 4));
+    int gx, gy;
+    sweep_march_blocks<AX>(g, gx, gy);
+    dim3 grid(gx, gy);
     switch (mode) {
       case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
       case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
@@ -587,3 +585,4 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
 }
 
 }  // extern "C"
+#include "batch_host.inc"

@@ -59,31 +59,39 @@ __device__ __forceinline__ int xcd_major_block(int b, int nb) {
   return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
-__device__ __forceinline__ PlaneIdx plane_index(const Geom& g, bool xcd_major = false) {
+// bx, by: block coordinates of a plane-indexed launch of gx x gy blocks.
+__device__ __forceinline__ PlaneIdx plane_index_at(const Geom& g, int bx, int by, int gx, int gy, bool xcd_major) {
   PlaneIdx p;
   const int plane = g.N[0] * g.N[1];
-  int bx = blockIdx.x, bz = blockIdx.y;
   if (xcd_major) {
-    const int logical = xcd_major_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-    bz = logical / gridDim.x;
-    bx = logical - bz * gridDim.x;
+    const int logical = xcd_major_block(by * gx + bx, gx * gy);
+    by = logical / gx;
+    bx = logical - by * gx;
   }
-  const int t = bx * blockDim.x + threadIdx.x;
+  const int t = bx * kBlock + threadIdx.x;
   p.in = t < plane;
   const int jj = t / g.N[0];
   const int ii = t - jj * g.N[0];
   p.i = ii - g.h[0];
   p.j = jj - g.h[1];
-  p.k = bz - g.h[2];
-  p.c = (long long)bz * plane + t;
+  p.k = by - g.h[2];
+  p.c = (long long)by * plane + t;
   return p;
+}
+
+__device__ __forceinline__ PlaneIdx plane_index(const Geom& g, bool xcd_major = false) {
+  return plane_index_at(g, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y, xcd_major);
+}
+
+// Number of blocks along x of a plane-indexed launch.
+__host__ __device__ __forceinline__ int plane_blocks_x(const Geom& g) {
+  return (g.N[0] * g.N[1] + kBlock - 1) / kBlock;
 }
 
 // ----------------------------------------------------------------------------
 // Halo refresh of a padded state (in place): halo cells copy their interior
 // source cell, interior cells do nothing.
-__global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) {
-  const PlaneIdx p = plane_index(g);
+__device__ __forceinline__ void fill_halo_body(double* U, const Geom& g, const PlaneIdx& p) {
   if (!p.in) return;
   const int si = bc_source(p.i, g.n[0], g.bc[0], g.bc[1]);
   const int sj = bc_source(p.j, g.n[1], g.bc[2], g.bc[3]);
@@ -93,6 +101,8 @@ __global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) {
 #pragma unroll
   for (int v = 0; v < 5; ++v) U[v * g.vs + p.c] = U[v * g.vs + s];
 }
+
+__global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) { fill_halo_body(U, g, plane_index(g)); }
 
 // Conservative interior state from primitive point values W (5 x interior, no halo).
 __global__ void __launch_bounds__(kBlock) k_state_init(const double* W, double* U, Geom g) {
@@ -125,6 +135,7 @@ __device__ __forceinline__ double block_max(double x) {
   if (threadIdx.x == 0) {
     for (int i = 1; i < (int)(blockDim.x >> 6); ++i) x = fmax(x, part[i]);
   }
+  __syncthreads();  // part[] may be reused by the block's next reduction
   return x;
 }
 
@@ -144,11 +155,9 @@ __device__ __forceinline__ double cfl_rate(const Geom& g, double rho, const doub
 // to partial[], one per block) and bit 1 the health bits.
 constexpr int PRIM_CFL = 1, PRIM_HEALTH = 2;
 
-__global__ void __launch_bounds__(kBlock) k_prim(const double* __restrict__ U, double* __restrict__ P,
-                                                 Geom g, DevCtl* ctl, int what, const double* dtp,
-                                                 double* __restrict__ partial) {
-  if (step_disabled(dtp)) return;
-  const PlaneIdx q = plane_index(g);
+__device__ __forceinline__ void prim_body(const double* __restrict__ U, double* __restrict__ P, const Geom& g,
+                                          DevCtl* ctl, int what, double* __restrict__ partial, const PlaneIdx& q,
+                                          int part_index) {
   double smax = 0.0;
   if (q.in) {
     const int si = bc_source(q.i, g.n[0], g.bc[0], g.bc[1]);
@@ -179,8 +188,15 @@ __global__ void __launch_bounds__(kBlock) k_prim(const double* __restrict__ U, d
   }
   if (what & PRIM_CFL) {
     smax = block_max(smax);
-    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = smax;
+    if (threadIdx.x == 0) partial[part_index] = smax;
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_prim(const double* __restrict__ U, double* __restrict__ P,
+                                                 Geom g, DevCtl* ctl, int what, const double* dtp,
+                                                 double* __restrict__ partial) {
+  if (step_disabled(dtp)) return;
+  prim_body(U, P, g, ctl, what, partial, plane_index(g), blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // CFL rate maxima of a state (interior cells only), for cfd_compute_dt.
@@ -203,9 +219,8 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const double* __restrict__ U, Ge
 // Step size of the current step: fixed, or cfl / (max of the npart CFL rate
 // partials); clipped to t_end (> 0) and zero once t_end is reached. Advances
 // *t. One block of kBlock threads.
-__global__ void __launch_bounds__(kBlock) k_dt(DevCtl* ctl, double cfl, double fixed_dt, double t_end,
-                                               double* t, double* dt_out, const double* __restrict__ partial,
-                                               int npart) {
+__device__ __forceinline__ void dt_body(DevCtl* ctl, double cfl, double fixed_dt, double t_end, double* t,
+                                        double* dt_out, const double* __restrict__ partial, int npart) {
   double dt = fixed_dt;
   if (!(fixed_dt > 0.0)) {
     double m = 0.0;
@@ -223,14 +238,18 @@ __global__ void __launch_bounds__(kBlock) k_dt(DevCtl* ctl, double cfl, double f
   if (dt_out != nullptr) *dt_out = dt;
 }
 
+__global__ void __launch_bounds__(kBlock) k_dt(DevCtl* ctl, double cfl, double fixed_dt, double t_end,
+                                               double* t, double* dt_out, const double* __restrict__ partial,
+                                               int npart) {
+  dt_body(ctl, cfl, fixed_dt, t_end, t, dt_out, partial, npart);
+}
+
 // ----------------------------------------------------------------------------
 // Cell-centred velocity gradient (fourth-order central, §3.4):
 // Gv[a*3+b] = d u_a / d x_b, written wherever coordinate b is interior (the
 // only places a face interpolation reads it).
-__global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ P, double* __restrict__ Gv,
-                                                 Geom g, const double* dtp) {
-  if (step_disabled(dtp)) return;
-  const PlaneIdx p = plane_index(g, true);
+__device__ __forceinline__ void grad_body(const double* __restrict__ P, double* __restrict__ Gv, const Geom& g,
+                                          const PlaneIdx& p) {
   if (!p.in) return;
   const int q[3] = {p.i, p.j, p.k};
   const long long c = p.c;
@@ -245,6 +264,12 @@ __global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ P, d
       Gv[(a * 3 + b) * g.vs + c] = (u[-2 * st] - 8.0 * u[-st] + 8.0 * u[st] - u[2 * st]) * i12;
     }
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ P, double* __restrict__ Gv,
+                                                 Geom g, const double* dtp) {
+  if (step_disabled(dtp)) return;
+  grad_body(P, Gv, g, plane_index(g, true));
 }
 
 // ----------------------------------------------------------------------------
@@ -301,12 +326,11 @@ __device__ __forceinline__ void emit(const StageIO& io, long long vs, long long 
 constexpr int kXIters = 4;
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P,
-                                                    const double* __restrict__ Gv, StageIO io, Geom g) {
-  if (step_disabled(io.dtp)) return;
+__device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const double* __restrict__ Gv,
+                                             const StageIO& io, const Geom& g, int bx) {
   // face numbering fits in 32 bits (checked when the solver is created)
   const int lane = threadIdx.x & 63;
-  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int wave = (bx * kBlock + (int)threadIdx.x) >> 6;
   const int F = g.n[0] + 1;
   const int total = F * g.n[1] * g.n[2];
   constexpr int Q = 64 * kXIters - 1;
@@ -355,20 +379,32 @@ __global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P
   }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P,
+                                                    const double* __restrict__ Gv, StageIO io, Geom g) {
+  if (step_disabled(io.dtp)) return;
+  sweep_x_body<MODE>(P, Gv, io, g, blockIdx.x);
+}
+
+// Blocks of an x sweep.
+__host__ __device__ __forceinline__ int sweep_x_blocks(const Geom& g) {
+  const long long faces = (long long)(g.n[0] + 1) * g.n[1] * g.n[2];
+  const long long waves = (faces + 64 * kXIters - 2) / (64 * kXIters - 1);
+  return (int)((waves + 3) / 4);
+}
+
 // y / z sweep: one lane per (x, other) column segment of kSeg cells along the
 // axis; lanes run along x so every load is coalesced. The segment's first
 // face is computed only to seed the left flux.
 constexpr int kSeg = 32;
 
 template <int AX, int MODE>
-__global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict__ P,
-                                                        const double* __restrict__ Gv, StageIO io,
-                                                        Geom g) {
-  if (step_disabled(io.dtp)) return;
+__device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const double* __restrict__ Gv,
+                                                 const StageIO& io, const Geom& g, int bx, int by) {
   constexpr int OT = AX == 1 ? 2 : 1;  // the other transverse axis
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int i = bx * 64 + (threadIdx.x & 63);
   const int nseg = (g.n[AX] + kSeg - 1) / kSeg;
-  const long long col = (long long)blockIdx.y * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long long col = (long long)by * (kBlock >> 6) + (threadIdx.x >> 6);
   if (i >= g.n[0] || col >= (long long)g.n[OT] * nseg) return;
   const int o = (int)(col / nseg);
   const int seg = (int)(col - (long long)o * nseg);
@@ -436,6 +472,23 @@ __global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict
       }
     }
   }
+}
+
+template <int AX, int MODE>
+__global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict__ P,
+                                                        const double* __restrict__ Gv, StageIO io,
+                                                        Geom g) {
+  if (step_disabled(io.dtp)) return;
+  sweep_march_body<AX, MODE>(P, Gv, io, g, blockIdx.x, blockIdx.y);
+}
+
+// Launch shape of a marching sweep along AX (x blocks, y blocks).
+template <int AX>
+__host__ __device__ __forceinline__ void sweep_march_blocks(const Geom& g, int& gx, int& gy) {
+  constexpr int OT = AX == 1 ? 2 : 1;
+  const int nseg = (g.n[AX] + kSeg - 1) / kSeg;
+  gx = (g.n[0] + 63) / 64;
+  gy = (int)(((long long)g.n[OT] * nseg + 3) / 4);
 }
 
 // Zero a buffer (graph-safe replacement for a memset node).

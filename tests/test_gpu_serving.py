@@ -1,0 +1,125 @@
+"""Serving batch: the batched persistent path against the CPU oracle, the same
+result alone and in a mix of other grids (bitwise), admission by arena
+footprint, and the scheduler end to end (batched vs one at a time)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_13760_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def normwise(a, b):
+    err = 0.0
+    for v in range(a.shape[0]):
+        den = float(np.max(np.abs(b[v])))
+        num = float(np.max(np.abs(a[v] - b[v])))
+        if num:
+            err = max(err, num / den if den > 0 else math.inf)
+    return err
+
+
+@pytest.fixture(scope="module")
+def cfd():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_13760_amd import cfd as c
+    return c
+
+
+def _mix():
+    P, Z = wl.PERIODIC, wl.ZERO_GRADIENT
+    return [
+        wl.taylor_green(0, shape=(20, 18, 16)),
+        wl.kelvin_helmholtz(48, seed=1),
+        wl.random_shocky((37, 13, 9), seed=11),
+        wl.sod(200),
+        wl.random_smooth((33, 29, 35), seed=3, mu=0.02, bc=(P, P, Z, Z, P, P)),
+    ]
+
+
+def _run(cfd, grids, steps):
+    b = cfd.cfd_batch_create(16, 2 << 30)
+    slots = []
+    for case, W in grids:
+        s = cfd.cfd_batch_add(b, case, torch.from_numpy(np.ascontiguousarray(W)).cuda())
+        assert s is not None
+        slots.append(s)
+    assert cfd.cfd_batch_count(b) == len(grids)
+    for _ in range(steps):
+        cfd.cfd_batch_step(b)
+    out = []
+    from paper_2203_13760_amd.solver import padded_shape
+    for (case, _), s in zip(grids, slots):
+        cfd.cfd_batch_finish(b, s)
+        U = torch.empty(padded_shape(case), dtype=torch.float64, device="cuda")
+        cfd.cfd_batch_copy_state(b, s, U)
+        out.append(U.cpu().numpy())
+    torch.cuda.synchronize()
+    cfd.cfd_batch_destroy(b)
+    return out
+
+
+def test_batched_path_matches_oracle(cfd):
+    grids = _mix()
+    print("batched parity: 5 mixed grids, 20 steps", flush=True)
+    got = _run(cfd, grids, 20)
+    for (case, W), U in zip(grids, got):
+        Uo, _, n = oracle.advance(case, oracle.state_init(case, W), 20)
+        e = normwise(U, Uo)
+        assert e <= 1e-10, (case["n"], e)
+
+
+def test_alone_equals_in_mix_bitwise(cfd):
+    grids = _mix()
+    print("alone vs in the mix", flush=True)
+    together = _run(cfd, grids, 10)
+    for k in (0, 1, 4):
+        alone = _run(cfd, [grids[k]], 10)[0]
+        assert np.array_equal(alone, together[k]), k
+
+
+def test_admission_by_footprint(cfd):
+    case, W = wl.taylor_green(32)
+    need = cfd.cfd_batch_footprint(case)
+    print(f"admission: footprint {need} bytes", flush=True)
+    b = cfd.cfd_batch_create(8, int(2.5 * need))
+    Wt = torch.from_numpy(W).cuda()
+    s0 = cfd.cfd_batch_add(b, case, Wt)
+    s1 = cfd.cfd_batch_add(b, case, Wt)
+    s2 = cfd.cfd_batch_add(b, case, Wt)
+    assert s0 is not None and s1 is not None and s2 is None
+    cfd.cfd_batch_step(b)
+    torch.cuda.synchronize()
+    cfd.cfd_batch_remove(b, s0)
+    s3 = cfd.cfd_batch_add(b, case, Wt)
+    assert s3 is not None and cfd.cfd_batch_count(b) == 2
+    cfd.cfd_batch_step(b)
+    torch.cuda.synchronize()
+    cfd.cfd_batch_destroy(b)
+
+
+def test_server_batched_and_one_at_a_time_agree(cfd):
+    from paper_2203_13760_amd import serving
+    reqs_a = serving.mixed_workload(n_requests=10, rate=500.0, seed=5, steps=15,
+                                    kh_range=(64, 96), tgv_range=(24, 40))
+    reqs_b = serving.mixed_workload(n_requests=10, rate=500.0, seed=5, steps=15,
+                                    kh_range=(64, 96), tgv_range=(24, 40))
+    print("server: 10 requests batched and one at a time", flush=True)
+    srv = serving.BatchServer(max_grids=32, arena_bytes=4 << 30)
+    ra = srv.run(reqs_a, keep_results=True)
+    rb = srv.run(reqs_b, max_resident=1, keep_results=True)
+    srv.close()
+    assert ra["requests"] == rb["requests"] == 10
+    for x, y in zip(sorted(reqs_a, key=lambda r: r.rid), sorted(reqs_b, key=lambda r: r.rid)):
+        assert torch.equal(x.result, y.result), x.rid
+    # the torch-built initial conditions are the generator's fields
+    r0 = sorted(reqs_a, key=lambda r: r.rid)[0]
+    n = r0.case["n"][0]
+    ref = wl.kelvin_helmholtz(n)[1] if r0.case["n"][2] == 1 else wl.taylor_green(n)[1]
+    if r0.case["n"][2] != 1:
+        assert np.allclose(r0.make_W().cpu().numpy(), ref, rtol=0, atol=1e-14)
