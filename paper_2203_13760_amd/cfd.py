@@ -12,7 +12,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcfd.so")
+# CFD_LIBRARY names an alternative build of the same library (e.g. for A/B timing)
+LIB_PATH = os.environ.get("CFD_LIBRARY") or os.path.join(_HERE, "libcfd.so")
 
 CFD_OK, CFD_EINVAL, CFD_ENOMEM, CFD_EHIP, CFD_ENONFINITE, CFD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CFD_BC_PERIODIC, CFD_BC_ZERO_GRADIENT = 0, 1

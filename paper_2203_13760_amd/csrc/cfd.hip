@@ -301,8 +301,12 @@ template <int D>
 static void launch_face_adj(cfd_solver* s, const double* Rbar, double rscale, hipStream_t st) {
   const Geom& g = s->g;
   long long faces = (long long)g.n[0] * g.n[1] * g.n[2] / g.n[D] * (g.n[D] + 1);
-  hipLaunchKernelGGL(k_face_adj<D>, dim3(grid_for(faces, 1LL << 31)), dim3(kBlock), 0, st, (const double*)s->P,
-                     (const double*)s->Gv, Rbar, rscale, s->Wbar, s->Dbar, g);
+  const dim3 grid(grid_for(faces, 1LL << 31));
+  if (g.inviscid)
+    hipLaunchKernelGGL(k_face_adj_inv<D>, grid, dim3(kBlock), 0, st, (const double*)s->P, Rbar, rscale, s->Wbar, g);
+  if (g.viscous || g.heat)
+    hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, st, (const double*)s->P, (const double*)s->Gv,
+                       Rbar, rscale, s->Wbar, s->Dbar, g);
 }
 
 // Ubar += (dR/dU(U))^T (rscale Rbar), interior cells.

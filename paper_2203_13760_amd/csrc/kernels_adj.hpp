@@ -54,19 +54,11 @@ __device__ __forceinline__ bool face_coords(const Geom& g, int t, int& i, int& j
   }
 }
 
-// Rbar is read as rscale * Rbar (interior cells only).
+// Face adjoint Gbar from Rbar (read as rscale * Rbar, interior cells only).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_adj(const double* __restrict__ P, const double* __restrict__ Gv,
-                                                     const double* __restrict__ Rbar, double rscale,
-                                                     double* __restrict__ Wbar, double* __restrict__ Dbar, Geom g) {
-  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k, f;
-  if (!face_coords<D>(g, t, i, j, k, f)) return;
+__device__ __forceinline__ bool face_gbar(const Geom& g, const double* __restrict__ Rbar, double rscale, long long cf,
+                                          int f, double* Gb) {
   const long long st = g.s[D];
-  // cell f of the face's line; the face lies between f-1 and f
-  const long long cf = cell_at(g, i, j, k);
-  double Gb[5];
   const bool hasL = f >= 1, hasR = f < g.n[D];
   double any = 0.0;
 #pragma unroll
@@ -76,19 +68,75 @@ __global__ void __launch_bounds__(kBlock) k_face_adj(const double* __restrict__ 
     Gb[v] = rscale * (rr - rl) * g.idx[D];
     any += fabs(Gb[v]);
   }
-  if (any == 0.0) return;
-  FaceWindow w;
+  return any != 0.0;
+}
+
+// Inviscid part of the face adjoint: WENO5-JS forward, HLLC reverse, then the
+// WENO reverse one variable at a time with that variable's stencil reloaded,
+// so the window is not held in registers across the HLLC reverse.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_adj_inv(const double* P, const double* __restrict__ Rbar,
+                                                         double rscale, double* Wbar, Geom g) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k, f;
+  if (!face_coords<D>(g, t, i, j, k, f)) return;
+  const long long st = g.s[D];
+  const long long cf = cell_at(g, i, j, k);  // cell f: the face lies between f-1 and f
+  double Gb[5];
+  if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) return;
   const long long c0 = cf - 3 * st;  // window cell 0 = cell f-3
+  double WL[5], WR[5];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) load_prims(P, g.vs, c0 + m * st, w.q[m]);
-  if (g.viscous || g.heat) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      w.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
-      if (g.viscous) load_tangential<D>(g, Gv, c0 + (1 + m) * st, w.tg[m]);
-    }
+  for (int v = 0; v < 5; ++v) {
+    const double* q = P + v * g.vs + c0;
+    const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
+    WL[v] = weno5(q0, q1, q2, q3, q4);
+    WR[v] = weno5(q5, q4, q3, q2, q1);
   }
-  // contributions go straight to the accumulators as the reverse produces them
+  double WLb[5] = {0, 0, 0, 0, 0}, WRb[5] = {0, 0, 0, 0, 0};
+  hllc_rev<D>(g.gamma, g.gm1i, WL, WR, Gb, WLb, WRb);
+  asm volatile("" ::: "memory");  // reload the stencils below instead of keeping them live
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double* q = P + v * g.vs + c0;
+    const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
+    double gs[6] = {0, 0, 0, 0, 0, 0};
+    weno5_rev(q0, q1, q2, q3, q4, WLb[v], gs);
+    double gr[5] = {0, 0, 0, 0, 0};
+    weno5_rev(q5, q4, q3, q2, q1, WRb[v], gr);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) atomic_add(&Wbar[v * g.vs + c0 + m * st], gs[m]);
+  }
+}
+
+// Dissipative part of the face adjoint (viscous and heat flux).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restrict__ P, const double* __restrict__ Gv,
+                                                         const double* __restrict__ Rbar, double rscale,
+                                                         double* Wbar, double* Dbar, Geom g) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k, f;
+  if (!face_coords<D>(g, t, i, j, k, f)) return;
+  const long long st = g.s[D];
+  const long long cf = cell_at(g, i, j, k);
+  double Gb[5];
+  if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) return;
+  const long long c0 = cf - 3 * st;
+  FaceWindow w;
+#pragma unroll
+  for (int m = 1; m < 5; ++m)
+#pragma unroll
+    for (int v = 1; v < 4; ++v) w.q[m][v] = P[v * g.vs + c0 + m * st];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    w.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
+    if (g.viscous) load_tangential<D>(g, Gv, c0 + (1 + m) * st, w.tg[m]);
+  }
+  Geom gd = g;
+  gd.inviscid = 0;  // the inviscid part is k_face_adj_inv
   struct AtomicSink {
     double* Wbar;
     double* Dbar;
@@ -102,31 +150,32 @@ __global__ void __launch_bounds__(kBlock) k_face_adj(const double* __restrict__ 
   } sink{Wbar, Dbar, c0, st, g.vs,
          {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2},
          {g.viscous && g.act[T1], g.viscous && g.act[T1], g.viscous && g.act[T2], g.viscous && g.act[T2]}};
-  face_flux_rev<D>(g, w, Gb, sink);
+  face_flux_rev<D>(gd, w, Gb, sink);
 }
 
 // Padded coordinates of axis d that the boundary map sends to interior
-// coordinate x (the halo images of x plus x itself).
-__device__ __forceinline__ int images(const Geom& g, int d, int x, int* out) {
+// coordinate x (its halo images plus x itself), as first, count and step:
+// periodic images are x - n, x, x + n where inside the padding; zero-gradient
+// edge cells own the whole halo run beside them.
+__device__ __forceinline__ void images(const Geom& g, int d, int x, int& first, int& count, int& step) {
   const int n = g.n[d], h = g.h[d];
   if (!g.act[d]) {
-    out[0] = 0;
-    return 1;
+    first = 0;
+    count = 1;
+    step = 1;
+    return;
   }
-  int cnt = 0;
-  const bool plo = g.bc[2 * d] == 0, phi = g.bc[2 * d + 1] == 0;
-  if (plo || phi) {  // periodic (pairs): images x - n and x + n when inside the padding
-    if (x - n >= -h) out[cnt++] = x - n;
-    out[cnt++] = x;
-    if (x + n < n + h) out[cnt++] = x + n;
-    return cnt;
+  if (g.bc[2 * d] == 0) {
+    first = x - n >= -h ? x - n : x;
+    const int last = x + n < n + h ? x + n : x;
+    step = n;
+    count = (last - first) / n + 1;
+    return;
   }
-  if (x == 0)
-    for (int y = -h; y < 0; ++y) out[cnt++] = y;
-  out[cnt++] = x;
-  if (x == n - 1)
-    for (int y = n; y < n + h; ++y) out[cnt++] = y;
-  return cnt;
+  step = 1;
+  first = x == 0 ? -h : x;
+  const int last = x == n - 1 ? n - 1 + h : x;
+  count = last - first + 1;
 }
 
 // Per interior cell s: gather the adjoints of all its images, apply the
@@ -137,13 +186,15 @@ __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ 
                                                      Geom g) {
   const PlaneIdx p = plane_index(g);
   if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
-  int ix[8], iy[8], iz[8];
-  const int nx = images(g, 0, p.i, ix), ny = images(g, 1, p.j, iy), nz = images(g, 2, p.k, iz);
+  int fx, cx, sx, fy, cy, sy, fz, cz, sz;
+  images(g, 0, p.i, fx, cx, sx);
+  images(g, 1, p.j, fy, cy, sy);
+  images(g, 2, p.k, fz, cz, sz);
   double wb[6] = {0, 0, 0, 0, 0, 0};
-  for (int c = 0; c < nz; ++c)
-    for (int b = 0; b < ny; ++b)
-      for (int a = 0; a < nx; ++a) {
-        const int q[3] = {ix[a], iy[b], iz[c]};
+  for (int c = 0; c < cz; ++c)
+    for (int b = 0; b < cy; ++b)
+      for (int a = 0; a < cx; ++a) {
+        const int q[3] = {fx + a * sx, fy + b * sy, fz + c * sz};
         const long long cc = cell_at(g, q[0], q[1], q[2]);
 #pragma unroll
         for (int v = 0; v < 6; ++v) wb[v] += Wbar[v * g.vs + cc];

@@ -145,19 +145,15 @@ struct FaceWindow {
 // part uses the fourth-order face derivative along the normal, the centred
 // derivatives interpolated with the fourth-order central interpolation along
 // the normal, and face velocities from the same interpolation.
+// Numerical flux from given reconstructed states WL, WR (inviscid part) and the
+// window's dissipative inputs (cells 1..4 of w: velocities, T~, tangential
+// derivatives).
 template <int D>
-__host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
+__host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const double* WL, const double* WR,
+                                                      const FaceWindow& w, double* G) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (g.inviscid) {
-    double WL[5], WR[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      WL[v] = weno5(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
-      WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
-    }
-    hllc<D>(g.gamma, g.gm1i, WL, WR, F);
-  }
+  if (g.inviscid) hllc<D>(g.gamma, g.gm1i, WL, WR, F);
   if (g.viscous || g.heat) {
     const double i24 = g.idx[D] / 24.0;
     auto dn = [&](double a, double b, double c, double d) { return (a - 27.0 * b + 27.0 * c - d) * i24; };
@@ -192,6 +188,21 @@ __host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWind
   }
 #pragma unroll
   for (int v = 0; v < 5; ++v) G[v] = F[v];
+}
+
+// Numerical flux G = F - F^d across the face (§3.3, §3.4): WENO5-JS left and
+// right of the face from the window, then face_flux_lr.
+template <int D>
+__host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
+  double WL[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WR[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (g.inviscid) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      WL[v] = weno5(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
+      WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
+    }
+  }
+  face_flux_lr<D>(g, WL, WR, w, G);
 }
 
 }  // namespace cfd
