@@ -177,7 +177,7 @@ static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t
 static cfd_status enqueue_fluxes(cfd_solver* s, const StageIO& io, bool rk, hipStream_t st) {
   const Geom& g = s->g;
   if (g.viscous) {
-    hipLaunchKernelGGL(k_grad, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
+    hipLaunchKernelGGL(k_grad, grad_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
     CFD_LAUNCHED();
   }
   int first = -1, last = -1;
@@ -316,7 +316,7 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
   cfd_status rc;
   if ((rc = enqueue_prim(s, U, 0, nullptr, st))) return rc;
   if (g.viscous) {
-    hipLaunchKernelGGL(k_grad, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g,
+    hipLaunchKernelGGL(k_grad, grad_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g,
                        (const double*)nullptr);
     CFD_LAUNCHED();
   }
@@ -505,7 +505,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
                        s->partial);
     (void)hipEventRecord(ev[1], st);
     if (g.viscous)
-      hipLaunchKernelGGL(k_grad, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
+      hipLaunchKernelGGL(k_grad, grad_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
     (void)hipEventRecord(ev[2], st);
     for (int d = 0; d < 3; ++d) {
       if (g.act[d]) {

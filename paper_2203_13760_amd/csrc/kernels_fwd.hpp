@@ -266,10 +266,81 @@ __device__ __forceinline__ void grad_body(const double* __restrict__ P, double* 
   }
 }
 
+// The same derivatives, marching along z: one thread per padded (x, y) column
+// and a segment of kGradSeg planes keeps u, v, w of five planes in registers
+// for the z derivatives, so each plane is read from memory once per segment;
+// x and y derivatives read the current plane. Blocks are taken in XCD-major
+// order so that neighbouring rows share an L2.
+constexpr int kGradSeg = 16;
+
 __global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ P, double* __restrict__ Gv,
                                                  Geom g, const double* dtp) {
   if (step_disabled(dtp)) return;
-  grad_body(P, Gv, g, plane_index(g, true));
+  const int logical = xcd_major_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int by = logical / gridDim.x;
+  const int bx = logical - by * gridDim.x;
+  const int plane = g.N[0] * g.N[1];
+  const int t = bx * kBlock + threadIdx.x;
+  if (t >= plane) return;
+  const int jj = t / g.N[0];
+  const int i = t - jj * g.N[0] - g.h[0];
+  const int j = jj - g.h[1];
+  const int kz0 = by * kGradSeg - g.h[2];
+  const int kz1 = min(kz0 + kGradSeg, g.n[2] + g.h[2]);
+  const bool dx = g.act[0] && i >= 0 && i < g.n[0];
+  const bool dy = g.act[1] && j >= 0 && j < g.n[1];
+  const bool dz = g.act[2] != 0;
+  const double* u = P + g.vs;  // velocity component a at u + a * vs
+  const long long sz = g.s[2];
+  double wz[5][3];
+  if (dz) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = kz0 - 2 + m;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        wz[m][a] = (k >= -g.h[2] && k < g.n[2] + g.h[2]) ? u[a * g.vs + (long long)(k + g.h[2]) * sz + t] : 0.0;
+    }
+  }
+  for (int k = kz0; k < kz1; ++k) {
+    const long long c = (long long)(k + g.h[2]) * sz + t;
+    if (dz) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wz[4][a] = (k + 2 < g.n[2] + g.h[2]) ? u[a * g.vs + c + 2 * sz] : 0.0;
+      if (k >= 0 && k < g.n[2]) {
+        const double i12 = g.idx[2] / 12.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          Gv[(a * 3 + 2) * g.vs + c] = (wz[0][a] - 8.0 * wz[1][a] + 8.0 * wz[3][a] - wz[4][a]) * i12;
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wz[m][a] = wz[m + 1][a];
+    }
+    if (dx) {
+      const double i12 = g.idx[0] / 12.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double* q = u + a * g.vs + c;
+        Gv[(a * 3 + 0) * g.vs + c] = (q[-2] - 8.0 * q[-1] + 8.0 * q[1] - q[2]) * i12;
+      }
+    }
+    if (dy) {
+      const long long sy = g.s[1];
+      const double i12 = g.idx[1] / 12.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double* q = u + a * g.vs + c;
+        Gv[(a * 3 + 1) * g.vs + c] = (q[-2 * sy] - 8.0 * q[-sy] + 8.0 * q[sy] - q[2 * sy]) * i12;
+      }
+    }
+  }
+}
+
+// Launch shape of k_grad.
+__host__ __device__ __forceinline__ dim3 grad_grid(const Geom& g) {
+  return dim3((unsigned)((g.N[0] * g.N[1] + kBlock - 1) / kBlock), (unsigned)((g.N[2] + kGradSeg - 1) / kGradSeg));
 }
 
 // ----------------------------------------------------------------------------
