@@ -68,7 +68,7 @@ struct cfd_solver {
   double* A3 = nullptr;
   double* Wbar = nullptr; // 6 x padded
   double* Dbar = nullptr; // 9 x padded (viscous runs)
-  double* partial = nullptr;  // CFL rate maxima, one per block of a plane-indexed launch
+  double* partial = nullptr;  // CFL rate maxima slots (kCflSlots)
   int npart = 0;
   DevCtl* ctl = nullptr;
   hipStream_t cap = nullptr;
@@ -214,7 +214,7 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   // stage 1: U1 = Un + dt R(Un); the prim pass runs before dt is known
   if ((rc = enqueue_prim(s, U, PRIM_HEALTH | (cfl ? PRIM_CFL : 0), nullptr, st))) return rc;
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out,
-                     (const double*)s->partial, s->npart);
+                     s->partial, s->npart);
   CFD_LAUNCHED();
   io.Uk = U;
   io.Uout = s->U1;
@@ -358,11 +358,8 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
             hipMalloc(&s->Racc, st) == hipSuccess &&
             hipMalloc(&s->P, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
             hipMalloc(&s->ctl, sizeof(DevCtl)) == hipSuccess;
-  {
-    const dim3 pg = plane_grid(s->g);
-    s->npart = (int)(pg.x * pg.y);
-    ok = ok && hipMalloc(&s->partial, sizeof(double) * (size_t)s->npart) == hipSuccess;
-  }
+  s->npart = kCflSlots;
+  ok = ok && hipMalloc(&s->partial, sizeof(double) * (size_t)s->npart) == hipSuccess;
   if (ok && s->g.viscous) ok = hipMalloc(&s->Gv, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -370,6 +367,7 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
     return fail(CFD_ENOMEM, "device allocation failed");
   }
   if (hipMemset(s->ctl, 0, sizeof(DevCtl)) != hipSuccess ||
+      hipMemset(s->partial, 0, sizeof(double) * (size_t)s->npart) != hipSuccess ||
       hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     cfd_destroy(s);
@@ -427,7 +425,7 @@ cfd_status cfd_compute_dt(cfd_solver* s, const double* U, double* dt_dev, void* 
   hipLaunchKernelGGL(k_cfl, plane_grid(s->g), dim3(kBlock), 0, st, U, s->g, s->partial);
   CFD_LAUNCHED();
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, 0.0, 0.0, (double*)nullptr, dt_dev,
-                     (const double*)s->partial, s->npart);
+                     s->partial, s->npart);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -479,7 +477,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
   const Geom& g = s->g;
   // a fixed nonzero step so that the stage kernels do their work
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, 1e-12, 0.0, (double*)nullptr,
-                     (double*)nullptr, (const double*)s->partial, s->npart);
+                     (double*)nullptr, s->partial, s->npart);
   CFD_LAUNCHED();
   StageIO io{};
   io.R = s->Racc;
@@ -550,7 +548,7 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   const Geom& g = s->g;
   // forward recompute of the stage states U1, U2 with the fixed step
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, dt, 0.0, (double*)nullptr,
-                     (double*)nullptr, (const double*)s->partial, s->npart);
+                     (double*)nullptr, s->partial, s->npart);
   CFD_LAUNCHED();
   const double* dtp = &s->ctl->dt;
   StageIO io{};

@@ -26,7 +26,7 @@ struct GridWork {
   double* P;       // 6 x padded
   double* Gv;      // 9 x padded (viscous grids)
   double* R;       // 5 x padded
-  double* partial; // CFL partials
+  double* partial; // CFL rate slots
   DevCtl* ctl;
   int npart;
   int last_axis;   // the last active axis applies the stage update

@@ -150,6 +150,19 @@ __device__ __forceinline__ double cfl_rate(const Geom& g, double rho, const doub
   return s;
 }
 
+// CFL rate maxima are kept in kCflSlots slots (the bits of non-negative
+// doubles order like unsigned integers, so atomicMax on the bits is a max).
+// Each block folds its maximum into slot (block index mod kCflSlots), which
+// spreads the atomics; k_dt reduces the slots and clears them for the next step.
+constexpr int kCflSlots = 256;
+
+__device__ __forceinline__ void publish_rate(double* slots, int block_index, double s) {
+  s = block_max(s);
+  if (threadIdx.x == 0 && s > 0.0)
+    atomicMax(reinterpret_cast<unsigned long long*>(slots) + (block_index & (kCflSlots - 1)),
+              (unsigned long long)__double_as_longlong(s));
+}
+
 // Primitive variables on the padded grid, gathered through the boundary map.
 // Over interior cells, `what` bit 0 adds the CFL rate (block maxima written
 // to partial[], one per block) and bit 1 the health bits.
@@ -186,10 +199,7 @@ __device__ __forceinline__ void prim_body(const double* __restrict__ U, double* 
       }
     }
   }
-  if (what & PRIM_CFL) {
-    smax = block_max(smax);
-    if (threadIdx.x == 0) partial[part_index] = smax;
-  }
+  if (what & PRIM_CFL) publish_rate(partial, part_index, smax);
 }
 
 __global__ void __launch_bounds__(kBlock) k_prim(const double* __restrict__ U, double* __restrict__ P,
@@ -212,20 +222,20 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const double* __restrict__ U, Ge
     const double p = (g.gamma - 1.0) * (E - 0.5 * (m0 * u[0] + m1 * u[1] + m2 * u[2]));
     smax = cfl_rate(g, rho, u, p);
   }
-  smax = block_max(smax);
-  if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = smax;
+  publish_rate(partial, blockIdx.y * gridDim.x + blockIdx.x, smax);
 }
 
 // Step size of the current step: fixed, or cfl / (max of the npart CFL rate
 // partials); clipped to t_end (> 0) and zero once t_end is reached. Advances
 // *t. One block of kBlock threads.
 __device__ __forceinline__ void dt_body(DevCtl* ctl, double cfl, double fixed_dt, double t_end, double* t,
-                                        double* dt_out, const double* __restrict__ partial, int npart) {
+                                        double* dt_out, double* __restrict__ partial, int npart) {
   double dt = fixed_dt;
   if (!(fixed_dt > 0.0)) {
     double m = 0.0;
     for (int i = threadIdx.x; i < npart; i += blockDim.x) m = fmax(m, partial[i]);
-    m = block_max(m);
+    m = block_max(m);  // every slot has been read once this returns
+    for (int i = threadIdx.x; i < npart; i += blockDim.x) partial[i] = 0.0;
     dt = cfl / m;
   }
   if (threadIdx.x != 0) return;
@@ -239,7 +249,7 @@ __device__ __forceinline__ void dt_body(DevCtl* ctl, double cfl, double fixed_dt
 }
 
 __global__ void __launch_bounds__(kBlock) k_dt(DevCtl* ctl, double cfl, double fixed_dt, double t_end,
-                                               double* t, double* dt_out, const double* __restrict__ partial,
+                                               double* t, double* dt_out, double* __restrict__ partial,
                                                int npart) {
   dt_body(ctl, cfl, fixed_dt, t_end, t, dt_out, partial, npart);
 }
