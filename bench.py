@@ -31,6 +31,39 @@ MI355X_HBM_PEAK = 8.0e12
 DIVERGENCE_FLOPS_PER_CELL_AXIS = 15
 RK_FLOPS_PER_CELL = 20
 KERNELS = ("k_prim", "k_grad", "k_sweep_x", "k_sweep_y", "k_sweep_z")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hit256_traffic.txt")
+
+
+def kernel_sources_hash():
+    """sha256 over the kernel sources (file name + bytes, sorted by name)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2203_13760_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(n):
+    """Calibrated HBM bytes per dispatch from the committed rocprofv3 counter
+    summary, or None when it does not describe this grid or these kernels."""
+    if n != 256 or not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    out = {}
+    for k in KERNELS:
+        if f"{k}.read_bytes" in vals:
+            out[k] = (float(vals[f"{k}.read_bytes"]), float(vals[f"{k}.write_bytes"]))
+    return out
 
 
 def parse():
@@ -232,6 +265,16 @@ def main():
                 "frac": achieved / MI355X_FP64_VECTOR_PEAK, "traffic": None,
                 "kernel_ms": {k: round(v, 4) for k, v in zip(KERNELS, ms)},
                 "flops_per_launch": flops}
+    traffic = measured_traffic(n)
+    if traffic and KERNELS[dom] in traffic:
+        rd, wr = traffic[KERNELS[dom]]
+        roofline["traffic"] = rd + wr
+        roofline["traffic_GBps"] = (rd + wr) / (ms[dom] * 1e-3) / 1e9
+        roofline["traffic_hbm_frac"] = (rd + wr) / (ms[dom] * 1e-3) / MI355X_HBM_PEAK
+        if all(k in traffic for k in KERNELS):
+            stage_bytes = sum(sum(traffic[k]) for k in KERNELS)
+            roofline["stage_traffic_bytes"] = stage_bytes
+            roofline["stage_traffic_GBps"] = stage_bytes / (sum(ms) * 1e-3) / 1e9
     # whole-step view: algorithmic flops per cell-update over the measured step time
     step_flops = 3 * (3 * face * (n + 1) / n + parts["prim_per_cell"] * ((n + 6) / n) ** 3
                       + 45.0 * ((n + 6) / n) ** 3 + 3 * DIVERGENCE_FLOPS_PER_CELL_AXIS + RK_FLOPS_PER_CELL)
