@@ -132,11 +132,11 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
                                 double* Ubar_n, void* stream);
 
 /* Measurement aid: enqueue the kernels of one right-hand-side stage on U
- * (primitive pass, velocity gradient, x/y/z sweeps; the last sweep applies a
- * stage update into solver scratch, so U is not modified) `reps` times, each
- * kernel bracketed by HIP events on `stream`, synchronise, and write the
- * average duration in milliseconds of each kernel to ms_out[0..4] in that
- * order (0 for kernels the configuration does not launch). Synchronises. */
+ * (primitive pass, x/y/z sweeps; the last sweep applies a stage update into
+ * solver scratch, so U is not modified) `reps` times, each kernel bracketed by
+ * HIP events on `stream`, synchronise, and write the average duration in
+ * milliseconds of each kernel to ms_out[0..3] in that order (0 for sweeps the
+ * configuration does not launch). Synchronises. */
 cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, double* ms_out, void* stream);
 
 /* Synchronise the solver's last stream use and report its health word:

@@ -61,7 +61,7 @@ struct cfd_solver {
   double* U1 = nullptr;
   double* U2 = nullptr;
   double* P = nullptr;    // 6 x padded
-  double* Gv = nullptr;   // 9 x padded (viscous runs)
+  double* Gv = nullptr;   // 9 x padded (viscous runs; adjoint scratch)
   double* Racc = nullptr; // 5 x padded
   double* A1 = nullptr;   // adjoint scratch (allocated on the first adjoint call)
   double* A2 = nullptr;
@@ -100,7 +100,8 @@ static cfd_status validate(const cfd_config* c) {
   long long N[3];
   for (int d = 0; d < 3; ++d) N[d] = c->n[d] > 1 ? c->n[d] + 2LL * c->nh : 1;
   for (int d = 0; d < 3; ++d) {
-    long long faces = (long long)c->n[0] * c->n[1] * c->n[2] / c->n[d] * (c->n[d] + 1);
+    // (the x sweep numbers its faces with 3 extra slots per row)
+    long long faces = (long long)c->n[0] * c->n[1] * c->n[2] / c->n[d] * (c->n[d] + (d == 0 ? 4 : 1));
     if (faces >= (1LL << 31)) return fail(CFD_EINVAL, "grid too large: faces per axis must fit in 31 bits");
   }
   if (N[0] * N[1] >= (1LL << 31) || N[2] > 65535) return fail(CFD_EINVAL, "grid too large for the launch shape");
@@ -152,10 +153,10 @@ static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t
   if (D == 0) {
     const unsigned blocks = (unsigned)sweep_x_blocks(g);
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL(k_sweep_x<MODE_ACC>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL(k_sweep_x<MODE_ACC_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
-      default: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL(k_sweep_x<MODE_ACC>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL(k_sweep_x<MODE_ACC_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
+      default: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
     }
   } else {
     constexpr int AX = D == 0 ? 1 : D;
@@ -163,23 +164,20 @@ static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t
     sweep_march_blocks<AX>(g, gx, gy);
     dim3 grid(gx, gy);
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
-      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK>), grid, dim3(kBlock), 0, st, s->P, s->Gv, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
     }
   }
 }
 
-// Enqueue the gradient pass and the per-axis sweeps after a primitive pass.
-// With rk set, the last active axis applies the stage update into io.Uout;
-// otherwise io.R receives the full right-hand side.
+// Enqueue the per-axis sweeps after a primitive pass (the sweeps take the
+// tangential velocity derivatives from the primitives themselves). With rk
+// set, the last active axis applies the stage update into io.Uout; otherwise
+// io.R receives the full right-hand side.
 static cfd_status enqueue_fluxes(cfd_solver* s, const StageIO& io, bool rk, hipStream_t st) {
   const Geom& g = s->g;
-  if (g.viscous) {
-    hipLaunchKernelGGL(k_grad, grad_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
-    CFD_LAUNCHED();
-  }
   int first = -1, last = -1;
   for (int d = 0; d < 3; ++d)
     if (g.act[d]) {
@@ -279,19 +277,21 @@ static cfd_status run_graph(cfd_solver* s, double* U, int mode, double fixed_dt,
 
 // ---------------------------------------------------------------------------
 // Adjoint scratch: two adjoint states, the primitive-adjoint and the
-// derivative-adjoint accumulators. Allocated on the first adjoint call.
+// derivative-adjoint accumulators, and the stored velocity gradient the
+// dissipative reverse reads. Allocated on the first adjoint call.
 static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   if (s->A1) return CFD_OK;
   const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
   bool ok = hipMalloc(&s->A1, st) == hipSuccess && hipMalloc(&s->A2, st) == hipSuccess &&
             hipMalloc(&s->Wbar, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess;
   if (ok && s->g.viscous) ok = hipMalloc(&s->Dbar, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
+  if (ok && s->g.viscous) ok = hipMalloc(&s->Gv, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
-    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar};
+    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar, s->Gv};
     for (double* x : b)
       if (x) (void)hipFree(x);
-    s->A1 = s->A2 = s->Wbar = s->Dbar = nullptr;
+    s->A1 = s->A2 = s->Wbar = s->Dbar = s->Gv = nullptr;
     return fail(CFD_ENOMEM, "adjoint scratch allocation failed");
   }
   return CFD_OK;
@@ -360,7 +360,6 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
             hipMalloc(&s->ctl, sizeof(DevCtl)) == hipSuccess;
   s->npart = kCflSlots;
   ok = ok && hipMalloc(&s->partial, sizeof(double) * (size_t)s->npart) == hipSuccess;
-  if (ok && s->g.viscous) ok = hipMalloc(&s->Gv, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     cfd_destroy(s);
@@ -493,18 +492,15 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
       if (first < 0) first = d;
       last = d;
     }
-  hipEvent_t ev[6];
-  for (int e = 0; e < 6; ++e) CFD_HIP(hipEventCreate(&ev[e]));
-  double acc[5] = {0, 0, 0, 0, 0};
+  hipEvent_t ev[5];
+  for (int e = 0; e < 5; ++e) CFD_HIP(hipEventCreate(&ev[e]));
+  double acc[4] = {0, 0, 0, 0};
   cfd_status rc = CFD_OK;
   for (int r = 0; r < reps && rc == CFD_OK; ++r) {
     (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0, io.dtp,
                        s->partial);
     (void)hipEventRecord(ev[1], st);
-    if (g.viscous)
-      hipLaunchKernelGGL(k_grad, grad_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g, io.dtp);
-    (void)hipEventRecord(ev[2], st);
     for (int d = 0; d < 3; ++d) {
       if (g.act[d]) {
         int mode = d == last ? (d == first ? MODE_WRITE_RK : MODE_ACC_RK) : (d == first ? MODE_WRITE : MODE_ACC);
@@ -512,20 +508,20 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
         else if (d == 1) launch_sweep<1>(s, mode, io, st);
         else launch_sweep<2>(s, mode, io, st);
       }
-      (void)hipEventRecord(ev[3 + d], st);
+      (void)hipEventRecord(ev[2 + d], st);
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
       rc = fail(CFD_EHIP, "profiled stage failed");
       break;
     }
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 4; ++k) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
       acc[k] += ms;
     }
   }
-  for (int e = 0; e < 6; ++e) (void)hipEventDestroy(ev[e]);
-  for (int k = 0; k < 5; ++k) ms_out[k] = acc[k] / reps;
+  for (int e = 0; e < 5; ++e) (void)hipEventDestroy(ev[e]);
+  for (int k = 0; k < 4; ++k) ms_out[k] = acc[k] / reps;
   return rc;
 }
 

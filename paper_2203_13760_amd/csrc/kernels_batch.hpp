@@ -2,7 +2,7 @@
 //
 // Many independent grids (mixed sizes, 2D and 3D, different physics) are
 // resident at once. For every phase of a TVD-RK3 stage (primitives, step size,
-// velocity gradient, x/y/z sweeps) one persistent launch of a fixed number of
+// x/y/z sweeps, halo refresh) one persistent launch of a fixed number of
 // workgroups covers the work of all resident grids: the work of grid k is
 // blocks [prefix[k], prefix[k+1]) of that phase, and each workgroup strides
 // over the concatenated block range, finds its grid by binary search, and runs
@@ -14,7 +14,7 @@
 
 namespace cfd {
 
-enum BatchPhase { PH_PRIM = 0, PH_DT, PH_GRAD, PH_SX, PH_SY, PH_SZ, PH_HALO, PH_COUNT };
+enum BatchPhase { PH_PRIM = 0, PH_DT, PH_SX, PH_SY, PH_SZ, PH_HALO, PH_COUNT };
 
 constexpr int kBatchMaxGrids = 512;
 
@@ -24,7 +24,6 @@ struct GridWork {
   double* U1;
   double* U2;
   double* P;       // 6 x padded
-  double* Gv;      // 9 x padded (viscous grids)
   double* R;       // 5 x padded
   double* partial; // CFL rate slots
   DevCtl* ctl;
@@ -55,13 +54,13 @@ __device__ __forceinline__ int find_grid(const int* __restrict__ prefix, int ngr
 template <int MODE>
 __device__ __forceinline__ void batch_sweep(int axis, const GridWork& w, const StageIO& io, int local) {
   if (axis == 0) {
-    sweep_x_body<MODE>(w.P, w.Gv, io, w.g, local);
+    sweep_x_body<MODE>(w.P, io, w.g, local);
   } else if (axis == 1) {
     const int by = local / w.sgx[1];
-    sweep_march_body<1, MODE>(w.P, w.Gv, io, w.g, local - by * w.sgx[1], by);
+    sweep_march_body<1, MODE>(w.P, io, w.g, local - by * w.sgx[1], by);
   } else {
     const int by = local / w.sgx[2];
-    sweep_march_body<2, MODE>(w.P, w.Gv, io, w.g, local - by * w.sgx[2], by);
+    sweep_march_body<2, MODE>(w.P, io, w.g, local - by * w.sgx[2], by);
   }
 }
 
@@ -91,10 +90,6 @@ __global__ void __launch_bounds__(kBlock) k_batch(const BatchTable* __restrict__
       prim_body(io.Uk, w.P, g, w.ctl, STAGE == 1 ? (PRIM_CFL | PRIM_HEALTH) : 0, w.partial, q, local);
     } else if (PHASE == PH_DT) {
       dt_body(w.ctl, g.cfl, 0.0, 0.0, nullptr, nullptr, w.partial, w.npart);
-    } else if (PHASE == PH_GRAD) {
-      const int by = local / w.pgx;
-      const int bx = local - by * w.pgx;
-      grad_body(w.P, w.Gv, g, plane_index_at(g, bx, by, w.pgx, g.N[2], false));
     } else if (PHASE == PH_HALO) {
       const int by = local / w.pgx;
       const int bx = local - by * w.pgx;

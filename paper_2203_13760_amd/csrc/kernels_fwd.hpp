@@ -255,28 +255,12 @@ __global__ void __launch_bounds__(kBlock) k_dt(DevCtl* ctl, double cfl, double f
 }
 
 // ----------------------------------------------------------------------------
-// Cell-centred velocity gradient (fourth-order central, §3.4):
-// Gv[a*3+b] = d u_a / d x_b, written wherever coordinate b is interior (the
-// only places a face interpolation reads it).
-__device__ __forceinline__ void grad_body(const double* __restrict__ P, double* __restrict__ Gv, const Geom& g,
-                                          const PlaneIdx& p) {
-  if (!p.in) return;
-  const int q[3] = {p.i, p.j, p.k};
-  const long long c = p.c;
-#pragma unroll
-  for (int b = 0; b < 3; ++b) {
-    if (!g.act[b] || q[b] < 0 || q[b] >= g.n[b]) continue;
-    const long long st = g.s[b];
-    const double i12 = g.idx[b] / 12.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double* u = P + (1 + a) * g.vs + c;
-      Gv[(a * 3 + b) * g.vs + c] = (u[-2 * st] - 8.0 * u[-st] + 8.0 * u[st] - u[2 * st]) * i12;
-    }
-  }
-}
-
-// The same derivatives, marching along z: one thread per padded (x, y) column
+// Cell-centred velocity gradient (fourth-order central, §3.4), stored for the
+// dissipative reverse of the adjoint: Gv[a*3+b] = d u_a / d x_b, written
+// wherever coordinate b is interior (the only places a face interpolation
+// reads it). The forward sweeps form the derivatives they need themselves.
+//
+// The kernel marches along z: one thread per padded (x, y) column
 // and a segment of kGradSeg planes keeps u, v, w of five planes in registers
 // for the z derivatives, so each plane is read from memory once per segment;
 // x and y derivatives read the current plane. Blocks are taken in XCD-major
@@ -361,7 +345,8 @@ __device__ __forceinline__ void load_prims(const double* __restrict__ P, long lo
   for (int v = 0; v < 5; ++v) q[v] = P[v * vs + c];
 }
 
-// Tangential derivatives at a cell for faces normal to D (see FaceWindow).
+// Tangential derivatives at a cell for faces normal to D (see FaceWindow),
+// read from the stored gradient Gv (the adjoint path keeps Gv).
 template <int D>
 __device__ __forceinline__ void load_tangential(const Geom& g, const double* __restrict__ Gv, long long c,
                                                 double* tg) {
@@ -376,6 +361,40 @@ __device__ __forceinline__ void load_tangential(const Geom& g, const double* __r
   if (g.act[T2]) {
     tg[2] = Gv[(D * 3 + T2) * g.vs + c];
     tg[3] = Gv[(T2 * 3 + T2) * g.vs + c];
+  } else {
+    tg[2] = 0.0;
+    tg[3] = 0.0;
+  }
+}
+
+// The same four derivatives computed from the primitives (fourth-order
+// central differences across the cell, the expression of k_grad):
+// d u_D / d x_T1, d u_T1 / d x_T1, d u_D / d x_T2, d u_T2 / d x_T2. The
+// tangential coordinates of every cell a face stencil touches are interior, so
+// the +-2 neighbours lie inside the padded block.
+__device__ __forceinline__ double central4(const double* __restrict__ q, long long st, double i12) {
+  return (q[-2 * st] - 8.0 * q[-st] + 8.0 * q[st] - q[2 * st]) * i12;
+}
+
+template <int D>
+__device__ __forceinline__ void tangential_at(const Geom& g, const double* __restrict__ P, long long c,
+                                              double* tg) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const double* uD = P + (1 + D) * g.vs + c;
+  if (g.act[T1]) {
+    const long long st = g.s[T1];
+    const double i12 = g.idx[T1] / 12.0;
+    tg[0] = central4(uD, st, i12);
+    tg[1] = central4(P + (1 + T1) * g.vs + c, st, i12);
+  } else {
+    tg[0] = 0.0;
+    tg[1] = 0.0;
+  }
+  if (g.act[T2]) {
+    const long long st = g.s[T2];
+    const double i12 = g.idx[T2] / 12.0;
+    tg[2] = central4(uD, st, i12);
+    tg[3] = central4(P + (1 + T2) * g.vs + c, st, i12);
   } else {
     tg[2] = 0.0;
     tg[3] = 0.0;
@@ -400,47 +419,70 @@ __device__ __forceinline__ void emit(const StageIO& io, long long vs, long long 
   }
 }
 
-// x sweep: faces of all interior rows are numbered row-major, face f of a row
-// lying between cells f-1 and f (f = 0..nx). Each wavefront takes
-// kXIters*64 consecutive faces, the first of which overlaps the previous
-// wavefront's last face and only seeds the carry.
+// x sweep: every interior row holds kXCtx context slots followed by its nx+1
+// faces, and the slots of all rows are numbered row-major; slot s of a row is
+// face f = s - kXCtx, lying between cells f-1 and f. The lane of slot s
+// computes the tangential velocity derivatives of cell f+1, and face f takes
+// those of cells f-2..f+1 from itself and the three lanes below it (context
+// slots only supply the first faces of their row). Each wavefront takes
+// kXIters*64 consecutive slots; its first kXCtx+1 slots overlap the previous
+// wavefront and only seed the derivative and flux carries.
 constexpr int kXIters = 4;
+constexpr int kXCtx = 3;
 
 template <int MODE>
-__device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const double* __restrict__ Gv,
-                                             const StageIO& io, const Geom& g, int bx) {
-  // face numbering fits in 32 bits (checked when the solver is created)
+__device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const StageIO& io, const Geom& g,
+                                             int bx) {
+  // slot numbering fits in 32 bits (checked when the solver is created)
   const int lane = threadIdx.x & 63;
   const int wave = (bx * kBlock + (int)threadIdx.x) >> 6;
-  const int F = g.n[0] + 1;
-  const int total = F * g.n[1] * g.n[2];
-  constexpr int Q = 64 * kXIters - 1;
+  const int S = g.n[0] + 1 + kXCtx;
+  const int total = S * g.n[1] * g.n[2];
+  constexpr int Q = 64 * kXIters - (kXCtx + 1);
   const int first = wave * Q;
   if (first >= total) return;  // whole wavefront exits together
   double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double dprev[4] = {0.0, 0.0, 0.0, 0.0};
   for (int it = 0; it < kXIters; ++it) {
-    const int gf = first - 1 + it * 64 + lane;
-    const bool valid = gf >= 0 && gf < total;
+    const int gs = first - (kXCtx + 1) + it * 64 + lane;
+    const bool inrange = gs >= 0 && gs < total;
+    int f = 0, j = 0, k = 0;
+    if (inrange) {
+      const int row = gs / S;
+      f = gs - row * S - kXCtx;
+      k = row / g.n[1];
+      j = row - k * g.n[1];
+    }
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    if (inrange && g.viscous) tangential_at<0>(g, P, cell_at(g, f + 1, j, k), d);
+    // face values of the derivatives from cells f-2..f+1 (lanes - 3 .. lane)
+    double tf[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      double t[3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int back = 3 - m;  // cell f-2+m lives in lane - back
+        const int src = (lane - back) & 63;
+        const double a = __shfl(d[v], src, 64);
+        const double b = __shfl(dprev[v], src, 64);
+        t[m] = lane >= back ? a : b;
+      }
+      tf[v] = rc4(t[0], t[1], t[2], d[v]);
+      dprev[v] = d[v];
+    }
+    const bool valid = inrange && f >= 0 && gs >= first - 1;
     double G[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    int row = 0;
-    int f = 0;
     if (valid) {
-      row = gf / F;
-      f = gf - row * F;
-      const int k = row / g.n[1];
-      const int j = row - k * g.n[1];
       FaceWindow w;
       const long long c0 = cell_at(g, f - 3, j, k);
 #pragma unroll
       for (int m = 0; m < 6; ++m) load_prims(P, g.vs, c0 + m, w.q[m]);
       if (g.viscous || g.heat) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          w.T[m] = P[5 * g.vs + c0 + 1 + m];
-          if (g.viscous) load_tangential<0>(g, Gv, c0 + 1 + m, w.tg[m]);
-        }
+        for (int m = 0; m < 4; ++m) w.T[m] = P[5 * g.vs + c0 + 1 + m];
       }
-      face_flux<0>(g, w, G);
+      face_flux_tf<0>(g, w, tf, G);
     }
     double Gm[5];
 #pragma unroll
@@ -449,9 +491,7 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
       Gm[v] = lane == 0 ? carry[v] : up;
       carry[v] = __shfl(G[v], 63, 64);
     }
-    if (valid && gf >= first && f >= 1) {
-      const int k = row / g.n[1];
-      const int j = row - k * g.n[1];
+    if (valid && gs >= first && f >= 1) {
       double D[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[0];
@@ -461,16 +501,16 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P,
-                                                    const double* __restrict__ Gv, StageIO io, Geom g) {
+__global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P, StageIO io, Geom g) {
   if (step_disabled(io.dtp)) return;
-  sweep_x_body<MODE>(P, Gv, io, g, blockIdx.x);
+  sweep_x_body<MODE>(P, io, g, blockIdx.x);
 }
 
 // Blocks of an x sweep.
 __host__ __device__ __forceinline__ int sweep_x_blocks(const Geom& g) {
-  const long long faces = (long long)(g.n[0] + 1) * g.n[1] * g.n[2];
-  const long long waves = (faces + 64 * kXIters - 2) / (64 * kXIters - 1);
+  const long long slots = (long long)(g.n[0] + 1 + kXCtx) * g.n[1] * g.n[2];
+  constexpr int Q = 64 * kXIters - (kXCtx + 1);
+  const long long waves = (slots + Q - 1) / Q;
   return (int)((waves + 3) / 4);
 }
 
@@ -480,8 +520,8 @@ __host__ __device__ __forceinline__ int sweep_x_blocks(const Geom& g) {
 constexpr int kSeg = 32;
 
 template <int AX, int MODE>
-__device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const double* __restrict__ Gv,
-                                                 const StageIO& io, const Geom& g, int bx, int by) {
+__device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const StageIO& io,
+                                                 const Geom& g, int bx, int by) {
   constexpr int OT = AX == 1 ? 2 : 1;  // the other transverse axis
   const int i = bx * 64 + (threadIdx.x & 63);
   const int nseg = (g.n[AX] + kSeg - 1) / kSeg;
@@ -505,7 +545,7 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       w.T[m] = P[5 * g.vs + c + (1 + m) * st];
-      if (g.viscous) load_tangential<AX>(g, Gv, c + (1 + m) * st, w.tg[m]);
+      if (g.viscous) tangential_at<AX>(g, P, c + (1 + m) * st, w.tg[m]);
     }
   }
   double Gm[5];
@@ -518,7 +558,7 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
       load_prims(P, g.vs, c + 6 * st, nq);
       if (dis) {
         nT = P[5 * g.vs + c + 5 * st];
-        if (g.viscous) load_tangential<AX>(g, Gv, c + 5 * st, ntg);
+        if (g.viscous) tangential_at<AX>(g, P, c + 5 * st, ntg);
       }
     }
     double G[5];
@@ -556,11 +596,9 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
 }
 
 template <int AX, int MODE>
-__global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict__ P,
-                                                        const double* __restrict__ Gv, StageIO io,
-                                                        Geom g) {
+__global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict__ P, StageIO io, Geom g) {
   if (step_disabled(io.dtp)) return;
-  sweep_march_body<AX, MODE>(P, Gv, io, g, blockIdx.x, blockIdx.y);
+  sweep_march_body<AX, MODE>(P, io, g, blockIdx.x, blockIdx.y);
 }
 
 // Launch shape of a marching sweep along AX (x blocks, y blocks).

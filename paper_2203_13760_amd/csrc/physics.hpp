@@ -141,33 +141,38 @@ struct FaceWindow {
   double tg[4][4];
 };
 
-// Numerical flux G = F - F^d across the face (§3.3, §3.4); the dissipative
-// part uses the fourth-order face derivative along the normal, the centred
-// derivatives interpolated with the fourth-order central interpolation along
-// the normal, and face velocities from the same interpolation.
-// Numerical flux from given reconstructed states WL, WR (inviscid part) and the
-// window's dissipative inputs (cells 1..4 of w: velocities, T~, tangential
-// derivatives).
+// Fourth-order central interpolation to the face between b and c (§3.4).
+__host__ __device__ __forceinline__ double rc4(double a, double b, double c, double d) {
+  return (-a + 9.0 * b + 9.0 * c - d) / 16.0;
+}
+
+// Face values of the four tangential derivatives of a window (same order as
+// FaceWindow::tg), interpolated along the normal from cells 1..4.
+__host__ __device__ __forceinline__ void face_tangential(const FaceWindow& w, double* tf) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) tf[k] = rc4(w.tg[0][k], w.tg[1][k], w.tg[2][k], w.tg[3][k]);
+}
+
+// Numerical flux G = F - F^d across the face (§3.3, §3.4) from given
+// reconstructed states WL, WR (inviscid part), the window's cells 1..4
+// (velocities and T~ for the fourth-order normal derivatives and the face
+// velocities) and the face values tf of the tangential derivatives.
 template <int D>
 __host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const double* WL, const double* WR,
-                                                      const FaceWindow& w, double* G) {
+                                                      const FaceWindow& w, const double* tf, double* G) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (g.inviscid) hllc<D>(g.gamma, g.gm1i, WL, WR, F);
   if (g.viscous || g.heat) {
     const double i24 = g.idx[D] / 24.0;
     auto dn = [&](double a, double b, double c, double d) { return (a - 27.0 * b + 27.0 * c - d) * i24; };
-    auto rc4 = [&](double a, double b, double c, double d) { return (-a + 9.0 * b + 9.0 * c - d) / 16.0; };
     double Fd1 = 0.0, Fd2 = 0.0, Fd3 = 0.0, Fd4 = 0.0;  // slots D, T1, T2 momentum; energy
     if (g.viscous) {
       // normal derivatives of the three velocity components
       const double dD = dn(w.q[1][1 + D], w.q[2][1 + D], w.q[3][1 + D], w.q[4][1 + D]);
       const double d1 = dn(w.q[1][1 + T1], w.q[2][1 + T1], w.q[3][1 + T1], w.q[4][1 + T1]);
       const double d2 = dn(w.q[1][1 + T2], w.q[2][1 + T2], w.q[3][1 + T2], w.q[4][1 + T2]);
-      const double uD_t1 = rc4(w.tg[0][0], w.tg[1][0], w.tg[2][0], w.tg[3][0]);
-      const double u1_t1 = rc4(w.tg[0][1], w.tg[1][1], w.tg[2][1], w.tg[3][1]);
-      const double uD_t2 = rc4(w.tg[0][2], w.tg[1][2], w.tg[2][2], w.tg[3][2]);
-      const double u2_t2 = rc4(w.tg[0][3], w.tg[1][3], w.tg[2][3], w.tg[3][3]);
+      const double uD_t1 = tf[0], u1_t1 = tf[1], uD_t2 = tf[2], u2_t2 = tf[3];
       const double div = dD + u1_t1 + u2_t2;
       const double tDD = g.mu * (dD + dD) - (2.0 / 3.0) * g.mu * div;
       const double tD1 = g.mu * (uD_t1 + d1);
@@ -190,10 +195,11 @@ __host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const doubl
   for (int v = 0; v < 5; ++v) G[v] = F[v];
 }
 
-// Numerical flux G = F - F^d across the face (§3.3, §3.4): WENO5-JS left and
-// right of the face from the window, then face_flux_lr.
+// Numerical flux from the window's primitives and given face tangential
+// derivatives tf: WENO5-JS left and right of the face, then face_flux_lr.
 template <int D>
-__host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
+__host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceWindow& w, const double* tf,
+                                                      double* G) {
   double WL[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WR[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (g.inviscid) {
 #pragma unroll
@@ -202,7 +208,15 @@ __host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWind
       WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
     }
   }
-  face_flux_lr<D>(g, WL, WR, w, G);
+  face_flux_lr<D>(g, WL, WR, w, tf, G);
+}
+
+// Numerical flux G = F - F^d across the face (§3.3, §3.4) from a full window.
+template <int D>
+__host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
+  double tf[4] = {0.0, 0.0, 0.0, 0.0};
+  if (g.viscous) face_tangential(w, tf);
+  face_flux_tf<D>(g, w, tf, G);
 }
 
 }  // namespace cfd
