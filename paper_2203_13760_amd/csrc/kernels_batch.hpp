@@ -66,7 +66,7 @@ __device__ __forceinline__ void batch_sweep(int axis, const GridWork& w, const S
 
 // STAGE 1..3 selects the stage input/output states and the stage weights.
 template <int PHASE, int STAGE>
-__global__ void __launch_bounds__(kBlock) k_batch(const BatchTable* __restrict__ tab) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_batch(const BatchTable* __restrict__ tab) {
   const int ng = tab->ngrids;
   const int* prefix = tab->prefix[PHASE];
   const int total = prefix[ng];

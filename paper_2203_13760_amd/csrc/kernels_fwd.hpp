@@ -419,6 +419,38 @@ __device__ __forceinline__ void emit(const StageIO& io, long long vs, long long 
   }
 }
 
+// The same in two halves, so that a marching sweep can issue the loads of a
+// cell's update (accumulated R, stage states) before the face arithmetic and
+// store after it: EmitIn holds the loaded values.
+struct EmitIn {
+  double r[5], un[5], uk[5];
+};
+
+template <int MODE>
+__device__ __forceinline__ void emit_fetch(const StageIO& io, long long vs, long long c, EmitIn& in) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long e = v * vs + c;
+    if (MODE == MODE_ACC || MODE == MODE_ACC_RK) in.r[v] = io.R[e];
+    if (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) {
+      in.un[v] = io.Un[e];
+      in.uk[v] = io.Uk[e];
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void emit_put(const StageIO& io, long long vs, long long c, const double* D,
+                                         const EmitIn& in, double dt) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long e = v * vs + c;
+    const double r = (MODE == MODE_WRITE || MODE == MODE_WRITE_RK) ? -D[v] : in.r[v] - D[v];
+    if (MODE == MODE_WRITE || MODE == MODE_ACC) io.R[e] = r;
+    else io.Uout[e] = io.a * in.un[v] + io.b * (in.uk[v] + dt * r);
+  }
+}
+
 // x sweep: every interior row holds kXCtx context slots followed by its nx+1
 // faces, and the slots of all rows are numbered row-major; slot s of a row is
 // face f = s - kXCtx, lying between cells f-1 and f. The lane of slot s
@@ -426,8 +458,10 @@ __device__ __forceinline__ void emit(const StageIO& io, long long vs, long long 
 // those of cells f-2..f+1 from itself and the three lanes below it (context
 // slots only supply the first faces of their row). Each wavefront takes
 // kXIters*64 consecutive slots; its first kXCtx+1 slots overlap the previous
-// wavefront and only seed the derivative and flux carries.
-constexpr int kXIters = 4;
+// wavefront and only seed the derivative and flux carries. One pass per
+// wavefront keeps the kernel at three wavefronts per SIMD (142 VGPRs); the
+// carries of longer runs cost more registers than the overlap saves.
+constexpr int kXIters = 1;
 constexpr int kXCtx = 3;
 
 template <int MODE>
@@ -549,10 +583,14 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
     }
   }
   double Gm[5];
+  const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
   for (int f = s0 - 1; f < s1; ++f) {
-    // issue the loads of the cell entering the window at the next face before
-    // this face's arithmetic, so their latency overlaps it
+    // issue the loads of the cell entering the window at the next face, and
+    // those of this face's cell update, before this face's arithmetic, so
+    // their latency overlaps it
     const bool more = f + 1 < s1;
+    EmitIn ein;
+    if (f >= s0) emit_fetch<MODE>(io, g.vs, c + 2 * st, ein);  // window cell 2 is cell f
     double nq[5], nT = 0.0, ntg[4] = {0.0, 0.0, 0.0, 0.0};
     if (more) {
       load_prims(P, g.vs, c + 6 * st, nq);
@@ -567,7 +605,7 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
       double D[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[AX];
-      emit<MODE>(io, g.vs, c + 2 * st, D);  // window cell 2 is cell f
+      emit_put<MODE>(io, g.vs, c + 2 * st, D, ein, dt);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) Gm[v] = G[v];
