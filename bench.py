@@ -31,7 +31,7 @@ MI355X_HBM_PEAK = 8.0e12
 DIVERGENCE_FLOPS_PER_CELL_AXIS = 15
 RK_FLOPS_PER_CELL = 20
 GRADIENT_FLOPS_PER_CELL = 45  # 9 fourth-order centred velocity derivatives, 5 flops each
-KERNELS = ("k_prim", "k_sweep_x", "k_sweep_y", "k_sweep_z")
+KERNELS = ("k_prim", "k_sweep_x", "k_sweep_y", "k_sweep_z", "k_prim_halo")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hit256_traffic.txt")
 
 
@@ -257,11 +257,14 @@ def main():
     # nine fourth-order central derivatives of a cell (5 flops each) are
     # credited a third to each sweep
     grad = GRADIENT_FLOPS_PER_CELL / 3.0
+    # the z sweep also forms the primitives of the updated cells
     flops = {
         0: parts["prim_per_cell"] * (n + 6) ** 3,
         1: face * faces_per_axis + (DIVERGENCE_FLOPS_PER_CELL_AXIS + grad) * cells,
         2: face * faces_per_axis + (DIVERGENCE_FLOPS_PER_CELL_AXIS + grad) * cells,
-        3: face * faces_per_axis + (DIVERGENCE_FLOPS_PER_CELL_AXIS + grad + RK_FLOPS_PER_CELL) * cells,
+        3: face * faces_per_axis + (DIVERGENCE_FLOPS_PER_CELL_AXIS + grad + RK_FLOPS_PER_CELL
+                                    + parts["prim_per_cell"]) * cells,
+        4: 0.0,
     }[dom]
     achieved = flops / (ms[dom] * 1e-3)
     roofline = {"bound": "alu", "kernel": KERNELS[dom], "achieved": achieved / 1e12,
@@ -275,10 +278,13 @@ def main():
         roofline["traffic"] = rd + wr
         roofline["traffic_GBps"] = (rd + wr) / (ms[dom] * 1e-3) / 1e9
         roofline["traffic_hbm_frac"] = (rd + wr) / (ms[dom] * 1e-3) / MI355X_HBM_PEAK
-        if all(k in traffic for k in KERNELS):
-            stage_bytes = sum(sum(traffic[k]) for k in KERNELS)
+        # a stage of a run of steps: the sweeps and the primitives' halo refresh
+        # (the primitive pass runs once per run, before the first step)
+        stage = KERNELS[1:]
+        if all(k in traffic for k in stage):
+            stage_bytes = sum(sum(traffic[k]) for k in stage)
             roofline["stage_traffic_bytes"] = stage_bytes
-            roofline["stage_traffic_GBps"] = stage_bytes / (sum(ms) * 1e-3) / 1e9
+            roofline["stage_traffic_GBps"] = stage_bytes / (sum(ms[1:]) * 1e-3) / 1e9
     # whole-step view: algorithmic flops per cell-update over the measured step time
     step_flops = 3 * (3 * face * (n + 1) / n + parts["prim_per_cell"] * ((n + 6) / n) ** 3
                       + GRADIENT_FLOPS_PER_CELL + 3 * DIVERGENCE_FLOPS_PER_CELL_AXIS + RK_FLOPS_PER_CELL)

@@ -67,8 +67,9 @@ typedef struct {
 typedef struct cfd_solver cfd_solver; /* opaque; owns the stage buffers and scratch */
 
 /* Validate `cfg` and allocate the solver on the current HIP device: two stage
- * states, the primitive and velocity-gradient scratch, a right-hand-side
- * accumulator and a small device control block. Active axes need n >= nh.
+ * states, three primitive buffers (one per stage input of a step), a
+ * right-hand-side accumulator and a small device control block (the adjoint
+ * entry points add their scratch on first use). Active axes need n >= nh.
  * Returns CFD_EINVAL (bad config), CFD_ENOMEM or CFD_EHIP. Synchronises. */
 cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out);
 
@@ -131,12 +132,15 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream);
 
-/* Measurement aid: enqueue the kernels of one right-hand-side stage on U
- * (primitive pass, x/y/z sweeps; the last sweep applies a stage update into
- * solver scratch, so U is not modified) `reps` times, each kernel bracketed by
- * HIP events on `stream`, synchronise, and write the average duration in
- * milliseconds of each kernel to ms_out[0..3] in that order (0 for sweeps the
- * configuration does not launch). Synchronises. */
+/* Measurement aid: enqueue the kernels of one TVD-RK3 stage on U as a step
+ * runs them (a middle stage: U2 = 3/4 U + 1/4 (U + dt R(U)) with dt = 1e-12,
+ * written to solver scratch, so U is not modified): the primitive pass, the
+ * x/y/z sweeps (the last one also storing the primitives of the updated
+ * cells), and the halo refresh of those primitives. Runs them `reps` times,
+ * each kernel bracketed by HIP events on `stream`, synchronises, and writes the
+ * average duration in milliseconds of each kernel to ms_out[0..4] in that
+ * order (0 for sweeps the configuration does not launch). Within a run of
+ * steps the primitive pass runs once, before the first step. */
 cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, double* ms_out, void* stream);
 
 /* Synchronise the solver's last stream use and report its health word:

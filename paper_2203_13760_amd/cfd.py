@@ -194,8 +194,8 @@ def cfd_rk3_step_adjoint(h, Un, dt, Ubar_np1, Ubar_n, stream=None):
 
 
 def cfd_profile_stage(h, U, reps=5, stream=None):
-    """Average ms of the stage kernels [prim, sweep_x, sweep_y, sweep_z]."""
-    out = (C.c_double * 4)()
+    """Average ms of the stage kernels [prim, sweep_x, sweep_y, sweep_z, prim_halo]."""
+    out = (C.c_double * 5)()
     _check(load().cfd_profile_stage(h, _ptr(U), int(reps), out, _stream(stream)))
     return list(out)
 

@@ -60,7 +60,8 @@ struct cfd_solver {
   long long nint = 0;   // interior cells
   double* U1 = nullptr;
   double* U2 = nullptr;
-  double* P = nullptr;    // 6 x padded
+  double* P = nullptr;    // 6 x padded (= Pb[0])
+  double* Pb[3] = {nullptr, nullptr, nullptr};  // primitives of the stage inputs of a step
   double* Gv = nullptr;   // 9 x padded (viscous runs; adjoint scratch)
   double* Racc = nullptr; // 5 x padded
   double* A1 = nullptr;   // adjoint scratch (allocated on the first adjoint call)
@@ -147,92 +148,136 @@ static cfd_status enqueue_prim(cfd_solver* s, const double* Uk, int what, const 
   return CFD_OK;
 }
 
-template <int D>
-static void launch_sweep(cfd_solver* s, int mode, const StageIO& io, hipStream_t st) {
+template <int D, bool PN>
+static void launch_sweep(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
   const Geom& g = s->g;
   if (D == 0) {
-    const unsigned blocks = (unsigned)sweep_x_blocks(g);
+    const dim3 grid((unsigned)sweep_x_blocks(g));
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL(k_sweep_x<MODE_ACC>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL(k_sweep_x<MODE_ACC_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
-      default: hipLaunchKernelGGL(k_sweep_x<MODE_WRITE_RK>, dim3(blocks), dim3(kBlock), 0, st, s->P, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_x<MODE_ACC, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_x<MODE_ACC_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
     }
   } else {
     constexpr int AX = D == 0 ? 1 : D;
     int gx, gy;
     sweep_march_blocks<AX>(g, gx, gy);
-    dim3 grid(gx, gy);
+    const dim3 grid(gx, gy);
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
-      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK>), grid, dim3(kBlock), 0, st, s->P, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
     }
   }
 }
 
-// Enqueue the per-axis sweeps after a primitive pass (the sweeps take the
-// tangential velocity derivatives from the primitives themselves). With rk
-// set, the last active axis applies the stage update into io.Uout; otherwise
-// io.R receives the full right-hand side.
-static cfd_status enqueue_fluxes(cfd_solver* s, const StageIO& io, bool rk, hipStream_t st) {
-  const Geom& g = s->g;
-  int first = -1, last = -1;
-  for (int d = 0; d < 3; ++d)
+template <bool PN>
+static void launch_sweep_axis(cfd_solver* s, int d, int mode, const double* P, const StageIO& io, hipStream_t st) {
+  if (d == 0) launch_sweep<0, PN>(s, mode, P, io, st);
+  else if (d == 1) launch_sweep<1, PN>(s, mode, P, io, st);
+  else launch_sweep<2, PN>(s, mode, P, io, st);
+}
+
+// Sweeps run z, y, x (active axes only): the x sweep, the lightest in
+// registers, takes the stage update and the next-stage primitives.
+static void sweep_order(const Geom& g, int& first, int& last) {
+  first = last = -1;
+  for (int d = 2; d >= 0; --d)
     if (g.act[d]) {
       if (first < 0) first = d;
       last = d;
     }
-  for (int d = 0; d < 3; ++d) {
+}
+
+// Enqueue the per-axis sweeps over primitives P. With rk set, the last active
+// axis applies the stage update into io.Uout (and, with io.Pn set, stores the
+// primitives of the updated interior cells into io.Pn, whose halo is then
+// refreshed); otherwise io.R receives the full right-hand side.
+static cfd_status enqueue_fluxes(cfd_solver* s, const double* P, const StageIO& io, bool rk, hipStream_t st) {
+  const Geom& g = s->g;
+  int first = -1, last = -1;
+  sweep_order(g, first, last);
+  for (int d = 2; d >= 0; --d) {
     if (!g.act[d]) continue;
     int mode;
     if (d == last && rk) mode = d == first ? MODE_WRITE_RK : MODE_ACC_RK;
     else mode = d == first ? MODE_WRITE : MODE_ACC;
-    if (d == 0) launch_sweep<0>(s, mode, io, st);
-    else if (d == 1) launch_sweep<1>(s, mode, io, st);
-    else launch_sweep<2>(s, mode, io, st);
+    if (d == last && rk && io.Pn) launch_sweep_axis<true>(s, d, mode, P, io, st);
+    else launch_sweep_axis<false>(s, d, mode, P, io, st);
+    CFD_LAUNCHED();
+  }
+  if (rk && io.Pn) {
+    hipLaunchKernelGGL(k_prim_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, io.Pn, g, io.dtp);
     CFD_LAUNCHED();
   }
   return CFD_OK;
 }
 
-// Enqueue one TVD-RK3 step on U in place. fixed_dt > 0 fixes the step;
-// otherwise the CFL step of Un, clipped against *t_dev and t_end when t_dev
-// is given. dt_out (nullable) receives the step.
+// Clear the CFL slots before a fresh accumulation: the last step of a run
+// leaves the maxima of its final state there, consumed by nobody.
+static cfd_status enqueue_clear_slots(cfd_solver* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, st, s->partial, (long long)s->npart);
+  CFD_LAUNCHED();
+  return CFD_OK;
+}
+
+// Step prologue: the primitives of U into Pb[0] with the health bits and,
+// for a CFL step, the CFL rate maxima of U.
+static cfd_status enqueue_step_prologue(cfd_solver* s, const double* U, bool cfl, hipStream_t st) {
+  if (cfl) {
+    cfd_status rc = enqueue_clear_slots(s, st);
+    if (rc) return rc;
+  }
+  return enqueue_prim(s, U, PRIM_HEALTH | (cfl ? PRIM_CFL : 0), nullptr, st);
+}
+
+// Enqueue one TVD-RK3 step on U in place; Pb[0] must hold the primitives of U
+// and, for a CFL step, the CFL slots its rate maxima (the prologue, or the
+// previous step, leaves both). fixed_dt > 0 fixes the step; otherwise the
+// CFL step of Un, clipped against *t_dev and t_end when t_dev is given.
+// dt_out (nullable) receives the step. Each stage's last sweep stores the
+// primitives of its output for the next stage (Pb[0] -> Pb[1] -> Pb[2] ->
+// Pb[0]); the third also the health bits of U^{n+1} and, for CFL steps, its
+// CFL rate maxima, so consecutive steps need no separate primitive pass.
 static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double t_end, double* t_dev,
                                double* dt_out, hipStream_t st) {
   const double* dtp = &s->ctl->dt;
   const bool cfl = !(fixed_dt > 0.0);
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out,
+                     s->partial, s->npart);
+  CFD_LAUNCHED();
   StageIO io{};
   io.R = s->Racc;
   io.Un = U;
   io.dtp = dtp;
+  io.partial = s->partial;
+  io.ctl = s->ctl;
   cfd_status rc;
-  // stage 1: U1 = Un + dt R(Un); the prim pass runs before dt is known
-  if ((rc = enqueue_prim(s, U, PRIM_HEALTH | (cfl ? PRIM_CFL : 0), nullptr, st))) return rc;
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out,
-                     s->partial, s->npart);
-  CFD_LAUNCHED();
+  // stage 1: U1 = Un + dt R(Un)
   io.Uk = U;
   io.Uout = s->U1;
   io.a = 0.0;
   io.b = 1.0;
-  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  io.Pn = s->Pb[1];
+  io.what = 0;
+  if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
   // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt R(U1))
-  if ((rc = enqueue_prim(s, s->U1, 0, dtp, st))) return rc;
   io.Uk = s->U1;
   io.Uout = s->U2;
   io.a = 0.75;
   io.b = 0.25;
-  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  io.Pn = s->Pb[2];
+  if ((rc = enqueue_fluxes(s, s->Pb[1], io, true, st))) return rc;
   // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2)), in place on U
-  if ((rc = enqueue_prim(s, s->U2, 0, dtp, st))) return rc;
   io.Uk = s->U2;
   io.Uout = U;
   io.a = 1.0 / 3.0;
   io.b = 2.0 / 3.0;
-  return enqueue_fluxes(s, io, true, st);
+  io.Pn = s->Pb[0];
+  io.what = PRIM_HEALTH | (cfl ? PRIM_CFL : 0);
+  return enqueue_fluxes(s, s->Pb[2], io, true, st);
 }
 
 static cfd_status enqueue_fill_halo(cfd_solver* s, double* U, hipStream_t st) {
@@ -271,6 +316,8 @@ static cfd_status run_graph(cfd_solver* s, double* U, int mode, double fixed_dt,
     gc.kd[0] = fixed_dt;
     gc.kd[1] = t_end;
   }
+  cfd_status rc = enqueue_step_prologue(s, U, !(fixed_dt > 0.0), st);
+  if (rc) return rc;
   for (int i = 0; i < n; ++i) CFD_HIP(hipGraphLaunch(gc.exec, st));
   return CFD_OK;
 }
@@ -356,8 +403,11 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
   const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
   bool ok = hipMalloc(&s->U1, st) == hipSuccess && hipMalloc(&s->U2, st) == hipSuccess &&
             hipMalloc(&s->Racc, st) == hipSuccess &&
-            hipMalloc(&s->P, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
+            hipMalloc(&s->Pb[0], sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
+            hipMalloc(&s->Pb[1], sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
+            hipMalloc(&s->Pb[2], sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
             hipMalloc(&s->ctl, sizeof(DevCtl)) == hipSuccess;
+  s->P = s->Pb[0];
   s->npart = kCflSlots;
   ok = ok && hipMalloc(&s->partial, sizeof(double) * (size_t)s->npart) == hipSuccess;
   if (!ok) {
@@ -381,7 +431,7 @@ void cfd_destroy(cfd_solver* s) {
   (void)hipDeviceSynchronize();
   if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
-  double* bufs[] = {s->U1, s->U2, s->P, s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->Dbar, s->partial};
+  double* bufs[] = {s->U1, s->U2, s->Pb[0], s->Pb[1], s->Pb[2], s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->Dbar, s->partial};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (s->ctl) (void)hipFree(s->ctl);
@@ -415,12 +465,14 @@ cfd_status cfd_rhs(cfd_solver* s, double* U, double* R, void* stream) {
   StageIO io{};
   io.R = R;
   io.dtp = nullptr;
-  return enqueue_fluxes(s, io, false, st);
+  return enqueue_fluxes(s, s->P, io, false, st);
 }
 
 cfd_status cfd_compute_dt(cfd_solver* s, const double* U, double* dt_dev, void* stream) {
   if (!s || !U || !dt_dev) return fail(CFD_EINVAL, "NULL argument");
   hipStream_t st = (hipStream_t)stream;
+  cfd_status rc = enqueue_clear_slots(s, st);
+  if (rc) return rc;
   hipLaunchKernelGGL(k_cfl, plane_grid(s->g), dim3(kBlock), 0, st, U, s->g, s->partial);
   CFD_LAUNCHED();
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, 0.0, 0.0, (double*)nullptr, dt_dev,
@@ -433,8 +485,9 @@ cfd_status cfd_rk3_step(cfd_solver* s, double* U, double dt, double* dt_used_dev
   if (!s || !U) return fail(CFD_EINVAL, "NULL argument");
   if (!std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be finite");
   hipStream_t st = (hipStream_t)stream;
-  cfd_status rc = enqueue_step(s, U, dt > 0.0 ? dt : 0.0, 0.0, nullptr, dt_used_dev, st);
+  cfd_status rc = enqueue_step_prologue(s, U, !(dt > 0.0), st);
   if (rc) return rc;
+  if ((rc = enqueue_step(s, U, dt > 0.0 ? dt : 0.0, 0.0, nullptr, dt_used_dev, st))) return rc;
   return enqueue_fill_halo(s, U, st);
 }
 
@@ -478,6 +531,8 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, 1e-12, 0.0, (double*)nullptr,
                      (double*)nullptr, s->partial, s->npart);
   CFD_LAUNCHED();
+  // a middle stage of a step: U2 = 3/4 U + 1/4 (U + dt R(U)) into scratch, its
+  // primitives into Pb[1]
   StageIO io{};
   io.R = s->Racc;
   io.Un = U;
@@ -486,42 +541,50 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
   io.a = 0.75;
   io.b = 0.25;
   io.dtp = &s->ctl->dt;
+  io.Pn = s->Pb[1];
+  io.partial = s->partial;
+  io.ctl = s->ctl;
+  io.what = 0;
   int first = -1, last = -1;
-  for (int d = 0; d < 3; ++d)
-    if (g.act[d]) {
-      if (first < 0) first = d;
-      last = d;
-    }
-  hipEvent_t ev[5];
-  for (int e = 0; e < 5; ++e) CFD_HIP(hipEventCreate(&ev[e]));
-  double acc[4] = {0, 0, 0, 0};
+  sweep_order(g, first, last);
+  // slots of ms_out: prim pass, x, y, z sweeps, halo refresh of the next
+  // primitives; event e+1 closes the kernel launched after event e
+  constexpr int K = 5;
+  hipEvent_t ev[K + 1];
+  for (int e = 0; e <= K; ++e) CFD_HIP(hipEventCreate(&ev[e]));
+  double acc[K] = {0, 0, 0, 0, 0};
   cfd_status rc = CFD_OK;
   for (int r = 0; r < reps && rc == CFD_OK; ++r) {
-    (void)hipEventRecord(ev[0], st);
+    int slot_of[K];
+    int e = 0;
+    (void)hipEventRecord(ev[e], st);
     hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0, io.dtp,
                        s->partial);
-    (void)hipEventRecord(ev[1], st);
-    for (int d = 0; d < 3; ++d) {
-      if (g.act[d]) {
-        int mode = d == last ? (d == first ? MODE_WRITE_RK : MODE_ACC_RK) : (d == first ? MODE_WRITE : MODE_ACC);
-        if (d == 0) launch_sweep<0>(s, mode, io, st);
-        else if (d == 1) launch_sweep<1>(s, mode, io, st);
-        else launch_sweep<2>(s, mode, io, st);
-      }
-      (void)hipEventRecord(ev[2 + d], st);
+    slot_of[e] = 0;
+    (void)hipEventRecord(ev[++e], st);
+    for (int d = 2; d >= 0; --d) {
+      if (!g.act[d]) continue;
+      int mode = d == last ? (d == first ? MODE_WRITE_RK : MODE_ACC_RK) : (d == first ? MODE_WRITE : MODE_ACC);
+      if (d == last) launch_sweep_axis<true>(s, d, mode, s->P, io, st);
+      else launch_sweep_axis<false>(s, d, mode, s->P, io, st);
+      slot_of[e] = 1 + d;
+      (void)hipEventRecord(ev[++e], st);
     }
+    hipLaunchKernelGGL(k_prim_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, io.Pn, g, io.dtp);
+    slot_of[e] = 4;
+    (void)hipEventRecord(ev[++e], st);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
       rc = fail(CFD_EHIP, "profiled stage failed");
       break;
     }
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < e; ++k) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-      acc[k] += ms;
+      acc[slot_of[k]] += ms;
     }
   }
-  for (int e = 0; e < 5; ++e) (void)hipEventDestroy(ev[e]);
-  for (int k = 0; k < 4; ++k) ms_out[k] = acc[k] / reps;
+  for (int e = 0; e <= K; ++e) (void)hipEventDestroy(ev[e]);
+  for (int k = 0; k < K; ++k) ms_out[k] = acc[k] / reps;
   return rc;
 }
 
@@ -556,13 +619,13 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   io.a = 0.0;
   io.b = 1.0;
   if ((rc = enqueue_prim(s, Un, 0, dtp, st))) return rc;
-  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  if ((rc = enqueue_fluxes(s, s->P, io, true, st))) return rc;
   io.Uk = s->U1;
   io.Uout = s->U2;
   io.a = 0.75;
   io.b = 0.25;
   if ((rc = enqueue_prim(s, s->U1, 0, dtp, st))) return rc;
-  if ((rc = enqueue_fluxes(s, io, true, st))) return rc;
+  if ((rc = enqueue_fluxes(s, s->P, io, true, st))) return rc;
   // reverse:  U3 = 1/3 Un + 2/3 (U2 + dt R(U2)),  U2 = 3/4 Un + 1/4 (U1 + dt R(U1)),
   //           U1 = Un + dt R(Un)
   // A2 = Ubar_2 = 2/3 Ubar_3 + (dR/dU(U2))^T (2/3 dt Ubar_3)

@@ -2,14 +2,19 @@
 //
 // Per stage:  prim  : U_k -> P = (rho,u,v,w,p,T~) on the padded grid, halos by
 //                     gather from their interior source cells (so U's own halo
-//                     is never read), plus the CFL rate max in stage 1;
-//             grad  : P -> cell-centred velocity gradient (viscous runs only);
+//                     is never read), plus the CFL rate max;
 //             sweep : one kernel per active axis; each face flux is computed
-//                     once in registers and differenced into its two cells.
+//                     once in registers and differenced into its two cells,
+//                     the tangential velocity derivatives of the viscous flux
+//                     formed from P on the way.
 //                     x: one lane per face, wavefront shuffles carry the
 //                        left-face flux; y, z: one lane per column segment
 //                        marching along the axis with a register window.
-//                     The last active axis applies the RK3 stage update.
+//                     The last active axis applies the RK3 stage update and
+//                     may also store the primitives of the updated cell for
+//                     the next stage (with the CFL rate and health bits), so
+//                     that within a run of steps the prim pass reduces to a
+//                     halo refresh of P.
 #pragma once
 #include "physics.hpp"
 
@@ -34,6 +39,10 @@ struct StageIO {
   double* Uout;      // stage output state (may alias Un in the last stage)
   double a, b;       // Uout = a Un + b (Uk + dt R)
   const double* dtp; // step size; nullptr for a plain right-hand side
+  double* Pn;        // primitives of Uout, interior cells (sweeps with PN set)
+  double* partial;   // CFL rate slots (PN sweeps with PRIM_CFL in `what`)
+  DevCtl* ctl;       // health bits (PN sweeps with PRIM_HEALTH in `what`)
+  int what;
 };
 
 __device__ __forceinline__ bool step_disabled(const double* dtp) { return dtp != nullptr && *dtp == 0.0; }
@@ -89,8 +98,9 @@ __host__ __device__ __forceinline__ int plane_blocks_x(const Geom& g) {
 }
 
 // ----------------------------------------------------------------------------
-// Halo refresh of a padded state (in place): halo cells copy their interior
-// source cell, interior cells do nothing.
+// Halo refresh of a padded field of NC components (in place): halo cells copy
+// their interior source cell, interior cells do nothing.
+template <int NC = 5>
 __device__ __forceinline__ void fill_halo_body(double* U, const Geom& g, const PlaneIdx& p) {
   if (!p.in) return;
   const int si = bc_source(p.i, g.n[0], g.bc[0], g.bc[1]);
@@ -99,10 +109,63 @@ __device__ __forceinline__ void fill_halo_body(double* U, const Geom& g, const P
   if (si == p.i && sj == p.j && sk == p.k) return;
   const long long s = cell_at(g, si, sj, sk);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) U[v * g.vs + p.c] = U[v * g.vs + s];
+  for (int v = 0; v < NC; ++v) U[v * g.vs + p.c] = U[v * g.vs + s];
 }
 
-__global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) { fill_halo_body(U, g, plane_index(g)); }
+__global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) { fill_halo_body<5>(U, g, plane_index(g)); }
+
+// Halo refresh of the primitives P (6 components) after a sweep stored the
+// interior ones, one thread per halo cell; skipped with the step. Halo cells
+// are numbered slab by slab: the z halo planes (whole padded planes), then
+// for interior z the y halo rows (whole padded rows), then for interior z and
+// y the x halo cells.
+__host__ __device__ __forceinline__ long long halo_cells(const Geom& g) {
+  return 2LL * g.h[2] * g.N[0] * g.N[1] + 2LL * g.h[1] * g.N[0] * g.n[2] + 2LL * g.h[0] * g.n[1] * g.n[2];
+}
+
+__host__ __device__ __forceinline__ int halo_blocks(const Geom& g) {
+  const long long n = halo_cells(g);
+  return (int)(n > 0 ? (n + kBlock - 1) / kBlock : 1);
+}
+
+__global__ void __launch_bounds__(kBlock) k_prim_halo(double* P, Geom g, const double* dtp) {
+  if (step_disabled(dtp)) return;
+  long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  int i, j, k;  // interior-relative coordinates of the halo cell
+  const long long zs = 2LL * g.h[2] * g.N[0] * g.N[1];
+  const long long ys = 2LL * g.h[1] * g.N[0] * g.n[2];
+  const long long xs = 2LL * g.h[0] * g.n[1] * g.n[2];
+  if (t < zs) {
+    const long long plane = (long long)g.N[0] * g.N[1];
+    const int kk = (int)(t / plane);  // 0 .. 2h-1
+    const long long r = t - kk * plane;
+    j = (int)(r / g.N[0]) - g.h[1];
+    i = (int)(r - (long long)(j + g.h[1]) * g.N[0]) - g.h[0];
+    k = kk < g.h[2] ? kk - g.h[2] : g.n[2] + (kk - g.h[2]);
+  } else if ((t -= zs) < ys) {
+    const long long slab = 2LL * g.h[1] * g.N[0];
+    k = (int)(t / slab);
+    const long long r = t - k * slab;
+    const int jj = (int)(r / g.N[0]);  // 0 .. 2h-1
+    i = (int)(r - (long long)jj * g.N[0]) - g.h[0];
+    j = jj < g.h[1] ? jj - g.h[1] : g.n[1] + (jj - g.h[1]);
+  } else if ((t -= ys) < xs) {
+    const long long row = 2LL * g.h[0];
+    const long long kj = t / row;
+    const int ii = (int)(t - kj * row);
+    k = (int)(kj / g.n[1]);
+    j = (int)(kj - (long long)k * g.n[1]);
+    i = ii < g.h[0] ? ii - g.h[0] : g.n[0] + (ii - g.h[0]);
+  } else {
+    return;
+  }
+  const int si = bc_source(i, g.n[0], g.bc[0], g.bc[1]);
+  const int sj = bc_source(j, g.n[1], g.bc[2], g.bc[3]);
+  const int sk = bc_source(k, g.n[2], g.bc[4], g.bc[5]);
+  const long long c = cell_at(g, i, j, k), s = cell_at(g, si, sj, sk);
+#pragma unroll
+  for (int v = 0; v < 6; ++v) P[v * g.vs + c] = P[v * g.vs + s];
+}
 
 // Conservative interior state from primitive point values W (5 x interior, no halo).
 __global__ void __launch_bounds__(kBlock) k_state_init(const double* W, double* U, Geom g) {
@@ -163,6 +226,26 @@ __device__ __forceinline__ void publish_rate(double* slots, int block_index, dou
               (unsigned long long)__double_as_longlong(s));
 }
 
+// Primitive variables w = (rho, u, v, w, p, p/rho) of conservative values q.
+__device__ __forceinline__ void cons_to_prim(const Geom& g, const double* q, double* w) {
+  const double rho = q[0];
+  w[0] = rho;
+  w[1] = q[1] / rho;
+  w[2] = q[2] / rho;
+  w[3] = q[3] / rho;
+  w[4] = (g.gamma - 1.0) * (q[4] - 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]));
+  w[5] = w[4] / rho;
+}
+
+// Health bits of a cell: 1 non-finite conservative value, 2 rho <= 0, 4 p <= 0.
+__device__ __forceinline__ int health_bits(const double* q, double p) {
+  int bad = 0;
+  if (!isfinite(q[0]) || !isfinite(q[1]) || !isfinite(q[2]) || !isfinite(q[3]) || !isfinite(q[4])) bad |= 1;
+  if (!(q[0] > 0.0)) bad |= 2;
+  if (!(p > 0.0)) bad |= 4;
+  return bad;
+}
+
 // Primitive variables on the padded grid, gathered through the boundary map.
 // Over interior cells, `what` bit 0 adds the CFL rate (block maxima written
 // to partial[], one per block) and bit 1 the health bits.
@@ -178,23 +261,16 @@ __device__ __forceinline__ void prim_body(const double* __restrict__ U, double* 
     const int sk = bc_source(q.k, g.n[2], g.bc[4], g.bc[5]);
     const long long s = cell_at(g, si, sj, sk);
     const long long c = q.c;
-    const double rho = U[s];
-    const double m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];
-    const double u[3] = {m0 / rho, m1 / rho, m2 / rho};
-    const double p = (g.gamma - 1.0) * (E - 0.5 * (m0 * u[0] + m1 * u[1] + m2 * u[2]));
-    P[c] = rho;
-    P[g.vs + c] = u[0];
-    P[2 * g.vs + c] = u[1];
-    P[3 * g.vs + c] = u[2];
-    P[4 * g.vs + c] = p;
-    P[5 * g.vs + c] = p / rho;
+    double u[5], w[6];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[v * g.vs + s];
+    cons_to_prim(g, u, w);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) P[v * g.vs + c] = w[v];
     if (what && s == c) {
-      if (what & PRIM_CFL) smax = cfl_rate(g, rho, u, p);
+      if (what & PRIM_CFL) smax = cfl_rate(g, w[0], w + 1, w[4]);
       if (what & PRIM_HEALTH) {
-        int bad = 0;
-        if (!isfinite(rho) || !isfinite(m0) || !isfinite(m1) || !isfinite(m2) || !isfinite(E)) bad |= 1;
-        if (!(rho > 0.0)) bad |= 2;
-        if (!(p > 0.0)) bad |= 4;
+        const int bad = health_bits(u, w[4]);
         if (bad) atomicOr(&ctl->status, bad);
       }
     }
@@ -401,27 +477,11 @@ __device__ __forceinline__ void tangential_at(const Geom& g, const double* __res
   }
 }
 
-// Write the divergence contribution D = (G+ - G-)/dx of one cell.
-template <int MODE>
-__device__ __forceinline__ void emit(const StageIO& io, long long vs, long long c, const double* D) {
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const long long e = v * vs + c;
-    double r;
-    if (MODE == MODE_WRITE || MODE == MODE_WRITE_RK) r = -D[v];
-    else r = io.R[e] - D[v];
-    if (MODE == MODE_WRITE || MODE == MODE_ACC) {
-      io.R[e] = r;
-    } else {
-      const double dt = *io.dtp;
-      io.Uout[e] = io.a * io.Un[e] + io.b * (io.Uk[e] + dt * r);
-    }
-  }
-}
-
-// The same in two halves, so that a marching sweep can issue the loads of a
-// cell's update (accumulated R, stage states) before the face arithmetic and
-// store after it: EmitIn holds the loaded values.
+// Writing the divergence contribution D = (G+ - G-)/dx of one cell, in two
+// halves so that a marching sweep can issue the loads of the cell's update
+// (accumulated R, stage states) before the face arithmetic and store after
+// it: EmitIn holds the loaded values. MODE_WRITE / MODE_ACC store R = -D or
+// R - D; the RK modes store Uout = a Un + b (Uk + dt R) instead of R.
 struct EmitIn {
   double r[5], un[5], uk[5];
 };
@@ -439,16 +499,37 @@ __device__ __forceinline__ void emit_fetch(const StageIO& io, long long vs, long
   }
 }
 
-template <int MODE>
-__device__ __forceinline__ void emit_put(const StageIO& io, long long vs, long long c, const double* D,
-                                         const EmitIn& in, double dt) {
+template <int MODE, bool PN = false>
+__device__ __forceinline__ void emit_put(const StageIO& io, const Geom& g, long long c, const double* D,
+                                         const EmitIn& in, double dt, double& smax, int& bad) {
+  double uo[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const long long e = v * vs + c;
+    const long long e = v * g.vs + c;
     const double r = (MODE == MODE_WRITE || MODE == MODE_WRITE_RK) ? -D[v] : in.r[v] - D[v];
-    if (MODE == MODE_WRITE || MODE == MODE_ACC) io.R[e] = r;
-    else io.Uout[e] = io.a * in.un[v] + io.b * (in.uk[v] + dt * r);
+    if (MODE == MODE_WRITE || MODE == MODE_ACC) {
+      io.R[e] = r;
+    } else {
+      uo[v] = io.a * in.un[v] + io.b * (in.uk[v] + dt * r);
+      io.Uout[e] = uo[v];
+    }
   }
+  if constexpr (PN && (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK)) {
+    double w[6];
+    cons_to_prim(g, uo, w);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) io.Pn[v * g.vs + c] = w[v];
+    if (io.what & PRIM_CFL) smax = fmax(smax, cfl_rate(g, w[0], w + 1, w[4]));
+    if (io.what & PRIM_HEALTH) bad |= health_bits(uo, w[4]);
+  }
+}
+
+// End of a sweep that stored next-stage primitives: the block's CFL rate
+// maximum into its slot, the health bits into the control block. Every thread
+// of the block calls it.
+__device__ __forceinline__ void finish_prims(const StageIO& io, double smax, int bad) {
+  if (io.what & PRIM_CFL) publish_rate(io.partial, blockIdx.y * gridDim.x + blockIdx.x, smax);
+  if (bad) atomicOr(&io.ctl->status, bad);
 }
 
 // x sweep: every interior row holds kXCtx context slots followed by its nx+1
@@ -464,7 +545,7 @@ __device__ __forceinline__ void emit_put(const StageIO& io, long long vs, long l
 constexpr int kXIters = 1;
 constexpr int kXCtx = 3;
 
-template <int MODE>
+template <int MODE, bool PN = false>
 __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const StageIO& io, const Geom& g,
                                              int bx) {
   // slot numbering fits in 32 bits (checked when the solver is created)
@@ -474,10 +555,12 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
   const int total = S * g.n[1] * g.n[2];
   constexpr int Q = 64 * kXIters - (kXCtx + 1);
   const int first = wave * Q;
-  if (first >= total) return;  // whole wavefront exits together
+  double smax = 0.0;
+  int bad = 0;
+  const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
   double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double dprev[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int it = 0; it < kXIters; ++it) {
+  for (int it = 0; it < kXIters && first < total; ++it) {
     const int gs = first - (kXCtx + 1) + it * 64 + lane;
     const bool inrange = gs >= 0 && gs < total;
     int f = 0, j = 0, k = 0;
@@ -529,15 +612,19 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
       double D[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[0];
-      emit<MODE>(io, g.vs, cell_at(g, f - 1, j, k), D);
+      const long long ce = cell_at(g, f - 1, j, k);
+      EmitIn ein;
+      emit_fetch<MODE>(io, g.vs, ce, ein);
+      emit_put<MODE, PN>(io, g, ce, D, ein, dt, smax, bad);
     }
   }
+  if (PN) finish_prims(io, smax, bad);
 }
 
-template <int MODE>
+template <int MODE, bool PN>
 __global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P, StageIO io, Geom g) {
   if (step_disabled(io.dtp)) return;
-  sweep_x_body<MODE>(P, io, g, blockIdx.x);
+  sweep_x_body<MODE, PN>(P, io, g, blockIdx.x);
 }
 
 // Blocks of an x sweep.
@@ -553,21 +640,28 @@ __host__ __device__ __forceinline__ int sweep_x_blocks(const Geom& g) {
 // face is computed only to seed the left flux.
 constexpr int kSeg = 32;
 
-template <int AX, int MODE>
+// y / z sweep body of one lane. Lanes beyond the grid (a partial last block)
+// march a valid column too but store nothing, so that every lane reaches the
+// block-wide CFL reduction of a sweep that stores next-stage primitives.
+template <int AX, int MODE, bool PN = false>
 __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const StageIO& io,
                                                  const Geom& g, int bx, int by) {
   constexpr int OT = AX == 1 ? 2 : 1;  // the other transverse axis
   const int i = bx * 64 + (threadIdx.x & 63);
   const int nseg = (g.n[AX] + kSeg - 1) / kSeg;
   const long long col = (long long)by * (kBlock >> 6) + (threadIdx.x >> 6);
-  if (i >= g.n[0] || col >= (long long)g.n[OT] * nseg) return;
-  const int o = (int)(col / nseg);
-  const int seg = (int)(col - (long long)o * nseg);
+  const bool in = i < g.n[0] && col < (long long)g.n[OT] * nseg;
+  if (!PN && !in) return;
+  double smax = 0.0;
+  int bad = 0;
+  const long long colc = in ? col : 0;
+  const int o = (int)(colc / nseg);
+  const int seg = (int)(colc - (long long)o * nseg);
   const int s0 = seg * kSeg;
   const int s1 = min(s0 + kSeg, g.n[AX]);
   const long long st = g.s[AX];
   int q3[3];
-  q3[0] = i;
+  q3[0] = in ? i : 0;
   q3[OT] = o;
   q3[AX] = s0 - 3;
   long long c = cell_at(g, q3[0], q3[1], q3[2]);  // window cell 0 (axis index f-2 for face f+1/2)
@@ -590,7 +684,7 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
     // their latency overlaps it
     const bool more = f + 1 < s1;
     EmitIn ein;
-    if (f >= s0) emit_fetch<MODE>(io, g.vs, c + 2 * st, ein);  // window cell 2 is cell f
+    if (f >= s0 && in) emit_fetch<MODE>(io, g.vs, c + 2 * st, ein);  // window cell 2 is cell f
     double nq[5], nT = 0.0, ntg[4] = {0.0, 0.0, 0.0, 0.0};
     if (more) {
       load_prims(P, g.vs, c + 6 * st, nq);
@@ -601,11 +695,11 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
     }
     double G[5];
     face_flux<AX>(g, w, G);
-    if (f >= s0) {
+    if (f >= s0 && in) {
       double D[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[AX];
-      emit_put<MODE>(io, g.vs, c + 2 * st, D, ein, dt);
+      emit_put<MODE, PN>(io, g, c + 2 * st, D, ein, dt, smax, bad);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) Gm[v] = G[v];
@@ -631,12 +725,14 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
       }
     }
   }
+  if (PN) finish_prims(io, smax, bad);
 }
 
-template <int AX, int MODE>
-__global__ void __launch_bounds__(kBlock) k_sweep_march(const double* __restrict__ P, StageIO io, Geom g) {
+template <int AX, int MODE, bool PN>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_march(const double* __restrict__ P, StageIO io,
+                                                                                             Geom g) {
   if (step_disabled(io.dtp)) return;
-  sweep_march_body<AX, MODE>(P, io, g, blockIdx.x, blockIdx.y);
+  sweep_march_body<AX, MODE, PN>(P, io, g, blockIdx.x, blockIdx.y);
 }
 
 // Launch shape of a marching sweep along AX (x blocks, y blocks).
