@@ -477,6 +477,46 @@ __device__ __forceinline__ void tangential_at(const Geom& g, const double* __res
   }
 }
 
+// The same without branches, in two halves: the sixteen loads, and the
+// arithmetic. An inactive axis gets stride 0 and weight 0 (the difference of
+// a cell with itself is exactly 0). Callers issue all loads before any use (a
+// scheduling barrier keeps the compiler from interleaving loads and uses,
+// which serialises their latencies).
+template <int D>
+__device__ __forceinline__ void tangential_load(const Geom& g, const double* __restrict__ P, long long c,
+                                                double (&x)[4][4]) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const long long s1 = g.act[T1] ? g.s[T1] : 0, s2 = g.act[T2] ? g.s[T2] : 0;
+  const double* q[4] = {P + (1 + D) * g.vs + c, P + (1 + T1) * g.vs + c, P + (1 + D) * g.vs + c,
+                        P + (1 + T2) * g.vs + c};
+  const long long st[4] = {s1, s1, s2, s2};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    x[m][0] = q[m][-2 * st[m]];
+    x[m][1] = q[m][-st[m]];
+    x[m][2] = q[m][st[m]];
+    x[m][3] = q[m][2 * st[m]];
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void tangential_combine(const Geom& g, const double (&x)[4][4], double* tg) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const double w1 = g.act[T1] ? g.idx[T1] / 12.0 : 0.0, w2 = g.act[T2] ? g.idx[T2] / 12.0 : 0.0;
+  const double w[4] = {w1, w1, w2, w2};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) tg[m] = (x[m][0] - 8.0 * x[m][1] + 8.0 * x[m][2] - x[m][3]) * w[m];
+}
+
+template <int D>
+__device__ __forceinline__ void tangential_at_flat(const Geom& g, const double* __restrict__ P, long long c,
+                                                   double* tg) {
+  double x[4][4];
+  tangential_load<D>(g, P, c, x);
+  __builtin_amdgcn_sched_barrier(0);
+  tangential_combine<D>(g, x, tg);
+}
+
 // Writing the divergence contribution D = (G+ - G-)/dx of one cell, in two
 // halves so that a marching sweep can issue the loads of the cell's update
 // (accumulated R, stage states) before the face arithmetic and store after
@@ -534,16 +574,16 @@ __device__ __forceinline__ void finish_prims(const StageIO& io, double smax, int
 
 // x sweep: every interior row holds kXCtx context slots followed by its nx+1
 // faces, and the slots of all rows are numbered row-major; slot s of a row is
-// face f = s - kXCtx, lying between cells f-1 and f. The lane of slot s
-// computes the tangential velocity derivatives of cell f+1, and face f takes
-// those of cells f-2..f+1 from itself and the three lanes below it (context
-// slots only supply the first faces of their row). Each wavefront takes
-// kXIters*64 consecutive slots; its first kXCtx+1 slots overlap the previous
-// wavefront and only seed the derivative and flux carries. One pass per
-// wavefront keeps the kernel at three wavefronts per SIMD (142 VGPRs); the
-// carries of longer runs cost more registers than the overlap saves.
-constexpr int kXIters = 1;
+// face f = s - kXCtx, lying between cells f-1 and f. A wavefront takes 64
+// consecutive slots, one per lane. The lane of slot s computes the tangential
+// velocity derivatives of cell f+1, and face f takes those of cells f-2..f+1
+// from itself and the three lanes below it (context slots only supply the
+// first faces of their row); the left-face flux of a cell comes from the lane
+// below. The first kXCtx+1 slots of a wavefront overlap its predecessor and
+// only seed these shuffles. One slot per lane keeps the kernel at three
+// wavefronts per SIMD (about 140 VGPRs).
 constexpr int kXCtx = 3;
+constexpr int kXFaces = 64 - (kXCtx + 1);  // faces a wavefront emits
 
 template <int MODE, bool PN = false>
 __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const StageIO& io, const Geom& g,
@@ -553,15 +593,12 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
   const int wave = (bx * kBlock + (int)threadIdx.x) >> 6;
   const int S = g.n[0] + 1 + kXCtx;
   const int total = S * g.n[1] * g.n[2];
-  constexpr int Q = 64 * kXIters - (kXCtx + 1);
-  const int first = wave * Q;
+  const int first = wave * kXFaces;
   double smax = 0.0;
   int bad = 0;
-  const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
-  double carry[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  double dprev[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int it = 0; it < kXIters && first < total; ++it) {
-    const int gs = first - (kXCtx + 1) + it * 64 + lane;
+  if (first < total) {  // uniform per wavefront
+    const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
+    const int gs = first - (kXCtx + 1) + lane;
     const bool inrange = gs >= 0 && gs < total;
     int f = 0, j = 0, k = 0;
     if (inrange) {
@@ -570,44 +607,34 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
       k = row / g.n[1];
       j = row - k * g.n[1];
     }
+    const bool valid = inrange && f >= 0 && gs >= first - 1;  // lanes whose face flux is used
+    // Every lane loads a window inside the padded block (context slots and
+    // lanes past the end take face 0 of their row) and computes a flux, so the
+    // window loads, the derivative loads and the shuffles need no branch and
+    // are in flight together.
+    const int fl = f < 0 ? 0 : f;
+    const long long c0 = cell_at(g, fl - 3, j, k);
+    FaceWindow w;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) load_prims(P, g.vs, c0 + m, w.q[m]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) w.T[m] = P[5 * g.vs + c0 + 1 + m];  // unused without heat flux
     double d[4] = {0.0, 0.0, 0.0, 0.0};
-    if (inrange && g.viscous) tangential_at<0>(g, P, cell_at(g, f + 1, j, k), d);
+    if (g.viscous) tangential_at_flat<0>(g, P, cell_at(g, f + 1, j, k), d);
     // face values of the derivatives from cells f-2..f+1 (lanes - 3 .. lane)
     double tf[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      double t[3];
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const int back = 3 - m;  // cell f-2+m lives in lane - back
-        const int src = (lane - back) & 63;
-        const double a = __shfl(d[v], src, 64);
-        const double b = __shfl(dprev[v], src, 64);
-        t[m] = lane >= back ? a : b;
-      }
-      tf[v] = rc4(t[0], t[1], t[2], d[v]);
-      dprev[v] = d[v];
+      const double t0 = __shfl(d[v], (lane - 3) & 63, 64);
+      const double t1 = __shfl(d[v], (lane - 2) & 63, 64);
+      const double t2 = __shfl(d[v], (lane - 1) & 63, 64);
+      tf[v] = rc4(t0, t1, t2, d[v]);
     }
-    const bool valid = inrange && f >= 0 && gs >= first - 1;
-    double G[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (valid) {
-      FaceWindow w;
-      const long long c0 = cell_at(g, f - 3, j, k);
-#pragma unroll
-      for (int m = 0; m < 6; ++m) load_prims(P, g.vs, c0 + m, w.q[m]);
-      if (g.viscous || g.heat) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) w.T[m] = P[5 * g.vs + c0 + 1 + m];
-      }
-      face_flux_tf<0>(g, w, tf, G);
-    }
+    double G[5];
+    face_flux_tf<0>(g, w, tf, G);
     double Gm[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const double up = __shfl_up(G[v], 1, 64);
-      Gm[v] = lane == 0 ? carry[v] : up;
-      carry[v] = __shfl(G[v], 63, 64);
-    }
+    for (int v = 0; v < 5; ++v) Gm[v] = __shfl_up(G[v], 1, 64);
     if (valid && gs >= first && f >= 1) {
       double D[5];
 #pragma unroll
@@ -630,8 +657,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P
 // Blocks of an x sweep.
 __host__ __device__ __forceinline__ int sweep_x_blocks(const Geom& g) {
   const long long slots = (long long)(g.n[0] + 1 + kXCtx) * g.n[1] * g.n[2];
-  constexpr int Q = 64 * kXIters - (kXCtx + 1);
-  const long long waves = (slots + Q - 1) / Q;
+  const long long waves = (slots + kXFaces - 1) / kXFaces;
   return (int)((waves + 3) / 4);
 }
 
@@ -685,14 +711,23 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
     const bool more = f + 1 < s1;
     EmitIn ein;
     if (f >= s0 && in) emit_fetch<MODE>(io, g.vs, c + 2 * st, ein);  // window cell 2 is cell f
-    double nq[5], nT = 0.0, ntg[4] = {0.0, 0.0, 0.0, 0.0};
+    // The entering cell's derivative stencil: in MODE_WRITE (no update loads
+    // in flight) the sixteen raw values are held across the face arithmetic
+    // and combined after it, so their latency is hidden; the other modes have
+    // no registers to spare for that and combine them at once.
+    constexpr bool kDeferTg = MODE == MODE_WRITE;
+    double nq[5], nT = 0.0, ntr[4][4], ntg[4] = {0.0, 0.0, 0.0, 0.0};
     if (more) {
       load_prims(P, g.vs, c + 6 * st, nq);
       if (dis) {
         nT = P[5 * g.vs + c + 5 * st];
-        if (g.viscous) tangential_at<AX>(g, P, c + 5 * st, ntg);
+        if (g.viscous) {
+          if (kDeferTg) tangential_load<AX>(g, P, c + 5 * st, ntr);
+          else tangential_at<AX>(g, P, c + 5 * st, ntg);
+        }
       }
     }
+    if (kDeferTg) __builtin_amdgcn_sched_barrier(0);
     double G[5];
     face_flux<AX>(g, w, G);
     if (f >= s0 && in) {
@@ -720,6 +755,7 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
           for (int v = 0; v < 4; ++v) w.tg[m][v] = w.tg[m + 1][v];
         }
         w.T[3] = nT;
+        if (kDeferTg && g.viscous) tangential_combine<AX>(g, ntr, ntg);
 #pragma unroll
         for (int v = 0; v < 4; ++v) w.tg[3][v] = ntg[v];
       }
