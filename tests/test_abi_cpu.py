@@ -37,3 +37,79 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(cfd, "_lib", None)
     with pytest.raises(RuntimeError):
         cfd.load()
+
+
+# ---------------------------------------------------------------- host-side validation
+# Every check below fails in the library's argument validation, before any HIP
+# call, so it runs without a GPU.
+
+def _lib_or_skip():
+    if not os.path.exists(cfd.LIB_PATH):
+        pytest.skip("libcfd.so not built")
+    return cfd.load()
+
+
+def _case(**kw):
+    case = {"n": (32, 24, 16), "lo": (0.0, 0.0, 0.0), "hi": (1.0, 1.0, 1.0), "nh": 3, "gamma": 1.4,
+            "mu": 1e-3, "prandtl": 0.72, "cfl": 0.5, "bc": (0,) * 6, "flags": 7}
+    case.update(kw)
+    return case
+
+
+BAD_CONFIGS = [
+    ("nh", dict(nh=2), "nh"),
+    ("short axis", dict(n=(32, 2, 16)), "n >= nh"),
+    ("zero cells", dict(n=(32, 0, 16)), "n must be"),
+    ("empty box", dict(hi=(1.0, 0.0, 1.0)), "lo < hi"),
+    ("boundary type", dict(bc=(0, 0, 7, 7, 0, 0)), "boundary"),
+    ("unpaired periodic", dict(bc=(0, 1, 0, 0, 0, 0)), "pairs"),
+    ("no active axis", dict(n=(1, 1, 1)), "no active axis"),
+    ("gamma", dict(gamma=1.0), "gamma"),
+    ("negative viscosity", dict(mu=-1.0), "mu"),
+    ("prandtl", dict(prandtl=0.0), "prandtl"),
+    ("cfl zero", dict(cfl=0.0), "cfl"),
+    ("cfl above one", dict(cfl=1.5), "cfl"),
+    ("unknown flag", dict(flags=8), "flag"),
+    ("too many faces", dict(n=(2048, 2048, 600)), "too large"),
+]
+
+
+@pytest.mark.parametrize("label,kw,msg", BAD_CONFIGS, ids=[b[0] for b in BAD_CONFIGS])
+def test_create_rejects_bad_config(label, kw, msg):
+    _lib_or_skip()
+    with pytest.raises(cfd.CfdError) as e:
+        cfd.cfd_create(_case(**kw))
+    assert e.value.code == cfd.CFD_EINVAL
+    assert msg in cfd.cfd_last_error()
+
+
+@pytest.mark.parametrize("label,kw,msg", BAD_CONFIGS[:4], ids=[b[0] for b in BAD_CONFIGS[:4]])
+def test_footprint_rejects_bad_config(label, kw, msg):
+    _lib_or_skip()
+    with pytest.raises(cfd.CfdError):
+        cfd.cfd_batch_footprint(_case(**kw))
+
+
+@pytest.mark.parametrize("n", [(32, 24, 16), (64, 48, 1), (200, 1, 1)])
+def test_footprint_counts_the_grid_buffers(n):
+    """U, U1, U2, R (5 components each) and P (6) on the padded grid, the CFL
+    slots and the control block, each rounded up to the arena alignment."""
+    _lib_or_skip()
+    need = cfd.cfd_batch_footprint(_case(n=n))
+    padded = 1
+    for d in range(3):
+        padded *= n[d] + 6 if n[d] > 1 else 1
+    base = 8 * padded * 26
+    assert base <= need <= base + 8 * 256 + 16 + 16 * 256, (need, base)
+
+
+def test_entry_points_reject_null_arguments():
+    lib = _lib_or_skip()
+    null = ctypes.c_void_p(0)
+    for name, args in [("cfd_rhs", (null, null, null, null)),
+                       ("cfd_rk3_step", (null, null, ctypes.c_double(0.0), null, null)),
+                       ("cfd_advance", (null, null, ctypes.c_int32(1), ctypes.c_double(0.0), null, null)),
+                       ("cfd_rhs_adjoint", (null, null, null, null, null)),
+                       ("cfd_state_init", (null, null, null, null))]:
+        assert getattr(lib, name)(*args) == cfd.CFD_EINVAL, name
+        assert cfd.cfd_last_error() != ""
