@@ -648,10 +648,13 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
   if (PN) finish_prims(io, smax, bad);
 }
 
+// Blocks are taken in XCD-major order, so that the neighbouring rows and
+// planes whose velocities the derivative stencils read are being processed in
+// the same XCD and stay in its L2.
 template <int MODE, bool PN>
 __global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P, StageIO io, Geom g) {
   if (step_disabled(io.dtp)) return;
-  sweep_x_body<MODE, PN>(P, io, g, blockIdx.x);
+  sweep_x_body<MODE, PN>(P, io, g, xcd_major_block(blockIdx.x, gridDim.x));
 }
 
 // Blocks of an x sweep.
@@ -768,7 +771,11 @@ template <int AX, int MODE, bool PN>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_march(const double* __restrict__ P, StageIO io,
                                                                                              Geom g) {
   if (step_disabled(io.dtp)) return;
-  sweep_march_body<AX, MODE, PN>(P, io, g, blockIdx.x, blockIdx.y);
+  // XCD-major block order (see k_sweep_x): consecutive column groups, hence
+  // neighbouring planes of the transverse derivatives, share an XCD
+  const int logical = xcd_major_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int by = logical / gridDim.x;
+  sweep_march_body<AX, MODE, PN>(P, io, g, logical - by * gridDim.x, by);
 }
 
 // Launch shape of a marching sweep along AX (x blocks, y blocks).
