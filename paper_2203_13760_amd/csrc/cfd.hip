@@ -62,7 +62,6 @@ struct cfd_solver {
   double* U2 = nullptr;
   double* P = nullptr;    // 6 x padded (= Pb[0])
   double* Pb[3] = {nullptr, nullptr, nullptr};  // primitives of the stage inputs of a step
-  double* Gv = nullptr;   // 9 x padded (viscous runs; adjoint scratch)
   double* Racc = nullptr; // 5 x padded
   double* A1 = nullptr;   // adjoint scratch (allocated on the first adjoint call)
   double* A2 = nullptr;
@@ -324,49 +323,40 @@ static cfd_status run_graph(cfd_solver* s, double* U, int mode, double fixed_dt,
 
 // ---------------------------------------------------------------------------
 // Adjoint scratch: two adjoint states, the primitive-adjoint and the
-// derivative-adjoint accumulators, and the stored velocity gradient the
-// dissipative reverse reads. Allocated on the first adjoint call.
+// derivative-adjoint accumulators. Allocated on the first adjoint call.
 static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   if (s->A1) return CFD_OK;
   const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
   bool ok = hipMalloc(&s->A1, st) == hipSuccess && hipMalloc(&s->A2, st) == hipSuccess &&
             hipMalloc(&s->Wbar, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess;
   if (ok && s->g.viscous) ok = hipMalloc(&s->Dbar, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
-  if (ok && s->g.viscous) ok = hipMalloc(&s->Gv, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
-    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar, s->Gv};
+    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar};
     for (double* x : b)
       if (x) (void)hipFree(x);
-    s->A1 = s->A2 = s->Wbar = s->Dbar = s->Gv = nullptr;
+    s->A1 = s->A2 = s->Wbar = s->Dbar = nullptr;
     return fail(CFD_ENOMEM, "adjoint scratch allocation failed");
   }
   return CFD_OK;
 }
 
 template <int D>
-static void launch_face_adj(cfd_solver* s, const double* Rbar, double rscale, hipStream_t st) {
+static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, double rscale, hipStream_t st) {
   const Geom& g = s->g;
   long long faces = (long long)g.n[0] * g.n[1] * g.n[2] / g.n[D] * (g.n[D] + 1);
   const dim3 grid(grid_for(faces, 1LL << 31));
   if (g.inviscid)
-    hipLaunchKernelGGL(k_face_adj_inv<D>, grid, dim3(kBlock), 0, st, (const double*)s->P, Rbar, rscale, s->Wbar, g);
+    hipLaunchKernelGGL(k_face_adj_inv<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
   if (g.viscous || g.heat)
-    hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, st, (const double*)s->P, (const double*)s->Gv,
-                       Rbar, rscale, s->Wbar, s->Dbar, g);
+    hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar, g);
 }
 
-// Ubar += (dR/dU(U))^T (rscale Rbar), interior cells.
-static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double rscale,
-                                      double* Ubar, hipStream_t st) {
+// Ubar += (dR/dU(U))^T (rscale Rbar), interior cells; P holds the primitives
+// of U (padded, halos included).
+static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const double* P, const double* Rbar,
+                                      double rscale, double* Ubar, hipStream_t st) {
   const Geom& g = s->g;
-  cfd_status rc;
-  if ((rc = enqueue_prim(s, U, 0, nullptr, st))) return rc;
-  if (g.viscous) {
-    hipLaunchKernelGGL(k_grad, grad_grid(g), dim3(kBlock), 0, st, (const double*)s->P, s->Gv, g,
-                       (const double*)nullptr);
-    CFD_LAUNCHED();
-  }
   hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * s->ncell)), dim3(kBlock), 0, st, s->Wbar, 6 * s->ncell);
   CFD_LAUNCHED();
   if (g.viscous) {
@@ -374,9 +364,9 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
                        kGradComps * s->ncell);
     CFD_LAUNCHED();
   }
-  if (g.act[0]) launch_face_adj<0>(s, Rbar, rscale, st);
-  if (g.act[1]) launch_face_adj<1>(s, Rbar, rscale, st);
-  if (g.act[2]) launch_face_adj<2>(s, Rbar, rscale, st);
+  if (g.act[0]) launch_face_adj<0>(s, P, Rbar, rscale, st);
+  if (g.act[1]) launch_face_adj<1>(s, P, Rbar, rscale, st);
+  if (g.act[2]) launch_face_adj<2>(s, P, Rbar, rscale, st);
   CFD_LAUNCHED();
   hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, U, (const double*)s->Wbar,
                      (const double*)s->Dbar, Ubar, g);
@@ -431,7 +421,7 @@ void cfd_destroy(cfd_solver* s) {
   (void)hipDeviceSynchronize();
   if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
-  double* bufs[] = {s->U1, s->U2, s->Pb[0], s->Pb[1], s->Pb[2], s->Gv, s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->Dbar, s->partial};
+  double* bufs[] = {s->U1, s->U2, s->Pb[0], s->Pb[1], s->Pb[2], s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->Dbar, s->partial};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (s->ctl) (void)hipFree(s->ctl);
@@ -593,7 +583,9 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
   if (Ubar == U || Ubar == Rbar) return fail(CFD_EINVAL, "Ubar must not alias U or Rbar");
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
-  return enqueue_rhs_adjoint(s, U, Rbar, 1.0, Ubar, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  if ((rc = enqueue_prim(s, U, 0, nullptr, st))) return rc;
+  return enqueue_rhs_adjoint(s, U, s->P, Rbar, 1.0, Ubar, st);
 }
 
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
@@ -605,7 +597,8 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   const Geom& g = s->g;
-  // forward recompute of the stage states U1, U2 with the fixed step
+  // forward recompute of the stage states U1, U2 with the fixed step; the
+  // stage updates leave the primitives of Un, U1, U2 in Pb[0], Pb[1], Pb[2]
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, dt, 0.0, (double*)nullptr,
                      (double*)nullptr, s->partial, s->npart);
   CFD_LAUNCHED();
@@ -614,35 +607,39 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   io.R = s->Racc;
   io.Un = Un;
   io.dtp = dtp;
+  io.partial = s->partial;
+  io.ctl = s->ctl;
+  io.what = 0;
   io.Uk = Un;
   io.Uout = s->U1;
   io.a = 0.0;
   io.b = 1.0;
+  io.Pn = s->Pb[1];
   if ((rc = enqueue_prim(s, Un, 0, dtp, st))) return rc;
-  if ((rc = enqueue_fluxes(s, s->P, io, true, st))) return rc;
+  if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
   io.Uk = s->U1;
   io.Uout = s->U2;
   io.a = 0.75;
   io.b = 0.25;
-  if ((rc = enqueue_prim(s, s->U1, 0, dtp, st))) return rc;
-  if ((rc = enqueue_fluxes(s, s->P, io, true, st))) return rc;
+  io.Pn = s->Pb[2];
+  if ((rc = enqueue_fluxes(s, s->Pb[1], io, true, st))) return rc;
   // reverse:  U3 = 1/3 Un + 2/3 (U2 + dt R(U2)),  U2 = 3/4 Un + 1/4 (U1 + dt R(U1)),
   //           U1 = Un + dt R(Un)
   // A2 = Ubar_2 = 2/3 Ubar_3 + (dR/dU(U2))^T (2/3 dt Ubar_3)
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
                      (const double*)nullptr, 0.0, (const double*)nullptr, g);
   CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->U2, Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
+  if ((rc = enqueue_rhs_adjoint(s, s->U2, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
   // A1 = Ubar_1 = 1/4 Ubar_2 + (dR/dU(U1))^T (1/4 dt Ubar_2)
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
                      (const double*)nullptr, 0.0, (const double*)nullptr, g);
   CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->U1, s->A2, 0.25 * dt, s->A1, st))) return rc;
+  if ((rc = enqueue_rhs_adjoint(s, s->U1, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
   // Ubar_n = 1/3 Ubar_3 + 3/4 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
                      (const double*)s->A2, 1.0, (const double*)s->A1, g);
   CFD_LAUNCHED();
-  return enqueue_rhs_adjoint(s, Un, s->A1, dt, Ubar_n, st);
+  return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
 }
 
 }  // extern "C"

@@ -1,7 +1,7 @@
 // Discrete adjoint of the right-hand side (gfx950).
 //
-//   1. forward recompute of the primitives P and the centred velocity
-//      gradient at the state (the forward kernels);
+//   1. the primitives P at the state (the forward kernels, or the buffers a
+//      forward recompute of the stages leaves);
 //   2. k_face_adj<D>: one thread per face normal to D. The face flux adjoint
 //      follows from Rbar (R_i = -(G_{i+1/2} - G_{i-1/2})/dx gives
 //      Gbar_{i+1/2} = (Rbar_{i+1} - Rbar_i)/dx), the face recomputes its
@@ -112,8 +112,10 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_inv(const double* P, const 
 }
 
 // Dissipative part of the face adjoint (viscous and heat flux).
+// The cell-centred tangential derivatives are formed from P as in the forward
+// sweeps; their adjoints go to Dbar and are transposed in k_adj_fold.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restrict__ P, const double* __restrict__ Gv,
+__global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restrict__ P,
                                                          const double* __restrict__ Rbar, double rscale,
                                                          double* Wbar, double* Dbar, Geom g) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restric
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     w.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
-    if (g.viscous) load_tangential<D>(g, Gv, c0 + (1 + m) * st, w.tg[m]);
+    if (g.viscous) tangential_at<D>(g, P, c0 + (1 + m) * st, w.tg[m]);
   }
   Geom gd = g;
   gd.inviscid = 0;  // the inviscid part is k_face_adj_inv

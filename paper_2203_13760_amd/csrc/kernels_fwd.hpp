@@ -28,7 +28,7 @@ struct DevCtl {
 };
 
 constexpr int kBlock = 256;
-constexpr int kGradComps = 9;  // d u_a / d x_b stored at component a*3+b
+constexpr int kGradComps = 9;  // adjoint of d u_a / d x_b accumulated at component a*3+b
 
 enum SweepMode { MODE_WRITE = 0, MODE_ACC = 1, MODE_ACC_RK = 2, MODE_WRITE_RK = 3 };
 
@@ -331,88 +331,6 @@ __global__ void __launch_bounds__(kBlock) k_dt(DevCtl* ctl, double cfl, double f
 }
 
 // ----------------------------------------------------------------------------
-// Cell-centred velocity gradient (fourth-order central, §3.4), stored for the
-// dissipative reverse of the adjoint: Gv[a*3+b] = d u_a / d x_b, written
-// wherever coordinate b is interior (the only places a face interpolation
-// reads it). The forward sweeps form the derivatives they need themselves.
-//
-// The kernel marches along z: one thread per padded (x, y) column
-// and a segment of kGradSeg planes keeps u, v, w of five planes in registers
-// for the z derivatives, so each plane is read from memory once per segment;
-// x and y derivatives read the current plane. Blocks are taken in XCD-major
-// order so that neighbouring rows share an L2.
-constexpr int kGradSeg = 16;
-
-__global__ void __launch_bounds__(kBlock) k_grad(const double* __restrict__ P, double* __restrict__ Gv,
-                                                 Geom g, const double* dtp) {
-  if (step_disabled(dtp)) return;
-  const int logical = xcd_major_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
-  const int by = logical / gridDim.x;
-  const int bx = logical - by * gridDim.x;
-  const int plane = g.N[0] * g.N[1];
-  const int t = bx * kBlock + threadIdx.x;
-  if (t >= plane) return;
-  const int jj = t / g.N[0];
-  const int i = t - jj * g.N[0] - g.h[0];
-  const int j = jj - g.h[1];
-  const int kz0 = by * kGradSeg - g.h[2];
-  const int kz1 = min(kz0 + kGradSeg, g.n[2] + g.h[2]);
-  const bool dx = g.act[0] && i >= 0 && i < g.n[0];
-  const bool dy = g.act[1] && j >= 0 && j < g.n[1];
-  const bool dz = g.act[2] != 0;
-  const double* u = P + g.vs;  // velocity component a at u + a * vs
-  const long long sz = g.s[2];
-  double wz[5][3];
-  if (dz) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int k = kz0 - 2 + m;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-        wz[m][a] = (k >= -g.h[2] && k < g.n[2] + g.h[2]) ? u[a * g.vs + (long long)(k + g.h[2]) * sz + t] : 0.0;
-    }
-  }
-  for (int k = kz0; k < kz1; ++k) {
-    const long long c = (long long)(k + g.h[2]) * sz + t;
-    if (dz) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) wz[4][a] = (k + 2 < g.n[2] + g.h[2]) ? u[a * g.vs + c + 2 * sz] : 0.0;
-      if (k >= 0 && k < g.n[2]) {
-        const double i12 = g.idx[2] / 12.0;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-          Gv[(a * 3 + 2) * g.vs + c] = (wz[0][a] - 8.0 * wz[1][a] + 8.0 * wz[3][a] - wz[4][a]) * i12;
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) wz[m][a] = wz[m + 1][a];
-    }
-    if (dx) {
-      const double i12 = g.idx[0] / 12.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double* q = u + a * g.vs + c;
-        Gv[(a * 3 + 0) * g.vs + c] = (q[-2] - 8.0 * q[-1] + 8.0 * q[1] - q[2]) * i12;
-      }
-    }
-    if (dy) {
-      const long long sy = g.s[1];
-      const double i12 = g.idx[1] / 12.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double* q = u + a * g.vs + c;
-        Gv[(a * 3 + 1) * g.vs + c] = (q[-2 * sy] - 8.0 * q[-sy] + 8.0 * q[sy] - q[2 * sy]) * i12;
-      }
-    }
-  }
-}
-
-// Launch shape of k_grad.
-__host__ __device__ __forceinline__ dim3 grad_grid(const Geom& g) {
-  return dim3((unsigned)((g.N[0] * g.N[1] + kBlock - 1) / kBlock), (unsigned)((g.N[2] + kGradSeg - 1) / kGradSeg));
-}
-
 // ----------------------------------------------------------------------------
 // Face window loads.
 __device__ __forceinline__ void load_prims(const double* __restrict__ P, long long vs, long long c,
@@ -421,30 +339,9 @@ __device__ __forceinline__ void load_prims(const double* __restrict__ P, long lo
   for (int v = 0; v < 5; ++v) q[v] = P[v * vs + c];
 }
 
-// Tangential derivatives at a cell for faces normal to D (see FaceWindow),
-// read from the stored gradient Gv (the adjoint path keeps Gv).
-template <int D>
-__device__ __forceinline__ void load_tangential(const Geom& g, const double* __restrict__ Gv, long long c,
-                                                double* tg) {
-  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  if (g.act[T1]) {
-    tg[0] = Gv[(D * 3 + T1) * g.vs + c];
-    tg[1] = Gv[(T1 * 3 + T1) * g.vs + c];
-  } else {
-    tg[0] = 0.0;
-    tg[1] = 0.0;
-  }
-  if (g.act[T2]) {
-    tg[2] = Gv[(D * 3 + T2) * g.vs + c];
-    tg[3] = Gv[(T2 * 3 + T2) * g.vs + c];
-  } else {
-    tg[2] = 0.0;
-    tg[3] = 0.0;
-  }
-}
-
-// The same four derivatives computed from the primitives (fourth-order
-// central differences across the cell, the expression of k_grad):
+// Tangential velocity derivatives at a cell for faces normal to D (the
+// layout of FaceWindow::tg), fourth-order central differences of the
+// primitives across the cell (§3.4):
 // d u_D / d x_T1, d u_T1 / d x_T1, d u_D / d x_T2, d u_T2 / d x_T2. The
 // tangential coordinates of every cell a face stencil touches are interior, so
 // the +-2 neighbours lie inside the padded block.
