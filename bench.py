@@ -127,9 +127,10 @@ def cpu_baseline(case, W, nz):
 def differentiation(n, nsteps, ckpt_every=20, reps=5):
     """Cost of the discrete adjoint on the Taylor-Green vortex with seeded noise
     (sigma 1e-3) at n^3: one fixed-dt TVD-RK3 step vs one step adjoint (which
-    recomputes its two inner stages), each timed with torch events on the
-    stream the library launches on, and the full gradient of the final kinetic
-    energy through an n_steps rollout with checkpoints every ckpt_every steps."""
+    recomputes its two inner stages) applied to a seeded Gaussian cotangent,
+    each timed with torch events on the stream the library launches on, and
+    the full gradient of the final kinetic energy through an n_steps rollout
+    with checkpoints every ckpt_every steps."""
     import torch
     from paper_2203_13760_amd import workloads as wl
     from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
@@ -138,7 +139,10 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     s = Solver(case)
     U = s.init(W)
     dt = float(s.compute_dt(U).item())
-    Ub = torch.ones_like(U)
+    # a dense seeded cotangent: a uniform one has zero face differences, so the
+    # face adjoints would skip their work
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    Ub = torch.randn(U.shape, generator=gen, dtype=torch.float64, device="cuda")
     out = torch.empty_like(U)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     s.step(U, dt)

@@ -180,48 +180,64 @@ __device__ __forceinline__ void images(const Geom& g, int d, int x, int& first, 
   count = last - first + 1;
 }
 
+// Transposed centred differences of Dbar at padded cell cc (coordinates q),
+// added to wb[1..3]: phi_bar(m) += (Dbar(m+2) - 8 Dbar(m+1) + 8 Dbar(m-1) -
+// Dbar(m-2)) / (12 dx_t). CHECK selects the range checks a halo image needs;
+// an interior cell's +-2 neighbours always lie inside the padded block.
+template <bool CHECK>
+__device__ __forceinline__ void fold_dbar(const Geom& g, const double* __restrict__ Dbar, long long cc,
+                                          const int* q, double* wb) {
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    if (!g.act[t]) continue;
+    const long long st = g.s[t];
+    const int lo = -g.h[t], hi = g.n[t] + g.h[t];
+    const int y = q[t];
+    const double i12 = g.idx[t] / 12.0;
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+      const double* Db = Dbar + (comp * 3 + t) * g.vs + cc;
+      double acc = 0.0;
+      if (!CHECK || y + 2 < hi) acc += Db[2 * st];
+      if (!CHECK || y + 1 < hi) acc -= 8.0 * Db[st];
+      if (!CHECK || y - 1 >= lo) acc += 8.0 * Db[-st];
+      if (!CHECK || y - 2 >= lo) acc -= Db[-2 * st];
+      wb[1 + comp] += acc * i12;
+    }
+  }
+}
+
 // Per interior cell s: gather the adjoints of all its images, apply the
 // transposed centred differences of Dbar, then the transposed primitive map
-// at U[s]; Ubar[s] += result. Halo entries of Ubar are not touched.
+// at U[s]; Ubar[s] += result. Halo entries of Ubar are not touched. Cells
+// without halo images (all but a layer nh deep at periodic or clamped
+// boundaries) take a path without loops or range checks.
 __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ U, const double* __restrict__ Wbar,
                                                      const double* __restrict__ Dbar, double* __restrict__ Ubar,
                                                      Geom g) {
-  const PlaneIdx p = plane_index(g);
+  const PlaneIdx p = plane_index(g, true);
   if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
   int fx, cx, sx, fy, cy, sy, fz, cz, sz;
   images(g, 0, p.i, fx, cx, sx);
   images(g, 1, p.j, fy, cy, sy);
   images(g, 2, p.k, fz, cz, sz);
   double wb[6] = {0, 0, 0, 0, 0, 0};
-  for (int c = 0; c < cz; ++c)
-    for (int b = 0; b < cy; ++b)
-      for (int a = 0; a < cx; ++a) {
-        const int q[3] = {fx + a * sx, fy + b * sy, fz + c * sz};
-        const long long cc = cell_at(g, q[0], q[1], q[2]);
+  if (cx == 1 && cy == 1 && cz == 1) {
+    const int q[3] = {p.i, p.j, p.k};
 #pragma unroll
-        for (int v = 0; v < 6; ++v) wb[v] += Wbar[v * g.vs + cc];
-        if (g.viscous) {
-          // phi_bar(m) += (Dbar(m+2) - 8 Dbar(m+1) + 8 Dbar(m-1) - Dbar(m-2)) / (12 dx_t)
+    for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + p.c];
+    if (g.viscous) fold_dbar<false>(g, Dbar, p.c, q, wb);
+  } else {
+    for (int c = 0; c < cz; ++c)
+      for (int b = 0; b < cy; ++b)
+        for (int a = 0; a < cx; ++a) {
+          const int q[3] = {fx + a * sx, fy + b * sy, fz + c * sz};
+          const long long cc = cell_at(g, q[0], q[1], q[2]);
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            if (!g.act[t]) continue;
-            const long long st = g.s[t];
-            const int lo = -g.h[t], hi = g.n[t] + g.h[t];
-            const int y = q[t];
-            const double i12 = g.idx[t] / 12.0;
-#pragma unroll
-            for (int comp = 0; comp < 3; ++comp) {
-              const double* Db = Dbar + (comp * 3 + t) * g.vs + cc;
-              double acc = 0.0;
-              if (y + 2 < hi) acc += Db[2 * st];
-              if (y + 1 < hi) acc -= 8.0 * Db[st];
-              if (y - 1 >= lo) acc += 8.0 * Db[-st];
-              if (y - 2 >= lo) acc -= Db[-2 * st];
-              wb[1 + comp] += acc * i12;
-            }
-          }
+          for (int v = 0; v < 6; ++v) wb[v] += Wbar[v * g.vs + cc];
+          if (g.viscous) fold_dbar<true>(g, Dbar, cc, q, wb);
         }
-      }
+  }
   // transposed primitive map at U[s]
   const long long s = p.c;
   const double rho = U[s], m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];
