@@ -2,12 +2,16 @@
 //
 //   1. the primitives P at the state (the forward kernels, or the buffers a
 //      forward recompute of the stages leaves);
-//   2. k_face_adj<D>: one thread per face normal to D. The face flux adjoint
+//   2. k_face_adj<D>: one lane per face normal to D. The face flux adjoint
 //      follows from Rbar (R_i = -(G_{i+1/2} - G_{i-1/2})/dx gives
 //      Gbar_{i+1/2} = (Rbar_{i+1} - Rbar_i)/dx), the face recomputes its
 //      forward flux and reverses it (physics_adj.hpp), and its contributions
-//      are added with hardware FP64 atomics into Wbar (rho,u,v,w,p,T~ of the
-//      stencil cells) and Dbar (the adjoints of the centred derivatives);
+//      go to Wbar (rho,u,v,w,p,T~ of the stencil cells) and Dbar (the adjoints
+//      of the centred derivatives) with hardware FP64 atomics. For x faces
+//      the lanes of a wavefront hold consecutive faces of a row and the
+//      contributions are first summed per cell by shuffles (one atomic per
+//      cell and variable); y and z faces keep x-consecutive lanes, whose
+//      loads coalesce, and add every contribution directly;
 //   3. k_adj_fold: per interior cell, the transposed halo fill (every padded
 //      cell that the boundary map sends to it), the transposed centred
 //      differences of Dbar, and the transposed primitive map at U give Ubar.
@@ -24,16 +28,18 @@ __device__ __forceinline__ void atomic_add(double* p, double v) {
 }
 
 // Face numbering for axis D: face f in [0, n_D] lies between cells f-1 and f.
-// D = 0: f runs fastest (faces of a row are consecutive); D = 1, 2: x runs
-// fastest so that lanes load consecutive cells.
+// D = 0: f runs fastest, so the lanes of a wavefront hold consecutive faces of
+// a row (col = the row) and also load consecutive cells; D = 1, 2: x runs
+// fastest so that lanes load consecutive cells (col = -1: no two lanes of a
+// wavefront share a column).
 template <int D>
-__device__ __forceinline__ bool face_coords(const Geom& g, int t, int& i, int& j, int& k, int& f) {
+__device__ __forceinline__ bool face_coords(const Geom& g, int t, int& i, int& j, int& k, int& f, int& col) {
   if (D == 0) {
     const int F = g.n[0] + 1;
-    const int row = t / F;
-    f = t - row * F;
-    k = row / g.n[1];
-    j = row - k * g.n[1];
+    col = t / F;
+    f = t - col * F;
+    k = col / g.n[1];
+    j = col - k * g.n[1];
     i = f;
     return k < g.n[2];
   } else if (D == 1) {
@@ -43,6 +49,7 @@ __device__ __forceinline__ bool face_coords(const Geom& g, int t, int& i, int& j
     k = r / F;
     f = r - k * F;
     j = f;
+    col = -1;
     return k < g.n[2];
   } else {
     const int r = t / g.n[0];
@@ -50,10 +57,51 @@ __device__ __forceinline__ bool face_coords(const Geom& g, int t, int& i, int& j
     f = r / g.n[1];
     j = r - f * g.n[1];
     k = f;
+    col = -1;
     return f <= g.n[2];
   }
 }
 
+// Summation across a wavefront whose lanes hold consecutive faces of rows.
+// A lane's contribution to cell f + d of its row (d in -3..2) belongs to the
+// lane holding face f + d of the same row (the cell's "owner"); the owner adds
+// up what it receives and adds the total to memory with one atomic. A
+// contribution whose owner is not in the wavefront (row ends, wavefront edges,
+// halo cells) is added to memory by its lane directly.
+struct LaneSum {
+  int lane;
+  int key;            // column of a lane with a face, -2 without a face
+  bool sent[6];       // offset d = idx - 3: the owner lane + d exists
+  bool got[6];        //                     the lane - d exists (sends to me)
+
+  // has: the lane holds a face; col: its column, or -1 when the lanes of the
+  // wavefront hold faces of different columns (every contribution but the
+  // lane's own cell is then added directly)
+  __device__ __forceinline__ void init(int lane_, bool has, int col) {
+    lane = lane_;
+    key = has ? col : -2;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int d = e - 3;
+      const int dst = lane + d, src = lane - d;
+      const int kd = __shfl(key, dst & 63, 64), ks = __shfl(key, src & 63, 64);
+      if (d == 0) {
+        sent[e] = got[e] = has;
+      } else {
+        sent[e] = has && col >= 0 && dst >= 0 && dst < 64 && kd == key;
+        got[e] = has && col >= 0 && src >= 0 && src < 64 && ks == key;
+      }
+    }
+  }
+  // Contribution x to cell f + d (address addr): returns the share this lane
+  // collects as owner from lane - d; adds x to memory when no owner exists.
+  __device__ __forceinline__ double pass(double x, int d, double* addr) const {
+    const int e = d + 3;
+    const double y = __shfl(x, (lane - d) & 63, 64);
+    if (key != -2 && !sent[e]) atomic_add(addr, x);
+    return got[e] ? y : 0.0;
+  }
+};
 // Face adjoint Gbar from Rbar (read as rscale * Rbar, interior cells only).
 template <int D>
 __device__ __forceinline__ bool face_gbar(const Geom& g, const double* __restrict__ Rbar, double rscale, long long cf,
@@ -73,86 +121,127 @@ __device__ __forceinline__ bool face_gbar(const Geom& g, const double* __restric
 
 // Inviscid part of the face adjoint: WENO5-JS forward, HLLC reverse, then the
 // WENO reverse one variable at a time with that variable's stencil reloaded,
-// so the window is not held in registers across the HLLC reverse.
+// so the window is not held in registers across the HLLC reverse. Every lane
+// takes part in the shuffles; lanes without a face (or with a zero face
+// adjoint) contribute zeros.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_adj_inv(const double* P, const double* __restrict__ Rbar,
                                                          double rscale, double* Wbar, Geom g) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k, f;
-  if (!face_coords<D>(g, t, i, j, k, f)) return;
+  int i = 0, j = 0, k = 0, f = 0, col = 0;
+  const bool has = face_coords<D>(g, t, i, j, k, f, col);
+  if (!has) i = j = k = f = 0;  // a valid cell for the (unused) address arithmetic
+  LaneSum ls;
+  ls.init(threadIdx.x & 63, has, col);
   const long long st = g.s[D];
   const long long cf = cell_at(g, i, j, k);  // cell f: the face lies between f-1 and f
-  double Gb[5];
-  if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) return;
-  const long long c0 = cf - 3 * st;  // window cell 0 = cell f-3
-  double WL[5], WR[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const double* q = P + v * g.vs + c0;
-    const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
-    WL[v] = weno5(q0, q1, q2, q3, q4);
-    WR[v] = weno5(q5, q4, q3, q2, q1);
-  }
+  const long long c0 = cf - 3 * st;          // window cell 0 = cell f-3
+  double Gb[5] = {0, 0, 0, 0, 0};
+  const bool active = has && face_gbar<D>(g, Rbar, rscale, cf, f, Gb);
   double WLb[5] = {0, 0, 0, 0, 0}, WRb[5] = {0, 0, 0, 0, 0};
-  hllc_rev<D>(g.gamma, g.gm1i, WL, WR, Gb, WLb, WRb);
+  if (active) {
+    double WL[5], WR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double* q = P + v * g.vs + c0;
+      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
+      WL[v] = weno5(q0, q1, q2, q3, q4);
+      WR[v] = weno5(q5, q4, q3, q2, q1);
+    }
+    hllc_rev<D>(g.gamma, g.gm1i, WL, WR, Gb, WLb, WRb);
+  }
   asm volatile("" ::: "memory");  // reload the stencils below instead of keeping them live
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const double* q = P + v * g.vs + c0;
-    const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
     double gs[6] = {0, 0, 0, 0, 0, 0};
-    weno5_rev(q0, q1, q2, q3, q4, WLb[v], gs);
-    double gr[5] = {0, 0, 0, 0, 0};
-    weno5_rev(q5, q4, q3, q2, q1, WRb[v], gr);
+    if (active) {
+      const double* q = P + v * g.vs + c0;
+      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
+      weno5_rev(q0, q1, q2, q3, q4, WLb[v], gs);
+      double gr[5] = {0, 0, 0, 0, 0};
+      weno5_rev(q5, q4, q3, q2, q1, WRb[v], gr);
 #pragma unroll
-    for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
+      for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
+    }
+    double* wv = Wbar + v * g.vs + c0;
+    double own = 0.0;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) atomic_add(&Wbar[v * g.vs + c0 + m * st], gs[m]);
+    for (int m = 0; m < 6; ++m) own += ls.pass(gs[m], m - 3, wv + m * st);
+    if (has) atomic_add(wv + 3 * st, own);
   }
 }
 
 // Dissipative part of the face adjoint (viscous and heat flux).
 // The cell-centred tangential derivatives are formed from P as in the forward
-// sweeps; their adjoints go to Dbar and are transposed in k_adj_fold.
+// sweeps; their adjoints go to Dbar and are transposed in k_adj_fold. The
+// window's adjoints (cells 1..4: u, v, w, T~ and the four derivative inputs)
+// are collected in registers, then summed across the wavefront.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restrict__ P,
                                                          const double* __restrict__ Rbar, double rscale,
                                                          double* Wbar, double* Dbar, Geom g) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i, j, k, f;
-  if (!face_coords<D>(g, t, i, j, k, f)) return;
+  int i = 0, j = 0, k = 0, f = 0, col = 0;
+  const bool has = face_coords<D>(g, t, i, j, k, f, col);
+  if (!has) i = j = k = f = 0;
+  LaneSum ls;
+  ls.init(threadIdx.x & 63, has, col);
   const long long st = g.s[D];
   const long long cf = cell_at(g, i, j, k);
-  double Gb[5];
-  if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) return;
   const long long c0 = cf - 3 * st;
-  FaceWindow w;
+  double Gb[5] = {0, 0, 0, 0, 0};
+  const bool active = has && face_gbar<D>(g, Rbar, rscale, cf, f, Gb);
+  struct RegSink {
+    double qb[4][4];   // window cells 1..4: u, v, w, T~
+    double tgb[4][4];  // window cells 1..4: derivative inputs
+    __device__ void q(int m, int v, double x) { qb[m - 1][v == 5 ? 3 : v - 1] += x; }
+    __device__ void tg(int m, int kk, double x) { tgb[m - 1][kk] += x; }
+  } sink;
 #pragma unroll
-  for (int m = 1; m < 5; ++m)
+  for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int v = 1; v < 4; ++v) w.q[m][v] = P[v * g.vs + c0 + m * st];
+    for (int v = 0; v < 4; ++v) sink.qb[m][v] = sink.tgb[m][v] = 0.0;
+  if (active) {
+    FaceWindow w;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    w.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
-    if (g.viscous) tangential_at<D>(g, P, c0 + (1 + m) * st, w.tg[m]);
-  }
-  Geom gd = g;
-  gd.inviscid = 0;  // the inviscid part is k_face_adj_inv
-  struct AtomicSink {
-    double* Wbar;
-    double* Dbar;
-    long long c0, st, vs;
-    int comp[4];
-    bool act[4];
-    __device__ void q(int m, int v, double x) { atomic_add(&Wbar[v * vs + c0 + m * st], x); }
-    __device__ void tg(int m, int k, double x) {
-      if (act[k]) atomic_add(&Dbar[comp[k] * vs + c0 + m * st], x);
+    for (int m = 1; m < 5; ++m)
+#pragma unroll
+      for (int v = 1; v < 4; ++v) w.q[m][v] = P[v * g.vs + c0 + m * st];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      w.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
+      if (g.viscous) tangential_at<D>(g, P, c0 + (1 + m) * st, w.tg[m]);
     }
-  } sink{Wbar, Dbar, c0, st, g.vs,
-         {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2},
-         {g.viscous && g.act[T1], g.viscous && g.act[T1], g.viscous && g.act[T2], g.viscous && g.act[T2]}};
-  face_flux_rev<D>(gd, w, Gb, sink);
+    Geom gd = g;
+    gd.inviscid = 0;  // the inviscid part is k_face_adj_inv
+    face_flux_rev<D>(gd, w, Gb, sink);
+  }
+  // window cell m (1..4) is cell f + (m - 3)
+  const int wslot[4] = {1, 2, 3, 5};  // u, v, w, T~ in Wbar
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    if (v == 3 && !g.heat) continue;
+    if (v < 3 && !g.viscous) continue;
+    double* wv = Wbar + wslot[v] * g.vs + c0;
+    double own = 0.0;
+#pragma unroll
+    for (int m = 1; m < 5; ++m) own += ls.pass(sink.qb[m - 1][v], m - 3, wv + m * st);
+    if (has) atomic_add(wv + 3 * st, own);
+  }
+  if (g.viscous) {
+    const int comp[4] = {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2};
+    const bool act[4] = {g.act[T1] != 0, g.act[T1] != 0, g.act[T2] != 0, g.act[T2] != 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      if (!act[kk]) continue;
+      double* dv = Dbar + comp[kk] * g.vs + c0;
+      double own = 0.0;
+#pragma unroll
+      for (int m = 1; m < 5; ++m) own += ls.pass(sink.tgb[m - 1][kk], m - 3, dv + m * st);
+      if (has) atomic_add(dv + 3 * st, own);
+    }
+  }
 }
 
 // Padded coordinates of axis d that the boundary map sends to interior
