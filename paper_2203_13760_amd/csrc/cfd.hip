@@ -344,12 +344,21 @@ static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
 template <int D>
 static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, double rscale, hipStream_t st) {
   const Geom& g = s->g;
-  long long faces = (long long)g.n[0] * g.n[1] * g.n[2] / g.n[D] * (g.n[D] + 1);
-  const dim3 grid(grid_for(faces, 1LL << 31));
-  if (g.inviscid)
-    hipLaunchKernelGGL(k_face_adj_inv<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
-  if (g.viscous || g.heat)
-    hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar, g);
+  if constexpr (D == 0) {
+    long long faces = (long long)g.n[0] * g.n[1] * g.n[2] / g.n[D] * (g.n[D] + 1);
+    const dim3 grid(grid_for(faces, 1LL << 31));
+    if (g.inviscid)
+      hipLaunchKernelGGL(k_face_adj_inv<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
+    if (g.viscous || g.heat)
+      hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar, g);
+  } else {
+    const dim3 grid = face_adj_tile_grid<D>(g);
+    if (g.inviscid)
+      hipLaunchKernelGGL(k_face_adj_inv_tiled<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
+    if (g.viscous || g.heat)
+      hipLaunchKernelGGL(k_face_adj_dis_tiled<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar,
+                         g);
+  }
 }
 
 // Ubar += (dR/dU(U))^T (rscale Rbar), interior cells; P holds the primitives

@@ -244,6 +244,163 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restric
   }
 }
 
+// y and z faces, tiled: a block takes 64 consecutive x (one per lane) and
+// kAdjTileFaces consecutive faces along D at one coordinate of the other
+// transverse axis, each wavefront kAdjTileFaces / 4 of those faces in turn.
+// The contributions of the block's faces are added into an LDS tile of the
+// cells they touch (LDS FP64 atomics), and the tile is then added to memory,
+// one global atomic per nonzero tile entry: about four times fewer global
+// atomics than adding each face's contributions directly, with the loads
+// still coalesced along x.
+constexpr int kAdjTileFaces = 8;
+constexpr int kAdjTileRows = kAdjTileFaces + 5;  // cells f0-3 .. f0+kAdjTileFaces+1
+
+template <int D>
+__host__ __device__ __forceinline__ dim3 face_adj_tile_grid(const Geom& g) {
+  constexpr int OT = D == 1 ? 2 : 1;
+  const int nfc = (g.n[D] + 1 + kAdjTileFaces - 1) / kAdjTileFaces;
+  return dim3((unsigned)((g.n[0] + 63) / 64), (unsigned)(nfc * g.n[OT]));
+}
+
+// Lane, x, first face of the tile, other-axis coordinate of a tiled launch.
+template <int D>
+__device__ __forceinline__ void face_adj_tile(const Geom& g, int& lane, int& x, int& f0, int& o) {
+  const int nfc = (g.n[D] + 1 + kAdjTileFaces - 1) / kAdjTileFaces;
+  lane = threadIdx.x & 63;
+  x = blockIdx.x * 64 + lane;
+  o = blockIdx.y / nfc;
+  f0 = (blockIdx.y - o * nfc) * kAdjTileFaces;
+}
+
+template <int D>
+__device__ __forceinline__ long long tile_cell(const Geom& g, int x, int c, int o) {
+  return D == 1 ? cell_at(g, x, c, o) : cell_at(g, x, o, c);
+}
+
+// Zero an LDS tile of nv components.
+__device__ __forceinline__ void tile_zero(double* tile, int n) {
+  for (int e = threadIdx.x; e < n; e += kBlock) tile[e] = 0.0;
+  __syncthreads();
+}
+
+// Add the LDS tile (component v at base[v], rows of cells f0-3+r) to memory.
+template <int D>
+__device__ __forceinline__ void tile_flush(const Geom& g, const double* tile, int nv, double* const* base, int f0,
+                                           int o) {
+  __syncthreads();
+  const int x0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < nv * kAdjTileRows * 64; e += kBlock) {
+    const double val = tile[e];
+    if (val == 0.0) continue;  // only cells a face of the tile touched are nonzero
+    const int l = e & 63;
+    const int r = (e >> 6) % kAdjTileRows;
+    const int v = (e >> 6) / kAdjTileRows;
+    unsafeAtomicAdd(base[v] + tile_cell<D>(g, x0 + l, f0 - 3 + r, o), val);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_adj_inv_tiled(const double* P, const double* __restrict__ Rbar,
+                                                               double rscale, double* Wbar, Geom g) {
+  __shared__ double tile[5 * kAdjTileRows * 64];
+  int lane, x, f0, o;
+  face_adj_tile<D>(g, lane, x, f0, o);
+  tile_zero(tile, 5 * kAdjTileRows * 64);
+  const int w = threadIdx.x >> 6;
+  constexpr int per_wave = kAdjTileFaces / (kBlock / 64);
+  const long long st = g.s[D];
+  for (int it = 0; it < per_wave; ++it) {
+    const int fl = w * per_wave + it;  // face of the tile, 0 .. kAdjTileFaces-1
+    const int f = f0 + fl;
+    if (x >= g.n[0] || f > g.n[D]) continue;
+    const long long cf = tile_cell<D>(g, x, f, o);
+    double Gb[5];
+    if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) continue;
+    const long long c0 = cf - 3 * st;
+    double WL[5], WR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double* q = P + v * g.vs + c0;
+      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
+      WL[v] = weno5(q0, q1, q2, q3, q4);
+      WR[v] = weno5(q5, q4, q3, q2, q1);
+    }
+    double WLb[5] = {0, 0, 0, 0, 0}, WRb[5] = {0, 0, 0, 0, 0};
+    hllc_rev<D>(g.gamma, g.gm1i, WL, WR, Gb, WLb, WRb);
+    asm volatile("" ::: "memory");  // reload the stencils below instead of keeping them live
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double* q = P + v * g.vs + c0;
+      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
+      double gs[6] = {0, 0, 0, 0, 0, 0};
+      weno5_rev(q0, q1, q2, q3, q4, WLb[v], gs);
+      double gr[5] = {0, 0, 0, 0, 0};
+      weno5_rev(q5, q4, q3, q2, q1, WRb[v], gr);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) atomicAdd(&tile[(v * kAdjTileRows + fl + m) * 64 + lane], gs[m]);
+    }
+  }
+  double* base[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) base[v] = Wbar + v * g.vs;
+  tile_flush<D>(g, tile, 5, base, f0, o);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_adj_dis_tiled(const double* __restrict__ P,
+                                                               const double* __restrict__ Rbar, double rscale,
+                                                               double* Wbar, double* Dbar, Geom g) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  // components: u, v, w, T~ of Wbar, then the four derivative inputs of Dbar
+  __shared__ double tile[8 * kAdjTileRows * 64];
+  int lane, x, f0, o;
+  face_adj_tile<D>(g, lane, x, f0, o);
+  tile_zero(tile, 8 * kAdjTileRows * 64);
+  const int w = threadIdx.x >> 6;
+  constexpr int per_wave = kAdjTileFaces / (kBlock / 64);
+  const long long st = g.s[D];
+  for (int it = 0; it < per_wave; ++it) {
+    const int fl = w * per_wave + it;
+    const int f = f0 + fl;
+    if (x >= g.n[0] || f > g.n[D]) continue;
+    const long long cf = tile_cell<D>(g, x, f, o);
+    double Gb[5];
+    if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) continue;
+    const long long c0 = cf - 3 * st;
+    FaceWindow win;
+#pragma unroll
+    for (int m = 1; m < 5; ++m)
+#pragma unroll
+      for (int v = 1; v < 4; ++v) win.q[m][v] = P[v * g.vs + c0 + m * st];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      win.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
+      if (g.viscous) tangential_at<D>(g, P, c0 + (1 + m) * st, win.tg[m]);
+    }
+    Geom gd = g;
+    gd.inviscid = 0;  // the inviscid part is k_face_adj_inv_tiled
+    struct TileSink {
+      double* tile;
+      int fl, lane;
+      bool act[4];
+      __device__ void q(int m, int v, double val) {
+        const int c = v == 5 ? 3 : v - 1;  // u, v, w, T~
+        atomicAdd(&tile[(c * kAdjTileRows + fl + m) * 64 + lane], val);
+      }
+      __device__ void tg(int m, int k, double val) {
+        if (act[k]) atomicAdd(&tile[((4 + k) * kAdjTileRows + fl + m) * 64 + lane], val);
+      }
+    } sink{tile, fl, lane, {g.act[T1] != 0, g.act[T1] != 0, g.act[T2] != 0, g.act[T2] != 0}};
+    face_flux_rev<D>(gd, win, Gb, sink);
+  }
+  const int comp[4] = {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2};
+  double* base[8] = {Wbar + 1 * g.vs, Wbar + 2 * g.vs, Wbar + 3 * g.vs, Wbar + 5 * g.vs,
+                     Dbar + comp[0] * g.vs, Dbar + comp[1] * g.vs, Dbar + comp[2] * g.vs, Dbar + comp[3] * g.vs};
+  tile_flush<D>(g, tile, 8, base, f0, o);
+}
+
 // Padded coordinates of axis d that the boundary map sends to interior
 // coordinate x (its halo images plus x itself), as first, count and step:
 // periodic images are x - n, x, x + n where inside the padding; zero-gradient
