@@ -28,7 +28,7 @@ struct GridWork {
   double* partial; // CFL rate slots
   DevCtl* ctl;
   int npart;
-  int last_axis;   // the last active axis applies the stage update
+  int last_axis;   // the last swept axis (the lowest active one) applies the stage update
   int first_axis;
   int pgx;         // x blocks of a plane-indexed launch
   int sgx[3], sgy[3];  // launch shapes of the marching sweeps (axes 1, 2)
