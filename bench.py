@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="grid side (the headline case is 256)")
     ap.add_argument("--reps", type=int, default=5, help="kernel-timing repetitions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slab", type=int, default=24, help="z-planes of the oracle's timed slab")
+    ap.add_argument("--cpu-slab", type=int, default=48, help="z-planes of the oracle's timed slab")
     ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--adj-n", type=int, default=128)
