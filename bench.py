@@ -167,10 +167,16 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     tgrad = time.perf_counter() - t0
     gnorm = float(Wt.grad[1:4].norm().item())
     s.close()
+    # the paper's gradient check: d(Delta S)/dM_S of a Mach 2 shock after 5 steps,
+    # adjoint against central differences (least-squares order over the steps)
+    import numpy as np
+    from paper_2203_13760_amd.experiments import shock_entropy_gradient
+    sg = shock_entropy_gradient()
+    sg["fd_order"] = float(np.polyfit(np.log(sg["eps"]), np.log(sg["fd_error"]), 1)[0])
     return {"workload": f"Taylor-Green vortex {n}^3 + Gaussian noise 1e-3 (seed 4), fixed dt {dt:.4g}",
             "step_ms": fwd, "step_adjoint_ms": adj, "adjoint_over_step": adj / fwd,
             "gradient_steps": nsteps, "checkpoint_every": ckpt_every, "gradient_s": tgrad,
-            "loss": float(L.item()), "grad_norm": gnorm}
+            "loss": float(L.item()), "grad_norm": gnorm, "shock_gradient": sg}
 
 
 def serving_bench(args):

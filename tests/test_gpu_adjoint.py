@@ -169,3 +169,36 @@ def test_gradient_of_long_rollout_matches_finite_differences(Solver):
     s.close()
     # same kinks as in the right-hand-side dot-product test
     assert abs(fd - ad) <= 1e-4 * abs(ad), (fd, ad)
+
+
+# ---------------------------------------------------------------- the paper's gradient check
+# §6.1 (validation of AD gradients), single phase: d(Delta S)/dM_S of a Mach 2
+# shock after 5 steps of dt = 1e-2, by the GPU adjoint, against the oracle's
+# taped reverse mode (same discrete operator) and against central differences.
+
+def test_shock_entropy_gradient_matches_oracle_tape(Solver):
+    from paper_2203_13760_amd import experiments as ex
+    print("shock entropy gradient: GPU adjoint vs oracle tape", flush=True)
+    from test_shock_gradient_cpu import oracle_shock_gradient
+    r = ex.shock_entropy_gradient(eps=(1e-3,))
+    dS_o, g_o = oracle_shock_gradient(ex.SHOCK_M)
+    assert r["delta_S"] > 0.0  # the shock raises the entropy
+    assert abs(r["delta_S"] - dS_o) <= 1e-12 * abs(dS_o), (r["delta_S"], dS_o)
+    assert abs(r["g_ad"] - g_o) <= 1e-10 * abs(g_o), (r["g_ad"], g_o)
+
+
+def test_shock_entropy_fd_converges_to_adjoint_at_second_order(Solver):
+    """The paper's observation: the central differences approach g_AD at
+    second order in the step, e in {1e-1, 3e-2, ..., 1e-4}. Delta S is only
+    piecewise smooth in M_S (WENO weights, Einfeldt min/max, HLLC wave
+    pattern), so single decades scatter; the least-squares order over all
+    steps is the measure, and the smallest step agrees to 1e-7."""
+    from paper_2203_13760_amd import experiments as ex
+    print("shock entropy gradient: central differences", flush=True)
+    r = ex.shock_entropy_gradient()
+    err = np.array(r["fd_error"])
+    eps = np.array(r["eps"])
+    print("g_ad", r["g_ad"], "errors", err.tolist(), flush=True)
+    order = np.polyfit(np.log(eps), np.log(err), 1)[0]
+    assert order >= 1.8, order
+    assert err[-1] <= 1e-7 * abs(r["g_ad"]), err

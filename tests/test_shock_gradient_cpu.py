@@ -1,0 +1,84 @@
+"""CPU checks of the shock-gradient experiment (§6.1, validation of AD
+gradients): the Rankine-Hugoniot initial state against closed forms, and the
+oracle's taped reverse-mode gradient of the entropy increase against its own
+central differences (second order, as the paper observes)."""
+import math
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import oracle
+from paper_2203_13760_amd import experiments as ex
+
+
+def test_post_shock_state_closed_forms():
+    g = 1.4
+    rho, u, p = (float(x) for x in ex.post_shock(torch.tensor(2.0, dtype=torch.float64), g))
+    # M = 2, gamma = 1.4: density ratio (g+1)M^2/((g-1)M^2+2) = 8/3, pressure ratio (2gM^2-(g-1))/(g+1) = 4.5
+    assert abs(rho - 8.0 / 3.0) < 1e-15
+    assert abs(p - 4.5) < 1e-14
+    assert abs(u - 2.0 * math.sqrt(1.4) * (1.0 - 3.0 / 8.0)) < 1e-14
+    # M = 1 is no shock at all
+    rho1, u1, p1 = (float(x) for x in ex.post_shock(torch.tensor(1.0, dtype=torch.float64), g))
+    assert abs(rho1 - 1.0) < 1e-15 and abs(u1) < 1e-15 and abs(p1 - 1.0) < 1e-15
+    # the mass flux through the shock is the same on both sides: rho_l (W - u_l) = rho_r W
+    W = 2.0 * math.sqrt(1.4)
+    assert abs(rho * (W - u) - W) < 1e-14
+
+
+def oracle_shock_gradient(M0):
+    """Delta S and d(Delta S)/dM_S from the oracle: forward steps, the taped
+    step adjoints (vjp_rk3_step) from the entropy derivative at the final
+    state, contracted with the derivative of the initial state (torch
+    autograd of the Rankine-Hugoniot state)."""
+    from paper_2203_13760_amd import experiments as ex
+    case = ex.shock_case()
+    dt, n = ex.SHOCK_DT, ex.SHOCK_STEPS
+    W = ex.initial_W(case, torch.tensor(M0, dtype=torch.float64)).numpy()
+    states = [oracle.state_init(case, W)]
+    for _ in range(n):
+        states.append(oracle.rk3_step(case, states[-1], dt)[0])
+
+    def padded_cons(M):
+        Wt = ex.initial_W(case, M)
+        g = case["gamma"]
+        rho, u, p = Wt[0], Wt[1], Wt[4]
+        Ui = torch.stack([rho, rho * u, torch.zeros_like(u), torch.zeros_like(u),
+                          p / (g - 1.0) + 0.5 * rho * u * u])
+        U = torch.zeros(oracle.padded_shape(case), dtype=torch.float64)
+        oracle.interior(case, U)[...] = Ui
+        return U
+
+    Un = torch.tensor(states[-1], requires_grad=True)
+    S_n = ex.integral_entropy(case, Un)
+    S_n.backward()
+    Ubar = Un.grad.numpy().copy()
+    for k in reversed(range(n)):
+        Ubar = oracle.vjp_rk3_step(case, states[k], dt, Ubar)
+    M = torch.tensor(M0, dtype=torch.float64, requires_grad=True)
+    U0 = padded_cons(M)
+    L = (torch.from_numpy(Ubar) * U0).sum() - ex.integral_entropy(case, U0)
+    L.backward()
+    dS = float(S_n.item()) - float(ex.integral_entropy(case, torch.from_numpy(states[0])).item())
+    return dS, float(M.grad.item())
+
+
+def _oracle_delta_S(M):
+    case = ex.shock_case()
+    W = ex.initial_W(case, torch.tensor(M, dtype=torch.float64)).numpy()
+    U = oracle.state_init(case, W)
+    S0 = float(ex.integral_entropy(case, torch.from_numpy(U)).item())
+    for _ in range(ex.SHOCK_STEPS):
+        U = oracle.rk3_step(case, U, ex.SHOCK_DT)[0]
+    return float(ex.integral_entropy(case, torch.from_numpy(U)).item()) - S0
+
+
+def test_oracle_tape_gradient_second_order_against_differences():
+    dS, g = oracle_shock_gradient(ex.SHOCK_M)
+    assert abs(dS - _oracle_delta_S(ex.SHOCK_M)) <= 1e-14 * abs(dS)
+    eps = np.array(ex.SHOCK_EPS)
+    err = np.array([abs((_oracle_delta_S(ex.SHOCK_M + e) - _oracle_delta_S(ex.SHOCK_M - e)) / (2 * e) - g)
+                    for e in eps])
+    order = np.polyfit(np.log(eps), np.log(err), 1)[0]
+    assert order >= 1.8, (order, err)
+    assert err[-1] <= 1e-7 * abs(g), err
