@@ -48,8 +48,10 @@ typedef enum {
 typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1 } cfd_bc;
 
 /* Physics switches, after the paper's is_inviscid_flux / is_viscous_flux /
- * is_heat_flux (Appendix A). */
-enum { CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u };
+ * is_heat_flux (Appendix A), and the reconstruction: WENO5-JS by default,
+ * WENO5-Z (Borges et al. 2008; listed beside WENO5-JS in the paper's table of
+ * methods, §3.3) with CFD_F_WENOZ. The adjoint covers WENO5-JS only. */
+enum { CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u, CFD_F_WENOZ = 8u };
 
 typedef struct {
   int32_t n[3];      /* interior cells (x,y,z); n[d] == 1 marks an inactive axis */
@@ -122,13 +124,15 @@ cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double d
 /* Discrete adjoint of cfd_rhs: Ubar += (dR/dU)^T Rbar, evaluated at U
  * (interior cells of Rbar are read; its halo is ignored). The transposed halo
  * fill folds halo contributions back into their source cells, so the halo
- * entries of Ubar are left unchanged. U is not modified. */
+ * entries of Ubar are left unchanged. U is not modified. CFD_EUNSUPPORTED for
+ * a WENO5-Z configuration. */
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar,
                            void* stream);
 
 /* Discrete adjoint of one fixed-dt TVD-RK3 step: with U^{n+1} = S(U^n),
  * Ubar_n = (dS/dU^n)^T Ubar_np1 (interior cells; Ubar_n's halo is zeroed).
- * The stage states are recomputed from Un. Ubar_n must not alias the others. */
+ * The stage states are recomputed from Un. Ubar_n must not alias the others.
+ * CFD_EUNSUPPORTED for a WENO5-Z configuration. */
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream);
 
@@ -175,7 +179,8 @@ cfd_status cfd_batch_footprint(const cfd_config* cfg, int64_t* bytes);
 /* Admit a grid: validate cfg, take a slot and arena space, and enqueue the
  * conservative initial state from W (device, 5 x interior primitives, as for
  * cfd_state_init). Returns CFD_ENOMEM, with nothing changed, when no slot or
- * arena space is free; the caller retries after removing finished grids. */
+ * arena space is free; the caller retries after removing finished grids.
+ * CFD_EUNSUPPORTED for a WENO5-Z configuration (the batch runs WENO5-JS). */
 cfd_status cfd_batch_add(cfd_batch* b, const cfd_config* cfg, const double* W, int32_t* slot_out, void* stream);
 
 /* Retire a grid and free its slot and arena space. The caller must have

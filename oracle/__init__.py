@@ -59,6 +59,8 @@ def _load():
     lib.oracle_advance.argtypes = [cfgp, dp, C.c_int, d, d, dp]
     lib.oracle_weno5.argtypes = [d, d, d, d, d]
     lib.oracle_weno5.restype = d
+    lib.oracle_weno5z.argtypes = [d, d, d, d, d]
+    lib.oracle_weno5z.restype = d
     lib.oracle_hllc.argtypes = [d, dp, dp, C.c_int, dp]
     lib.oracle_hllc.restype = None
     lib.oracle_opcount.argtypes = [cfgp, dp, dp]
@@ -176,6 +178,10 @@ def advance(case, U, n_steps, t_end=0.0, fixed_dt=0.0, t=0.0):
 
 def weno5(a, b, c, d, e):
     return float(_load().oracle_weno5(float(a), float(b), float(c), float(d), float(e)))
+
+
+def weno5z(a, b, c, d, e):
+    return float(_load().oracle_weno5z(float(a), float(b), float(c), float(d), float(e)))
 
 
 def hllc(gamma, WL, WR, axis):

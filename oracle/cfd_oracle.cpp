@@ -35,14 +35,14 @@ typedef struct {
   double prandtl;      // Prandtl number (> 0)
   double cfl;          // CFL number
   int32_t bc[6];       // x-, x+, y-, y+, z-, z+ : 0 periodic, 1 zero gradient
-  uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux
+  uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux, 8 WENO5-Z reconstruction
 } oracle_cfg;
 }
 
 namespace oracle {
 
 enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
-enum : uint32_t { F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u };
+enum : uint32_t { F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u, F_WENOZ = 8u };
 
 // --------------------------------------------------------------------------
 // Grid: cell (i,j,k), interior indices 0..n-1, halo indices -nh..-1, n..n+nh-1.
@@ -162,6 +162,26 @@ R weno5_js(R a, R b, R c, R d, R e) {
   const R alpha0 = 0.1 / sq(eps + beta0);
   const R alpha1 = 0.6 / sq(eps + beta1);
   const R alpha2 = 0.3 / sq(eps + beta2);
+  return (alpha0 * p0 + alpha1 * p1 + alpha2 * p2) / (alpha0 + alpha1 + alpha2);
+}
+
+// WENO5-Z (Borges, Carmona, Costa & Don 2008; the paper lists WENO5-JS/Z among
+// its reconstructions, §3.3): the same candidates and smoothness indicators,
+// with the global indicator tau5 = |beta0 - beta2| and nonlinear weights
+// alpha_k = d_k (1 + tau5 / (beta_k + eps)), eps = 1e-40, normalised.
+template <class R>
+R weno5_z(R a, R b, R c, R d, R e) {
+  const double eps = 1.0e-40;
+  const R beta0 = (13.0 / 12.0) * sq(a - 2.0 * b + c) + 0.25 * sq(a - 4.0 * b + 3.0 * c);
+  const R beta1 = (13.0 / 12.0) * sq(b - 2.0 * c + d) + 0.25 * sq(b - d);
+  const R beta2 = (13.0 / 12.0) * sq(c - 2.0 * d + e) + 0.25 * sq(3.0 * c - 4.0 * d + e);
+  const R tau5 = abs_(beta0 - beta2);
+  const R p0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  const R p1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  const R p2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  const R alpha0 = 0.1 * (1.0 + tau5 / (beta0 + eps));
+  const R alpha1 = 0.6 * (1.0 + tau5 / (beta1 + eps));
+  const R alpha2 = 0.3 * (1.0 + tau5 / (beta2 + eps));
   return (alpha0 * p0 + alpha1 * p1 + alpha2 * p2) / (alpha0 + alpha1 + alpha2);
 }
 
@@ -312,8 +332,13 @@ void face_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d, con
     for (int v = 0; v < 5; ++v) {
       const std::vector<R>& s = *q[v];
       auto at = [&](int o) { return s[g.shift(d, a[0], a[1], a[2], o)]; };
-      WL[v] = weno5_js(at(-2), at(-1), at(0), at(1), at(2));
-      WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
+      if (c.flags & F_WENOZ) {
+        WL[v] = weno5_z(at(-2), at(-1), at(0), at(1), at(2));
+        WR[v] = weno5_z(at(3), at(2), at(1), at(0), at(-1));
+      } else {
+        WL[v] = weno5_js(at(-2), at(-1), at(0), at(1), at(2));
+        WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
+      }
     }
     hllc_flux(c.gamma, WL, WR, d, Fc);
   }
@@ -553,6 +578,9 @@ int oracle_advance(const oracle_cfg* c, double* U, int n_steps, double t_end, do
 // Single-face building blocks, for unit tests of the method's pieces.
 double oracle_weno5(double a, double b, double c, double d, double e) {
   return weno5_js(a, b, c, d, e);
+}
+double oracle_weno5z(double a, double b, double c, double d, double e) {
+  return weno5_z(a, b, c, d, e);
 }
 void oracle_hllc(double gamma, const double* WL, const double* WR, int d, double* F) {
   hllc_flux(gamma, WL, WR, d, F);

@@ -94,7 +94,7 @@ static cfd_status validate(const cfd_config* c) {
   if (!(c->mu >= 0.0)) return fail(CFD_EINVAL, "mu must be >= 0");
   if (!(c->prandtl > 0.0)) return fail(CFD_EINVAL, "prandtl must be > 0");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return fail(CFD_EINVAL, "cfl must lie in (0, 1]");
-  if (c->flags & ~7u) return fail(CFD_EINVAL, "unknown physics flag");
+  if (c->flags & ~15u) return fail(CFD_EINVAL, "unknown physics flag");
   // index ranges of the kernels: faces per axis and padded planes in 32 bits,
   // padded z extent within the launch grid's y limit
   long long N[3];
@@ -132,6 +132,7 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.cfl = c.cfl;
   g.visc_rate = 2.0 * std::max(4.0 / 3.0, c.gamma / c.prandtl) * inv2;
   g.inviscid = (c.flags & CFD_F_INVISCID) ? 1 : 0;
+  g.wenoz = (c.flags & CFD_F_WENOZ) ? 1 : 0;
   g.viscous = ((c.flags & CFD_F_VISCOUS) && c.mu > 0.0) ? 1 : 0;
   g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
 }
@@ -147,16 +148,16 @@ static cfd_status enqueue_prim(cfd_solver* s, const double* Uk, int what, const 
   return CFD_OK;
 }
 
-template <int D, bool PN>
-static void launch_sweep(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
+template <int D, bool PN, bool WZ>
+static void launch_sweep_r(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
   const Geom& g = s->g;
   if (D == 0) {
     const dim3 grid((unsigned)sweep_x_blocks(g));
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL((k_sweep_x<MODE_ACC, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_x<MODE_ACC_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      default: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_x<MODE_ACC, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_x<MODE_ACC_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
     }
   } else {
     constexpr int AX = D == 0 ? 1 : D;
@@ -164,12 +165,20 @@ static void launch_sweep(cfd_solver* s, int mode, const double* P, const StageIO
     sweep_march_blocks<AX>(g, gx, gy);
     const dim3 grid(gx, gy);
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC, false>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK, PN>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
     }
   }
+}
+
+// The reconstruction (WENO5-JS or WENO5-Z) is a template parameter of the
+// sweep kernels; pick the instantiation for the solver's configuration.
+template <int D, bool PN>
+static void launch_sweep(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
+  if (s->g.wenoz) launch_sweep_r<D, PN, true>(s, mode, P, io, st);
+  else launch_sweep_r<D, PN, false>(s, mode, P, io, st);
 }
 
 template <bool PN>
@@ -589,6 +598,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
 
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
   if (!s || !U || !Rbar || !Ubar) return fail(CFD_EINVAL, "NULL argument");
+  if (s->g.wenoz) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS only");
   if (Ubar == U || Ubar == Rbar) return fail(CFD_EINVAL, "Ubar must not alias U or Rbar");
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
@@ -600,6 +610,7 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream) {
   if (!s || !Un || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
+  if (s->g.wenoz) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == Ubar_np1) return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
   cfd_status rc = ensure_adjoint_scratch(s);

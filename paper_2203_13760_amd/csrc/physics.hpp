@@ -29,6 +29,7 @@ struct Geom {
   double cfl;
   double visc_rate;  // 2 max(4/3, gamma/Pr) sum_d dx_d^-2 (times mu/rho gives the diffusive rate)
   int inviscid, viscous, heat;
+  int wenoz;       // WENO5-Z instead of WENO5-JS
 };
 
 __host__ __device__ __forceinline__ double sq(double x) { return x * x; }
@@ -65,6 +66,30 @@ __host__ __device__ __forceinline__ double weno5(double a, double b, double c, d
   const double s1 = sq(eps + (k13 * t1 * t1 + 0.25 * u1 * u1));
   const double s2 = sq(eps + (k13 * t2 * t2 + 0.25 * u2 * u2));
   const double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
+  const double P0 = 2.0 * a - 7.0 * b + 11.0 * c;
+  const double P1 = -b + 5.0 * c + 2.0 * d;
+  const double P2 = 2.0 * c + 5.0 * d - e;
+  return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
+}
+
+// WENO5-Z (Borges, Carmona, Costa & Don 2008): the same candidates and
+// smoothness indicators, global indicator tau5 = |beta0 - beta2|, weights
+// alpha_k = d_k (1 + tau5 / e_k) with e_k = beta_k + 1e-40, normalised.
+// Single division as in weno5: with alpha_k = d_k (e_k + tau5) / e_k the
+// weights are proportional to d_k (e_k + tau5) prod_{j != k} e_j.
+__host__ __device__ __forceinline__ double weno5z(double a, double b, double c, double d, double e) {
+  constexpr double k13 = 13.0 / 12.0;
+  constexpr double eps = 1.0e-40;
+  const double t0 = a - 2.0 * b + c, u0 = a - 4.0 * b + 3.0 * c;
+  const double t1 = b - 2.0 * c + d, u1 = b - d;
+  const double t2 = c - 2.0 * d + e, u2 = 3.0 * c - 4.0 * d + e;
+  const double b0 = k13 * t0 * t0 + 0.25 * u0 * u0;
+  const double b1 = k13 * t1 * t1 + 0.25 * u1 * u1;
+  const double b2 = k13 * t2 * t2 + 0.25 * u2 * u2;
+  const double tau = fabs(b0 - b2);
+  const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+  const double w0 = 0.1 * (e0 + tau) * (e1 * e2), w1 = 0.6 * (e1 + tau) * (e0 * e2),
+               w2 = 0.3 * (e2 + tau) * (e0 * e1);
   const double P0 = 2.0 * a - 7.0 * b + 11.0 * c;
   const double P1 = -b + 5.0 * c + 2.0 * d;
   const double P2 = 2.0 * c + 5.0 * d - e;
@@ -196,27 +221,34 @@ __host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const doubl
 }
 
 // Numerical flux from the window's primitives and given face tangential
-// derivatives tf: WENO5-JS left and right of the face, then face_flux_lr.
-template <int D>
+// derivatives tf: WENO5-JS (WENO5-Z with WZ) left and right of the face, then
+// face_flux_lr. The reconstruction is a compile-time choice: a run-time
+// branch between the two doubles the live registers of the sweeps.
+template <int D, bool WZ = false>
 __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceWindow& w, const double* tf,
                                                       double* G) {
   double WL[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WR[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (g.inviscid) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      WL[v] = weno5(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
-      WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
+      if constexpr (WZ) {
+        WL[v] = weno5z(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
+        WR[v] = weno5z(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
+      } else {
+        WL[v] = weno5(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
+        WR[v] = weno5(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
+      }
     }
   }
   face_flux_lr<D>(g, WL, WR, w, tf, G);
 }
 
 // Numerical flux G = F - F^d across the face (§3.3, §3.4) from a full window.
-template <int D>
+template <int D, bool WZ = false>
 __host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
   double tf[4] = {0.0, 0.0, 0.0, 0.0};
   if (g.viscous) face_tangential(w, tf);
-  face_flux_tf<D>(g, w, tf, G);
+  face_flux_tf<D, WZ>(g, w, tf, G);
 }
 
 }  // namespace cfd

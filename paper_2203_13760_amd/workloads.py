@@ -9,7 +9,7 @@ CPU oracle can both consume exactly the same arrays.
 Case keys: ``n`` (interior extents x, y, z; 1 = inactive axis), ``nh`` (halo
 width), ``lo``/``hi`` (box), ``gamma``, ``mu``, ``prandtl``, ``cfl``, ``bc``
 (x-, x+, y-, y+, z-, z+; 0 periodic, 1 zero gradient) and ``flags``
-(1 inviscid, 2 viscous, 4 heat).
+(1 inviscid, 2 viscous, 4 heat, 8 WENO5-Z instead of WENO5-JS).
 """
 from __future__ import annotations
 
@@ -20,6 +20,7 @@ import numpy as np
 PERIODIC = 0
 ZERO_GRADIENT = 1
 INVISCID, VISCOUS, HEAT = 1, 2, 4
+WENOZ = 8
 ALL_PHYSICS = INVISCID | VISCOUS | HEAT
 
 
@@ -65,6 +66,22 @@ def sod(n=200, nh=3):
     zero = np.zeros_like(X)
     case["t_end"] = 0.2
     return case, _stack(rho, zero, zero, zero, p, X.shape)
+
+
+def lax(n=100, nh=3):
+    """Lax's shock tube (§5.1.2 runs it to t = 0.14 on N = 100 cells of [0,1]
+    and leaves the states to its reference): (rho, u, p) = (0.445, 0.698,
+    3.528) | (0.5, 0, 0.571), diaphragm at 0.5, zero-gradient ends, inviscid,
+    CFL 0.5."""
+    case = make_case((n, 1, 1), bc=(ZERO_GRADIENT,) * 6, flags=INVISCID, cfl=0.5, nh=nh)
+    X, _, _ = _mesh(case)
+    left = X <= 0.5
+    rho = np.where(left, 0.445, 0.5)
+    u = np.where(left, 0.698, 0.0)
+    p = np.where(left, 3.528, 0.571)
+    zero = np.zeros_like(X)
+    case["t_end"] = 0.14
+    return case, _stack(rho, u, zero, zero, p, X.shape)
 
 
 def entropy_wave(n, nh=3):

@@ -69,7 +69,7 @@ BAD_CONFIGS = [
     ("prandtl", dict(prandtl=0.0), "prandtl"),
     ("cfl zero", dict(cfl=0.0), "cfl"),
     ("cfl above one", dict(cfl=1.5), "cfl"),
-    ("unknown flag", dict(flags=8), "flag"),
+    ("unknown flag", dict(flags=16), "flag"),
     ("too many faces", dict(n=(2048, 2048, 600)), "too large"),
 ]
 

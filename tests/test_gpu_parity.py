@@ -136,6 +136,19 @@ def test_sod_advance_to_t_end_matches_oracle(Solver):
     assert e <= TOL_100, e
 
 
+def test_lax_advance_to_t_end_matches_oracle(Solver):
+    case, W = wl.lax(100)
+    _say("lax advance to t_end parity")
+    s = Solver(case)
+    U = s.init(W)
+    t = s.advance(U, 300, t_end=0.14)
+    Uo, to, n = oracle.advance(case, oracle.state_init(case, W), 300, t_end=0.14)
+    assert abs(float(t.item()) - 0.14) < 1e-15 and abs(to - 0.14) < 1e-15
+    e = normwise(U.cpu().numpy(), Uo)
+    s.close()
+    assert e <= TOL_100, e
+
+
 def test_fixed_dt_rollout_matches_oracle(Solver):
     case, W = wl.taylor_green_noisy(16)
     _say("fixed-dt rollout parity")
@@ -264,3 +277,73 @@ def test_full_size_sampled_step(Solver, which):
         # normwise per variable (momenta share one scale)
         rel = np.max(np.abs(got - want) / scale)
         assert rel <= 1e-12, (c, got, want)
+
+
+# ---------------------------------------------------------------- WENO5-Z
+def _z(case_W):
+    case, W = case_W
+    case = dict(case)
+    case["flags"] = case["flags"] | wl.WENOZ
+    return case, W
+
+
+@pytest.mark.parametrize("name", ["shocky3d", "smooth_mixed_bc", "kh64x48", "sod200"])
+def test_wenoz_rhs_and_step_match_oracle(Solver, name):
+    case, W = _z(CASES[name])
+    _say(f"WENO5-Z rhs + 1-step parity: {name}")
+    s = Solver(case)
+    U = s.init(W)
+    R = s.rhs(U).cpu().numpy()
+    Uo = oracle.state_init(case, W)
+    Ro = oracle.rhs(case, Uo)
+    bound = oracle.rhs_rounding_bound(case, Uo)
+    for v in range(5):
+        err = float(np.max(np.abs(R[v] - Ro[v])))
+        assert err <= max(TOL_ONE * float(np.max(np.abs(Ro[v]))), bound[v]), (name, v, err, bound[v])
+    # WENO5-Z differs from WENO5-JS wherever the data are not smooth
+    Rjs = oracle.rhs(CASES[name][0], Uo)
+    assert np.max(np.abs(Rjs - Ro)) > 0.0
+    dt_gpu = s.step(U)
+    Uo1, dto = oracle.rk3_step(case, Uo)
+    assert abs(float(dt_gpu.item()) - dto) <= 1e-14 * dto
+    e = normwise(U.cpu().numpy(), Uo1)
+    s.close()
+    assert e <= TOL_ONE, (name, e)
+
+
+@pytest.mark.parametrize("name,shape", [("tgv", (24, 20, 18)), ("lax", (100, 1, 1))])
+def test_wenoz_many_steps_match_oracle(Solver, name, shape):
+    if name == "tgv":
+        case, W = _z(wl.taylor_green(0, shape=shape))
+        nsteps, t_end = 100, 0.0
+    else:
+        case, W = _z(wl.lax(shape[0]))
+        nsteps, t_end = 300, 0.14
+    _say(f"WENO5-Z multi-step parity: {name} {shape}")
+    s = Solver(case)
+    U = s.init(W)
+    t = s.advance(U, nsteps, t_end=t_end) if t_end > 0 else s.advance(U, nsteps)
+    Uo, to, _ = oracle.advance(case, oracle.state_init(case, W), nsteps, t_end=t_end)
+    assert abs(float(t.item()) - to) <= 1e-12 * to
+    e = normwise(U.cpu().numpy(), Uo)
+    s.close()
+    assert e <= TOL_100, (name, e)
+
+
+def test_wenoz_is_rejected_where_unsupported(Solver):
+    """The adjoint and the serving batch cover WENO5-JS only."""
+    from paper_2203_13760_amd import cfd
+    case, W = _z(wl.random_smooth((12, 10, 8), seed=1, mu=0.01))
+    s = Solver(case)
+    U = s.init(W)
+    with pytest.raises(cfd.CfdError) as e:
+        s.step_adjoint(U, 1e-3, torch.ones_like(U), torch.empty_like(U))
+    assert e.value.code == cfd.CFD_EUNSUPPORTED
+    s.close()
+    b = cfd.cfd_batch_create(4, 1 << 26)
+    try:
+        with pytest.raises(cfd.CfdError) as e:
+            cfd.cfd_batch_add(b, case, torch.from_numpy(W).cuda())
+        assert e.value.code == cfd.CFD_EUNSUPPORTED
+    finally:
+        cfd.cfd_batch_destroy(b)

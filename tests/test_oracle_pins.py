@@ -8,7 +8,7 @@ dropped term, a wrong sign or index, a transposed operand, a wrong coefficient.
   P4  free-stream preservation, bitwise
   P5  dissipative operator against closed forms (§2 stresses/heat flux, §3.4 stencils)
   P6  HLLC special cases (consistency, upwinding, stationary contact, symmetry)
-  P7  WENO5-JS special cases (constants, exact on quadratics, ENO at a jump)
+  P7  WENO5-JS and WENO5-Z special cases (constants, exact on quadratics, ENO at a jump)
   P8  TVD-RK3 third order in time (§3.2)
   P9  the taped reverse-mode derivative against central finite differences
 """
@@ -79,6 +79,32 @@ def test_sod_shock_tube_against_exact_solution():
             assert np.all(np.abs(rho[x < 0.1] - 1.0) < 1e-10)
             assert np.all(np.abs(rho[x > 0.95] - 0.125) < 1e-10)
     assert l1[200] <= 5e-3
+    assert l1[100] > l1[200] > l1[400]
+
+
+def test_lax_shock_tube_against_exact_solution():
+    """Lax's shock tube at t = 0.14 (§5.1.2, N = 100 on [0,1] in the paper):
+    the density error against the exact solution falls with the grid, the
+    plateau between contact and shock sits at the exact star density, and
+    the undisturbed ends are untouched."""
+    e = ExactRiemann((0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
+    l1 = {}
+    for n in (100, 200, 400):
+        case, W = wl.lax(n)
+        U = oracle.state_init(case, W)
+        U, t, steps = oracle.advance(case, U, 100000, t_end=case["t_end"])
+        assert abs(t - 0.14) < 1e-14
+        Ui = oracle.interior(case, U).reshape(5, n)
+        rho = Ui[0]
+        ra, _, _ = e.cell_average_profile(n, 0.14)
+        l1[n] = float(np.mean(np.abs(rho - ra)))
+        x = (np.arange(n) + 0.5) / n
+        if n == 400:
+            # contact at 0.714, shock at 0.847
+            m = (x > 0.74) & (x < 0.83)
+            assert np.max(np.abs(rho[m] - e.rho_star_R)) < 2e-2
+            assert np.all(np.abs(rho[x > 0.95] - 0.5) < 1e-10)
+    assert l1[100] <= 0.015
     assert l1[100] > l1[200] > l1[400]
 
 
@@ -280,6 +306,62 @@ def test_weno5_special_cases():
         avg = [(-np.cos(2 * (m + 0.5) * h) + np.cos(2 * (m - 0.5) * h)) / (2 * h) for m in (-2, -1, 0, 1, 2)]
         lin = (2 * avg[0] - 13 * avg[1] + 47 * avg[2] + 27 * avg[3] - 3 * avg[4]) / 60
         assert abs(oracle.weno5(*avg) - lin) < 50 * h ** 4
+
+
+def test_weno5z_special_cases():
+    """WENO5-Z (Borges et al. 2008): the same candidates as WENO5-JS, so the
+    same exactness on constants and quadratics and the same ENO property; on
+    smooth data its weights lie closer to the linear ones, so it sits closer
+    to the fifth-order linear combination than WENO5-JS (an order of h
+    better: the weights deviate by O(h^3) instead of O(h^2) at a smooth
+    extremum-free point)."""
+    # (the weights stay the linear ones here, so only the candidates' rounding remains)
+    for c in (0.0, 1.0, -3.7, 1e5, 2.5e-3):
+        assert abs(oracle.weno5z(c, c, c, c, c) - c) <= 4 * np.spacing(abs(c) + 1e-300)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        a0, a1, a2 = rng.uniform(-1, 1, 3)
+        h = rng.uniform(0.05, 1.0)
+        P = lambda x: a0 * x + a1 * x ** 2 / 2 + a2 * x ** 3 / 3
+        q = lambda x: a0 + a1 * x + a2 * x ** 2
+        avg = [(P((m + 0.5) * h) - P((m - 0.5) * h)) / h for m in (-2, -1, 0, 1, 2)]
+        assert abs(oracle.weno5z(*avg) - q(0.5 * h)) < 1e-12
+    assert abs(oracle.weno5z(0, 0, 0, 1, 1)) < 1e-10
+    assert abs(oracle.weno5z(1, 1, 1, 0, 0) - 1) < 1e-10
+    dz, djs = [], []
+    for h in (0.1, 0.05, 0.025):
+        avg = [(-np.cos(2 * (m + 0.5) * h + 0.3) + np.cos(2 * (m - 0.5) * h + 0.3)) / (2 * h)
+               for m in (-2, -1, 0, 1, 2)]
+        lin = (2 * avg[0] - 13 * avg[1] + 47 * avg[2] + 27 * avg[3] - 3 * avg[4]) / 60
+        dz.append(abs(oracle.weno5z(*avg) - lin))
+        djs.append(abs(oracle.weno5(*avg) - lin))
+    assert all(z < j for z, j in zip(dz, djs)), (dz, djs)
+    assert math.log2(dz[1] / dz[2]) > math.log2(djs[1] / djs[2]) + 0.5, (dz, djs)
+
+
+def test_weno5z_entropy_wave_fifth_order_and_shock_tubes():
+    """WENO5-Z through the whole oracle: fifth order on the entropy wave, and
+    Sod and Lax against their exact solutions."""
+    errs = []
+    for n in (20, 40, 80, 160):
+        case, W = wl.entropy_wave(n)
+        case["flags"] |= wl.WENOZ
+        U0 = oracle.state_init(case, W)
+        U, t, _ = oracle.advance(case, U0, 10 ** 7, t_end=1.0, fixed_dt=1e-4)
+        errs.append(float(np.mean(np.abs(oracle.interior(case, U)[0] - oracle.interior(case, U0)[0]))))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert order[-1] >= 4.7, order
+    for make, left, right, t_end in ((wl.sod, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.2),
+                                      (wl.lax, (0.445, 0.698, 3.528), (0.5, 0.0, 0.571), 0.14)):
+        e = ExactRiemann(left, right)
+        l1 = []
+        for n in (100, 200):
+            case, W = make(n)
+            case["flags"] |= wl.WENOZ
+            U, t, _ = oracle.advance(case, oracle.state_init(case, W), 100000, t_end=t_end)
+            rho = oracle.interior(case, U).reshape(5, n)[0]
+            l1.append(float(np.mean(np.abs(rho - e.cell_average_profile(n, t_end)[0]))))
+        assert l1[0] > l1[1] and l1[0] < 0.015, (make.__name__, l1)
 
 
 # ---------------------------------------------------------------- O1/O2 ----
