@@ -128,9 +128,7 @@ __host__ __device__ __forceinline__ int halo_blocks(const Geom& g) {
   return (int)(n > 0 ? (n + kBlock - 1) / kBlock : 1);
 }
 
-__global__ void __launch_bounds__(kBlock) k_prim_halo(double* P, Geom g, const double* dtp) {
-  if (step_disabled(dtp)) return;
-  long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void prim_halo_body(double* P, const Geom& g, long long t) {
   int i, j, k;  // interior-relative coordinates of the halo cell
   const long long zs = 2LL * g.h[2] * g.N[0] * g.N[1];
   const long long ys = 2LL * g.h[1] * g.N[0] * g.n[2];
@@ -165,6 +163,11 @@ __global__ void __launch_bounds__(kBlock) k_prim_halo(double* P, Geom g, const d
   const long long c = cell_at(g, i, j, k), s = cell_at(g, si, sj, sk);
 #pragma unroll
   for (int v = 0; v < 6; ++v) P[v * g.vs + c] = P[v * g.vs + s];
+}
+
+__global__ void __launch_bounds__(kBlock) k_prim_halo(double* P, Geom g, const double* dtp) {
+  if (step_disabled(dtp)) return;
+  prim_halo_body(P, g, (long long)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // Conservative interior state from primitive point values W (5 x interior, no halo).
