@@ -63,6 +63,12 @@ def _load():
     lib.oracle_weno5z.restype = d
     lib.oracle_hllc.argtypes = [d, dp, dp, C.c_int, dp]
     lib.oracle_hllc.restype = None
+    lib.oracle_roe_eigen.argtypes = [d, dp, dp, C.c_int, dp, dp, dp]
+    lib.oracle_roe_eigen.restype = None
+    lib.oracle_roe_flux.argtypes = [d, dp, C.c_int, dp]
+    lib.oracle_roe_flux.restype = None
+    lib.oracle_euler_flux.argtypes = [d, dp, C.c_int, dp]
+    lib.oracle_euler_flux.restype = None
     lib.oracle_opcount.argtypes = [cfgp, dp, dp]
     lib.oracle_opcount_parts.argtypes = [cfgp, dp, dp]
     lib.oracle_vjp_rhs.argtypes = [cfgp, dp, dp, dp]
@@ -190,6 +196,34 @@ def hllc(gamma, WL, WR, axis):
     WR = np.ascontiguousarray(WR, dtype=np.float64)
     F = np.zeros(5)
     lib.oracle_hllc(float(gamma), _ptr(WL), _ptr(WR), int(axis), _ptr(F))
+    return F
+
+
+def roe_eigen(gamma, wl, wr, axis):
+    """Roe average of primitive states wl | wr along `axis`: (R, L, lam) with
+    the right eigenvectors as the columns of R, L = R^-1 (by elimination)."""
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    R = np.zeros(25)
+    L = np.zeros(25)
+    lam = np.zeros(5)
+    _load().oracle_roe_eigen(float(gamma), _ptr(wl), _ptr(wr), int(axis), _ptr(R), _ptr(L), _ptr(lam))
+    return R.reshape(5, 5), L.reshape(5, 5), lam
+
+
+def roe_flux(gamma, w6, axis):
+    """Roe flux-splitting convective flux at the face between the third and
+    fourth of six primitive states w6 (6 x 5)."""
+    w6 = np.ascontiguousarray(w6, dtype=np.float64).reshape(30)
+    F = np.zeros(5)
+    _load().oracle_roe_flux(float(gamma), _ptr(w6), int(axis), _ptr(F))
+    return F
+
+
+def euler_flux(gamma, w, axis):
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    F = np.zeros(5)
+    _load().oracle_euler_flux(float(gamma), _ptr(w), int(axis), _ptr(F))
     return F
 
 

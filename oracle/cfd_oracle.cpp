@@ -35,14 +35,15 @@ typedef struct {
   double prandtl;      // Prandtl number (> 0)
   double cfl;          // CFL number
   int32_t bc[6];       // x-, x+, y-, y+, z-, z+ : 0 periodic, 1 zero gradient
-  uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux, 8 WENO5-Z reconstruction
+  uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux, 8 WENO5-Z reconstruction,
+                       // 16 Roe flux splitting in characteristic space (the paper's ROE setup)
 } oracle_cfg;
 }
 
 namespace oracle {
 
 enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
-enum : uint32_t { F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u, F_WENOZ = 8u };
+enum : uint32_t { F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u, F_WENOZ = 8u, F_ROE = 16u };
 
 // --------------------------------------------------------------------------
 // Grid: cell (i,j,k), interior indices 0..n-1, halo indices -nh..-1, n..n+nh-1.
@@ -243,6 +244,139 @@ void hllc_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]) {
 }
 
 // --------------------------------------------------------------------------
+// Flux-splitting approach of §3.3 (the paper's ROE setup of §5: Roe average,
+// WENO5-JS flux reconstruction in characteristic space). For the face between
+// cells i and i+1 along axis d, in the order the paper lists the steps:
+//   1. the Roe average (Roe 1981; Toro 2009, §11.2) of cells i and i+1:
+//      sqrt(rho)-weighted velocity and total enthalpy H = (E + p)/rho,
+//      a^2 = (gamma - 1)(H - |u|^2/2);
+//   2. the eigen-decomposition A = R Lambda R^-1 of the Euler flux Jacobian
+//      along d at that state: eigenvalues u_d - a, u_d (three times), u_d + a
+//      and the right eigenvectors of Toro 2009, §3.2, with the shear waves
+//      carrying the unit vectors of the two tangential axes; R^-1 is formed
+//      here by Gauss-Jordan elimination of R (not from its closed form);
+//   3. V_j = R^-1 U_j and G_j = R^-1 F_j for the six stencil cells
+//      j = i-2 .. i+3, F the Euler flux along d;
+//   4. G+-_j = (G_j +- |Lambda| V_j) / 2: the Roe splitting takes the moduli of
+//      the face's eigenvalues (reading: no entropy fix);
+//   5. WENO5-JS of G+ over cells i-2..i+2 and of G- over cells i+3..i-1
+//      (mirrored), characteristic field by field;
+//   6. G_face = G+ + G-;
+//   7. F_face = R G_face.
+template <class R>
+void euler_flux(double gamma, const R w[5], int d, R F[5]) {
+  const R rho = w[0], un = w[1 + d], p = w[4];
+  const R E = p / (gamma - 1.0) + 0.5 * rho * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+  F[0] = rho * un;
+  for (int a = 0; a < 3; ++a) F[1 + a] = rho * un * w[1 + a] + (a == d ? p : R(0.0));
+  F[4] = un * (E + p);
+}
+
+template <class R>
+void conservative(double gamma, const R w[5], R U[5]) {
+  U[0] = w[0];
+  for (int a = 0; a < 3; ++a) U[1 + a] = w[0] * w[1 + a];
+  U[4] = w[4] / (gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+}
+
+// Steps 1 and 2 for primitive states wl (cell i) and wr (cell i+1): right
+// eigenvectors as the columns of Rm (row-major 5x5), Lm = Rm^-1, eigenvalues lam.
+template <class R>
+void roe_eigen(double gamma, const R wl[5], const R wr[5], int d, R Rm[25], R Lm[25], R lam[5]) {
+  const R sl = sqrt_(wl[0]), sr = sqrt_(wr[0]);
+  const R Hl = (gamma / (gamma - 1.0)) * wl[4] / wl[0] + 0.5 * (wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
+  const R Hr = (gamma / (gamma - 1.0)) * wr[4] / wr[0] + 0.5 * (wr[1] * wr[1] + wr[2] * wr[2] + wr[3] * wr[3]);
+  R u[3];
+  for (int a = 0; a < 3; ++a) u[a] = (sl * wl[1 + a] + sr * wr[1 + a]) / (sl + sr);
+  const R H = (sl * Hl + sr * Hr) / (sl + sr);
+  const R q2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const R c = sqrt_((gamma - 1.0) * (H - 0.5 * q2));
+  const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+  // columns: acoustic (u_d - a), entropy, shear t1, shear t2, acoustic (u_d + a)
+  R col[5][5];
+  col[0][0] = R(1.0);
+  col[1][0] = R(1.0);
+  col[2][0] = R(0.0);
+  col[3][0] = R(0.0);
+  col[4][0] = R(1.0);
+  for (int a = 0; a < 3; ++a) {
+    const R n = R(a == d ? 1.0 : 0.0);
+    col[0][1 + a] = u[a] - c * n;
+    col[1][1 + a] = u[a];
+    col[2][1 + a] = R(a == t1 ? 1.0 : 0.0);
+    col[3][1 + a] = R(a == t2 ? 1.0 : 0.0);
+    col[4][1 + a] = u[a] + c * n;
+  }
+  col[0][4] = H - u[d] * c;
+  col[1][4] = 0.5 * q2;
+  col[2][4] = u[t1];
+  col[3][4] = u[t2];
+  col[4][4] = H + u[d] * c;
+  for (int r = 0; r < 5; ++r)
+    for (int k = 0; k < 5; ++k) Rm[r * 5 + k] = col[k][r];
+  lam[0] = u[d] - c;
+  lam[1] = u[d];
+  lam[2] = u[d];
+  lam[3] = u[d];
+  lam[4] = u[d] + c;
+  // Gauss-Jordan elimination with partial pivoting on [Rm | I]
+  R A[5][10];
+  for (int r = 0; r < 5; ++r)
+    for (int k = 0; k < 10; ++k) A[r][k] = k < 5 ? Rm[r * 5 + k] : R(k - 5 == r ? 1.0 : 0.0);
+  for (int k = 0; k < 5; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < 5; ++r)
+      if (std::fabs(val(A[r][k])) > std::fabs(val(A[piv][k]))) piv = r;
+    if (piv != k)
+      for (int m = 0; m < 10; ++m) std::swap(A[k][m], A[piv][m]);
+    const R inv = 1.0 / A[k][k];
+    for (int m = 0; m < 10; ++m) A[k][m] = A[k][m] * inv;
+    for (int r = 0; r < 5; ++r) {
+      if (r == k) continue;
+      const R f = A[r][k];
+      for (int m = 0; m < 10; ++m) A[r][m] = A[r][m] - f * A[k][m];
+    }
+  }
+  for (int r = 0; r < 5; ++r)
+    for (int k = 0; k < 5; ++k) Lm[r * 5 + k] = A[r][5 + k];
+}
+
+// Convective flux by Roe flux splitting from the primitive states of the six
+// stencil cells w[0..5] = cells i-2 .. i+3 (steps 1-7 above).
+template <class R>
+void roe_split_flux(double gamma, const R w[6][5], int d, R F[5]) {
+  R Rm[25], Lm[25], lam[5];
+  roe_eigen(gamma, w[2], w[3], d, Rm, Lm, lam);
+  R Gp[6][5], Gm[6][5];
+  for (int j = 0; j < 6; ++j) {
+    R U[5], Fj[5];
+    conservative(gamma, w[j], U);
+    euler_flux(gamma, w[j], d, Fj);
+    for (int k = 0; k < 5; ++k) {
+      R V = R(0.0), G = R(0.0);
+      for (int m = 0; m < 5; ++m) {
+        V = V + Lm[k * 5 + m] * U[m];
+        G = G + Lm[k * 5 + m] * Fj[m];
+      }
+      const R al = abs_(lam[k]);
+      Gp[j][k] = 0.5 * (G + al * V);
+      Gm[j][k] = 0.5 * (G - al * V);
+    }
+  }
+  R Gf[5];
+  for (int k = 0; k < 5; ++k) {
+    const R plus = weno5_js(Gp[0][k], Gp[1][k], Gp[2][k], Gp[3][k], Gp[4][k]);
+    const R minus = weno5_js(Gm[5][k], Gm[4][k], Gm[3][k], Gm[2][k], Gm[1][k]);
+    Gf[k] = plus + minus;
+  }
+  for (int r = 0; r < 5; ++r) {
+    R acc = R(0.0);
+    for (int k = 0; k < 5; ++k) acc = acc + Rm[r * 5 + k] * Gf[k];
+    F[r] = acc;
+  }
+}
+
+// --------------------------------------------------------------------------
 // Dissipative flux at the face between cells i and i+1 along axis d
 // (§2: stresses tau with the Stokes hypothesis, Fourier heat flux q = -lambda
 // grad T; §3.4: fourth-order central differences).
@@ -327,7 +461,12 @@ void face_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d, con
                bool inviscid, bool viscous, bool heat, R G[5]) {
   const std::vector<R>* q[5] = {&W.rho, &W.u[0], &W.u[1], &W.u[2], &W.p};
   R Fc[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
-  if (inviscid) {
+  if (inviscid && (c.flags & F_ROE)) {
+    R w[6][5];
+    for (int j = 0; j < 6; ++j)
+      for (int v = 0; v < 5; ++v) w[j][v] = (*q[v])[g.shift(d, a[0], a[1], a[2], j - 2)];
+    roe_split_flux(c.gamma, w, d, Fc);
+  } else if (inviscid) {
     R WL[5], WR[5];
     for (int v = 0; v < 5; ++v) {
       const std::vector<R>& s = *q[v];
@@ -585,6 +724,22 @@ double oracle_weno5z(double a, double b, double c, double d, double e) {
 void oracle_hllc(double gamma, const double* WL, const double* WR, int d, double* F) {
   hllc_flux(gamma, WL, WR, d, F);
 }
+// Roe average and eigen-decomposition between primitive states wl, wr
+// (rho, u, v, w, p) along axis d: Rm, Lm row-major 5x5, lam[5].
+void oracle_roe_eigen(double gamma, const double* wl, const double* wr, int d, double* Rm, double* Lm,
+                      double* lam) {
+  roe_eigen(gamma, wl, wr, d, Rm, Lm, lam);
+}
+// Roe flux-splitting convective flux from six primitive states w (6 x 5,
+// cells i-2 .. i+3) at the face between the third and the fourth.
+void oracle_roe_flux(double gamma, const double* w, int d, double* F) {
+  double ww[6][5];
+  for (int j = 0; j < 6; ++j)
+    for (int v = 0; v < 5; ++v) ww[j][v] = w[j * 5 + v];
+  roe_split_flux(gamma, ww, d, F);
+}
+// Euler flux along axis d of one primitive state.
+void oracle_euler_flux(double gamma, const double* w, int d, double* F) { euler_flux(gamma, w, d, F); }
 
 // Operation counts of one right-hand-side evaluation of state U:
 // out = {add, mul, div, sqrt, cmp}.

@@ -21,6 +21,7 @@ PERIODIC = 0
 ZERO_GRADIENT = 1
 INVISCID, VISCOUS, HEAT = 1, 2, 4
 WENOZ = 8
+ROE = 16  # flux splitting in characteristic space with Roe eigenvalues (the ROE setup)
 ALL_PHYSICS = INVISCID | VISCOUS | HEAT
 
 

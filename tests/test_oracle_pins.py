@@ -364,6 +364,117 @@ def test_weno5z_entropy_wave_fifth_order_and_shock_tubes():
         assert l1[0] > l1[1] and l1[0] < 0.015, (make.__name__, l1)
 
 
+# ---------------------------------------------------------------- ROE ------
+def _cons(w, g=1.4):
+    return np.array([w[0], w[0] * w[1], w[0] * w[2], w[0] * w[3],
+                     w[4] / (g - 1) + 0.5 * w[0] * (w[1] ** 2 + w[2] ** 2 + w[3] ** 2)])
+
+
+def _prim(U, g=1.4):
+    u = U[1:4] / U[0]
+    return np.array([U[0], *u, (g - 1) * (U[4] - 0.5 * U[0] * np.dot(u, u))])
+
+
+def test_roe_decomposition_pins():
+    """The Roe matrix A = R Lambda R^-1 (§3.3 flux splitting, step 2): R^-1 R = I;
+    the eigenvalues are u_d - a, u_d, u_d, u_d, u_d + a; A (U_R - U_L) =
+    F(U_R) - F(U_L) exactly for any two states (Roe's defining property); for
+    equal states A is the flux Jacobian (central differences of the Euler flux
+    in the conservative variables)."""
+    rng = np.random.default_rng(7)
+    g = 1.4
+    for t in range(60):
+        d = t % 3
+        wl = np.array([rng.uniform(0.2, 3), *rng.uniform(-2, 2, 3), rng.uniform(0.1, 4)])
+        wr = np.array([rng.uniform(0.2, 3), *rng.uniform(-2, 2, 3), rng.uniform(0.1, 4)])
+        R, L, lam = oracle.roe_eigen(g, wl, wr, d)
+        assert np.allclose(L @ R, np.eye(5), rtol=0, atol=1e-12)
+        # eigenvalues from the Roe-averaged state, computed here independently
+        sl, sr = np.sqrt(wl[0]), np.sqrt(wr[0])
+        Hl = g / (g - 1) * wl[4] / wl[0] + 0.5 * np.dot(wl[1:4], wl[1:4])
+        Hr = g / (g - 1) * wr[4] / wr[0] + 0.5 * np.dot(wr[1:4], wr[1:4])
+        u = (sl * wl[1:4] + sr * wr[1:4]) / (sl + sr)
+        H = (sl * Hl + sr * Hr) / (sl + sr)
+        a = np.sqrt((g - 1) * (H - 0.5 * np.dot(u, u)))
+        assert np.allclose(lam, [u[d] - a, u[d], u[d], u[d], u[d] + a], rtol=0, atol=1e-13)
+        A = R @ np.diag(lam) @ L
+        dU = _cons(wr) - _cons(wl)
+        dF = oracle.euler_flux(g, wr, d) - oracle.euler_flux(g, wl, d)
+        assert np.max(np.abs(A @ dU - dF)) <= 1e-12 * np.max(np.abs(dF)), t
+        # equal states: the Jacobian dF/dU by central differences
+        R0, L0, lam0 = oracle.roe_eigen(g, wl, wl, d)
+        A0 = R0 @ np.diag(lam0) @ L0
+        U0 = _cons(wl)
+        J = np.empty((5, 5))
+        for k in range(5):
+            h = 1e-6 * max(1.0, abs(U0[k]))
+            e = np.zeros(5)
+            e[k] = h
+            J[:, k] = (oracle.euler_flux(g, _prim(U0 + e), d) - oracle.euler_flux(g, _prim(U0 - e), d)) / (2 * h)
+        assert np.allclose(A0, J, rtol=1e-7, atol=1e-7), t
+
+
+def test_roe_flux_special_cases():
+    """A constant stencil gives the exact Euler flux; mirroring the stencil and
+    flipping the normal velocity flips the mass and energy flux (reflection
+    symmetry of the split scheme)."""
+    rng = np.random.default_rng(8)
+    g = 1.4
+    for d in range(3):
+        w = np.array([1.3, 0.4, -0.7, 0.2, 2.1])
+        F = oracle.roe_flux(g, np.tile(w, (6, 1)), d)
+        assert np.allclose(F, oracle.euler_flux(g, w, d), rtol=1e-14, atol=1e-14)
+        w6 = np.column_stack([rng.uniform(0.3, 2, 6), rng.uniform(-1, 1, (6, 3)), rng.uniform(0.3, 2, 6)])
+        m6 = w6[::-1].copy()
+        m6[:, 1 + d] *= -1.0
+        F1 = oracle.roe_flux(g, w6, d)
+        F2 = oracle.roe_flux(g, m6, d)
+        sign = np.ones(5)
+        sign[[0, 4]] = -1.0
+        t = [a for a in range(3) if a != d]
+        sign[1 + t[0]] = sign[1 + t[1]] = -1.0
+        assert np.allclose(F2, sign * F1, rtol=1e-11, atol=1e-12), (d, F1, F2)
+
+
+def test_roe_setup_through_the_oracle():
+    """The ROE setup through the whole oracle: fifth order on the entropy wave,
+    Sod and Lax against their exact solutions, conservation on a periodic grid
+    and bitwise free-stream preservation."""
+    errs = []
+    for n in (20, 40, 80, 160):
+        case, W = wl.entropy_wave(n)
+        case["flags"] |= wl.ROE
+        U0 = oracle.state_init(case, W)
+        U, t, _ = oracle.advance(case, U0, 10 ** 7, t_end=1.0, fixed_dt=1e-4)
+        errs.append(float(np.mean(np.abs(oracle.interior(case, U)[0] - oracle.interior(case, U0)[0]))))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert order[-1] >= 4.7, order
+    for make, left, right, t_end in ((wl.sod, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.2),
+                                      (wl.lax, (0.445, 0.698, 3.528), (0.5, 0.0, 0.571), 0.14)):
+        e = ExactRiemann(left, right)
+        l1 = []
+        for n in (100, 200, 400):
+            case, W = make(n)
+            case["flags"] |= wl.ROE
+            U, t, _ = oracle.advance(case, oracle.state_init(case, W), 100000, t_end=t_end)
+            rho = oracle.interior(case, U).reshape(5, n)[0]
+            l1.append(float(np.mean(np.abs(rho - e.cell_average_profile(n, t_end)[0]))))
+        assert l1[0] > l1[1] > l1[2] and l1[0] < 0.015, (make.__name__, l1)
+    case, W = wl.taylor_green(0, shape=(12, 10, 8))
+    case["flags"] |= wl.ROE
+    R = oracle.interior(case, oracle.rhs(case, oracle.state_init(case, W)))
+    for v in range(5):
+        s = math.fsum(R[v].ravel().tolist())
+        assert abs(s) <= 1e-13 * np.abs(R[v]).sum() + 1e-300, (v, s)
+    for bc in (wl.PERIODIC, wl.ZERO_GRADIENT):
+        case = wl.make_case((9, 7, 6), bc=(bc,) * 6, mu=0.05, flags=wl.ALL_PHYSICS | wl.ROE)
+        W = np.empty((5, 6, 7, 9))
+        for v, val in enumerate((1.3, 0.3, -0.2, 0.1, 0.8)):
+            W[v] = val
+        U = oracle.state_init(case, W)
+        assert np.all(oracle.rhs(case, U) == 0.0)
+
+
 # ---------------------------------------------------------------- O1/O2 ----
 @pytest.mark.parametrize("bc", [wl.PERIODIC, wl.ZERO_GRADIENT])
 def test_halo_fill_matches_independent_padding(bc):
