@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--adj-n", type=int, default=128)
     ap.add_argument("--adj-steps", type=int, default=200)
+    ap.add_argument("--no-roe", action="store_true", help="skip the ROE setup leg")
+    ap.add_argument("--roe-steps", type=int, default=10)
     ap.add_argument("--serving", action="store_true",
                     help="run the serving benchmark (batched vs one at a time) instead")
     ap.add_argument("--serving-requests", type=int, default=400)
@@ -177,6 +179,39 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
             "step_ms": fwd, "step_adjoint_ms": adj, "adjoint_over_step": adj / fwd,
             "gradient_steps": nsteps, "checkpoint_every": ckpt_every, "gradient_s": tgrad,
             "loss": float(L.item()), "grad_norm": gnorm, "shock_gradient": sg}
+
+
+def roe_leg(case, W, steps, reps, hllc_ms_per_step):
+    """The paper's ROE setup (Roe flux splitting, WENO5-JS in characteristic
+    space) on the same field and grid: CFL steps per second and the stage
+    kernels' durations."""
+    import torch
+    from paper_2203_13760_amd import cfd
+    from paper_2203_13760_amd import workloads as wl
+    from paper_2203_13760_amd.solver import Solver
+    case = dict(case)
+    case["flags"] = case["flags"] | wl.ROE
+    n = case["n"][0]
+    s = Solver(case)
+    try:
+        U = s.init(W)
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        s.advance(U, 2, t=t)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(U, steps, t=t)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ms = cfd.cfd_profile_stage(s.h, U, reps)
+        health = s.check()
+    finally:
+        s.close()
+    ms_per_step = sec / steps * 1e3
+    return {"value": n ** 3 * steps / sec / 1e6, "unit": "Mcell-updates/s", "steps": steps,
+            "ms_per_step": ms_per_step, "over_hllc": ms_per_step / hllc_ms_per_step,
+            "kernel_ms": {k: round(v, 4) for k, v in zip(KERNELS, ms)}, "health": health,
+            "paper_context": {"value": 1000.0 / 760.09, "unit": "Mcell-updates/s",
+                              "workload": "256^3, ROE float64, JAX on one RTX A6000 (8.2 x its HLLC step)"}}
 
 
 def serving_bench(args):
@@ -302,6 +337,13 @@ def main():
     del U
     torch.cuda.empty_cache()
 
+    roe = None
+    if not args.no_roe:
+        roe = roe_leg(case, W, args.roe_steps, args.reps, ms_per_step)
+        print(f"bench: ROE setup {roe['value']:.1f} Mcell-updates/s, {roe['ms_per_step']:.3f} ms per step "
+              f"({roe['over_hllc']:.2f} x the HLLC step)", flush=True)
+        torch.cuda.empty_cache()
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = differentiation(args.adj_n, args.adj_steps)
@@ -337,6 +379,7 @@ def main():
         "fused_min_traffic_GBps": 320.0 * value * 1e6 / 1e9,
         "cpu_baseline": cpu,
         "differentiation": adjoint,
+        "roe_setup": roe,
         "paper_context": {"value": 1000.0 / 92.76, "unit": "Mcell-updates/s",
                           "workload": "Taylor-Green vortex 256^3, HLLC float64, JAX on one RTX A6000"},
         "health": health,

@@ -48,10 +48,17 @@ typedef enum {
 typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1 } cfd_bc;
 
 /* Physics switches, after the paper's is_inviscid_flux / is_viscous_flux /
- * is_heat_flux (Appendix A), and the reconstruction: WENO5-JS by default,
- * WENO5-Z (Borges et al. 2008; listed beside WENO5-JS in the paper's table of
- * methods, §3.3) with CFD_F_WENOZ. The adjoint covers WENO5-JS only. */
-enum { CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u, CFD_F_WENOZ = 8u };
+ * is_heat_flux (Appendix A), and the convective scheme. By default the
+ * high-order Godunov approach of §3.3 with WENO5-JS on the primitives and
+ * HLLC (the paper's HLLC setup, §5); CFD_F_WENOZ reconstructs with WENO5-Z
+ * instead (Borges et al. 2008; listed beside WENO5-JS in the paper's table of
+ * methods, §3.3). CFD_F_ROE selects the flux-splitting approach of §3.3 with
+ * the paper's ROE setup (§5): Roe-averaged eigen-decomposition at each face,
+ * the stencil's states and fluxes projected on its characteristic fields,
+ * split with the moduli of the Roe eigenvalues (no entropy fix), WENO5-JS per
+ * field, transformed back. CFD_F_ROE with CFD_F_WENOZ is CFD_EINVAL. The
+ * adjoint and the serving batch cover the default scheme only. */
+enum { CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u, CFD_F_WENOZ = 8u, CFD_F_ROE = 16u };
 
 typedef struct {
   int32_t n[3];      /* interior cells (x,y,z); n[d] == 1 marks an inactive axis */
@@ -125,14 +132,14 @@ cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double d
  * (interior cells of Rbar are read; its halo is ignored). The transposed halo
  * fill folds halo contributions back into their source cells, so the halo
  * entries of Ubar are left unchanged. U is not modified. CFD_EUNSUPPORTED for
- * a WENO5-Z configuration. */
+ * a WENO5-Z or ROE configuration. */
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar,
                            void* stream);
 
 /* Discrete adjoint of one fixed-dt TVD-RK3 step: with U^{n+1} = S(U^n),
  * Ubar_n = (dS/dU^n)^T Ubar_np1 (interior cells; Ubar_n's halo is zeroed).
  * The stage states are recomputed from Un. Ubar_n must not alias the others.
- * CFD_EUNSUPPORTED for a WENO5-Z configuration. */
+ * CFD_EUNSUPPORTED for a WENO5-Z or ROE configuration. */
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream);
 
@@ -180,7 +187,8 @@ cfd_status cfd_batch_footprint(const cfd_config* cfg, int64_t* bytes);
  * conservative initial state from W (device, 5 x interior primitives, as for
  * cfd_state_init). Returns CFD_ENOMEM, with nothing changed, when no slot or
  * arena space is free; the caller retries after removing finished grids.
- * CFD_EUNSUPPORTED for a WENO5-Z configuration (the batch runs WENO5-JS). */
+ * CFD_EUNSUPPORTED for a WENO5-Z or ROE configuration (the batch runs the
+ * default scheme). */
 cfd_status cfd_batch_add(cfd_batch* b, const cfd_config* cfg, const double* W, int32_t* slot_out, void* stream);
 
 /* Retire a grid and free its slot and arena space. The caller must have

@@ -94,7 +94,9 @@ static cfd_status validate(const cfd_config* c) {
   if (!(c->mu >= 0.0)) return fail(CFD_EINVAL, "mu must be >= 0");
   if (!(c->prandtl > 0.0)) return fail(CFD_EINVAL, "prandtl must be > 0");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return fail(CFD_EINVAL, "cfl must lie in (0, 1]");
-  if (c->flags & ~15u) return fail(CFD_EINVAL, "unknown physics flag");
+  if (c->flags & ~31u) return fail(CFD_EINVAL, "unknown physics flag");
+  if ((c->flags & CFD_F_ROE) && (c->flags & CFD_F_WENOZ))
+    return fail(CFD_EINVAL, "the Roe flux splitting reconstructs with WENO5-JS (flag WENOZ with ROE)");
   // index ranges of the kernels: faces per axis and padded planes in 32 bits,
   // padded z extent within the launch grid's y limit
   long long N[3];
@@ -133,6 +135,7 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.visc_rate = 2.0 * std::max(4.0 / 3.0, c.gamma / c.prandtl) * inv2;
   g.inviscid = (c.flags & CFD_F_INVISCID) ? 1 : 0;
   g.wenoz = (c.flags & CFD_F_WENOZ) ? 1 : 0;
+  g.roe = (c.flags & CFD_F_ROE) ? 1 : 0;
   g.viscous = ((c.flags & CFD_F_VISCOUS) && c.mu > 0.0) ? 1 : 0;
   g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
 }
@@ -148,16 +151,16 @@ static cfd_status enqueue_prim(cfd_solver* s, const double* Uk, int what, const 
   return CFD_OK;
 }
 
-template <int D, bool PN, bool WZ>
+template <int D, bool PN, int SCH>
 static void launch_sweep_r(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
   const Geom& g = s->g;
   if (D == 0) {
     const dim3 grid((unsigned)sweep_x_blocks(g));
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL((k_sweep_x<MODE_ACC, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_x<MODE_ACC_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      default: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE, false, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_x<MODE_ACC, false, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_x<MODE_ACC_RK, PN, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE_RK, PN, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
     }
   } else {
     constexpr int AX = D == 0 ? 1 : D;
@@ -165,20 +168,22 @@ static void launch_sweep_r(cfd_solver* s, int mode, const double* P, const Stage
     sweep_march_blocks<AX>(g, gx, gy);
     const dim3 grid(gx, gy);
     switch (mode) {
-      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC, false, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
-      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK, PN, WZ>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_WRITE: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE, false, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC, false, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_march<AX, MODE_ACC_RK, PN, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      default: hipLaunchKernelGGL((k_sweep_march<AX, MODE_WRITE_RK, PN, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
     }
   }
 }
 
-// The reconstruction (WENO5-JS or WENO5-Z) is a template parameter of the
-// sweep kernels; pick the instantiation for the solver's configuration.
+// The convective scheme (WENO5-JS or WENO5-Z with HLLC, or the Roe flux
+// splitting) is a template parameter of the sweep kernels; pick the
+// instantiation for the solver's configuration.
 template <int D, bool PN>
 static void launch_sweep(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
-  if (s->g.wenoz) launch_sweep_r<D, PN, true>(s, mode, P, io, st);
-  else launch_sweep_r<D, PN, false>(s, mode, P, io, st);
+  if (s->g.roe) launch_sweep_r<D, PN, SCH_ROE>(s, mode, P, io, st);
+  else if (s->g.wenoz) launch_sweep_r<D, PN, SCH_Z>(s, mode, P, io, st);
+  else launch_sweep_r<D, PN, SCH_JS>(s, mode, P, io, st);
 }
 
 template <bool PN>
@@ -598,7 +603,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
 
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
   if (!s || !U || !Rbar || !Ubar) return fail(CFD_EINVAL, "NULL argument");
-  if (s->g.wenoz) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS only");
+  if (s->g.wenoz || s->g.roe) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS with HLLC only");
   if (Ubar == U || Ubar == Rbar) return fail(CFD_EINVAL, "Ubar must not alias U or Rbar");
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
@@ -610,7 +615,7 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream) {
   if (!s || !Un || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
-  if (s->g.wenoz) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS only");
+  if (s->g.wenoz || s->g.roe) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS with HLLC only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == Ubar_np1) return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
   cfd_status rc = ensure_adjoint_scratch(s);

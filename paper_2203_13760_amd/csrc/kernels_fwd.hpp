@@ -485,7 +485,7 @@ __device__ __forceinline__ void finish_prims(const StageIO& io, double smax, int
 constexpr int kXCtx = 3;
 constexpr int kXFaces = 64 - (kXCtx + 1);  // faces a wavefront emits
 
-template <int MODE, bool PN = false, bool WZ = false>
+template <int MODE, bool PN = false, int SCH = SCH_JS>
 __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const StageIO& io, const Geom& g,
                                              int bx) {
   // slot numbering fits in 32 bits (checked when the solver is created)
@@ -531,7 +531,7 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
       tf[v] = rc4(t0, t1, t2, d[v]);
     }
     double G[5];
-    face_flux_tf<0, WZ>(g, w, tf, G);
+    face_flux_tf<0, SCH>(g, w, tf, G);
     double Gm[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) Gm[v] = __shfl_up(G[v], 1, 64);
@@ -551,10 +551,10 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
 // Blocks are taken in XCD-major order, so that the neighbouring rows and
 // planes whose velocities the derivative stencils read are being processed in
 // the same XCD and stay in its L2.
-template <int MODE, bool PN, bool WZ>
+template <int MODE, bool PN, int SCH>
 __global__ void __launch_bounds__(kBlock) k_sweep_x(const double* __restrict__ P, StageIO io, Geom g) {
   if (step_disabled(io.dtp)) return;
-  sweep_x_body<MODE, PN, WZ>(P, io, g, xcd_major_block(blockIdx.x, gridDim.x));
+  sweep_x_body<MODE, PN, SCH>(P, io, g, xcd_major_block(blockIdx.x, gridDim.x));
 }
 
 // Blocks of an x sweep.
@@ -572,7 +572,7 @@ constexpr int kSeg = 32;
 // y / z sweep body of one lane. Lanes beyond the grid (a partial last block)
 // march a valid column too but store nothing, so that every lane reaches the
 // block-wide CFL reduction of a sweep that stores next-stage primitives.
-template <int AX, int MODE, bool PN = false, bool WZ = false>
+template <int AX, int MODE, bool PN = false, int SCH = SCH_JS>
 __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const StageIO& io,
                                                  const Geom& g, int bx, int by) {
   constexpr int OT = AX == 1 ? 2 : 1;  // the other transverse axis
@@ -632,7 +632,7 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
     }
     if (kDeferTg) __builtin_amdgcn_sched_barrier(0);
     double G[5];
-    face_flux<AX, WZ>(g, w, G);
+    face_flux<AX, SCH>(g, w, G);
     if (f >= s0 && in) {
       double D[5];
 #pragma unroll
@@ -667,15 +667,18 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
   if (PN) finish_prims(io, smax, bad);
 }
 
-template <int AX, int MODE, bool PN, bool WZ>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_march(const double* __restrict__ P, StageIO io,
-                                                                                             Geom g) {
+// The Roe flux splitting does not fit the marching window in the register
+// budget of two wavefronts per SIMD; its marches run one wavefront per SIMD,
+// which leaves the accumulation registers to the compiler.
+template <int AX, int MODE, bool PN, int SCH>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SCH == SCH_ROE ? 1 : 2)))
+k_sweep_march(const double* __restrict__ P, StageIO io, Geom g) {
   if (step_disabled(io.dtp)) return;
   // XCD-major block order (see k_sweep_x): consecutive column groups, hence
   // neighbouring planes of the transverse derivatives, share an XCD
   const int logical = xcd_major_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
   const int by = logical / gridDim.x;
-  sweep_march_body<AX, MODE, PN, WZ>(P, io, g, logical - by * gridDim.x, by);
+  sweep_march_body<AX, MODE, PN, SCH>(P, io, g, logical - by * gridDim.x, by);
 }
 
 // Launch shape of a marching sweep along AX (x blocks, y blocks).

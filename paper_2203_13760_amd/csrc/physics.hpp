@@ -30,7 +30,14 @@ struct Geom {
   double visc_rate;  // 2 max(4/3, gamma/Pr) sum_d dx_d^-2 (times mu/rho gives the diffusive rate)
   int inviscid, viscous, heat;
   int wenoz;       // WENO5-Z instead of WENO5-JS
+  int roe;         // Roe flux splitting in characteristic space instead of HLLC
 };
+
+// Convective schemes of the sweeps, a compile-time parameter: WENO5-JS or
+// WENO5-Z on the primitives with HLLC (the high-order Godunov approach), or
+// the flux-splitting approach with Roe eigenvalues and WENO5-JS in
+// characteristic space (§3.3; the ROE setup of §5).
+constexpr int SCH_JS = 0, SCH_Z = 1, SCH_ROE = 2;
 
 __host__ __device__ __forceinline__ double sq(double x) { return x * x; }
 
@@ -182,12 +189,14 @@ __host__ __device__ __forceinline__ void face_tangential(const FaceWindow& w, do
 // reconstructed states WL, WR (inviscid part), the window's cells 1..4
 // (velocities and T~ for the fourth-order normal derivatives and the face
 // velocities) and the face values tf of the tangential derivatives.
+// Subtracts the dissipative flux F^d (§3.4) across the face from F: the
+// window's cells 1..4 (velocities and T~ for the fourth-order normal
+// derivatives and the face velocities) and the face values tf of the
+// tangential derivatives.
 template <int D>
-__host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const double* WL, const double* WR,
-                                                      const FaceWindow& w, const double* tf, double* G) {
+__host__ __device__ __forceinline__ void sub_dissipative(const Geom& g, const FaceWindow& w, const double* tf,
+                                                         double* F) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (g.inviscid) hllc<D>(g.gamma, g.gm1i, WL, WR, F);
   if (g.viscous || g.heat) {
     const double i24 = g.idx[D] / 24.0;
     auto dn = [&](double a, double b, double c, double d) { return (a - 27.0 * b + 27.0 * c - d) * i24; };
@@ -216,22 +225,125 @@ __host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const doubl
     F[1 + T2] -= Fd3;
     F[4] -= Fd4;
   }
+}
+
+template <int D>
+__host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const double* WL, const double* WR,
+                                                      const FaceWindow& w, const double* tf, double* G) {
+  double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (g.inviscid) hllc<D>(g.gamma, g.gm1i, WL, WR, F);
+  sub_dissipative<D>(g, w, tf, F);
 #pragma unroll
   for (int v = 0; v < 5; ++v) G[v] = F[v];
 }
 
+// ---------------------------------------------------------------------------
+// Flux-splitting approach of §3.3 with the ROE setup of §5: convective flux
+// across the face between window cells 2 and 3 (primitives q[0..5] = cells
+// f-2 .. f+3). Roe average (sqrt(rho) weights) of cells 2 and 3: velocity u,
+// total enthalpy H, sound speed c, c^2 = (gamma-1)(H - |u|^2/2). With
+// b = (gamma-1)/c^2 and the waves ordered (u_D - c, entropy, shear T1,
+// shear T2, u_D + c), the closed-form left eigenvectors (Toro 2009, §3.2)
+// project cell j (velocity v, pressure p) to
+//   A   = b (rho |v - u|^2 / 2 + p/(gamma-1)),  S = rho (u_D - v_D) / c,
+//   V   = ((A + S)/2, rho - A, rho (v_T1 - u_T1), rho (v_T2 - u_T2), (A - S)/2),
+// and, because the Euler flux is F = v_D U + p (0, e_D, v_D), the projected
+// flux G = v_D V + p (l_D + l_E v_D) with the left eigenvectors' momentum-D
+// and energy entries:
+//   G   = v_D V + p (b (v_D - u_D)/2 - 1/(2c), -b (v_D - u_D), 0, 0, b (v_D - u_D)/2 + 1/(2c)).
+// Each field is split, G+- = (G +- |lambda| V)/2, reconstructed with WENO5-JS
+// (G+ from cells 0..4, G- mirrored from cells 5..1), summed, and transformed
+// back with the right eigenvectors (columns (1, u - c e_D, H - u_D c),
+// (1, u, |u|^2/2), (0, e_T1, u_T1), (0, e_T2, u_T2), (1, u + c e_D, H + u_D c)).
+// No entropy fix (the splitting uses the moduli of the Roe eigenvalues as they are).
+template <int D>
+__host__ __device__ __forceinline__ void roe_flux(const Geom& g, const double (&q)[6][5], double* F) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const double gm1 = g.gamma - 1.0;
+  const double sl = sqrt(q[2][0]), sr = sqrt(q[3][0]);
+  const double isum = 1.0 / (sl + sr);
+  const double al = sl * isum, ar = sr * isum;
+  const double uD = al * q[2][1 + D] + ar * q[3][1 + D];
+  const double u1 = al * q[2][1 + T1] + ar * q[3][1 + T1];
+  const double u2 = al * q[2][1 + T2] + ar * q[3][1 + T2];
+  const double kl = 0.5 * (q[2][1] * q[2][1] + q[2][2] * q[2][2] + q[2][3] * q[2][3]);
+  const double kr = 0.5 * (q[3][1] * q[3][1] + q[3][2] * q[3][2] + q[3][3] * q[3][3]);
+  const double hp = g.gamma * g.gm1i;  // gamma/(gamma-1): H = hp p/rho + |v|^2/2
+  const double H = al * (hp * q[2][4] / q[2][0] + kl) + ar * (hp * q[3][4] / q[3][0] + kr);
+  const double q2 = uD * uD + u1 * u1 + u2 * u2;
+  const double c2 = gm1 * (H - 0.5 * q2);
+  const double c = sqrt(c2);
+  const double ic = 1.0 / c;
+  const double b = gm1 * ic * ic;
+  const double lam[5] = {fabs(uD - c), fabs(uD), fabs(uD), fabs(uD), fabs(uD + c)};
+  // per cell: A, S and the pressure terms of the projected fluxes; the fields
+  // are then split and reconstructed one at a time (fewer live registers)
+  double A[6], S[6], pb[6], pc[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const double rho = q[j][0], p = q[j][4];
+    const double dD = q[j][1 + D] - uD, d1 = q[j][1 + T1] - u1, d2 = q[j][1 + T2] - u2;
+    A[j] = b * (0.5 * rho * (dD * dD + d1 * d1 + d2 * d2) + p * g.gm1i);
+    S[j] = -rho * dD * ic;
+    pb[j] = 0.5 * p * b * dD;
+    pc[j] = 0.5 * p * ic;
+  }
+  double Gf[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double Gp[6], Gm[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const double rho = q[j][0], vD = q[j][1 + D];
+      double V, G;
+      if (k == 0) {
+        V = 0.5 * (A[j] + S[j]);
+        G = vD * V + (pb[j] - pc[j]);
+      } else if (k == 1) {
+        V = rho - A[j];
+        G = vD * V - 2.0 * pb[j];
+      } else if (k == 4) {
+        V = 0.5 * (A[j] - S[j]);
+        G = vD * V + (pb[j] + pc[j]);
+      } else {
+        V = rho * (k == 2 ? q[j][1 + T1] - u1 : q[j][1 + T2] - u2);
+        G = vD * V;
+      }
+      Gp[j] = 0.5 * (G + lam[k] * V);
+      Gm[j] = 0.5 * (G - lam[k] * V);
+    }
+    Gf[k] = weno5(Gp[0], Gp[1], Gp[2], Gp[3], Gp[4]) + weno5(Gm[5], Gm[4], Gm[3], Gm[2], Gm[1]);
+  }
+  const double sac = Gf[0] + Gf[4], dac = Gf[4] - Gf[0];
+  const double s3 = sac + Gf[1];
+  F[0] = s3;
+  F[1 + D] = uD * s3 + c * dac;
+  F[1 + T1] = u1 * s3 + Gf[2];
+  F[1 + T2] = u2 * s3 + Gf[3];
+  F[4] = H * sac + uD * c * dac + 0.5 * q2 * Gf[1] + u1 * Gf[2] + u2 * Gf[3];
+}
+
 // Numerical flux from the window's primitives and given face tangential
-// derivatives tf: WENO5-JS (WENO5-Z with WZ) left and right of the face, then
-// face_flux_lr. The reconstruction is a compile-time choice: a run-time
-// branch between the two doubles the live registers of the sweeps.
-template <int D, bool WZ = false>
+// derivatives tf: WENO5-JS (or WENO5-Z) left and right of the face and HLLC,
+// or the Roe flux splitting, then the dissipative flux. The scheme is a
+// compile-time choice: a run-time branch between them multiplies the live
+// registers of the sweeps.
+template <int D, int SCH = SCH_JS>
 __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceWindow& w, const double* tf,
                                                       double* G) {
+  if constexpr (SCH == SCH_ROE) {
+    double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (g.inviscid) roe_flux<D>(g, w.q, F);
+    sub_dissipative<D>(g, w, tf, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) G[v] = F[v];
+    return;
+  }
   double WL[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WR[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (g.inviscid) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      if constexpr (WZ) {
+      if constexpr (SCH == SCH_Z) {
         WL[v] = weno5z(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
         WR[v] = weno5z(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
       } else {
@@ -244,11 +356,11 @@ __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceW
 }
 
 // Numerical flux G = F - F^d across the face (§3.3, §3.4) from a full window.
-template <int D, bool WZ = false>
+template <int D, int SCH = SCH_JS>
 __host__ __device__ __forceinline__ void face_flux(const Geom& g, const FaceWindow& w, double* G) {
   double tf[4] = {0.0, 0.0, 0.0, 0.0};
   if (g.viscous) face_tangential(w, tf);
-  face_flux_tf<D, WZ>(g, w, tf, G);
+  face_flux_tf<D, SCH>(g, w, tf, G);
 }
 
 }  // namespace cfd

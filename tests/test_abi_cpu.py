@@ -69,7 +69,8 @@ BAD_CONFIGS = [
     ("prandtl", dict(prandtl=0.0), "prandtl"),
     ("cfl zero", dict(cfl=0.0), "cfl"),
     ("cfl above one", dict(cfl=1.5), "cfl"),
-    ("unknown flag", dict(flags=16), "flag"),
+    ("unknown flag", dict(flags=32), "flag"),
+    ("roe with wenoz", dict(flags=1 | 8 | 16), "WENO5-JS"),
     ("too many faces", dict(n=(2048, 2048, 600)), "too large"),
 ]
 
