@@ -128,11 +128,12 @@ def cpu_baseline(case, W, nz):
 
 def differentiation(n, nsteps, ckpt_every=20, reps=5):
     """Cost of the discrete adjoint on the Taylor-Green vortex with seeded noise
-    (sigma 1e-3) at n^3: one fixed-dt TVD-RK3 step vs one step adjoint (which
-    recomputes its two inner stages) applied to a seeded Gaussian cotangent,
-    each timed with torch events on the stream the library launches on, and
-    the full gradient of the final kinetic energy through an n_steps rollout
-    with checkpoints every ckpt_every steps."""
+    (sigma 1e-3) at n^3: one fixed-dt TVD-RK3 step vs one step adjoint applied
+    to a seeded Gaussian cotangent, the adjoint either recomputing its two
+    inner stages or taking them from a step that kept them, each timed with
+    torch events on the stream the library launches on; and the full gradient
+    of the final kinetic energy through an n_steps rollout with checkpoints
+    every ckpt_every steps (kept stages, and recomputed stages)."""
     import torch
     from paper_2203_13760_amd import workloads as wl
     from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
@@ -160,14 +161,33 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     torch.cuda.synchronize()
     fwd = ev[0].elapsed_time(ev[1]) / reps
     adj = ev[1].elapsed_time(ev[2]) / reps
-    Wt = torch.from_numpy(W).cuda().requires_grad_(True)
+    U1, U2 = torch.empty_like(U), torch.empty_like(U)
+    s.step_stages(U, dt, U1, U2)
+    s.step_adjoint_stages(U, U1, U2, dt, Ub, out)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    L = kinetic_energy(s, rollout(conservative_from_primitive(s, Wt), s, dt, nsteps, ckpt_every))
-    L.backward()
+    ev[0].record()
+    for _ in range(reps):
+        s.step_stages(U, dt, U1, U2)
+    ev[1].record()
+    for _ in range(reps):
+        s.step_adjoint_stages(U, U1, U2, dt, Ub, out)
+    ev[2].record()
     torch.cuda.synchronize()
-    tgrad = time.perf_counter() - t0
-    gnorm = float(Wt.grad[1:4].norm().item())
+    fwd_keep = ev[0].elapsed_time(ev[1]) / reps
+    adj_kept = ev[1].elapsed_time(ev[2]) / reps
+    del U1, U2
+    tgrad = {}
+    for keep in (True, False):
+        Wt = torch.from_numpy(W).cuda().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = kinetic_energy(s, rollout(conservative_from_primitive(s, Wt), s, dt, nsteps, ckpt_every,
+                                      keep_stages=keep))
+        L.backward()
+        torch.cuda.synchronize()
+        tgrad[keep] = time.perf_counter() - t0
+        if keep:
+            gnorm = float(Wt.grad[1:4].norm().item())
     s.close()
     # the paper's gradient check: d(Delta S)/dM_S of a Mach 2 shock after 5 steps,
     # adjoint against central differences (least-squares order over the steps)
@@ -177,7 +197,10 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     sg["fd_order"] = float(np.polyfit(np.log(sg["eps"]), np.log(sg["fd_error"]), 1)[0])
     return {"workload": f"Taylor-Green vortex {n}^3 + Gaussian noise 1e-3 (seed 4), fixed dt {dt:.4g}",
             "step_ms": fwd, "step_adjoint_ms": adj, "adjoint_over_step": adj / fwd,
-            "gradient_steps": nsteps, "checkpoint_every": ckpt_every, "gradient_s": tgrad,
+            "step_keeping_stages_ms": fwd_keep, "step_adjoint_kept_stages_ms": adj_kept,
+            "adjoint_kept_stages_over_step": adj_kept / fwd,
+            "gradient_steps": nsteps, "checkpoint_every": ckpt_every, "gradient_s": tgrad[True],
+            "gradient_recomputing_stages_s": tgrad[False],
             "loss": float(L.item()), "grad_norm": gnorm, "shock_gradient": sg}
 
 
@@ -347,7 +370,8 @@ def main():
     adjoint = None
     if not args.no_adjoint:
         adjoint = differentiation(args.adj_n, args.adj_steps)
-        print(f"bench: adjoint step / step = {adjoint['adjoint_over_step']:.3f} at {args.adj_n}^3, "
+        print(f"bench: adjoint step / step = {adjoint['adjoint_over_step']:.3f} recomputing the stages, "
+              f"{adjoint['adjoint_kept_stages_over_step']:.3f} with kept stages, at {args.adj_n}^3, "
               f"gradient through {args.adj_steps} steps in {adjoint['gradient_s']:.2f} s", flush=True)
         torch.cuda.empty_cache()
 

@@ -143,6 +143,23 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream);
 
+/* One fixed-dt TVD-RK3 step on U in place (§3.2; as cfd_rk3_step with dt > 0)
+ * that also leaves its two stage states U1 = Un + dt R(Un) and
+ * U2 = 3/4 Un + 1/4 (U1 + dt R(U1)) in U1_out and U2_out: caller-owned device
+ * buffers of cfd_state_numel doubles, distinct from U and each other; their
+ * interior cells are written, their halo entries are unspecified. For
+ * checkpointed reverse passes that keep the stages of a recomputed segment
+ * instead of recomputing them in every step adjoint. */
+cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_out, double* U2_out, void* stream);
+
+/* cfd_rk3_step_adjoint with the stage states U1, U2 of the step from Un
+ * supplied (as cfd_rk3_step_stages leaves them; interior cells are read)
+ * instead of recomputed: the same result up to the summation order of the
+ * atomics, without the two forward stages. Ubar_n must not alias any input.
+ * CFD_EUNSUPPORTED for a WENO5-Z or ROE configuration. */
+cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
+                                       const double* Ubar_np1, double* Ubar_n, void* stream);
+
 /* Measurement aid: enqueue the kernels of one TVD-RK3 stage on U as a step
  * runs them (a middle stage: U2 = 3/4 U + 1/4 (U + dt R(U)) with dt = 1e-12,
  * written to solver scratch, so U is not modified): the primitive pass, the

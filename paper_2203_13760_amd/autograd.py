@@ -2,13 +2,16 @@
 differentiable `feed_forward` rollout, §4.5) backed by the hand-written
 discrete adjoint of libcfd.
 
-RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every) returns U_N; its
-backward pass walks the rollout in reverse segment by segment: the segment's
-states are recomputed from its checkpoint (kept every `ckpt_every` steps in the
-forward pass), then cfd_rk3_step_adjoint maps the adjoint back one step at a
-time (each step adjoint recomputes its two inner stages). Memory: the
-checkpoints plus one segment of states. Gradients flow to the interior cells of
-U0; halo entries of the returned gradient are zero.
+RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every, keep_stages) returns
+U_N; its backward pass walks the rollout in reverse segment by segment: the
+segment's states are recomputed from its checkpoint (kept every `ckpt_every`
+steps in the forward pass), then the step adjoint maps the adjoint back one
+step at a time. With keep_stages (the default) the recompute keeps each step's
+two stage states (cfd_rk3_step_stages) and cfd_rk3_step_adjoint_stages uses
+them; otherwise cfd_rk3_step_adjoint recomputes them in every step adjoint.
+Memory: the checkpoints plus one segment of states (three per step with
+keep_stages). Gradients flow to the interior cells of U0; halo entries of the
+returned gradient are zero.
 """
 from __future__ import annotations
 
@@ -19,7 +22,8 @@ from .solver import Solver, interior
 
 class RK3Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, solver: Solver, dt: float, n_steps: int, ckpt_every: int = 20):
+    def forward(ctx, U0, solver: Solver, dt: float, n_steps: int, ckpt_every: int = 20,
+                keep_stages: bool = True):
         if n_steps < 0 or ckpt_every < 1:
             raise ValueError("need n_steps >= 0 and ckpt_every >= 1")
         U = U0.detach().clone().contiguous()
@@ -36,6 +40,7 @@ class RK3Rollout(torch.autograd.Function):
         ctx.n_steps = int(n_steps)
         ctx.ckpt_every = int(ckpt_every)
         ctx.ckpts = ckpts
+        ctx.keep_stages = bool(keep_stages)
         return U
 
     @staticmethod
@@ -47,19 +52,30 @@ class RK3Rollout(torch.autograd.Function):
         for start, ck in reversed(ctx.ckpts):
             k = min(ctx.ckpt_every, ctx.n_steps - start)
             states = [ck]
+            stages = []
             U = ck.clone()
-            for _ in range(k - 1):
-                solver.advance_fixed(U, 1, dt)
-                states.append(U.clone())
+            for i in range(k - 1 if not ctx.keep_stages else k):
+                if ctx.keep_stages:
+                    U1, U2 = torch.empty_like(U), torch.empty_like(U)
+                    solver.step_stages(U, dt, U1, U2)
+                    stages.append((U1, U2))
+                else:
+                    solver.advance_fixed(U, 1, dt)
+                if i < k - 1:
+                    states.append(U.clone())
             for s in reversed(range(k)):
-                solver.step_adjoint(states[s], dt, Ub, scratch)
+                if ctx.keep_stages:
+                    solver.step_adjoint_stages(states[s], stages[s][0], stages[s][1], dt, Ub, scratch)
+                else:
+                    solver.step_adjoint(states[s], dt, Ub, scratch)
                 Ub, scratch = scratch, Ub
+            del states, stages
         ctx.ckpts = None
-        return Ub, None, None, None, None
+        return Ub, None, None, None, None, None
 
 
-def rollout(U0, solver: Solver, dt: float, n_steps: int, ckpt_every: int = 20):
-    return RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every)
+def rollout(U0, solver: Solver, dt: float, n_steps: int, ckpt_every: int = 20, keep_stages: bool = True):
+    return RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every, keep_stages)
 
 
 def conservative_from_primitive(solver: Solver, W):

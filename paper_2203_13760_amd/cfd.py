@@ -44,7 +44,7 @@ class cfd_config(C.Structure):
 EXPORTS = (
     "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_fill_halo", "cfd_rhs",
     "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
-    "cfd_rk3_step_adjoint", "cfd_profile_stage", "cfd_check", "cfd_last_error",
+    "cfd_rk3_step_adjoint", "cfd_rk3_step_stages", "cfd_rk3_step_adjoint_stages", "cfd_profile_stage", "cfd_check", "cfd_last_error",
     "cfd_batch_create", "cfd_batch_destroy", "cfd_batch_footprint", "cfd_batch_add", "cfd_batch_remove",
     "cfd_batch_state", "cfd_batch_step", "cfd_batch_finish", "cfd_batch_copy_state", "cfd_batch_count",
 )
@@ -77,6 +77,8 @@ def load():
         "cfd_advance_fixed": ([vp, dp, C.c_int32, C.c_double, vp], st),
         "cfd_rhs_adjoint": ([vp, dp, dp, dp, vp], st),
         "cfd_rk3_step_adjoint": ([vp, dp, C.c_double, dp, dp, vp], st),
+        "cfd_rk3_step_stages": ([vp, dp, C.c_double, dp, dp, vp], st),
+        "cfd_rk3_step_adjoint_stages": ([vp, dp, dp, dp, C.c_double, dp, dp, vp], st),
         "cfd_profile_stage": ([vp, dp, C.c_int32, C.POINTER(C.c_double), vp], st),
         "cfd_check": ([vp, C.POINTER(C.c_int32)], st),
         "cfd_last_error": ([], C.c_char_p),
@@ -191,6 +193,15 @@ def cfd_rhs_adjoint(h, U, Rbar, Ubar, stream=None):
 def cfd_rk3_step_adjoint(h, Un, dt, Ubar_np1, Ubar_n, stream=None):
     _check(load().cfd_rk3_step_adjoint(h, _ptr(Un), float(dt), _ptr(Ubar_np1), _ptr(Ubar_n),
                                        _stream(stream)))
+
+
+def cfd_rk3_step_stages(h, U, dt, U1_out, U2_out, stream=None):
+    _check(load().cfd_rk3_step_stages(h, _ptr(U), float(dt), _ptr(U1_out), _ptr(U2_out), _stream(stream)))
+
+
+def cfd_rk3_step_adjoint_stages(h, Un, U1, U2, dt, Ubar_np1, Ubar_n, stream=None):
+    _check(load().cfd_rk3_step_adjoint_stages(h, _ptr(Un), _ptr(U1), _ptr(U2), float(dt), _ptr(Ubar_np1),
+                                              _ptr(Ubar_n), _stream(stream)))
 
 
 def cfd_profile_stage(h, U, reps=5, stream=None):

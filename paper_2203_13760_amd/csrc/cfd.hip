@@ -255,7 +255,9 @@ static cfd_status enqueue_step_prologue(cfd_solver* s, const double* U, bool cfl
 // Pb[0]); the third also the health bits of U^{n+1} and, for CFL steps, its
 // CFL rate maxima, so consecutive steps need no separate primitive pass.
 static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double t_end, double* t_dev,
-                               double* dt_out, hipStream_t st) {
+                               double* dt_out, hipStream_t st, double* U1 = nullptr, double* U2 = nullptr) {
+  if (!U1) U1 = s->U1;
+  if (!U2) U2 = s->U2;
   const double* dtp = &s->ctl->dt;
   const bool cfl = !(fixed_dt > 0.0);
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out,
@@ -270,21 +272,21 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   cfd_status rc;
   // stage 1: U1 = Un + dt R(Un)
   io.Uk = U;
-  io.Uout = s->U1;
+  io.Uout = U1;
   io.a = 0.0;
   io.b = 1.0;
   io.Pn = s->Pb[1];
   io.what = 0;
   if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
   // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt R(U1))
-  io.Uk = s->U1;
-  io.Uout = s->U2;
+  io.Uk = U1;
+  io.Uout = U2;
   io.a = 0.75;
   io.b = 0.25;
   io.Pn = s->Pb[2];
   if ((rc = enqueue_fluxes(s, s->Pb[1], io, true, st))) return rc;
   // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2)), in place on U
-  io.Uk = s->U2;
+  io.Uk = U2;
   io.Uout = U;
   io.a = 1.0 / 3.0;
   io.b = 2.0 / 3.0;
@@ -391,8 +393,11 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
   if (g.act[1]) launch_face_adj<1>(s, P, Rbar, rscale, st);
   if (g.act[2]) launch_face_adj<2>(s, P, Rbar, rscale, st);
   CFD_LAUNCHED();
-  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, U, (const double*)s->Wbar,
-                     (const double*)s->Dbar, Ubar, g);
+  if (g.viscous) {
+    hipLaunchKernelGGL(k_adj_dbar, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->Dbar, s->Wbar, g);
+    CFD_LAUNCHED();
+  }
+  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, U, (const double*)s->Wbar, Ubar, g);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -661,6 +666,50 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   CFD_LAUNCHED();
   if ((rc = enqueue_rhs_adjoint(s, s->U1, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
   // Ubar_n = 1/3 Ubar_3 + 3/4 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
+                     (const double*)s->A2, 1.0, (const double*)s->A1, g);
+  CFD_LAUNCHED();
+  return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
+}
+
+cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_out, double* U2_out, void* stream) {
+  if (!s || !U || !U1_out || !U2_out) return fail(CFD_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
+  if (U1_out == U || U2_out == U || U1_out == U2_out) return fail(CFD_EINVAL, "the stage buffers must be distinct");
+  hipStream_t st = (hipStream_t)stream;
+  cfd_status rc = enqueue_step_prologue(s, U, false, st);
+  if (rc) return rc;
+  if ((rc = enqueue_step(s, U, dt, 0.0, nullptr, nullptr, st, U1_out, U2_out))) return rc;
+  return enqueue_fill_halo(s, U, st);
+}
+
+cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
+                                       const double* Ubar_np1, double* Ubar_n, void* stream) {
+  if (!s || !Un || !U1 || !U2 || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
+  if (s->g.wenoz || s->g.roe) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS with HLLC only");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
+  if (Ubar_n == Un || Ubar_n == U1 || Ubar_n == U2 || Ubar_n == Ubar_np1)
+    return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
+  cfd_status rc = ensure_adjoint_scratch(s);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Geom& g = s->g;
+  // primitives of the three stage inputs (halos gathered through the boundary map)
+  const double* Us[3] = {Un, U1, U2};
+  for (int k = 0; k < 3; ++k) {
+    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, Us[k], s->Pb[k], g, s->ctl, 0,
+                       (const double*)nullptr, s->partial);
+    CFD_LAUNCHED();
+  }
+  // the reverse sweep of cfd_rk3_step_adjoint
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
+                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_rhs_adjoint(s, U2, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
+                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_rhs_adjoint(s, U1, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
                      (const double*)s->A2, 1.0, (const double*)s->A1, g);
   CFD_LAUNCHED();

@@ -12,9 +12,11 @@
 //      contributions are first summed per cell by shuffles (one atomic per
 //      cell and variable); y and z faces keep x-consecutive lanes, whose
 //      loads coalesce, and add every contribution directly;
-//   3. k_adj_fold: per interior cell, the transposed halo fill (every padded
-//      cell that the boundary map sends to it), the transposed centred
-//      differences of Dbar, and the transposed primitive map at U give Ubar.
+//   3. k_adj_dbar (viscous): the transposed centred differences of Dbar,
+//      added to Wbar at every padded cell;
+//   4. k_adj_fold: per interior cell, the transposed halo fill (every padded
+//      cell that the boundary map sends to it) and the transposed primitive
+//      map at U give Ubar.
 // The atomics make the summation order, and so the last bits, vary between
 // runs; everything else is deterministic.
 #pragma once
@@ -453,14 +455,28 @@ __device__ __forceinline__ void fold_dbar(const Geom& g, const double* __restric
   }
 }
 
-// Per interior cell s: gather the adjoints of all its images, apply the
-// transposed centred differences of Dbar, then the transposed primitive map
-// at U[s]; Ubar[s] += result. Halo entries of Ubar are not touched. Cells
-// without halo images (all but a layer nh deep at periodic or clamped
-// boundaries) take a path without loops or range checks.
-__global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ U, const double* __restrict__ Wbar,
-                                                     const double* __restrict__ Dbar, double* __restrict__ Ubar,
+// Transposed centred differences of Dbar, for every padded cell c:
+// Wbar(u, v, w)[c] += the adjoint the tangential derivatives give c. Every
+// padded cell is the image of exactly one interior cell, so after this pass
+// the fold only sums Wbar over images. Each thread updates its own cell.
+__global__ void __launch_bounds__(kBlock) k_adj_dbar(const double* __restrict__ Dbar, double* __restrict__ Wbar,
                                                      Geom g) {
+  const PlaneIdx p = plane_index(g, true);
+  if (!p.in) return;
+  const int q[3] = {p.i, p.j, p.k};
+  double wb[4] = {0.0, 0.0, 0.0, 0.0};
+  fold_dbar<true>(g, Dbar, p.c, q, wb);
+#pragma unroll
+  for (int c = 1; c < 4; ++c) Wbar[c * g.vs + p.c] += wb[c];
+}
+
+// Per interior cell s: gather the adjoints of all its images (the transposed
+// halo fill), then apply the transposed primitive map at U[s]; Ubar[s] +=
+// result. Halo entries of Ubar are not touched. Cells without halo images
+// (all but a layer nh deep at periodic or clamped boundaries) take a path
+// without loops. With viscous fluxes k_adj_dbar has run first.
+__global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ U, const double* __restrict__ Wbar,
+                                                     double* __restrict__ Ubar, Geom g) {
   const PlaneIdx p = plane_index(g, true);
   if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
   int fx, cx, sx, fy, cy, sy, fz, cz, sz;
@@ -469,19 +485,15 @@ __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ 
   images(g, 2, p.k, fz, cz, sz);
   double wb[6] = {0, 0, 0, 0, 0, 0};
   if (cx == 1 && cy == 1 && cz == 1) {
-    const int q[3] = {p.i, p.j, p.k};
 #pragma unroll
     for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + p.c];
-    if (g.viscous) fold_dbar<false>(g, Dbar, p.c, q, wb);
   } else {
     for (int c = 0; c < cz; ++c)
       for (int b = 0; b < cy; ++b)
         for (int a = 0; a < cx; ++a) {
-          const int q[3] = {fx + a * sx, fy + b * sy, fz + c * sz};
-          const long long cc = cell_at(g, q[0], q[1], q[2]);
+          const long long cc = cell_at(g, fx + a * sx, fy + b * sy, fz + c * sz);
 #pragma unroll
           for (int v = 0; v < 6; ++v) wb[v] += Wbar[v * g.vs + cc];
-          if (g.viscous) fold_dbar<true>(g, Dbar, cc, q, wb);
         }
   }
   // transposed primitive map at U[s]

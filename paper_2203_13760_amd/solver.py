@@ -97,5 +97,15 @@ class Solver:
         cfd.cfd_rk3_step_adjoint(self.h, Un, float(dt), Ubar_np1, Ubar_n)
         return Ubar_n
 
+    def step_stages(self, U, dt, U1, U2):
+        """One fixed-dt step in place, keeping its stage states in U1 and U2."""
+        cfd.cfd_rk3_step_stages(self.h, U, float(dt), U1, U2)
+        return U
+
+    def step_adjoint_stages(self, Un, U1, U2, dt, Ubar_np1, Ubar_n=None):
+        Ubar_n = self.empty_state() if Ubar_n is None else Ubar_n
+        cfd.cfd_rk3_step_adjoint_stages(self.h, Un, U1, U2, float(dt), Ubar_np1, Ubar_n)
+        return Ubar_n
+
     def check(self):
         return cfd.cfd_check(self.h)

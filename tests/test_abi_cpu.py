@@ -112,6 +112,9 @@ def test_entry_points_reject_null_arguments():
                        ("cfd_rk3_step", (null, null, ctypes.c_double(0.0), null, null)),
                        ("cfd_advance", (null, null, ctypes.c_int32(1), ctypes.c_double(0.0), null, null)),
                        ("cfd_rhs_adjoint", (null, null, null, null, null)),
+                       ("cfd_rk3_step_stages", (null, null, ctypes.c_double(1e-3), null, null, null)),
+                       ("cfd_rk3_step_adjoint_stages", (null, null, null, null, ctypes.c_double(1e-3), null, null,
+                                                        null)),
                        ("cfd_state_init", (null, null, null, null))]:
         assert getattr(lib, name)(*args) == cfd.CFD_EINVAL, name
         assert cfd.cfd_last_error() != ""

@@ -93,6 +93,40 @@ def test_step_adjoint_matches_oracle_tape(Solver, name):
     assert e <= 1e-10, (name, e)
 
 
+@pytest.mark.parametrize("name", ["tgv_noisy", "shocky3d", "kh", "smooth_mixed_bc", "sod"])
+def test_kept_stages_and_their_step_adjoint_match_oracle(Solver, name):
+    """cfd_rk3_step_stages: the step equals the oracle's fixed-dt step and the
+    kept stages equal U1 = Un + dt R(Un), U2 = 3/4 Un + 1/4 (U1 + dt R(U1)) with
+    the oracle's R; cfd_rk3_step_adjoint_stages on them matches the oracle tape."""
+    case, W = CASES[name]
+    print(f"kept stages + their step adjoint: {name}", flush=True)
+    s = Solver(case)
+    U = s.init(W)
+    Un = U.clone()
+    Uo = oracle.state_init(case, W)
+    dt = 0.8 * oracle.cfl_dt(case, Uo)
+    U1, U2 = torch.empty_like(U), torch.empty_like(U)
+    s.step_stages(U, dt, U1, U2)
+    m = _interior_mask(case, Uo.shape) > 0
+    R0 = oracle.rhs(case, Uo)
+    W1 = np.where(m, Uo + dt * R0, 0.0)
+    o1 = oracle.fill_halo(case, W1.copy())
+    R1 = oracle.rhs(case, o1)
+    W2 = np.where(m, 0.75 * Uo + 0.25 * (o1 + dt * R1), 0.0)
+    for got, want in ((U1, W1), (U2, W2)):
+        g = np.where(m, got.cpu().numpy(), 0.0)
+        assert normwise(g, want) <= 1e-12, name
+    Uo3, _ = oracle.rk3_step(case, Uo, dt)
+    assert normwise(U.cpu().numpy(), Uo3) <= 1e-12, name
+    rng = np.random.default_rng(8)
+    Ub1 = rng.standard_normal(Uo.shape) * _interior_mask(case, Uo.shape)
+    want = oracle.vjp_rk3_step(case, Uo, dt, Ub1)
+    got = s.step_adjoint_stages(Un, U1, U2, dt, torch.from_numpy(Ub1).cuda()).cpu().numpy()
+    s.close()
+    e = normwise(got, want)
+    assert e <= 1e-10, (name, e)
+
+
 def test_rhs_adjoint_dot_product_on_gpu(Solver):
     # <w, J v> by fourth-order central differences of the GPU right-hand side
     # against <J^T w, v> from the GPU adjoint, at a size spanning several tiles
@@ -137,6 +171,27 @@ def test_gradient_through_checkpointed_rollout_matches_oracle(Solver):
     assert abs(float(L.item()) - Lo) <= 1e-12 * abs(Lo)
     e = normwise(g, go)
     assert e <= 1e-9, e
+
+
+def test_rollout_gradient_with_and_without_kept_stages(Solver):
+    """The rollout's reverse pass with the stages kept from the segment
+    recompute equals the one that recomputes them in every step adjoint: the
+    stages are bitwise the same, the atomic sums of the face adjoints are not
+    ordered, and their rounding differences compound over the 11 step
+    adjoints (about 1e-11 here), so the bar is this file's 1e-10."""
+    from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
+    case, W = wl.taylor_green_noisy(16, sigma=1e-3, seed=4)
+    dt = oracle.cfl_dt(case, oracle.state_init(case, W))
+    print("rollout gradient, kept vs recomputed stages", flush=True)
+    s = Solver(case)
+    grads = []
+    for keep in (True, False):
+        Wt = torch.from_numpy(W).cuda().requires_grad_(True)
+        L = kinetic_energy(s, rollout(conservative_from_primitive(s, Wt), s, dt, 11, 4, keep_stages=keep))
+        L.backward()
+        grads.append(Wt.grad.cpu().numpy())
+    s.close()
+    assert normwise(grads[0], grads[1]) <= 1e-10
 
 
 def test_gradient_of_long_rollout_matches_finite_differences(Solver):
