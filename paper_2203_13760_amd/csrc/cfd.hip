@@ -368,11 +368,12 @@ static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, 
     if (g.viscous || g.heat)
       hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar, g);
   } else {
-    const dim3 grid = face_adj_tile_grid<D>(g);
+    const dim3 grid_inv = face_adj_tile_grid<D, kAdjTileFacesInv>(g);
+    const dim3 grid_dis = face_adj_tile_grid<D, kAdjTileFacesDis>(g);
     if (g.inviscid)
-      hipLaunchKernelGGL(k_face_adj_inv_tiled<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
+      hipLaunchKernelGGL(k_face_adj_inv_tiled<D>, grid_inv, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
     if (g.viscous || g.heat)
-      hipLaunchKernelGGL(k_face_adj_dis_tiled<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar,
+      hipLaunchKernelGGL(k_face_adj_dis_tiled<D>, grid_dis, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar,
                          g);
   }
 }

@@ -247,31 +247,34 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restric
 }
 
 // y and z faces, tiled: a block takes 64 consecutive x (one per lane) and
-// kAdjTileFaces consecutive faces along D at one coordinate of the other
-// transverse axis, each wavefront kAdjTileFaces / 4 of those faces in turn.
+// TF consecutive faces along D at one coordinate of the other transverse
+// axis, each wavefront TF / 4 of those faces in turn.
 // The contributions of the block's faces are added into an LDS tile of the
 // cells they touch (LDS FP64 atomics), and the tile is then added to memory,
 // one global atomic per nonzero tile entry: about four times fewer global
 // atomics than adding each face's contributions directly, with the loads
 // still coalesced along x.
-constexpr int kAdjTileFaces = 8;
-constexpr int kAdjTileRows = kAdjTileFaces + 5;  // cells f0-3 .. f0+kAdjTileFaces+1
+// Faces per tile along D: the inviscid kernel's tile holds 5 components, the
+// dissipative kernel's 8, so the dissipative tile stays short to keep its
+// LDS within three workgroups per CU.
+constexpr int kAdjTileFacesInv = 8;
+constexpr int kAdjTileFacesDis = 8;
 
-template <int D>
+template <int D, int TF>
 __host__ __device__ __forceinline__ dim3 face_adj_tile_grid(const Geom& g) {
   constexpr int OT = D == 1 ? 2 : 1;
-  const int nfc = (g.n[D] + 1 + kAdjTileFaces - 1) / kAdjTileFaces;
+  const int nfc = (g.n[D] + 1 + TF - 1) / TF;
   return dim3((unsigned)((g.n[0] + 63) / 64), (unsigned)(nfc * g.n[OT]));
 }
 
 // Lane, x, first face of the tile, other-axis coordinate of a tiled launch.
-template <int D>
+template <int D, int TF>
 __device__ __forceinline__ void face_adj_tile(const Geom& g, int& lane, int& x, int& f0, int& o) {
-  const int nfc = (g.n[D] + 1 + kAdjTileFaces - 1) / kAdjTileFaces;
+  const int nfc = (g.n[D] + 1 + TF - 1) / TF;
   lane = threadIdx.x & 63;
   x = blockIdx.x * 64 + lane;
   o = blockIdx.y / nfc;
-  f0 = (blockIdx.y - o * nfc) * kAdjTileFaces;
+  f0 = (blockIdx.y - o * nfc) * TF;
 }
 
 template <int D>
@@ -285,18 +288,20 @@ __device__ __forceinline__ void tile_zero(double* tile, int n) {
   __syncthreads();
 }
 
-// Add the LDS tile (component v at base[v], rows of cells f0-3+r) to memory.
-template <int D>
+// Add the LDS tile (component v at base[v], rows of cells f0-3+r, TF + 5
+// rows) to memory.
+template <int D, int TF>
 __device__ __forceinline__ void tile_flush(const Geom& g, const double* tile, int nv, double* const* base, int f0,
                                            int o) {
+  constexpr int rows = TF + 5;
   __syncthreads();
   const int x0 = blockIdx.x * 64;
-  for (int e = threadIdx.x; e < nv * kAdjTileRows * 64; e += kBlock) {
+  for (int e = threadIdx.x; e < nv * rows * 64; e += kBlock) {
     const double val = tile[e];
     if (val == 0.0) continue;  // only cells a face of the tile touched are nonzero
     const int l = e & 63;
-    const int r = (e >> 6) % kAdjTileRows;
-    const int v = (e >> 6) / kAdjTileRows;
+    const int r = (e >> 6) % rows;
+    const int v = (e >> 6) / rows;
     unsafeAtomicAdd(base[v] + tile_cell<D>(g, x0 + l, f0 - 3 + r, o), val);
   }
 }
@@ -304,15 +309,16 @@ __device__ __forceinline__ void tile_flush(const Geom& g, const double* tile, in
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_adj_inv_tiled(const double* P, const double* __restrict__ Rbar,
                                                                double rscale, double* Wbar, Geom g) {
-  __shared__ double tile[5 * kAdjTileRows * 64];
+  constexpr int TF = kAdjTileFacesInv, rows = TF + 5;
+  __shared__ double tile[5 * rows * 64];
   int lane, x, f0, o;
-  face_adj_tile<D>(g, lane, x, f0, o);
-  tile_zero(tile, 5 * kAdjTileRows * 64);
+  face_adj_tile<D, TF>(g, lane, x, f0, o);
+  tile_zero(tile, 5 * rows * 64);
   const int w = threadIdx.x >> 6;
-  constexpr int per_wave = kAdjTileFaces / (kBlock / 64);
+  constexpr int per_wave = TF / (kBlock / 64);
   const long long st = g.s[D];
   for (int it = 0; it < per_wave; ++it) {
-    const int fl = w * per_wave + it;  // face of the tile, 0 .. kAdjTileFaces-1
+    const int fl = w * per_wave + it;  // face of the tile, 0 .. TF-1
     const int f = f0 + fl;
     if (x >= g.n[0] || f > g.n[D]) continue;
     const long long cf = tile_cell<D>(g, x, f, o);
@@ -341,13 +347,13 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_inv_tiled(const double* P, 
 #pragma unroll
       for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
 #pragma unroll
-      for (int m = 0; m < 6; ++m) atomicAdd(&tile[(v * kAdjTileRows + fl + m) * 64 + lane], gs[m]);
+      for (int m = 0; m < 6; ++m) atomicAdd(&tile[(v * rows + fl + m) * 64 + lane], gs[m]);
     }
   }
   double* base[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) base[v] = Wbar + v * g.vs;
-  tile_flush<D>(g, tile, 5, base, f0, o);
+  tile_flush<D, TF>(g, tile, 5, base, f0, o);
 }
 
 template <int D>
@@ -356,12 +362,13 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis_tiled(const double* __r
                                                                double* Wbar, double* Dbar, Geom g) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   // components: u, v, w, T~ of Wbar, then the four derivative inputs of Dbar
-  __shared__ double tile[8 * kAdjTileRows * 64];
+  constexpr int TF = kAdjTileFacesDis, rows = TF + 5;
+  __shared__ double tile[8 * rows * 64];
   int lane, x, f0, o;
-  face_adj_tile<D>(g, lane, x, f0, o);
-  tile_zero(tile, 8 * kAdjTileRows * 64);
+  face_adj_tile<D, TF>(g, lane, x, f0, o);
+  tile_zero(tile, 8 * rows * 64);
   const int w = threadIdx.x >> 6;
-  constexpr int per_wave = kAdjTileFaces / (kBlock / 64);
+  constexpr int per_wave = TF / (kBlock / 64);
   const long long st = g.s[D];
   for (int it = 0; it < per_wave; ++it) {
     const int fl = w * per_wave + it;
@@ -389,10 +396,10 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis_tiled(const double* __r
       bool act[4];
       __device__ void q(int m, int v, double val) {
         const int c = v == 5 ? 3 : v - 1;  // u, v, w, T~
-        atomicAdd(&tile[(c * kAdjTileRows + fl + m) * 64 + lane], val);
+        atomicAdd(&tile[(c * rows + fl + m) * 64 + lane], val);
       }
       __device__ void tg(int m, int k, double val) {
-        if (act[k]) atomicAdd(&tile[((4 + k) * kAdjTileRows + fl + m) * 64 + lane], val);
+        if (act[k]) atomicAdd(&tile[((4 + k) * rows + fl + m) * 64 + lane], val);
       }
     } sink{tile, fl, lane, {g.act[T1] != 0, g.act[T1] != 0, g.act[T2] != 0, g.act[T2] != 0}};
     face_flux_rev<D>(gd, win, Gb, sink);
@@ -400,7 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis_tiled(const double* __r
   const int comp[4] = {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2};
   double* base[8] = {Wbar + 1 * g.vs, Wbar + 2 * g.vs, Wbar + 3 * g.vs, Wbar + 5 * g.vs,
                      Dbar + comp[0] * g.vs, Dbar + comp[1] * g.vs, Dbar + comp[2] * g.vs, Dbar + comp[3] * g.vs};
-  tile_flush<D>(g, tile, 8, base, f0, o);
+  tile_flush<D, TF>(g, tile, 8, base, f0, o);
 }
 
 // Padded coordinates of axis d that the boundary map sends to interior

@@ -233,11 +233,12 @@ __device__ __forceinline__ void publish_rate(double* slots, int block_index, dou
 __device__ __forceinline__ void cons_to_prim(const Geom& g, const double* q, double* w) {
   const double rho = q[0];
   w[0] = rho;
-  w[1] = q[1] / rho;
-  w[2] = q[2] / rho;
-  w[3] = q[3] / rho;
+  const double ir = 1.0 / rho;
+  w[1] = q[1] * ir;
+  w[2] = q[2] * ir;
+  w[3] = q[3] * ir;
   w[4] = (g.gamma - 1.0) * (q[4] - 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]));
-  w[5] = w[4] / rho;
+  w[5] = w[4] * ir;
 }
 
 // Health bits of a cell: 1 non-finite conservative value, 2 rho <= 0, 4 p <= 0.

@@ -41,6 +41,27 @@ constexpr int SCH_JS = 0, SCH_Z = 1, SCH_ROE = 2;
 
 __host__ __device__ __forceinline__ double sq(double x) { return x * x; }
 
+// a / b within about one ulp, for denominators that are finite and nonzero
+// wherever the result is used: the hardware reciprocal estimate (v_rcp_f64)
+// refined by two Newton-Raphson steps r <- r + r (1 - b r), then one residual
+// correction of the quotient q <- q + r (a - b q) (Markstein 1990). It skips
+// the range scaling and special-case fixup of the correctly rounded division,
+// about a third of its instructions; results differ from a / b in the last
+// bit at most. The host pass (host-compiled tests of the face code) divides.
+__host__ __device__ __forceinline__ double div_nr(double a, double b) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(e, r, r);
+  e = fma(-b, r, 1.0);
+  r = fma(e, r, r);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+#else
+  return a / b;
+#endif
+}
+
 // Cell index of interior-relative coordinates (i,j,k) (halo cells negative).
 __device__ __forceinline__ long long cell_at(const Geom& g, int i, int j, int k) {
   return (long long)(k + g.h[2]) * g.s[2] + (long long)(j + g.h[1]) * g.s[1] + (i + g.h[0]);
@@ -76,7 +97,7 @@ __host__ __device__ __forceinline__ double weno5(double a, double b, double c, d
   const double P0 = 2.0 * a - 7.0 * b + 11.0 * c;
   const double P1 = -b + 5.0 * c + 2.0 * d;
   const double P2 = 2.0 * c + 5.0 * d - e;
-  return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
+  return div_nr(w0 * P0 + w1 * P1 + w2 * P2, 6.0 * (w0 + w1 + w2));
 }
 
 // WENO5-Z (Borges, Carmona, Costa & Don 2008): the same candidates and
@@ -117,21 +138,21 @@ __host__ __device__ __forceinline__ void hllc(double gamma, double gm1i, const d
   const double rR = WR[0], uR = WR[1 + D], aR = WR[1 + T1], bR = WR[1 + T2], pR = WR[4];
   const double EL = pL * gm1i + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
   const double ER = pR * gm1i + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
-  const double c2L = gamma * pL / rL, c2R = gamma * pR / rR;
+  const double c2L = div_nr(gamma * pL, rL), c2R = div_nr(gamma * pR, rR);
   const double cL = sqrt(c2L), cR = sqrt(c2R);
   // Einfeldt: Roe-averaged normal velocity and sound-speed bound
   const double sL = sqrt(rL), sR = sqrt(rR);
-  const double isum = 1.0 / (sL + sR);
+  const double isum = div_nr(1.0, sL + sR);
   const double ubar = (sL * uL + sR * uR) * isum;
   const double eta2 = 0.5 * sL * sR * isum * isum;
   const double dbar = sqrt((sL * c2L + sR * c2R) * isum + eta2 * sq(uR - uL));
   const double SL = fmin(uL - cL, ubar - dbar);
   const double SR = fmax(uR + cR, ubar + dbar);
   const double mL = rL * (SL - uL), mR = rR * (SR - uR);  // mass fluxes relative to the waves
-  const double Ss = (pR - pL + uL * mL - uR * mR) / (mL - mR);
+  const double Ss = div_nr(pR - pL + uL * mL - uR * mR, mL - mR);
   // star states U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S*, t1, t2, E_K/rho_K + (S*-u_K)(S* + p_K/(rho_K (S_K-u_K))));
   // the energy slot is rearranged so that no division by rho_K or m_K remains
-  const double iL = 1.0 / (SL - Ss), iR = 1.0 / (SR - Ss);
+  const double iL = div_nr(1.0, SL - Ss), iR = div_nr(1.0, SR - Ss);
   const double fL = mL * iL, fR = mR * iR;
   const double eL = (SL - uL) * iL * EL + (Ss - uL) * (fL * Ss + pL * iL);
   const double eR = (SR - uR) * iR * ER + (Ss - uR) * (fR * Ss + pR * iR);
