@@ -69,6 +69,10 @@ def _load():
     lib.oracle_roe_flux.restype = None
     lib.oracle_euler_flux.argtypes = [d, dp, C.c_int, dp]
     lib.oracle_euler_flux.restype = None
+    lib.oracle_weno3.argtypes = [d, d, d]
+    lib.oracle_weno3.restype = d
+    lib.oracle_rusanov.argtypes = [d, dp, dp, C.c_int, dp]
+    lib.oracle_rusanov.restype = None
     lib.oracle_opcount.argtypes = [cfgp, dp, dp]
     lib.oracle_opcount_parts.argtypes = [cfgp, dp, dp]
     lib.oracle_vjp_rhs.argtypes = [cfgp, dp, dp, dp]
@@ -217,6 +221,18 @@ def roe_flux(gamma, w6, axis):
     w6 = np.ascontiguousarray(w6, dtype=np.float64).reshape(30)
     F = np.zeros(5)
     _load().oracle_roe_flux(float(gamma), _ptr(w6), int(axis), _ptr(F))
+    return F
+
+
+def weno3(a, b, c):
+    return float(_load().oracle_weno3(float(a), float(b), float(c)))
+
+
+def rusanov(gamma, WL, WR, axis):
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    F = np.zeros(5)
+    _load().oracle_rusanov(float(gamma), _ptr(WL), _ptr(WR), int(axis), _ptr(F))
     return F
 
 

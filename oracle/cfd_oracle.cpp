@@ -34,16 +34,20 @@ typedef struct {
   double mu;           // dynamic viscosity (>= 0)
   double prandtl;      // Prandtl number (> 0)
   double cfl;          // CFL number
-  int32_t bc[6];       // x-, x+, y-, y+, z-, z+ : 0 periodic, 1 zero gradient
+  int32_t bc[6];       // x-, x+, y-, y+, z-, z+ : 0 periodic, 1 zero gradient, 2 reflecting wall
   uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux, 8 WENO5-Z reconstruction,
-                       // 16 Roe flux splitting in characteristic space (the paper's ROE setup)
+                       // 16 Roe flux splitting in characteristic space (the paper's ROE setup),
+                       // 32 WENO3-JS reconstruction, 64 Rusanov flux, 128 TVD-RK2 time integration
 } oracle_cfg;
 }
 
 namespace oracle {
 
-enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
-enum : uint32_t { F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u, F_WENOZ = 8u, F_ROE = 16u };
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_REFLECT = 2 };
+enum : uint32_t {
+  F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u, F_WENOZ = 8u, F_ROE = 16u, F_WENO3 = 32u, F_RUSANOV = 64u,
+  F_RK2 = 128u
+};
 
 // --------------------------------------------------------------------------
 // Grid: cell (i,j,k), interior indices 0..n-1, halo indices -nh..-1, n..n+nh-1.
@@ -77,9 +81,11 @@ struct Grid {
 // --------------------------------------------------------------------------
 // Boundary conditions (§3.7 and Table of numerical methods: periodic and zero
 // gradient; the setup file of Appendix A calls zero gradient "neumann" without
-// a value). Halo layers are filled axis by axis, x then y then z; each later
-// axis sweeps the full extent of the earlier axes including their halos, so
-// edge and corner halo cells are filled consistently.
+// a value; the implosion of §6.2 reflects its shock at walls, read as a slip
+// wall: the halo mirrors the interior about the boundary face and the momentum
+// normal to it changes sign). Halo layers are filled axis by axis, x then y
+// then z; each later axis sweeps the full extent of the earlier axes including
+// their halos, so edge and corner halo cells are filled consistently.
 template <class R>
 void fill_halo(const oracle_cfg& c, const Grid& g, std::vector<R>& U) {
   for (int d = 0; d < 3; ++d) {
@@ -97,14 +103,17 @@ void fill_halo(const oracle_cfg& c, const Grid& g, std::vector<R>& U) {
         for (int i = lo[0]; i < hi[0]; ++i) {
           for (int m = 1; m <= g.h[d]; ++m) {
             // low side: halo cell -m; high side: halo cell n-1+m
-            const int src_lo = (c.bc[2 * d] == BC_PERIODIC) ? n - m : 0;
-            const int src_hi = (c.bc[2 * d + 1] == BC_PERIODIC) ? m - 1 : n - 1;
+            const int blo = c.bc[2 * d], bhi = c.bc[2 * d + 1];
+            const int src_lo = blo == BC_PERIODIC ? n - m : (blo == BC_REFLECT ? m - 1 : 0);
+            const int src_hi = bhi == BC_PERIODIC ? m - 1 : (bhi == BC_REFLECT ? n - m : n - 1);
             int q[3] = {i, j, k};
             q[d] = 0;
             for (int v = 0; v < 5; ++v) {
               R* Uv = U.data() + (long)v * g.ncell;
-              Uv[g.shift(d, q[0], q[1], q[2], -m)] = Uv[g.shift(d, q[0], q[1], q[2], src_lo)];
-              Uv[g.shift(d, q[0], q[1], q[2], n - 1 + m)] = Uv[g.shift(d, q[0], q[1], q[2], src_hi)];
+              const double slo = (blo == BC_REFLECT && v == 1 + d) ? -1.0 : 1.0;
+              const double shi = (bhi == BC_REFLECT && v == 1 + d) ? -1.0 : 1.0;
+              Uv[g.shift(d, q[0], q[1], q[2], -m)] = slo * Uv[g.shift(d, q[0], q[1], q[2], src_lo)];
+              Uv[g.shift(d, q[0], q[1], q[2], n - 1 + m)] = shi * Uv[g.shift(d, q[0], q[1], q[2], src_hi)];
             }
           }
         }
@@ -185,6 +194,32 @@ R weno5_z(R a, R b, R c, R d, R e) {
   const R alpha2 = 0.3 * (1.0 + tau5 / (beta2 + eps));
   return (alpha0 * p0 + alpha1 * p1 + alpha2 * p2) / (alpha0 + alpha1 + alpha2);
 }
+
+// WENO3-JS (Jiang & Shu 1996, r = 2; the implosion of §6.2 reconstructs with
+// it): value at the right face of the centre cell b of the stencil (a, b, c) =
+// (q_{i-1}, q_i, q_{i+1}): candidates p0 = (3b - a)/2 and p1 = (b + c)/2,
+// smoothness indicators (b - a)^2 and (c - b)^2, linear weights (1/3, 2/3),
+// alpha_k = d_k/(eps + beta_k)^2 with eps = 1e-6 (reading: as WENO5-JS),
+// normalised.
+template <class R>
+R weno3_js(R a, R b, R c) {
+  const double eps = 1.0e-6;
+  const R beta0 = sq(b - a);
+  const R beta1 = sq(c - b);
+  const R p0 = 1.5 * b - 0.5 * a;
+  const R p1 = 0.5 * b + 0.5 * c;
+  const R alpha0 = (1.0 / 3.0) / sq(eps + beta0);
+  const R alpha1 = (2.0 / 3.0) / sq(eps + beta1);
+  return (alpha0 * p0 + alpha1 * p1) / (alpha0 + alpha1);
+}
+
+// Rusanov (local Lax-Friedrichs) flux of §6.2 across a face normal to axis d
+// from the reconstructed primitive states WL, WR:
+//   F = (F_L + F_R)/2 - alpha (U_R - U_L)/2,
+//   alpha = max(|u_L - c_L|, |u_L + c_L|, |u_R - c_R|, |u_R + c_R|),
+// u the face-normal velocity and c the speed of sound of each state.
+template <class R>
+void rusanov_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]);
 
 // --------------------------------------------------------------------------
 // HLLC approximate Riemann solver (Toro, Spruce & Speares 1994; §3.3 step 3)
@@ -277,6 +312,19 @@ void conservative(double gamma, const R w[5], R U[5]) {
   U[0] = w[0];
   for (int a = 0; a < 3; ++a) U[1 + a] = w[0] * w[1 + a];
   U[4] = w[4] / (gamma - 1.0) + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+}
+
+template <class R>
+void rusanov_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]) {
+  R UL[5], UR[5], FL[5], FR[5];
+  conservative(gamma, WL, UL);
+  conservative(gamma, WR, UR);
+  euler_flux(gamma, WL, d, FL);
+  euler_flux(gamma, WR, d, FR);
+  const R cL = sqrt_(gamma * WL[4] / WL[0]), cR = sqrt_(gamma * WR[4] / WR[0]);
+  const R uL = WL[1 + d], uR = WR[1 + d];
+  const R alpha = max_(max_(abs_(uL - cL), abs_(uL + cL)), max_(abs_(uR - cR), abs_(uR + cR)));
+  for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * alpha * (UR[v] - UL[v]);
 }
 
 // Steps 1 and 2 for primitive states wl (cell i) and wr (cell i+1): right
@@ -471,7 +519,10 @@ void face_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d, con
     for (int v = 0; v < 5; ++v) {
       const std::vector<R>& s = *q[v];
       auto at = [&](int o) { return s[g.shift(d, a[0], a[1], a[2], o)]; };
-      if (c.flags & F_WENOZ) {
+      if (c.flags & F_WENO3) {
+        WL[v] = weno3_js(at(-1), at(0), at(1));
+        WR[v] = weno3_js(at(2), at(1), at(0));
+      } else if (c.flags & F_WENOZ) {
         WL[v] = weno5_z(at(-2), at(-1), at(0), at(1), at(2));
         WR[v] = weno5_z(at(3), at(2), at(1), at(0), at(-1));
       } else {
@@ -479,7 +530,8 @@ void face_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d, con
         WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
       }
     }
-    hllc_flux(c.gamma, WL, WR, d, Fc);
+    if (c.flags & F_RUSANOV) rusanov_flux(c.gamma, WL, WR, d, Fc);
+    else hllc_flux(c.gamma, WL, WR, d, Fc);
   }
   R Fd[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
   if (viscous || heat) dissipative_flux(c, g, W, d, a[0], a[1], a[2], viscous, heat, Fd);
@@ -575,7 +627,11 @@ inline double cfl_dt(const oracle_cfg& c, const Grid& g, const std::vector<doubl
 //   U2   = 3/4 Un + 1/4 (U1 + dt R(U1))
 //   Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2))
 // dt stays fixed over the three stages. Only interior cells are updated; the
-// halos of the result are refreshed afterwards.
+// halos of the result are refreshed afterwards. With F_RK2 the step is the
+// second-order TVD Runge-Kutta scheme of the same paper (the implosion of §6.2
+// integrates with TVD-RK2):
+//   U1   = Un + dt R(Un)
+//   Un+1 = 1/2 Un + 1/2 (U1 + dt R(U1))
 template <class R>
 void rk3_step(const oracle_cfg& c, const Grid& g, std::vector<R>& U, double dt) {
   std::vector<R> Un = U, U1 = U, U2 = U, Rh;
@@ -587,6 +643,12 @@ void rk3_step(const oracle_cfg& c, const Grid& g, std::vector<R>& U, double dt) 
   };
   rhs(c, g, Un, Rh);
   interior([&](long q) { U1[q] = Un[q] + dt * Rh[q]; });
+  if (c.flags & F_RK2) {
+    rhs(c, g, U1, Rh);
+    interior([&](long q) { U[q] = 0.5 * Un[q] + 0.5 * (U1[q] + dt * Rh[q]); });
+    fill_halo(c, g, U);
+    return;
+  }
   rhs(c, g, U1, Rh);
   interior([&](long q) { U2[q] = 0.75 * Un[q] + 0.25 * (U1[q] + dt * Rh[q]); });
   rhs(c, g, U2, Rh);
@@ -629,6 +691,8 @@ static int check_cfg(const oracle_cfg* c) {
     if (c->n[d] > 1 && c->n[d] < c->nh) return -1;  // periodic images need n >= nh
     if (!(c->hi[d] > c->lo[d])) return -1;
     if (c->n[d] > 1 && ((c->bc[2 * d] == BC_PERIODIC) != (c->bc[2 * d + 1] == BC_PERIODIC))) return -1;
+    if (c->bc[2 * d] < 0 || c->bc[2 * d] > BC_REFLECT || c->bc[2 * d + 1] < 0 || c->bc[2 * d + 1] > BC_REFLECT)
+      return -1;
   }
   if (c->nh < 3 || !(c->gamma > 1.0) || !(c->mu >= 0.0) || !(c->prandtl > 0.0)) return -1;
   return 0;
@@ -737,6 +801,10 @@ void oracle_roe_flux(double gamma, const double* w, int d, double* F) {
   for (int j = 0; j < 6; ++j)
     for (int v = 0; v < 5; ++v) ww[j][v] = w[j * 5 + v];
   roe_split_flux(gamma, ww, d, F);
+}
+double oracle_weno3(double a, double b, double c) { return weno3_js(a, b, c); }
+void oracle_rusanov(double gamma, const double* WL, const double* WR, int d, double* F) {
+  rusanov_flux(gamma, WL, WR, d, F);
 }
 // Euler flux along axis d of one primitive state.
 void oracle_euler_flux(double gamma, const double* w, int d, double* F) { euler_flux(gamma, w, d, F); }

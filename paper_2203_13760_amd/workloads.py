@@ -19,9 +19,13 @@ import numpy as np
 
 PERIODIC = 0
 ZERO_GRADIENT = 1
+REFLECT = 2  # slip wall: mirrored halo, normal momentum negated
 INVISCID, VISCOUS, HEAT = 1, 2, 4
 WENOZ = 8
 ROE = 16  # flux splitting in characteristic space with Roe eigenvalues (the ROE setup)
+WENO3 = 32
+RUSANOV = 64
+RK2 = 128
 ALL_PHYSICS = INVISCID | VISCOUS | HEAT
 
 
@@ -83,6 +87,21 @@ def lax(n=100, nh=3):
     zero = np.zeros_like(X)
     case["t_end"] = 0.14
     return case, _stack(rho, u, zero, zero, p, X.shape)
+
+
+def implosion(n=128, nh=3, flags=INVISCID | WENO3 | RK2):
+    """The implosion of §6.2 as printed: (rho, u, v, p) = (0.14, 0, 0, 0.125)
+    where x + y <= 0.15 and (1, 0, 0, 1) elsewhere on [0,1]^2, reflecting walls
+    on all four sides, inviscid; the paper's ground truth runs WENO3-JS, TVD-RK2
+    and HLLC at 128^2 with a fixed dt = 2.5e-4."""
+    case = make_case((n, n, 1), bc=(REFLECT,) * 4 + (PERIODIC,) * 2, flags=flags, nh=nh)
+    X, Y, _ = _mesh(case)
+    inner = X + Y <= 0.15
+    rho = np.where(inner, 0.14, 1.0)
+    p = np.where(inner, 0.125, 1.0)
+    zero = np.zeros_like(X)
+    case["dt"] = 2.5e-4
+    return case, _stack(rho, zero, zero, zero, p, X.shape)
 
 
 def entropy_wave(n, nh=3):

@@ -475,6 +475,139 @@ def test_roe_setup_through_the_oracle():
         assert np.all(oracle.rhs(case, U) == 0.0)
 
 
+# ---------------------------------------------------------------- implosion substrate (§6.2)
+def _mirror_pair(axis, n=24, steps=30, flags=wl.INVISCID, dt=2e-3):
+    """A state on [0,1] along `axis` with reflecting walls at both ends, and the
+    same state mirrored onto [0,2] with periodic ends (density and pressure
+    even about x = 1, the normal velocity odd): the walled run must equal the
+    first half of the periodic one."""
+    other = 7 if axis == 1 else 1
+    nw = [1, 1, 1]
+    nw[axis] = n
+    if axis == 1:
+        nw[0] = other
+    bcw = [wl.PERIODIC] * 6
+    bcw[2 * axis] = bcw[2 * axis + 1] = wl.REFLECT
+    hi = [1.0, 1.0, 1.0]
+    cw = wl.make_case(tuple(nw), bc=tuple(bcw), flags=flags)
+    nf = list(nw)
+    nf[axis] = 2 * n
+    hi[axis] = 2.0
+    cf = wl.make_case(tuple(nf), hi=tuple(hi), bc=(wl.PERIODIC,) * 6, flags=flags)
+    shape = (nw[2], nw[1], nw[0])
+    x = (np.arange(n) + 0.5) / n
+    prof = lambda a, k: a + 0.3 * np.sin(np.pi * k * x) + 0.2 * (x > 0.4 + 0.1 * k)
+    Ww = np.empty((5,) + shape)
+    cols = [prof(1.0, 1), 0.4 * np.sin(np.pi * x) * (1.0 + 0.5 * x), 0.2 * np.cos(3 * x), 0.1 * x, prof(1.5, 2)]
+    for v in range(5):
+        f = cols[v]
+        f = f.reshape((1, n, 1)) if axis == 1 else f.reshape((1, 1, n))
+        Ww[v] = np.broadcast_to(f, shape)
+    Wf = np.concatenate([Ww, np.flip(Ww, axis=3 - axis)], axis=3 - axis)
+    Wf[1 + axis] = np.concatenate([Ww[1 + axis], -np.flip(Ww[1 + axis], axis=2 - axis)], axis=2 - axis)
+    Uw, _, _ = oracle.advance(cw, oracle.state_init(cw, Ww), steps, fixed_dt=dt)
+    Uf, _, _ = oracle.advance(cf, oracle.state_init(cf, Wf), steps, fixed_dt=dt)
+    iw = oracle.interior(cw, Uw)
+    i_f = oracle.interior(cf, Uf)
+    half = [slice(None)] * 4
+    half[3 - axis] = slice(0, n)
+    return iw, i_f[tuple(half)]
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+@pytest.mark.parametrize("flags", [wl.INVISCID, wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV])
+def test_reflecting_wall_equals_mirrored_periodic_domain(axis, flags):
+    """Reflecting walls (the implosion of §6.2): the walled run equals the
+    first half of the run on the mirrored domain twice as long, for a jump and
+    a smooth profile, along x and along y (the sign flip must hit the wall's
+    normal momentum and only it)."""
+    a, b = _mirror_pair(axis, flags=flags)
+    scale = np.abs(b).reshape(5, -1).max(axis=1) + 1e-300
+    err = np.abs(a - b).reshape(5, -1).max(axis=1) / scale
+    assert np.all(err <= 1e-13), err
+
+
+def test_weno3_special_cases():
+    """WENO3-JS: exact on linear data (both candidates are), the smooth side's
+    candidate at a jump, and third order on smooth monotone data (the weights
+    approach (1/3, 2/3) to O(h))."""
+    for a, b, c in ((1.0, 2.0, 3.0), (-4.0, -1.5, 1.0)):
+        assert abs(oracle.weno3(a, b, c) - (b + 0.5 * (c - b))) < 1e-14
+    assert abs(oracle.weno3(0.0, 1.0, 1.0) - 1.0) < 1e-6
+    assert abs(oracle.weno3(0.0, 0.0, 1.0) - 0.0) < 1e-6
+    errs = []
+    for n in (40, 80, 160, 320):
+        h = 1.0 / n
+        xl = 0.3 + np.arange(n) * h * 0.5
+        avg = lambda x0: (np.exp(x0 + h) - np.exp(x0)) / h
+        e = max(abs(oracle.weno3(avg(x - h), avg(x), avg(x + h)) - np.exp(x + h)) for x in xl[5:-5])
+        errs.append(e)
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert order[-1] >= 2.8, order
+
+
+def test_tvd_rk2_second_order_in_time():
+    n, t_end = 40, 0.5
+    case, W = wl.entropy_wave(n)
+    case["flags"] |= wl.RK2
+    U0 = oracle.state_init(case, W)
+    ref, _, _ = oracle.advance(case, U0, 10 ** 7, t_end=t_end, fixed_dt=0.01 / 64)
+    errs = []
+    for dt in (0.01, 0.005, 0.0025):
+        U, t, _ = oracle.advance(case, U0, 10 ** 7, t_end=t_end, fixed_dt=dt)
+        errs.append(float(np.max(np.abs(U - ref))))
+    order = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(order - 2.0) < 0.2), order
+
+
+def test_rusanov_flux_pins():
+    """Rusanov (§6.2): equal states give the physical flux; alpha is the
+    largest |u -+ c| of the two states; at a stationary contact (u = 0, equal
+    pressures) HLLC gives the exact flux (0, p, 0, 0, 0) and Rusanov adds the
+    dissipation -alpha (U_R - U_L)/2."""
+    g = 1.4
+    w = np.array([1.2, 0.3, -0.1, 0.2, 0.9])
+    for d in range(3):
+        assert np.allclose(oracle.rusanov(g, w, w, d), oracle.euler_flux(g, w, d), rtol=1e-15, atol=1e-15)
+    wl_ = np.array([1.0, 0.0, 0.0, 0.0, 1.0])
+    wr_ = np.array([0.25, 0.0, 0.0, 0.0, 1.0])
+    a = max(math.sqrt(g * 1.0 / 1.0), math.sqrt(g * 1.0 / 0.25))
+    F = oracle.rusanov(g, wl_, wr_, 0)
+    Fh = oracle.hllc(g, wl_, wr_, 0)
+    assert np.allclose(Fh, [0.0, 1.0, 0.0, 0.0, 0.0], atol=1e-15)
+    assert np.allclose(F, [-0.5 * a * (0.25 - 1.0), 1.0, 0.0, 0.0, 0.0], rtol=1e-14)
+    assert abs(F[4] - (-0.5 * a * (1.0 / 0.4 - 1.0 / 0.4))) < 1e-14
+
+
+def test_implosion_scheme_sod_and_walled_conservation():
+    """The implosion's scheme (WENO3-JS + TVD-RK2, HLLC or Rusanov): Sod
+    converges to the exact solution, Rusanov more diffusively than HLLC; on the
+    walled implosion mass and energy are conserved to rounding (the wall
+    fluxes of mirrored states carry neither)."""
+    e = ExactRiemann((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    l1 = {}
+    for flux in (0, wl.RUSANOV):
+        for n in (100, 200, 400):
+            case, W = wl.sod(n)
+            case["flags"] |= wl.WENO3 | wl.RK2 | flux
+            U, t, _ = oracle.advance(case, oracle.state_init(case, W), 100000, t_end=0.2)
+            rho = oracle.interior(case, U).reshape(5, n)[0]
+            l1[(flux, n)] = float(np.mean(np.abs(rho - e.cell_average_profile(n, 0.2)[0])))
+        assert l1[(flux, 100)] > l1[(flux, 200)] > l1[(flux, 400)], l1
+    for n in (100, 200, 400):
+        assert l1[(wl.RUSANOV, n)] > l1[(0, n)], l1
+    for flux in (0, wl.RUSANOV):
+        case, W = wl.implosion(32, flags=wl.INVISCID | wl.WENO3 | wl.RK2 | flux)
+        U0 = oracle.state_init(case, W)
+        U, _, _ = oracle.advance(case, U0, 40, fixed_dt=1e-3)
+        a, b = oracle.interior(case, U0), oracle.interior(case, U)
+        for v in (0, 4):
+            s0 = math.fsum(a[v].ravel().tolist())
+            s1 = math.fsum(b[v].ravel().tolist())
+            assert abs(s1 - s0) <= 1e-13 * abs(s0), (flux, v, s0, s1)
+        assert np.max(np.abs(b - a)) > 1e-3  # the state has moved
+
+
 # ---------------------------------------------------------------- O1/O2 ----
 @pytest.mark.parametrize("bc", [wl.PERIODIC, wl.ZERO_GRADIENT])
 def test_halo_fill_matches_independent_padding(bc):
