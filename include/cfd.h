@@ -44,8 +44,11 @@ typedef enum {
 } cfd_status;
 
 /* Boundary types (§3.7): periodic (in pairs) and zero gradient, the paper's
- * "neumann" without a value. */
-typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1 } cfd_bc;
+ * "neumann" without a value; and the reflecting (slip) wall at which the
+ * implosion of §6.2 reflects its shock: the halo mirrors the interior about
+ * the boundary face with the wall-normal momentum negated. The adjoint
+ * entry points return CFD_EUNSUPPORTED for a reflecting wall. */
+typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1, CFD_BC_REFLECT = 2 } cfd_bc;
 
 /* Physics switches, after the paper's is_inviscid_flux / is_viscous_flux /
  * is_heat_flux (Appendix A), and the convective scheme. By default the
@@ -56,9 +59,17 @@ typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1 } cfd_bc;
  * the paper's ROE setup (§5): Roe-averaged eigen-decomposition at each face,
  * the stencil's states and fluxes projected on its characteristic fields,
  * split with the moduli of the Roe eigenvalues (no entropy fix), WENO5-JS per
- * field, transformed back. CFD_F_ROE with CFD_F_WENOZ is CFD_EINVAL. The
- * adjoint and the serving batch cover the default scheme only. */
-enum { CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u, CFD_F_WENOZ = 8u, CFD_F_ROE = 16u };
+ * field, transformed back. The implosion of §6.2 adds CFD_F_WENO3 (WENO3-JS
+ * reconstruction of the primitives), CFD_F_RUSANOV (the Rusanov flux
+ * (F_L + F_R)/2 - alpha (U_R - U_L)/2, alpha the largest |u -+ c| of the two
+ * states, in place of HLLC) and CFD_F_RK2 (TVD-RK2 steps in place of TVD-RK3).
+ * CFD_F_ROE combines with none of WENOZ, WENO3, RUSANOV, and CFD_F_WENOZ with
+ * neither WENO3 nor RUSANOV (CFD_EINVAL). The adjoint covers the default
+ * scheme only; the serving batch the default scheme with any boundaries. */
+enum {
+  CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u, CFD_F_WENOZ = 8u, CFD_F_ROE = 16u, CFD_F_WENO3 = 32u,
+  CFD_F_RUSANOV = 64u, CFD_F_RK2 = 128u
+};
 
 typedef struct {
   int32_t n[3];      /* interior cells (x,y,z); n[d] == 1 marks an inactive axis */
@@ -132,14 +143,14 @@ cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double d
  * (interior cells of Rbar are read; its halo is ignored). The transposed halo
  * fill folds halo contributions back into their source cells, so the halo
  * entries of Ubar are left unchanged. U is not modified. CFD_EUNSUPPORTED for
- * a WENO5-Z or ROE configuration. */
+ * a scheme other than the default or a reflecting wall. */
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar,
                            void* stream);
 
 /* Discrete adjoint of one fixed-dt TVD-RK3 step: with U^{n+1} = S(U^n),
  * Ubar_n = (dS/dU^n)^T Ubar_np1 (interior cells; Ubar_n's halo is zeroed).
  * The stage states are recomputed from Un. Ubar_n must not alias the others.
- * CFD_EUNSUPPORTED for a WENO5-Z or ROE configuration. */
+ * CFD_EUNSUPPORTED for a scheme other than the default or a reflecting wall. */
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream);
 
@@ -149,14 +160,15 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
  * buffers of cfd_state_numel doubles, distinct from U and each other; their
  * interior cells are written, their halo entries are unspecified. For
  * checkpointed reverse passes that keep the stages of a recomputed segment
- * instead of recomputing them in every step adjoint. */
+ * instead of recomputing them in every step adjoint. CFD_EUNSUPPORTED with
+ * CFD_F_RK2. */
 cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_out, double* U2_out, void* stream);
 
 /* cfd_rk3_step_adjoint with the stage states U1, U2 of the step from Un
  * supplied (as cfd_rk3_step_stages leaves them; interior cells are read)
  * instead of recomputed: the same result up to the summation order of the
  * atomics, without the two forward stages. Ubar_n must not alias any input.
- * CFD_EUNSUPPORTED for a WENO5-Z or ROE configuration. */
+ * CFD_EUNSUPPORTED for a scheme other than the default or a reflecting wall. */
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream);
 
@@ -204,8 +216,8 @@ cfd_status cfd_batch_footprint(const cfd_config* cfg, int64_t* bytes);
  * conservative initial state from W (device, 5 x interior primitives, as for
  * cfd_state_init). Returns CFD_ENOMEM, with nothing changed, when no slot or
  * arena space is free; the caller retries after removing finished grids.
- * CFD_EUNSUPPORTED for a WENO5-Z or ROE configuration (the batch runs the
- * default scheme). */
+ * CFD_EUNSUPPORTED for a WENO5-Z, ROE, WENO3, RUSANOV or RK2 configuration
+ * (the batch runs the default scheme). */
 cfd_status cfd_batch_add(cfd_batch* b, const cfd_config* cfg, const double* W, int32_t* slot_out, void* stream);
 
 /* Retire a grid and free its slot and arena space. The caller must have

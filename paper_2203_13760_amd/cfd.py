@@ -16,8 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("CFD_LIBRARY") or os.path.join(_HERE, "libcfd.so")
 
 CFD_OK, CFD_EINVAL, CFD_ENOMEM, CFD_EHIP, CFD_ENONFINITE, CFD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-CFD_BC_PERIODIC, CFD_BC_ZERO_GRADIENT = 0, 1
+CFD_BC_PERIODIC, CFD_BC_ZERO_GRADIENT, CFD_BC_REFLECT = 0, 1, 2
 CFD_F_INVISCID, CFD_F_VISCOUS, CFD_F_HEAT, CFD_F_WENOZ, CFD_F_ROE = 1, 2, 4, 8, 16
+CFD_F_WENO3, CFD_F_RUSANOV, CFD_F_RK2 = 32, 64, 128
 
 
 class CfdError(RuntimeError):

@@ -84,7 +84,8 @@ static cfd_status validate(const cfd_config* c) {
     if (!(c->hi[d] > c->lo[d]) || !std::isfinite(c->hi[d] - c->lo[d]))
       return fail(CFD_EINVAL, "box must satisfy lo < hi");
     for (int s = 0; s < 2; ++s)
-      if (c->bc[2 * d + s] != CFD_BC_PERIODIC && c->bc[2 * d + s] != CFD_BC_ZERO_GRADIENT)
+      if (c->bc[2 * d + s] != CFD_BC_PERIODIC && c->bc[2 * d + s] != CFD_BC_ZERO_GRADIENT &&
+          c->bc[2 * d + s] != CFD_BC_REFLECT)
         return fail(CFD_EINVAL, "unknown boundary type");
     if (c->n[d] > 1 && ((c->bc[2 * d] == CFD_BC_PERIODIC) != (c->bc[2 * d + 1] == CFD_BC_PERIODIC)))
       return fail(CFD_EINVAL, "periodic boundaries come in pairs");
@@ -94,9 +95,11 @@ static cfd_status validate(const cfd_config* c) {
   if (!(c->mu >= 0.0)) return fail(CFD_EINVAL, "mu must be >= 0");
   if (!(c->prandtl > 0.0)) return fail(CFD_EINVAL, "prandtl must be > 0");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return fail(CFD_EINVAL, "cfl must lie in (0, 1]");
-  if (c->flags & ~31u) return fail(CFD_EINVAL, "unknown physics flag");
-  if ((c->flags & CFD_F_ROE) && (c->flags & CFD_F_WENOZ))
-    return fail(CFD_EINVAL, "the Roe flux splitting reconstructs with WENO5-JS (flag WENOZ with ROE)");
+  if (c->flags & ~255u) return fail(CFD_EINVAL, "unknown physics flag");
+  if ((c->flags & CFD_F_ROE) && (c->flags & (CFD_F_WENOZ | CFD_F_WENO3 | CFD_F_RUSANOV)))
+    return fail(CFD_EINVAL, "the Roe flux splitting reconstructs with WENO5-JS (flag WENOZ, WENO3 or RUSANOV with ROE)");
+  if ((c->flags & CFD_F_WENOZ) && (c->flags & (CFD_F_WENO3 | CFD_F_RUSANOV)))
+    return fail(CFD_EINVAL, "WENO5-Z is combined with HLLC only (flag WENO3 or RUSANOV with WENOZ)");
   // index ranges of the kernels: faces per axis and padded planes in 32 bits,
   // padded z extent within the launch grid's y limit
   long long N[3];
@@ -136,6 +139,9 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.inviscid = (c.flags & CFD_F_INVISCID) ? 1 : 0;
   g.wenoz = (c.flags & CFD_F_WENOZ) ? 1 : 0;
   g.roe = (c.flags & CFD_F_ROE) ? 1 : 0;
+  g.weno3 = (c.flags & CFD_F_WENO3) ? 1 : 0;
+  g.rusanov = (c.flags & CFD_F_RUSANOV) ? 1 : 0;
+  g.rk2 = (c.flags & CFD_F_RK2) ? 1 : 0;
   g.viscous = ((c.flags & CFD_F_VISCOUS) && c.mu > 0.0) ? 1 : 0;
   g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
 }
@@ -181,8 +187,12 @@ static void launch_sweep_r(cfd_solver* s, int mode, const double* P, const Stage
 // instantiation for the solver's configuration.
 template <int D, bool PN>
 static void launch_sweep(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
-  if (s->g.roe) launch_sweep_r<D, PN, SCH_ROE>(s, mode, P, io, st);
-  else if (s->g.wenoz) launch_sweep_r<D, PN, SCH_Z>(s, mode, P, io, st);
+  const Geom& g = s->g;
+  if (g.roe) launch_sweep_r<D, PN, SCH_ROE>(s, mode, P, io, st);
+  else if (g.wenoz) launch_sweep_r<D, PN, SCH_Z>(s, mode, P, io, st);
+  else if (g.weno3 && g.rusanov) launch_sweep_r<D, PN, SCH_W3_RUS>(s, mode, P, io, st);
+  else if (g.weno3) launch_sweep_r<D, PN, SCH_W3>(s, mode, P, io, st);
+  else if (g.rusanov) launch_sweep_r<D, PN, SCH_JS_RUS>(s, mode, P, io, st);
   else launch_sweep_r<D, PN, SCH_JS>(s, mode, P, io, st);
 }
 
@@ -278,6 +288,16 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   io.Pn = s->Pb[1];
   io.what = 0;
   if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
+  if (s->g.rk2) {
+    // TVD-RK2, second stage: Un+1 = 1/2 Un + 1/2 (U1 + dt R(U1)), in place on U
+    io.Uk = U1;
+    io.Uout = U;
+    io.a = 0.5;
+    io.b = 0.5;
+    io.Pn = s->Pb[0];
+    io.what = PRIM_HEALTH | (cfl ? PRIM_CFL : 0);
+    return enqueue_fluxes(s, s->Pb[1], io, true, st);
+  }
   // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt R(U1))
   io.Uk = U1;
   io.Uout = U2;
@@ -401,6 +421,16 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
   hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, U, (const double*)s->Wbar, Ubar, g);
   CFD_LAUNCHED();
   return CFD_OK;
+}
+
+// The adjoint covers the default scheme (WENO5-JS, HLLC, TVD-RK3) with periodic
+// and zero-gradient boundaries.
+static bool adjoint_supported(const cfd_solver* s) {
+  const Geom& g = s->g;
+  if (g.wenoz || g.roe || g.weno3 || g.rusanov || g.rk2) return false;
+  for (int b = 0; b < 6; ++b)
+    if (g.bc[b] == CFD_BC_REFLECT) return false;
+  return true;
 }
 
 // ===========================================================================
@@ -609,7 +639,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
 
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
   if (!s || !U || !Rbar || !Ubar) return fail(CFD_EINVAL, "NULL argument");
-  if (s->g.wenoz || s->g.roe) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS with HLLC only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC, TVD-RK3 and periodic or zero-gradient boundaries only");
   if (Ubar == U || Ubar == Rbar) return fail(CFD_EINVAL, "Ubar must not alias U or Rbar");
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
@@ -621,7 +651,7 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream) {
   if (!s || !Un || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
-  if (s->g.wenoz || s->g.roe) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS with HLLC only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC, TVD-RK3 and periodic or zero-gradient boundaries only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == Ubar_np1) return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
   cfd_status rc = ensure_adjoint_scratch(s);
@@ -677,6 +707,7 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
   if (!s || !U || !U1_out || !U2_out) return fail(CFD_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (U1_out == U || U2_out == U || U1_out == U2_out) return fail(CFD_EINVAL, "the stage buffers must be distinct");
+  if (s->g.rk2) return fail(CFD_EUNSUPPORTED, "the stages kept are those of TVD-RK3");
   hipStream_t st = (hipStream_t)stream;
   cfd_status rc = enqueue_step_prologue(s, U, false, st);
   if (rc) return rc;
@@ -687,7 +718,7 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream) {
   if (!s || !Un || !U1 || !U2 || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
-  if (s->g.wenoz || s->g.roe) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS with HLLC only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC, TVD-RK3 and periodic or zero-gradient boundaries only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == U1 || Ubar_n == U2 || Ubar_n == Ubar_np1)
     return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");

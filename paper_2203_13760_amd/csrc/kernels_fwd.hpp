@@ -108,8 +108,10 @@ __device__ __forceinline__ void fill_halo_body(double* U, const Geom& g, const P
   const int sk = bc_source(p.k, g.n[2], g.bc[4], g.bc[5]);
   if (si == p.i && sj == p.j && sk == p.k) return;
   const long long s = cell_at(g, si, sj, sk);
+  const double sg[3] = {bc_sign(p.i, g.n[0], g.bc[0], g.bc[1]), bc_sign(p.j, g.n[1], g.bc[2], g.bc[3]),
+                        bc_sign(p.k, g.n[2], g.bc[4], g.bc[5])};
 #pragma unroll
-  for (int v = 0; v < NC; ++v) U[v * g.vs + p.c] = U[v * g.vs + s];
+  for (int v = 0; v < NC; ++v) U[v * g.vs + p.c] = (v >= 1 && v <= 3 ? sg[v - 1] : 1.0) * U[v * g.vs + s];
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_halo(double* U, Geom g) { fill_halo_body<5>(U, g, plane_index(g)); }
@@ -161,8 +163,10 @@ __device__ __forceinline__ void prim_halo_body(double* P, const Geom& g, long lo
   const int sj = bc_source(j, g.n[1], g.bc[2], g.bc[3]);
   const int sk = bc_source(k, g.n[2], g.bc[4], g.bc[5]);
   const long long c = cell_at(g, i, j, k), s = cell_at(g, si, sj, sk);
+  const double sg[3] = {bc_sign(i, g.n[0], g.bc[0], g.bc[1]), bc_sign(j, g.n[1], g.bc[2], g.bc[3]),
+                        bc_sign(k, g.n[2], g.bc[4], g.bc[5])};
 #pragma unroll
-  for (int v = 0; v < 6; ++v) P[v * g.vs + c] = P[v * g.vs + s];
+  for (int v = 0; v < 6; ++v) P[v * g.vs + c] = (v >= 1 && v <= 3 ? sg[v - 1] : 1.0) * P[v * g.vs + s];
 }
 
 __global__ void __launch_bounds__(kBlock) k_prim_halo(double* P, Geom g, const double* dtp) {
@@ -268,6 +272,9 @@ __device__ __forceinline__ void prim_body(const double* __restrict__ U, double* 
     double u[5], w[6];
 #pragma unroll
     for (int v = 0; v < 5; ++v) u[v] = U[v * g.vs + s];
+    u[1] *= bc_sign(q.i, g.n[0], g.bc[0], g.bc[1]);
+    u[2] *= bc_sign(q.j, g.n[1], g.bc[2], g.bc[3]);
+    u[3] *= bc_sign(q.k, g.n[2], g.bc[4], g.bc[5]);
     cons_to_prim(g, u, w);
 #pragma unroll
     for (int v = 0; v < 6; ++v) P[v * g.vs + c] = w[v];

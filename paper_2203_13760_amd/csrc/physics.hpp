@@ -31,6 +31,9 @@ struct Geom {
   int inviscid, viscous, heat;
   int wenoz;       // WENO5-Z instead of WENO5-JS
   int roe;         // Roe flux splitting in characteristic space instead of HLLC
+  int weno3;       // WENO3-JS instead of WENO5
+  int rusanov;     // Rusanov flux instead of HLLC
+  int rk2;         // TVD-RK2 instead of TVD-RK3
 };
 
 // Convective schemes of the sweeps, a compile-time parameter: WENO5-JS or
@@ -38,6 +41,11 @@ struct Geom {
 // the flux-splitting approach with Roe eigenvalues and WENO5-JS in
 // characteristic space (§3.3; the ROE setup of §5).
 constexpr int SCH_JS = 0, SCH_Z = 1, SCH_ROE = 2;
+// and the schemes of the implosion of §6.2: WENO3-JS with HLLC, WENO3-JS or
+// WENO5-JS with the Rusanov flux
+constexpr int SCH_W3 = 3, SCH_JS_RUS = 4, SCH_W3_RUS = 5;
+__host__ __device__ constexpr bool sch_weno3(int sch) { return sch == SCH_W3 || sch == SCH_W3_RUS; }
+__host__ __device__ constexpr bool sch_rusanov(int sch) { return sch == SCH_JS_RUS || sch == SCH_W3_RUS; }
 
 __host__ __device__ __forceinline__ double sq(double x) { return x * x; }
 
@@ -68,12 +76,19 @@ __device__ __forceinline__ long long cell_at(const Geom& g, int i, int j, int k)
 }
 
 // Interior source coordinate of a (possibly halo) coordinate c on an axis with
-// n cells: periodic image or zero-gradient clamp (§3.7). Applying it per axis
-// reproduces the axis-by-axis halo fill, corners included.
+// n cells: periodic image, zero-gradient clamp (§3.7), or the mirror image
+// about a reflecting wall (the slip walls of the implosion, §6.2). Applying it
+// per axis reproduces the axis-by-axis halo fill, corners included.
 __device__ __forceinline__ int bc_source(int c, int n, int bc_lo, int bc_hi) {
-  if (c < 0) return bc_lo == 0 ? c + n : 0;
-  if (c >= n) return bc_hi == 0 ? c - n : n - 1;
+  if (c < 0) return bc_lo == 0 ? c + n : (bc_lo == 2 ? -1 - c : 0);
+  if (c >= n) return bc_hi == 0 ? c - n : (bc_hi == 2 ? 2 * n - 1 - c : n - 1);
   return c;
+}
+
+// Factor of the axis's velocity (momentum) component in the image of c: -1
+// through a reflecting wall, else 1. Corner cells take the product over axes.
+__device__ __forceinline__ double bc_sign(int c, int n, int bc_lo, int bc_hi) {
+  return ((c < 0 && bc_lo == 2) || (c >= n && bc_hi == 2)) ? -1.0 : 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -122,6 +137,46 @@ __host__ __device__ __forceinline__ double weno5z(double a, double b, double c, 
   const double P1 = -b + 5.0 * c + 2.0 * d;
   const double P2 = 2.0 * c + 5.0 * d - e;
   return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
+}
+
+// WENO3-JS (Jiang & Shu 1996, r = 2) value at the right face of the centre
+// cell b of the stencil (a, b, c): candidates (3b - a)/2 and (b + c)/2,
+// smoothness indicators (b - a)^2 and (c - b)^2, linear weights (1/3, 2/3),
+// alpha_k = d_k/(1e-6 + beta_k)^2, normalised; one division as in weno5.
+__host__ __device__ __forceinline__ double weno3(double a, double b, double c) {
+  constexpr double eps = 1.0e-6;
+  const double s0 = sq(eps + sq(b - a)), s1 = sq(eps + sq(c - b));
+  const double w0 = s1, w1 = 2.0 * s0;  // (1/3)/s0 : (2/3)/s1, times 3 s0 s1
+  return div_nr(w0 * (3.0 * b - a) + w1 * (b + c), 2.0 * (w0 + w1));
+}
+
+// Rusanov (local Lax-Friedrichs) flux of §6.2 across a face normal to axis D
+// from reconstructed primitive states: (F_L + F_R)/2 - alpha (U_R - U_L)/2 with
+// alpha the largest |u -+ c| of the two states (u normal to the face).
+template <int D>
+__host__ __device__ __forceinline__ void rusanov(double gamma, double gm1i, const double* WL, const double* WR,
+                                                 double* F) {
+  const double rL = WL[0], pL = WL[4], rR = WR[0], pR = WR[4];
+  const double uL = WL[1 + D], uR = WR[1 + D];
+  const double kL = 0.5 * rL * (WL[1] * WL[1] + WL[2] * WL[2] + WL[3] * WL[3]);
+  const double kR = 0.5 * rR * (WR[1] * WR[1] + WR[2] * WR[2] + WR[3] * WR[3]);
+  const double EL = pL * gm1i + kL, ER = pR * gm1i + kR;
+  const double cL = sqrt(div_nr(gamma * pL, rL)), cR = sqrt(div_nr(gamma * pR, rR));
+  const double alpha = fmax(fmax(fabs(uL - cL), fabs(uL + cL)), fmax(fabs(uR - cR), fabs(uR + cR)));
+  const double UL[5] = {rL, rL * WL[1], rL * WL[2], rL * WL[3], EL};
+  const double UR[5] = {rR, rR * WR[1], rR * WR[2], rR * WR[3], ER};
+  double FL[5], FR[5];
+  FL[0] = rL * uL;
+  FR[0] = rR * uR;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    FL[1 + a] = FL[0] * WL[1 + a] + (a == D ? pL : 0.0);
+    FR[1 + a] = FR[0] * WR[1 + a] + (a == D ? pR : 0.0);
+  }
+  FL[4] = uL * (EL + pL);
+  FR[4] = uR * (ER + pR);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * alpha * (UR[v] - UL[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,11 +303,14 @@ __host__ __device__ __forceinline__ void sub_dissipative(const Geom& g, const Fa
   }
 }
 
-template <int D>
+template <int D, bool RUS = false>
 __host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const double* WL, const double* WR,
                                                       const FaceWindow& w, const double* tf, double* G) {
   double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (g.inviscid) hllc<D>(g.gamma, g.gm1i, WL, WR, F);
+  if (g.inviscid) {
+    if constexpr (RUS) rusanov<D>(g.gamma, g.gm1i, WL, WR, F);
+    else hllc<D>(g.gamma, g.gm1i, WL, WR, F);
+  }
   sub_dissipative<D>(g, w, tf, F);
 #pragma unroll
   for (int v = 0; v < 5; ++v) G[v] = F[v];
@@ -364,7 +422,10 @@ __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceW
   if (g.inviscid) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      if constexpr (SCH == SCH_Z) {
+      if constexpr (sch_weno3(SCH)) {
+        WL[v] = weno3(w.q[1][v], w.q[2][v], w.q[3][v]);
+        WR[v] = weno3(w.q[4][v], w.q[3][v], w.q[2][v]);
+      } else if constexpr (SCH == SCH_Z) {
         WL[v] = weno5z(w.q[0][v], w.q[1][v], w.q[2][v], w.q[3][v], w.q[4][v]);
         WR[v] = weno5z(w.q[5][v], w.q[4][v], w.q[3][v], w.q[2][v], w.q[1][v]);
       } else {
@@ -373,7 +434,7 @@ __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceW
       }
     }
   }
-  face_flux_lr<D>(g, WL, WR, w, tf, G);
+  face_flux_lr<D, sch_rusanov(SCH)>(g, WL, WR, w, tf, G);
 }
 
 // Numerical flux G = F - F^d across the face (§3.3, §3.4) from a full window.

@@ -61,7 +61,7 @@ BAD_CONFIGS = [
     ("short axis", dict(n=(32, 2, 16)), "n >= nh"),
     ("zero cells", dict(n=(32, 0, 16)), "n must be"),
     ("empty box", dict(hi=(1.0, 0.0, 1.0)), "lo < hi"),
-    ("boundary type", dict(bc=(0, 0, 7, 7, 0, 0)), "boundary"),
+    ("boundary type", dict(bc=(0, 0, 3, 3, 0, 0)), "boundary"),
     ("unpaired periodic", dict(bc=(0, 1, 0, 0, 0, 0)), "pairs"),
     ("no active axis", dict(n=(1, 1, 1)), "no active axis"),
     ("gamma", dict(gamma=1.0), "gamma"),
@@ -69,8 +69,10 @@ BAD_CONFIGS = [
     ("prandtl", dict(prandtl=0.0), "prandtl"),
     ("cfl zero", dict(cfl=0.0), "cfl"),
     ("cfl above one", dict(cfl=1.5), "cfl"),
-    ("unknown flag", dict(flags=32), "flag"),
+    ("unknown flag", dict(flags=256), "flag"),
     ("roe with wenoz", dict(flags=1 | 8 | 16), "WENO5-JS"),
+    ("roe with rusanov", dict(flags=1 | 16 | 64), "WENO5-JS"),
+    ("wenoz with weno3", dict(flags=1 | 8 | 32), "WENO5-Z"),
     ("too many faces", dict(n=(2048, 2048, 600)), "too large"),
 ]
 

@@ -428,3 +428,105 @@ def test_roe_is_rejected_where_unsupported(Solver):
         assert e.value.code == cfd.CFD_EUNSUPPORTED
     finally:
         cfd.cfd_batch_destroy(b)
+
+
+# ---------------------------------------------------------------- implosion substrate (§6.2)
+def _walls(case_W, axes):
+    case, W = case_W
+    case = dict(case)
+    bc = list(case["bc"])
+    for d in axes:
+        bc[2 * d] = bc[2 * d + 1] = wl.REFLECT
+    case["bc"] = tuple(bc)
+    return case, W
+
+
+F3_CASES = {
+    # reflecting walls on each sweep kind (x sweep, y and z marches), default scheme;
+    # smooth data: on random blocks the WENO5 reconstruction next to a wall can
+    # give a negative pressure, where the sound speed is not a number and
+    # neither side's flux means anything (the implosion cases carry jumps to
+    # the walls within the scheme's range)
+    "walls_x_sod": _walls(wl.sod(120), [0]),
+    "walls_yz_smooth": _walls(wl.random_smooth((21, 19, 17), seed=13, mu=0.0, flags=wl.INVISCID), [1, 2]),
+    "walls_xyz_smooth_viscous": _walls(wl.random_smooth((17, 15, 13), seed=14, mu=0.02), [0, 1, 2]),
+    # the implosion's schemes
+    "w3_hllc_rk2_shocky": (lambda c: (dict(c[0], flags=c[0]["flags"] | wl.WENO3 | wl.RK2), c[1]))(
+        wl.random_shocky((37, 13, 9), seed=11)),
+    "js_rusanov_shocky": (lambda c: (dict(c[0], flags=c[0]["flags"] | wl.RUSANOV), c[1]))(
+        wl.random_shocky((37, 13, 9), seed=11)),
+    "w3_rusanov_rk2_viscous": (lambda c: (dict(c[0], flags=c[0]["flags"] | wl.WENO3 | wl.RUSANOV | wl.RK2), c[1]))(
+        wl.random_smooth((24, 20, 18), seed=15, mu=0.02)),
+    "implosion32_hllc": wl.implosion(32),
+    "implosion32_rusanov": wl.implosion(32, flags=wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV),
+}
+
+
+@pytest.mark.parametrize("name", list(F3_CASES))
+def test_implosion_substrate_rhs_and_step_match_oracle(Solver, name):
+    """Reflecting walls, WENO3-JS, Rusanov and TVD-RK2 against the oracle: the
+    right-hand side and one CFL step."""
+    case, W = F3_CASES[name]
+    _say(f"implosion substrate rhs + 1-step parity: {name}")
+    s = Solver(case)
+    U = s.init(W)
+    R = s.rhs(U).cpu().numpy()
+    Uo = oracle.state_init(case, W)
+    Ro = oracle.rhs(case, Uo)
+    bound = oracle.rhs_rounding_bound(case, Uo)
+    for v in range(5):
+        err = float(np.max(np.abs(R[v] - Ro[v])))
+        assert err <= max(TOL_ONE * float(np.max(np.abs(Ro[v]))), bound[v]), (name, v, err, bound[v])
+    dt_gpu = s.step(U)
+    Uo1, dto = oracle.rk3_step(case, Uo)
+    assert abs(float(dt_gpu.item()) - dto) <= 1e-14 * dto
+    e = normwise(U.cpu().numpy(), Uo1)
+    s.close()
+    assert e <= TOL_ONE, (name, e)
+
+
+@pytest.mark.parametrize("name", ["implosion32_hllc", "implosion32_rusanov"])
+def test_implosion_100_fixed_steps_match_oracle(Solver, name):
+    """The implosion at 32^2 through 100 fixed steps of 1e-3 (the coarse step
+    of §6.2), shock reflected at the walls."""
+    case, W = F3_CASES[name]
+    _say(f"implosion 100-step parity: {name}")
+    s = Solver(case)
+    U = s.init(W)
+    s.advance_fixed(U, 100, 1e-3)
+    Uo, _, _ = oracle.advance(case, oracle.state_init(case, W), 100, fixed_dt=1e-3)
+    e = normwise(U.cpu().numpy(), Uo)
+    s.close()
+    assert e <= TOL_100, (name, e)
+
+
+def test_implosion_substrate_is_rejected_where_unsupported(Solver):
+    """The adjoint covers the default scheme without walls; the serving batch
+    the default scheme (walls included); the kept-stage step TVD-RK3."""
+    from paper_2203_13760_amd import cfd
+    for flags, walls in ((wl.INVISCID | wl.WENO3, False), (wl.INVISCID | wl.RUSANOV, False),
+                         (wl.INVISCID | wl.RK2, False), (wl.INVISCID, True)):
+        case, W = wl.random_smooth((12, 10, 8), seed=1, mu=0.0, flags=flags)
+        if walls:
+            case, W = _walls((case, W), [0])
+        s = Solver(case)
+        U = s.init(W)
+        with pytest.raises(cfd.CfdError) as e:
+            s.step_adjoint(U, 1e-3, torch.ones_like(U), torch.empty_like(U))
+        assert e.value.code == cfd.CFD_EUNSUPPORTED
+        if flags & wl.RK2:
+            with pytest.raises(cfd.CfdError) as e:
+                s.step_stages(U, 1e-3, torch.empty_like(U), torch.empty_like(U))
+            assert e.value.code == cfd.CFD_EUNSUPPORTED
+        s.close()
+        b = cfd.cfd_batch_create(4, 1 << 26)
+        try:
+            if walls:
+                assert cfd.cfd_batch_add(b, case, torch.from_numpy(W).cuda()) is not None
+            else:
+                with pytest.raises(cfd.CfdError) as e:
+                    cfd.cfd_batch_add(b, case, torch.from_numpy(W).cuda())
+                assert e.value.code == cfd.CFD_EUNSUPPORTED
+        finally:
+            torch.cuda.synchronize()
+            cfd.cfd_batch_destroy(b)

@@ -41,6 +41,8 @@ def _mix():
         wl.random_smooth((33, 29, 35), seed=3, mu=0.02, bc=(P, P, Z, Z, P, P)),
         # no x axis: the primitive pass at every stage instead of the x sweep's
         wl.random_shocky((1, 26, 19), seed=5),
+        # reflecting walls (the implosion of §6.2 with the default scheme)
+        wl.implosion(40, flags=wl.INVISCID),
     ]
 
 
@@ -68,7 +70,7 @@ def _run(cfd, grids, steps):
 
 def test_batched_path_matches_oracle(cfd):
     grids = _mix()
-    print("batched parity: 6 mixed grids, 20 steps", flush=True)
+    print("batched parity: 7 mixed grids, 20 steps", flush=True)
     got = _run(cfd, grids, 20)
     for (case, W), U in zip(grids, got):
         Uo, _, n = oracle.advance(case, oracle.state_init(case, W), 20)
@@ -80,7 +82,7 @@ def test_alone_equals_in_mix_bitwise(cfd):
     grids = _mix()
     print("alone vs in the mix", flush=True)
     together = _run(cfd, grids, 10)
-    for k in (0, 1, 4, 5):
+    for k in (0, 1, 4, 5, 6):
         alone = _run(cfd, [grids[k]], 10)[0]
         assert np.array_equal(alone, together[k]), k
 
