@@ -81,6 +81,7 @@ def parse():
     ap.add_argument("--adj-n", type=int, default=128)
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--no-roe", action="store_true", help="skip the ROE setup leg")
+    ap.add_argument("--no-implosion", action="store_true", help="skip the implosion (Rusanov vs HLLC) leg")
     ap.add_argument("--roe-steps", type=int, default=10)
     ap.add_argument("--serving", action="store_true",
                     help="run the serving benchmark (batched vs one at a time) instead")
@@ -202,6 +203,27 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
             "gradient_steps": nsteps, "checkpoint_every": ckpt_every, "gradient_s": tgrad[True],
             "gradient_recomputing_stages_s": tgrad[False],
             "loss": float(L.item()), "grad_norm": gnorm, "shock_gradient": sg}
+
+
+def implosion_leg():
+    """The implosion of §6.2 (the Rusanov-NN experiment's data): the 128^2
+    ground truth (WENO3-JS, TVD-RK2, HLLC, dt 2.5e-4) coarse-grained onto 32^2
+    every 1e-3, against the 32^2 solvers with the classical Rusanov flux and
+    with HLLC, over the paper's 2500 coarse steps: relative L1 errors of
+    density and pressure (the quantity of the paper's error figure)."""
+    import numpy as np
+    from paper_2203_13760_amd.experiments import implosion_trajectories
+    out = implosion_trajectories(n_cg_steps=2500, every=100)
+    keys = ("rusanov_rho", "rusanov_p", "hllc_rho", "hllc_p")
+    pick = {}
+    for t in (0.1, 1.0, 2.5):
+        i = int(np.argmin(np.abs(np.array(out["t"]) - t)))
+        pick[f"t={t}"] = {k: out[k][i] for k in keys}
+    return {"workload": "implosion of §6.2 as printed, 128^2 truth coarse-grained to 32^2, 2500 coarse steps",
+            "coarse_steps": 2500, "seconds": out["seconds"], "health": out["health"],
+            "mean": {k: float(np.mean(out[k])) for k in keys}, "at": pick,
+            "note": "the Rusanov-NN network and its training are not built; the classical Rusanov flux and "
+                    "HLLC on the coarse grid bracket what it is trained to improve"}
 
 
 def roe_leg(case, W, steps, reps, hllc_ms_per_step):
@@ -367,6 +389,14 @@ def main():
               f"({roe['over_hllc']:.2f} x the HLLC step)", flush=True)
         torch.cuda.empty_cache()
 
+    implosion = None
+    if not args.no_implosion:
+        implosion = implosion_leg()
+        print(f"bench: implosion 128^2 -> 32^2 over {implosion['coarse_steps']} coarse steps in "
+              f"{implosion['seconds']:.1f} s; mean relative L1 density error Rusanov "
+              f"{implosion['mean']['rusanov_rho']:.4f}, HLLC {implosion['mean']['hllc_rho']:.4f}", flush=True)
+        torch.cuda.empty_cache()
+
     adjoint = None
     if not args.no_adjoint:
         adjoint = differentiation(args.adj_n, args.adj_steps)
@@ -404,6 +434,7 @@ def main():
         "cpu_baseline": cpu,
         "differentiation": adjoint,
         "roe_setup": roe,
+        "implosion": implosion,
         "paper_context": {"value": 1000.0 / 92.76, "unit": "Mcell-updates/s",
                           "workload": "Taylor-Green vortex 256^3, HLLC float64, JAX on one RTX A6000"},
         "health": health,

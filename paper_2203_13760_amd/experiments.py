@@ -1,6 +1,11 @@
-"""The paper's validation of reverse-mode gradients (§6.1, "Validation of
-Automatic Differentiation Gradients"), single-phase case, on the discrete
-adjoint of libcfd.
+"""Two experiments of the paper on libcfd: the validation of reverse-mode
+gradients (§6.1, "Validation of Automatic Differentiation Gradients"),
+single-phase case, on the discrete adjoint; and the implosion of §6.2 that
+the Rusanov-NN flux is trained on, with the classical Rusanov flux and HLLC
+on the coarse grid against the coarse-grained ground truth (the network and its
+training are not part of this library).
+
+Gradient validation:
 
 A shock of Mach number M_S runs to the right into gas at rest
 (rho = p = 1, u = 0); the state behind it follows from the Rankine-Hugoniot
@@ -109,3 +114,73 @@ def shock_entropy_gradient(M0=SHOCK_M, eps=SHOCK_EPS, n=40):
                 "ad_seconds": t_ad}
     finally:
         s.close()
+
+
+# ---------------------------------------------------------------- §6.2 implosion
+def coarse_grain(U_fine, case_fine, n_cg):
+    """Block averages of the fine interior conservative state onto n_cg x n_cg
+    cells (reading: the paper's coarse-graining of the 128^2 trajectory onto
+    32^2 points, done finite-volume consistently on the conserved variables)."""
+    Ui = interior(case_fine, U_fine)  # (5, 1, n, n)
+    n = case_fine["n"][0]
+    r = n // n_cg
+    return Ui.reshape(5, 1, n_cg, r, n_cg, r).mean(dim=(3, 5))
+
+
+def _set_interior(solver, U, Ui):
+    interior(solver.case, U).copy_(Ui)
+    solver.fill_halo(U)
+
+
+def _rho_p(Ui, gamma):
+    rho = Ui[0]
+    p = (gamma - 1.0) * (Ui[4] - 0.5 * (Ui[1] ** 2 + Ui[2] ** 2 + Ui[3] ** 2) / rho)
+    return rho, p
+
+
+def implosion_trajectories(n_fine=128, n_cg=32, dt=2.5e-4, dt_cg=1e-3, n_cg_steps=2500, every=100):
+    """The implosion of §6.2: the ground truth on n_fine^2 (WENO3-JS, TVD-RK2,
+    HLLC, fixed dt), coarse-grained onto n_cg^2 every dt_cg, and the coarse
+    solvers with the Rusanov flux and with HLLC (WENO3-JS, TVD-RK2, dt_cg) run
+    from the coarse-grained initial state. Returns the relative L1 errors of
+    density and pressure against the coarse-grained truth every `every` coarse
+    steps (the quantity of the paper's error figure), on one GPU."""
+    case_f, W = wl.implosion(n_fine)
+    fine = Solver(case_f)
+    coarse = {}
+    try:
+        Uf = fine.init(W)
+        r = int(round(dt_cg / dt))
+        cg0 = coarse_grain(Uf, case_f, n_cg)
+        states = {}
+        for name, flux in (("rusanov", wl.RUSANOV), ("hllc", 0)):
+            case_c, Wc = wl.implosion(n_cg, flags=wl.INVISCID | wl.WENO3 | wl.RK2 | flux)
+            s = Solver(case_c)
+            coarse[name] = s
+            Uc = s.init(Wc)
+            _set_interior(s, Uc, cg0)
+            states[name] = Uc
+        g = case_f["gamma"]
+        out = {"step": [], "t": [], "rusanov_rho": [], "rusanov_p": [], "hllc_rho": [], "hllc_p": []}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, n_cg_steps + 1):
+            fine.advance_fixed(Uf, r, dt)
+            for name, s in coarse.items():
+                s.advance_fixed(states[name], 1, dt_cg)
+            if k % every == 0 or k == n_cg_steps:
+                rho_t, p_t = _rho_p(coarse_grain(Uf, case_f, n_cg), g)
+                out["step"].append(k)
+                out["t"].append(k * dt_cg)
+                for name, s in coarse.items():
+                    rho, p = _rho_p(interior(s.case, states[name]), g)
+                    out[f"{name}_rho"].append(float((rho - rho_t).abs().sum() / rho_t.abs().sum()))
+                    out[f"{name}_p"].append(float((p - p_t).abs().sum() / p_t.abs().sum()))
+        torch.cuda.synchronize()
+        out["seconds"] = time.perf_counter() - t0
+        out["health"] = {"fine": fine.check(), **{n: s.check() for n, s in coarse.items()}}
+        return out
+    finally:
+        fine.close()
+        for s in coarse.values():
+            s.close()

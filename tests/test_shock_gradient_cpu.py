@@ -82,3 +82,21 @@ def test_oracle_tape_gradient_second_order_against_differences():
     order = np.polyfit(np.log(eps), np.log(err), 1)[0]
     assert order >= 1.8, (order, err)
     assert err[-1] <= 1e-7 * abs(g), err
+
+
+def test_coarse_graining_conserves_totals():
+    """The implosion's coarse-graining (block averages of the conserved
+    variables): totals are kept up to the area ratio, constants stay constant."""
+    import torch
+    from paper_2203_13760_amd import workloads as wl
+    from paper_2203_13760_amd.experiments import coarse_grain
+    from paper_2203_13760_amd.solver import padded_shape, interior
+    case, _ = wl.implosion(16)
+    g = torch.Generator().manual_seed(1)
+    U = torch.rand(padded_shape(case), dtype=torch.float64, generator=g)
+    C = coarse_grain(U, case, 4)
+    assert C.shape == (5, 1, 4, 4)
+    tot_f = interior(case, U).sum(dim=(1, 2, 3))
+    assert torch.allclose(C.sum(dim=(1, 2, 3)) * 16, tot_f, rtol=1e-14, atol=0)
+    interior(case, U).fill_(2.5)
+    assert torch.all(coarse_grain(U, case, 4) == 2.5)
