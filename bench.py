@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256, help="grid side (the headline case is 256)")
-    ap.add_argument("--reps", type=int, default=5, help="kernel-timing repetitions")
+    ap.add_argument("--reps", type=int, default=30, help="kernel-timing repetitions (stages 1, 2, 3 in turn)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slab", type=int, default=48, help="z-planes of the oracle's timed slab")
     ap.add_argument("--copy-bytes", type=int, default=0)

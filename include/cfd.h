@@ -172,15 +172,16 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream);
 
-/* Measurement aid: enqueue the kernels of one TVD-RK3 stage on U as a step
- * runs them (a middle stage: U2 = 3/4 U + 1/4 (U + dt R(U)) with dt = 1e-12,
- * written to solver scratch, so U is not modified): the primitive pass, the
- * x/y/z sweeps (the last one also storing the primitives of the updated
- * cells), and the halo refresh of those primitives. Runs them `reps` times,
- * each kernel bracketed by HIP events on `stream`, synchronises, and writes the
- * average duration in milliseconds of each kernel to ms_out[0..4] in that
- * order (0 for sweeps the configuration does not launch). Within a run of
- * steps the primitive pass runs once, before the first step. */
+/* Measurement aid: enqueue the kernels of TVD-RK3 stages on U as a run of
+ * steps runs them (stage r % 3 + 1 in repetition r, with dt = 1e-12, written to
+ * solver scratch, so U is not modified; the third stage also forms the CFL
+ * maxima and health bits of its output): the primitive pass, the x/y/z sweeps
+ * (the last one also storing the primitives of the updated cells), and the
+ * halo refresh of those primitives. Runs them `reps` times (1..4096) back to
+ * back, each kernel bracketed by HIP events on `stream`, synchronises once,
+ * and writes the average duration in milliseconds of each kernel to
+ * ms_out[0..4] in that order (0 for sweeps the configuration does not launch).
+ * Within a run of steps the primitive pass runs once, before the first step. */
 cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, double* ms_out, void* stream);
 
 /* Synchronise the solver's last stream use and report its health word:

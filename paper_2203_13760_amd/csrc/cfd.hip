@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/cfd.h"
 #include "kernels_adj.hpp"
@@ -573,66 +574,77 @@ cfd_status cfd_check(cfd_solver* s, int32_t* status_out) {
 }
 
 cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, double* ms_out, void* stream) {
-  if (!s || !U || !ms_out || reps < 1) return fail(CFD_EINVAL, "bad argument");
+  if (!s || !U || !ms_out || reps < 1 || reps > 4096) return fail(CFD_EINVAL, "bad argument");
   hipStream_t st = (hipStream_t)stream;
   const Geom& g = s->g;
   // a fixed nonzero step so that the stage kernels do their work
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, 1e-12, 0.0, (double*)nullptr,
                      (double*)nullptr, s->partial, s->npart);
   CFD_LAUNCHED();
-  // a middle stage of a step: U2 = 3/4 U + 1/4 (U + dt R(U)) into scratch, its
-  // primitives into Pb[1]
-  StageIO io{};
-  io.R = s->Racc;
-  io.Un = U;
-  io.Uk = U;
-  io.Uout = s->U2;
-  io.a = 0.75;
-  io.b = 0.25;
-  io.dtp = &s->ctl->dt;
-  io.Pn = s->Pb[1];
-  io.partial = s->partial;
-  io.ctl = s->ctl;
-  io.what = 0;
   int first = -1, last = -1;
   sweep_order(g, first, last);
   // slots of ms_out: prim pass, x, y, z sweeps, halo refresh of the next
-  // primitives; event e+1 closes the kernel launched after event e
+  // primitives. Repetition r runs stage r % 3 + 1 of a step as a run of steps
+  // does (the third with the CFL maxima and health bits of its output), into
+  // scratch; all repetitions run back to back, each kernel between two events,
+  // and the stream is synchronised once at the end.
   constexpr int K = 5;
-  hipEvent_t ev[K + 1];
-  for (int e = 0; e <= K; ++e) CFD_HIP(hipEventCreate(&ev[e]));
-  double acc[K] = {0, 0, 0, 0, 0};
+  std::vector<hipEvent_t> ev((size_t)reps * (K + 1));
+  std::vector<int> slot((size_t)reps * (K + 1), -1);
   cfd_status rc = CFD_OK;
+  size_t made = 0;
+  for (; made < ev.size(); ++made)
+    if (hipEventCreate(&ev[made]) != hipSuccess) {
+      rc = fail(CFD_EHIP, "hipEventCreate failed");
+      break;
+    }
   for (int r = 0; r < reps && rc == CFD_OK; ++r) {
-    int slot_of[K];
-    int e = 0;
-    (void)hipEventRecord(ev[e], st);
-    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0, io.dtp,
-                       s->partial);
-    slot_of[e] = 0;
-    (void)hipEventRecord(ev[++e], st);
+    const int stage = r % 3;
+    StageIO io{};
+    io.R = s->Racc;
+    io.Un = U;
+    io.Uk = U;
+    io.Uout = s->U2;
+    io.a = stage == 0 ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+    io.b = stage == 0 ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+    io.dtp = &s->ctl->dt;
+    io.Pn = s->Pb[1];
+    io.partial = s->partial;
+    io.ctl = s->ctl;
+    io.what = stage == 2 ? (PRIM_HEALTH | PRIM_CFL) : 0;
+    hipEvent_t* e = ev.data() + (size_t)r * (K + 1);
+    int* sl = slot.data() + (size_t)r * (K + 1);
+    int n = 0;
+    (void)hipEventRecord(e[n], st);
+    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0, io.dtp, s->partial);
+    sl[n] = 0;
+    (void)hipEventRecord(e[++n], st);
     for (int d = 2; d >= 0; --d) {
       if (!g.act[d]) continue;
       int mode = d == last ? (d == first ? MODE_WRITE_RK : MODE_ACC_RK) : (d == first ? MODE_WRITE : MODE_ACC);
       if (d == last) launch_sweep_axis<true>(s, d, mode, s->P, io, st);
       else launch_sweep_axis<false>(s, d, mode, s->P, io, st);
-      slot_of[e] = 1 + d;
-      (void)hipEventRecord(ev[++e], st);
+      sl[n] = 1 + d;
+      (void)hipEventRecord(e[++n], st);
     }
     hipLaunchKernelGGL(k_prim_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, io.Pn, g, io.dtp);
-    slot_of[e] = 4;
-    (void)hipEventRecord(ev[++e], st);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
-      rc = fail(CFD_EHIP, "profiled stage failed");
-      break;
-    }
-    for (int k = 0; k < e; ++k) {
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-      acc[slot_of[k]] += ms;
-    }
+    sl[n] = 4;
+    (void)hipEventRecord(e[++n], st);
+    if (hipGetLastError() != hipSuccess) rc = fail(CFD_EHIP, "profiled stage failed");
   }
-  for (int e = 0; e <= K; ++e) (void)hipEventDestroy(ev[e]);
+  double acc[K] = {0, 0, 0, 0, 0};
+  if (rc == CFD_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(CFD_EHIP, "profiled stage failed");
+  for (int r = 0; r < reps && rc == CFD_OK; ++r)
+    for (int k = 0; k < K; ++k) {
+      const int sl = slot[(size_t)r * (K + 1) + k];
+      if (sl < 0) continue;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[(size_t)r * (K + 1) + k], ev[(size_t)r * (K + 1) + k + 1]);
+      acc[sl] += ms;
+    }
+  for (size_t e = 0; e < made; ++e) (void)hipEventDestroy(ev[e]);
+  // the CFL maxima of the third stages are nobody's: clear them
+  if (rc == CFD_OK) rc = enqueue_clear_slots(s, st);
   for (int k = 0; k < K; ++k) ms_out[k] = acc[k] / reps;
   return rc;
 }
