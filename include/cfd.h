@@ -105,7 +105,8 @@ int64_t cfd_state_numel(const cfd_solver* s);
 cfd_status cfd_state_init(cfd_solver* s, const double* W, double* U, void* stream);
 
 /* Refresh the halo cells of U in place from its interior, per the boundary
- * types (§3.7): periodic images or zero-gradient copies, x then y then z. */
+ * types (§3.7): periodic images, zero-gradient copies or mirror images with
+ * the wall-normal momentum negated (reflecting walls), x then y then z. */
 cfd_status cfd_fill_halo(cfd_solver* s, double* U, void* stream);
 
 /* Right-hand side of the semi-discrete scheme (§3.1, Eq. FVD):
