@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--adj-n", type=int, default=128)
     ap.add_argument("--adj-steps", type=int, default=200)
-    ap.add_argument("--no-roe", action="store_true", help="skip the ROE setup leg")
+    ap.add_argument("--no-roe", action="store_true", help="skip the ROE setup and WENO5-Z legs")
     ap.add_argument("--no-implosion", action="store_true", help="skip the implosion (Rusanov vs HLLC) leg")
     ap.add_argument("--roe-steps", type=int, default=10)
     ap.add_argument("--serving", action="store_true",
@@ -226,16 +226,14 @@ def implosion_leg():
                     "HLLC on the coarse grid bracket what it is trained to improve"}
 
 
-def roe_leg(case, W, steps, reps, hllc_ms_per_step):
-    """The paper's ROE setup (Roe flux splitting, WENO5-JS in characteristic
-    space) on the same field and grid: CFL steps per second and the stage
-    kernels' durations."""
+def scheme_leg(case, W, steps, reps, hllc_ms_per_step, flag):
+    """Another convective scheme (a configuration flag) on the same field and
+    grid: CFL steps per second and the stage kernels' durations."""
     import torch
     from paper_2203_13760_amd import cfd
-    from paper_2203_13760_amd import workloads as wl
     from paper_2203_13760_amd.solver import Solver
     case = dict(case)
-    case["flags"] = case["flags"] | wl.ROE
+    case["flags"] = case["flags"] | flag
     n = case["n"][0]
     s = Solver(case)
     try:
@@ -254,9 +252,17 @@ def roe_leg(case, W, steps, reps, hllc_ms_per_step):
     ms_per_step = sec / steps * 1e3
     return {"value": n ** 3 * steps / sec / 1e6, "unit": "Mcell-updates/s", "steps": steps,
             "ms_per_step": ms_per_step, "over_hllc": ms_per_step / hllc_ms_per_step,
-            "kernel_ms": {k: round(v, 4) for k, v in zip(KERNELS, ms)}, "health": health,
-            "paper_context": {"value": 1000.0 / 760.09, "unit": "Mcell-updates/s",
-                              "workload": "256^3, ROE float64, JAX on one RTX A6000 (8.2 x its HLLC step)"}}
+            "kernel_ms": {k: round(v, 4) for k, v in zip(KERNELS, ms)}, "health": health}
+
+
+def roe_leg(case, W, steps, reps, hllc_ms_per_step):
+    """The paper's ROE setup (Roe flux splitting, WENO5-JS in characteristic
+    space) on the same field and grid."""
+    from paper_2203_13760_amd import workloads as wl
+    out = scheme_leg(case, W, steps, reps, hllc_ms_per_step, wl.ROE)
+    out["paper_context"] = {"value": 1000.0 / 760.09, "unit": "Mcell-updates/s",
+                            "workload": "256^3, ROE float64, JAX on one RTX A6000 (8.2 x its HLLC step)"}
+    return out
 
 
 def serving_bench(args):
@@ -389,6 +395,13 @@ def main():
               f"({roe['over_hllc']:.2f} x the HLLC step)", flush=True)
         torch.cuda.empty_cache()
 
+    wenoz = None
+    if not args.no_roe:
+        wenoz = scheme_leg(case, W, args.roe_steps, args.reps, ms_per_step, wl.WENOZ)
+        print(f"bench: WENO5-Z {wenoz['value']:.1f} Mcell-updates/s ({wenoz['over_hllc']:.2f} x the WENO5-JS step)",
+              flush=True)
+        torch.cuda.empty_cache()
+
     implosion = None
     if not args.no_implosion:
         implosion = implosion_leg()
@@ -434,6 +447,7 @@ def main():
         "cpu_baseline": cpu,
         "differentiation": adjoint,
         "roe_setup": roe,
+        "wenoz": wenoz,
         "implosion": implosion,
         "paper_context": {"value": 1000.0 / 92.76, "unit": "Mcell-updates/s",
                           "workload": "Taylor-Green vortex 256^3, HLLC float64, JAX on one RTX A6000"},
