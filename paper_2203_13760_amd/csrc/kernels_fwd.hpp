@@ -480,6 +480,15 @@ __device__ __forceinline__ void finish_prims(const StageIO& io, double smax, int
   if (bad) atomicOr(&io.ctl->status, bad);
 }
 
+// Value of x in the lane below (lane - 1) across the whole wavefront, by one
+// DPP move per 32-bit half (wavefront shift right by one lane, a VALU
+// operation instead of an LDS permute); lane 0 receives 0.
+__device__ __forceinline__ double lane_shr1(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // x sweep: every interior row holds kXCtx context slots followed by its nx+1
 // faces, and the slots of all rows are numbered row-major; slot s of a row is
 // face f = s - kXCtx, lying between cells f-1 and f. A wavefront takes 64
@@ -533,16 +542,16 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
     double tf[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const double t0 = __shfl(d[v], (lane - 3) & 63, 64);
-      const double t1 = __shfl(d[v], (lane - 2) & 63, 64);
-      const double t2 = __shfl(d[v], (lane - 1) & 63, 64);
+      const double t2 = lane_shr1(d[v]);
+      const double t1 = lane_shr1(t2);
+      const double t0 = lane_shr1(t1);
       tf[v] = rc4(t0, t1, t2, d[v]);
     }
     double G[5];
     face_flux_tf<0, SCH>(g, w, tf, G);
     double Gm[5];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) Gm[v] = __shfl_up(G[v], 1, 64);
+    for (int v = 0; v < 5; ++v) Gm[v] = lane_shr1(G[v]);
     if (valid && gs >= first && f >= 1) {
       double D[5];
 #pragma unroll
