@@ -587,3 +587,63 @@ def test_full_size_run_conserves_mass_momentum_energy(Solver, which, steps):
         assert abs(t1[v] - t0[v]) <= 1e-12 * abs(t0[v]), (which, v, t0[v], t1[v])
     for v in (1, 2, 3):
         assert abs(t1[v] - t0[v]) <= 1e-12 * mscale, (which, v, t0[v], t1[v])
+
+
+# ---------------------------------------------------------------- randomized configurations
+def _random_config(rng):
+    """A small valid configuration: 1-3 active axes of 3..22 cells (ragged),
+    per-axis boundaries (periodic pair, zero gradient, reflecting walls, mixed
+    zero-gradient/wall), a scheme (WENO5-JS/Z, ROE, WENO3 with HLLC or
+    Rusanov), TVD-RK3 or RK2, with or without viscous and heat fluxes; smooth
+    seeded data (the schemes' positivity limits stay out of the way)."""
+    while True:
+        n = [int(rng.integers(3, 23)) if rng.random() < 0.75 else 1 for _ in range(3)]
+        if any(x > 1 for x in n):
+            break
+    bc = []
+    for d in range(3):
+        r = rng.random()
+        if r < 0.35:
+            bc += [wl.PERIODIC, wl.PERIODIC]
+        elif r < 0.6:
+            bc += [wl.ZERO_GRADIENT, wl.ZERO_GRADIENT]
+        elif r < 0.85:
+            bc += [wl.REFLECT, wl.REFLECT]
+        else:
+            bc += [wl.ZERO_GRADIENT, wl.REFLECT]
+    scheme = [0, wl.WENOZ, wl.ROE, wl.WENO3, wl.WENO3 | wl.RUSANOV, wl.RUSANOV][int(rng.integers(0, 6))]
+    flags = wl.INVISCID | scheme
+    if rng.random() < 0.5:
+        flags |= wl.RK2
+    mu = 0.0
+    if rng.random() < 0.5:
+        flags |= [wl.VISCOUS, wl.HEAT, wl.VISCOUS | wl.HEAT][int(rng.integers(0, 3))]
+        mu = float(rng.uniform(0.005, 0.05))
+    case, W = wl.random_smooth(tuple(n), seed=int(rng.integers(1 << 30)), mu=mu, flags=flags, bc=tuple(bc))
+    return case, W
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_random_configurations_match_oracle(Solver, k):
+    """Ten seeded random configurations per case (80 in all): the right-hand
+    side against the oracle within the rounding bound, one CFL step within
+    1e-12 normwise, the step sizes within 1e-14."""
+    rng = np.random.default_rng(1000 + k)
+    for t in range(10):
+        case, W = _random_config(rng)
+        _say(f"random config {k}.{t}: n={case['n']} bc={case['bc']} flags={case['flags']} mu={case['mu']:.3g}")
+        s = Solver(case)
+        U = s.init(W)
+        R = s.rhs(U).cpu().numpy()
+        Uo = oracle.state_init(case, W)
+        Ro = oracle.rhs(case, Uo)
+        bound = oracle.rhs_rounding_bound(case, Uo)
+        for v in range(5):
+            err = float(np.max(np.abs(R[v] - Ro[v])))
+            assert err <= max(TOL_ONE * float(np.max(np.abs(Ro[v]))), bound[v]), (k, t, case, v, err, bound[v])
+        dt_gpu = s.step(U)
+        Uo1, dto = oracle.rk3_step(case, Uo)
+        assert abs(float(dt_gpu.item()) - dto) <= 1e-14 * dto, (k, t, case)
+        e = normwise(U.cpu().numpy(), Uo1)
+        s.close()
+        assert e <= TOL_ONE, (k, t, case, e)

@@ -127,3 +127,25 @@ def test_server_batched_and_one_at_a_time_agree(cfd):
     ref = wl.kelvin_helmholtz(n)[1] if r0.case["n"][2] == 1 else wl.taylor_green(n)[1]
     if r0.case["n"][2] != 1:
         assert np.allclose(r0.make_W().cpu().numpy(), ref, rtol=0, atol=1e-14)
+
+
+def test_random_mix_matches_oracle(cfd):
+    """Eight seeded random grids of the default scheme (1-3 active axes,
+    periodic, zero-gradient or reflecting boundaries, with and without viscous
+    and heat fluxes) resident together, 10 steps each, against the oracle."""
+    rng = np.random.default_rng(77)
+    grids = []
+    while len(grids) < 8:
+        n = tuple(int(rng.integers(3, 30)) if rng.random() < 0.75 else 1 for _ in range(3))
+        if all(x == 1 for x in n):
+            continue
+        bc = []
+        for _ in range(3):
+            bc += [[wl.PERIODIC] * 2, [wl.ZERO_GRADIENT] * 2, [wl.REFLECT] * 2][int(rng.integers(0, 3))]
+        flags = wl.INVISCID | [0, wl.VISCOUS | wl.HEAT][int(rng.integers(0, 2))]
+        grids.append(wl.random_smooth(n, seed=int(rng.integers(1 << 30)), mu=0.02, flags=flags, bc=tuple(bc)))
+    print("random batched mix: 8 grids, 10 steps", flush=True)
+    got = _run(cfd, grids, 10)
+    for (case, W), U in zip(grids, got):
+        Uo, _, _ = oracle.advance(case, oracle.state_init(case, W), 10)
+        assert normwise(U, Uo) <= 1e-10, (case["n"], case["bc"], case["flags"])
