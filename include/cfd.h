@@ -46,8 +46,7 @@ typedef enum {
 /* Boundary types (§3.7): periodic (in pairs) and zero gradient, the paper's
  * "neumann" without a value; and the reflecting (slip) wall at which the
  * implosion of §6.2 reflects its shock: the halo mirrors the interior about
- * the boundary face with the wall-normal momentum negated. The adjoint
- * entry points return CFD_EUNSUPPORTED for a reflecting wall. */
+ * the boundary face with the wall-normal momentum negated. */
 typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1, CFD_BC_REFLECT = 2 } cfd_bc;
 
 /* Physics switches, after the paper's is_inviscid_flux / is_viscous_flux /
@@ -144,14 +143,14 @@ cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double d
  * (interior cells of Rbar are read; its halo is ignored). The transposed halo
  * fill folds halo contributions back into their source cells, so the halo
  * entries of Ubar are left unchanged. U is not modified. CFD_EUNSUPPORTED for
- * a scheme other than the default or a reflecting wall. */
+ * a scheme other than the default. */
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar,
                            void* stream);
 
 /* Discrete adjoint of one fixed-dt TVD-RK3 step: with U^{n+1} = S(U^n),
  * Ubar_n = (dS/dU^n)^T Ubar_np1 (interior cells; Ubar_n's halo is zeroed).
  * The stage states are recomputed from Un. Ubar_n must not alias the others.
- * CFD_EUNSUPPORTED for a scheme other than the default or a reflecting wall. */
+ * CFD_EUNSUPPORTED for a scheme other than the default. */
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream);
 
@@ -169,7 +168,7 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
  * supplied (as cfd_rk3_step_stages leaves them; interior cells are read)
  * instead of recomputed: the same result up to the summation order of the
  * atomics, without the two forward stages. Ubar_n must not alias any input.
- * CFD_EUNSUPPORTED for a scheme other than the default or a reflecting wall. */
+ * CFD_EUNSUPPORTED for a scheme other than the default. */
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream);
 

@@ -424,14 +424,11 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
   return CFD_OK;
 }
 
-// The adjoint covers the default scheme (WENO5-JS, HLLC, TVD-RK3) with periodic
-// and zero-gradient boundaries.
+// The adjoint covers the default scheme (WENO5-JS, HLLC, TVD-RK3), with any
+// boundaries.
 static bool adjoint_supported(const cfd_solver* s) {
   const Geom& g = s->g;
-  if (g.wenoz || g.roe || g.weno3 || g.rusanov || g.rk2) return false;
-  for (int b = 0; b < 6; ++b)
-    if (g.bc[b] == CFD_BC_REFLECT) return false;
-  return true;
+  return !(g.wenoz || g.roe || g.weno3 || g.rusanov || g.rk2);
 }
 
 // ===========================================================================
@@ -651,7 +648,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
 
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
   if (!s || !U || !Rbar || !Ubar) return fail(CFD_EINVAL, "NULL argument");
-  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC, TVD-RK3 and periodic or zero-gradient boundaries only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC and TVD-RK3 only");
   if (Ubar == U || Ubar == Rbar) return fail(CFD_EINVAL, "Ubar must not alias U or Rbar");
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
@@ -663,7 +660,7 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream) {
   if (!s || !Un || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
-  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC, TVD-RK3 and periodic or zero-gradient boundaries only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC and TVD-RK3 only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == Ubar_np1) return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
   cfd_status rc = ensure_adjoint_scratch(s);
@@ -730,7 +727,7 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream) {
   if (!s || !Un || !U1 || !U2 || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
-  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC, TVD-RK3 and periodic or zero-gradient boundaries only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC and TVD-RK3 only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == U1 || Ubar_n == U2 || Ubar_n == Ubar_np1)
     return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");

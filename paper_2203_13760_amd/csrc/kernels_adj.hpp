@@ -410,29 +410,27 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis_tiled(const double* __r
   tile_flush<D, TF>(g, tile, 8, base, f0, o);
 }
 
-// Padded coordinates of axis d that the boundary map sends to interior
-// coordinate x (its halo images plus x itself), as first, count and step:
-// periodic images are x - n, x, x + n where inside the padding; zero-gradient
-// edge cells own the whole halo run beside them.
-__device__ __forceinline__ void images(const Geom& g, int d, int x, int& first, int& count, int& step) {
+// Halo coordinates of axis d that the boundary map sends to interior
+// coordinate x exist only within nh of an edge of an active axis (periodic
+// images, the zero-gradient run beside an edge cell, mirror images at a
+// reflecting wall).
+__device__ __forceinline__ bool near_edge(const Geom& g, int d, int x) {
+  return g.act[d] && (x < g.h[d] || x >= g.n[d] - g.h[d]);
+}
+
+// Candidate m of axis d for interior coordinate x: m = 0 is x itself; m = 1 ..
+// 2h are the halo coordinates -h .. -1, n .. n+h-1, taken when the boundary map
+// sends them to x, with the factor their image gives the axis's velocity.
+__device__ __forceinline__ bool image_of(const Geom& g, int d, int x, int m, int& y, double& sgn) {
+  if (m == 0) {
+    y = x;
+    sgn = 1.0;
+    return true;
+  }
   const int n = g.n[d], h = g.h[d];
-  if (!g.act[d]) {
-    first = 0;
-    count = 1;
-    step = 1;
-    return;
-  }
-  if (g.bc[2 * d] == 0) {
-    first = x - n >= -h ? x - n : x;
-    const int last = x + n < n + h ? x + n : x;
-    step = n;
-    count = (last - first) / n + 1;
-    return;
-  }
-  step = 1;
-  first = x == 0 ? -h : x;
-  const int last = x == n - 1 ? n - 1 + h : x;
-  count = last - first + 1;
+  y = m <= h ? m - 1 - h : n + (m - 1 - h);
+  sgn = bc_sign(y, n, g.bc[2 * d], g.bc[2 * d + 1]);
+  return bc_source(y, n, g.bc[2 * d], g.bc[2 * d + 1]) == x;
 }
 
 // Transposed centred differences of Dbar at padded cell cc (coordinates q),
@@ -478,30 +476,43 @@ __global__ void __launch_bounds__(kBlock) k_adj_dbar(const double* __restrict__ 
 }
 
 // Per interior cell s: gather the adjoints of all its images (the transposed
-// halo fill), then apply the transposed primitive map at U[s]; Ubar[s] +=
-// result. Halo entries of Ubar are not touched. Cells without halo images
-// (all but a layer nh deep at periodic or clamped boundaries) take a path
-// without loops. With viscous fluxes k_adj_dbar has run first.
+// halo fill, reflecting walls included), then apply the transposed primitive
+// map at U[s]; Ubar[s] += result. Halo entries of Ubar are not touched. Cells
+// more than nh from every boundary take a path without loops. With viscous
+// fluxes k_adj_dbar has run first.
 __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ U, const double* __restrict__ Wbar,
                                                      double* __restrict__ Ubar, Geom g) {
   const PlaneIdx p = plane_index(g, true);
   if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
-  int fx, cx, sx, fy, cy, sy, fz, cz, sz;
-  images(g, 0, p.i, fx, cx, sx);
-  images(g, 1, p.j, fy, cy, sy);
-  images(g, 2, p.k, fz, cz, sz);
   double wb[6] = {0, 0, 0, 0, 0, 0};
-  if (cx == 1 && cy == 1 && cz == 1) {
+  if (!near_edge(g, 0, p.i) && !near_edge(g, 1, p.j) && !near_edge(g, 2, p.k)) {
 #pragma unroll
     for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + p.c];
   } else {
-    for (int c = 0; c < cz; ++c)
-      for (int b = 0; b < cy; ++b)
-        for (int a = 0; a < cx; ++a) {
-          const long long cc = cell_at(g, fx + a * sx, fy + b * sy, fz + c * sz);
+    // the transpose of the gather: every padded cell whose source is this
+    // cell, its velocity adjoint taken through the image's factors
+    const int q[3] = {p.i, p.j, p.k};
+    int mm[3];
+    for (int d = 0; d < 3; ++d) mm[d] = near_edge(g, d, q[d]) ? 2 * g.h[d] + 1 : 1;
+    for (int c = 0; c < mm[2]; ++c) {
+      int z;
+      double sz;
+      if (!image_of(g, 2, q[2], c, z, sz)) continue;
+      for (int b = 0; b < mm[1]; ++b) {
+        int y;
+        double sy;
+        if (!image_of(g, 1, q[1], b, y, sy)) continue;
+        for (int a = 0; a < mm[0]; ++a) {
+          int x;
+          double sx;
+          if (!image_of(g, 0, q[0], a, x, sx)) continue;
+          const long long cc = cell_at(g, x, y, z);
+          const double f[6] = {1.0, sx, sy, sz, 1.0, 1.0};
 #pragma unroll
-          for (int v = 0; v < 6; ++v) wb[v] += Wbar[v * g.vs + cc];
+          for (int v = 0; v < 6; ++v) wb[v] += f[v] * Wbar[v * g.vs + cc];
         }
+      }
+    }
   }
   // transposed primitive map at U[s]
   const long long s = p.c;

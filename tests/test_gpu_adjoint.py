@@ -263,9 +263,9 @@ def test_shock_entropy_fd_converges_to_adjoint_at_second_order(Solver):
 def test_random_configurations_adjoint_match_oracle_tape(Solver, k):
     """Four seeded random configurations per case (12 in all) of the scheme
     the adjoint covers: 1-3 active axes of 3..12 cells, periodic or
-    zero-gradient boundaries per axis, with and without viscous and heat
-    fluxes; the right-hand-side adjoint and the kept-stage step adjoint on a
-    Gaussian cotangent against the oracle's tape (1e-10)."""
+    zero-gradient, reflecting or mixed boundaries per axis, with and without
+    viscous and heat fluxes; the right-hand-side adjoint and the kept-stage
+    step adjoint on a Gaussian cotangent against the oracle's tape (1e-10)."""
     rng = np.random.default_rng(2000 + k)
     for t in range(4):
         while True:
@@ -274,7 +274,8 @@ def test_random_configurations_adjoint_match_oracle_tape(Solver, k):
                 break
         bc = []
         for _ in range(3):
-            bc += [[wl.PERIODIC] * 2, [wl.ZERO_GRADIENT] * 2][int(rng.integers(0, 2))]
+            bc += [[wl.PERIODIC] * 2, [wl.ZERO_GRADIENT] * 2, [wl.REFLECT] * 2,
+                   [wl.ZERO_GRADIENT, wl.REFLECT]][int(rng.integers(0, 4))]
         flags = wl.INVISCID | [0, wl.VISCOUS, wl.HEAT, wl.VISCOUS | wl.HEAT][int(rng.integers(0, 4))]
         case, W = wl.random_smooth(n, seed=int(rng.integers(1 << 30)), mu=0.03, flags=flags, bc=tuple(bc))
         print(f"random adjoint config {k}.{t}: n={n} bc={tuple(bc)} flags={flags}", flush=True)
@@ -293,3 +294,24 @@ def test_random_configurations_adjoint_match_oracle_tape(Solver, k):
         got = s.step_adjoint_stages(Un, U1, U2, dt, torch.from_numpy(Rb).cuda()).cpu().numpy()
         s.close()
         assert normwise(got, want) <= 1e-10, (k, t, "step", normwise(got, want))
+
+
+def test_walled_implosion_adjoint_matches_oracle_tape(Solver):
+    """Reflecting walls in the adjoint (the implosion of §6.2 with the default
+    scheme at 12^2, after 30 steps so the shock meets the walls): the
+    right-hand-side adjoint and the step adjoint against the tape."""
+    case, W = wl.implosion(12, flags=wl.INVISCID)
+    print("walled implosion adjoint", flush=True)
+    s = Solver(case)
+    U = s.init(W)
+    s.advance_fixed(U, 30, 2e-3)
+    Uo, _, _ = oracle.advance(case, oracle.state_init(case, W), 30, fixed_dt=2e-3)
+    rng = np.random.default_rng(12)
+    Rb = rng.standard_normal(Uo.shape) * _interior_mask(case, Uo.shape)
+    want = oracle.vjp_rhs(case, Uo, Rb)
+    got = s.rhs_adjoint(U, torch.from_numpy(Rb).cuda(), torch.zeros_like(U)).cpu().numpy()
+    assert normwise(got, want) <= 1e-10, normwise(got, want)
+    want = oracle.vjp_rk3_step(case, Uo, 2e-3, Rb)
+    got = s.step_adjoint(U, 2e-3, torch.from_numpy(Rb).cuda()).cpu().numpy()
+    s.close()
+    assert normwise(got, want) <= 1e-10, normwise(got, want)
