@@ -419,6 +419,8 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
     hipLaunchKernelGGL(k_adj_dbar, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->Dbar, s->Wbar, g);
     CFD_LAUNCHED();
   }
+  hipLaunchKernelGGL(k_adj_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, s->Wbar, g);
+  CFD_LAUNCHED();
   hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, U, (const double*)s->Wbar, Ubar, g);
   CFD_LAUNCHED();
   return CFD_OK;

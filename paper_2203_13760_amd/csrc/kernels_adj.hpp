@@ -14,9 +14,10 @@
 //      loads coalesce, and add every contribution directly;
 //   3. k_adj_dbar (viscous): the transposed centred differences of Dbar,
 //      added to Wbar at every padded cell;
-//   4. k_adj_fold: per interior cell, the transposed halo fill (every padded
-//      cell that the boundary map sends to it) and the transposed primitive
-//      map at U give Ubar.
+//   4. k_adj_halo: the transposed halo fill, every halo cell's Wbar added to
+//      its interior source cell;
+//   5. k_adj_fold: per interior cell, the transposed primitive map at U gives
+//      Ubar.
 // The atomics make the summation order, and so the last bits, vary between
 // runs; everything else is deterministic.
 #pragma once
@@ -410,29 +411,6 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis_tiled(const double* __r
   tile_flush<D, TF>(g, tile, 8, base, f0, o);
 }
 
-// Halo coordinates of axis d that the boundary map sends to interior
-// coordinate x exist only within nh of an edge of an active axis (periodic
-// images, the zero-gradient run beside an edge cell, mirror images at a
-// reflecting wall).
-__device__ __forceinline__ bool near_edge(const Geom& g, int d, int x) {
-  return g.act[d] && (x < g.h[d] || x >= g.n[d] - g.h[d]);
-}
-
-// Candidate m of axis d for interior coordinate x: m = 0 is x itself; m = 1 ..
-// 2h are the halo coordinates -h .. -1, n .. n+h-1, taken when the boundary map
-// sends them to x, with the factor their image gives the axis's velocity.
-__device__ __forceinline__ bool image_of(const Geom& g, int d, int x, int m, int& y, double& sgn) {
-  if (m == 0) {
-    y = x;
-    sgn = 1.0;
-    return true;
-  }
-  const int n = g.n[d], h = g.h[d];
-  y = m <= h ? m - 1 - h : n + (m - 1 - h);
-  sgn = bc_sign(y, n, g.bc[2 * d], g.bc[2 * d + 1]);
-  return bc_source(y, n, g.bc[2 * d], g.bc[2 * d + 1]) == x;
-}
-
 // Transposed centred differences of Dbar at padded cell cc (coordinates q),
 // added to wb[1..3]: phi_bar(m) += (Dbar(m+2) - 8 Dbar(m+1) + 8 Dbar(m-1) -
 // Dbar(m-2)) / (12 dx_t). CHECK selects the range checks a halo image needs;
@@ -475,45 +453,34 @@ __global__ void __launch_bounds__(kBlock) k_adj_dbar(const double* __restrict__ 
   for (int c = 1; c < 4; ++c) Wbar[c * g.vs + p.c] += wb[c];
 }
 
-// Per interior cell s: gather the adjoints of all its images (the transposed
-// halo fill, reflecting walls included), then apply the transposed primitive
-// map at U[s]; Ubar[s] += result. Halo entries of Ubar are not touched. Cells
-// more than nh from every boundary take a path without loops. With viscous
-// fluxes k_adj_dbar has run first.
+// Transposed halo fill of the primitive adjoints: every halo cell adds its
+// adjoint to its interior source cell (the wall-normal velocity's through the
+// image's sign at a reflecting wall), with atomics, since an edge cell can
+// own several halo cells. One thread per halo cell, numbered as in the
+// primitive halo refresh.
+__global__ void __launch_bounds__(kBlock) k_adj_halo(double* Wbar, Geom g) {
+  int i, j, k;
+  if (!halo_cell(g, (long long)blockIdx.x * kBlock + threadIdx.x, i, j, k)) return;
+  const int si = bc_source(i, g.n[0], g.bc[0], g.bc[1]);
+  const int sj = bc_source(j, g.n[1], g.bc[2], g.bc[3]);
+  const int sk = bc_source(k, g.n[2], g.bc[4], g.bc[5]);
+  const long long c = cell_at(g, i, j, k), s = cell_at(g, si, sj, sk);
+  const double f[6] = {1.0, bc_sign(i, g.n[0], g.bc[0], g.bc[1]), bc_sign(j, g.n[1], g.bc[2], g.bc[3]),
+                       bc_sign(k, g.n[2], g.bc[4], g.bc[5]), 1.0, 1.0};
+#pragma unroll
+  for (int v = 0; v < 6; ++v) atomic_add(Wbar + v * g.vs + s, f[v] * Wbar[v * g.vs + c]);
+}
+
+// Per interior cell s, after k_adj_halo (and, with viscous fluxes,
+// k_adj_dbar): the transposed primitive map at U[s] applied to Wbar[s];
+// Ubar[s] += result. Halo entries of Ubar are not touched.
 __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ U, const double* __restrict__ Wbar,
                                                      double* __restrict__ Ubar, Geom g) {
   const PlaneIdx p = plane_index(g, true);
   if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
-  double wb[6] = {0, 0, 0, 0, 0, 0};
-  if (!near_edge(g, 0, p.i) && !near_edge(g, 1, p.j) && !near_edge(g, 2, p.k)) {
+  double wb[6];
 #pragma unroll
-    for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + p.c];
-  } else {
-    // the transpose of the gather: every padded cell whose source is this
-    // cell, its velocity adjoint taken through the image's factors
-    const int q[3] = {p.i, p.j, p.k};
-    int mm[3];
-    for (int d = 0; d < 3; ++d) mm[d] = near_edge(g, d, q[d]) ? 2 * g.h[d] + 1 : 1;
-    for (int c = 0; c < mm[2]; ++c) {
-      int z;
-      double sz;
-      if (!image_of(g, 2, q[2], c, z, sz)) continue;
-      for (int b = 0; b < mm[1]; ++b) {
-        int y;
-        double sy;
-        if (!image_of(g, 1, q[1], b, y, sy)) continue;
-        for (int a = 0; a < mm[0]; ++a) {
-          int x;
-          double sx;
-          if (!image_of(g, 0, q[0], a, x, sx)) continue;
-          const long long cc = cell_at(g, x, y, z);
-          const double f[6] = {1.0, sx, sy, sz, 1.0, 1.0};
-#pragma unroll
-          for (int v = 0; v < 6; ++v) wb[v] += f[v] * Wbar[v * g.vs + cc];
-        }
-      }
-    }
-  }
+  for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + p.c];
   // transposed primitive map at U[s]
   const long long s = p.c;
   const double rho = U[s], m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];

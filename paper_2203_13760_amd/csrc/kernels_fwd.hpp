@@ -130,8 +130,9 @@ __host__ __device__ __forceinline__ int halo_blocks(const Geom& g) {
   return (int)(n > 0 ? (n + kBlock - 1) / kBlock : 1);
 }
 
-__device__ __forceinline__ void prim_halo_body(double* P, const Geom& g, long long t) {
-  int i, j, k;  // interior-relative coordinates of the halo cell
+// Interior-relative coordinates of halo cell number t (numbered as above);
+// false past the last halo cell.
+__device__ __forceinline__ bool halo_cell(const Geom& g, long long t, int& i, int& j, int& k) {
   const long long zs = 2LL * g.h[2] * g.N[0] * g.N[1];
   const long long ys = 2LL * g.h[1] * g.N[0] * g.n[2];
   const long long xs = 2LL * g.h[0] * g.n[1] * g.n[2];
@@ -157,8 +158,14 @@ __device__ __forceinline__ void prim_halo_body(double* P, const Geom& g, long lo
     j = (int)(kj - (long long)k * g.n[1]);
     i = ii < g.h[0] ? ii - g.h[0] : g.n[0] + (ii - g.h[0]);
   } else {
-    return;
+    return false;
   }
+  return true;
+}
+
+__device__ __forceinline__ void prim_halo_body(double* P, const Geom& g, long long t) {
+  int i, j, k;  // interior-relative coordinates of the halo cell
+  if (!halo_cell(g, t, i, j, k)) return;
   const int si = bc_source(i, g.n[0], g.bc[0], g.bc[1]);
   const int sj = bc_source(j, g.n[1], g.bc[2], g.bc[3]);
   const int sk = bc_source(k, g.n[2], g.bc[4], g.bc[5]);
