@@ -78,6 +78,12 @@ def _load():
     lib.oracle_vjp_rhs.argtypes = [cfgp, dp, dp, dp]
     lib.oracle_vjp_rk3_step.argtypes = [cfgp, dp, d, dp, dp]
     lib.oracle_grad_ke.argtypes = [cfgp, dp, C.c_int, d, dp, dp]
+    lib.oracle_vjp_rhs_theta.argtypes = [cfgp, dp, dp, dp, dp]
+    lib.oracle_vjp_step_theta.argtypes = [cfgp, dp, d, dp, dp, dp]
+    lib.oracle_set_nn.argtypes = [dp]
+    lib.oracle_nn_alpha.argtypes = [dp]
+    lib.oracle_nn_alpha.restype = d
+    lib.oracle_rusanov_nn.argtypes = [d, dp, dp, C.c_int, dp]
     _lib = lib
     return lib
 
@@ -327,3 +333,61 @@ def rhs_rounding_bound(case, U, k=16.0):
     for v in range(5):
         scale[v] = float(acc[v].max())
     return k * np.finfo(np.float64).eps * scale
+
+
+# --------------------------------------------------------------------------
+# Rusanov-NN flux (§6.2): Rusanov with alpha = exp(MLP(|du|, u_M, c_M, |ds|)),
+# three hidden ReLU layers of 32 units; NN_PARAMS weights in the order
+# W1 (32x4), b1, W2 (32x32), b2, W3 (32x32), b3, W4 (1x32), b4.
+NN_PARAMS = 2305
+
+
+def set_nn(theta):
+    """Network weights used by every later call whose flags carry the Rusanov-NN
+    flux (256); None clears them."""
+    lib = _load()
+    if theta is None:
+        lib.oracle_set_nn(None)
+        return
+    th = np.ascontiguousarray(theta, dtype=np.float64).ravel()
+    if th.size != NN_PARAMS:
+        raise ValueError(f"expected {NN_PARAMS} weights, got {th.size}")
+    lib.oracle_set_nn(_ptr(th))
+
+
+def nn_alpha(f):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    return float(_load().oracle_nn_alpha(_ptr(f)))
+
+
+def rusanov_nn(gamma, WL, WR, axis):
+    lib = _load()
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    F = np.zeros(5)
+    _ok(lib.oracle_rusanov_nn(float(gamma), _ptr(WL), _ptr(WR), int(axis), _ptr(F)))
+    return F
+
+
+def vjp_rhs_theta(case, U, Rbar):
+    """(Ubar, theta_bar) for R = rhs(U) with the Rusanov-NN flux."""
+    lib = _load()
+    cfg = make_cfg(case)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    Rbar = np.ascontiguousarray(Rbar, dtype=np.float64)
+    Ubar = np.zeros_like(U)
+    tb = np.zeros(NN_PARAMS)
+    _ok(lib.oracle_vjp_rhs_theta(C.byref(cfg), _ptr(U), _ptr(Rbar), _ptr(Ubar), _ptr(tb)))
+    return Ubar, tb
+
+
+def vjp_step_theta(case, Un, dt, Ubar_np1):
+    """(Ubar_n, theta_bar) for one fixed-dt step with the Rusanov-NN flux."""
+    lib = _load()
+    cfg = make_cfg(case)
+    Un = np.ascontiguousarray(Un, dtype=np.float64)
+    Ub = np.ascontiguousarray(Ubar_np1, dtype=np.float64)
+    out = np.zeros_like(Un)
+    tb = np.zeros(NN_PARAMS)
+    _ok(lib.oracle_vjp_step_theta(C.byref(cfg), _ptr(Un), float(dt), _ptr(Ub), _ptr(out), _ptr(tb)))
+    return out, tb

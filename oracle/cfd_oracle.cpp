@@ -37,7 +37,8 @@ typedef struct {
   int32_t bc[6];       // x-, x+, y-, y+, z-, z+ : 0 periodic, 1 zero gradient, 2 reflecting wall
   uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux, 8 WENO5-Z reconstruction,
                        // 16 Roe flux splitting in characteristic space (the paper's ROE setup),
-                       // 32 WENO3-JS reconstruction, 64 Rusanov flux, 128 TVD-RK2 time integration
+                       // 32 WENO3-JS reconstruction, 64 Rusanov flux, 128 TVD-RK2 time integration,
+                       // 256 Rusanov-NN flux (Rusanov with the learned dissipation of §6.2)
 } oracle_cfg;
 }
 
@@ -46,7 +47,7 @@ namespace oracle {
 enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_REFLECT = 2 };
 enum : uint32_t {
   F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u, F_WENOZ = 8u, F_ROE = 16u, F_WENO3 = 32u, F_RUSANOV = 64u,
-  F_RK2 = 128u
+  F_RK2 = 128u, F_RUSANOV_NN = 256u
 };
 
 // --------------------------------------------------------------------------
@@ -221,6 +222,52 @@ R weno3_js(R a, R b, R c) {
 template <class R>
 void rusanov_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]);
 
+// Rusanov-NN flux of §6.2: the Rusanov form with alpha replaced by the output
+// of a multi-layer perceptron. Inputs are the face-normal velocity jump
+// |u_R - u_L|, the mean normal velocity (u_L + u_R)/2, the mean speed of sound
+// (c_L + c_R)/2 and the entropy jump |s_R - s_L|; three hidden layers of 32
+// units with ReLU; one output through exp, so alpha >= 0. The entropy is
+// s = ln(p / rho^gamma) / (gamma - 1) (specific entropy in units of c_v, up to
+// an additive constant that the jump cancels; the same s as in §6.1).
+// Parameters theta, 2305 values in this order: W1 (32 x 4, row-major), b1
+// (32), W2 (32 x 32), b2, W3 (32 x 32), b3, W4 (1 x 32), b4 (1); a layer maps
+// h -> W h + b.
+constexpr int NN_IN = 4, NN_H = 32;
+constexpr int NN_PARAMS = NN_H * NN_IN + NN_H + 2 * (NN_H * NN_H + NN_H) + NN_H + 1;
+
+template <class R>
+R nn_alpha(const R* th, const R f[NN_IN]) {
+  R h[NN_H], g[NN_H];
+  for (int o = 0; o < NN_H; ++o) {
+    R s = th[NN_H * NN_IN + o];
+    for (int i = 0; i < NN_IN; ++i) s = s + th[o * NN_IN + i] * f[i];
+    h[o] = max_(s, R(0.0));
+  }
+  const R* L = th + NN_H * NN_IN + NN_H;
+  for (int layer = 0; layer < 2; ++layer, L += NN_H * NN_H + NN_H) {
+    for (int o = 0; o < NN_H; ++o) {
+      R s = L[NN_H * NN_H + o];
+      for (int i = 0; i < NN_H; ++i) s = s + L[o * NN_H + i] * h[i];
+      g[o] = max_(s, R(0.0));
+    }
+    for (int o = 0; o < NN_H; ++o) h[o] = g[o];
+  }
+  R s = L[NN_H];
+  for (int i = 0; i < NN_H; ++i) s = s + L[i] * h[i];
+  return exp_(s);
+}
+
+// Network weights for the scalar type in use, set by the entry points that
+// evaluate the Rusanov-NN flux (the taped entry points hold them as leaves).
+template <class R>
+const R*& nn_weights() {
+  static const R* w = nullptr;
+  return w;
+}
+
+template <class R>
+void rusanov_nn_flux(double gamma, const R WL[5], const R WR[5], int d, const R* th, R F[5]);
+
 // --------------------------------------------------------------------------
 // HLLC approximate Riemann solver (Toro, Spruce & Speares 1994; §3.3 step 3)
 // with the Einfeldt (1988) signal-speed estimate (the setup file of Appendix A
@@ -324,6 +371,22 @@ void rusanov_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]) {
   const R cL = sqrt_(gamma * WL[4] / WL[0]), cR = sqrt_(gamma * WR[4] / WR[0]);
   const R uL = WL[1 + d], uR = WR[1 + d];
   const R alpha = max_(max_(abs_(uL - cL), abs_(uL + cL)), max_(abs_(uR - cR), abs_(uR + cR)));
+  for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * alpha * (UR[v] - UL[v]);
+}
+
+template <class R>
+void rusanov_nn_flux(double gamma, const R WL[5], const R WR[5], int d, const R* th, R F[5]) {
+  R UL[5], UR[5], FL[5], FR[5];
+  conservative(gamma, WL, UL);
+  conservative(gamma, WR, UR);
+  euler_flux(gamma, WL, d, FL);
+  euler_flux(gamma, WR, d, FR);
+  const R cL = sqrt_(gamma * WL[4] / WL[0]), cR = sqrt_(gamma * WR[4] / WR[0]);
+  const R uL = WL[1 + d], uR = WR[1 + d];
+  const R sL = (log_(WL[4]) - gamma * log_(WL[0])) / (gamma - 1.0);
+  const R sR = (log_(WR[4]) - gamma * log_(WR[0])) / (gamma - 1.0);
+  const R f[NN_IN] = {abs_(uR - uL), 0.5 * (uL + uR), 0.5 * (cL + cR), abs_(sR - sL)};
+  const R alpha = nn_alpha(th, f);
   for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * alpha * (UR[v] - UL[v]);
 }
 
@@ -530,7 +593,8 @@ void face_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d, con
         WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
       }
     }
-    if (c.flags & F_RUSANOV) rusanov_flux(c.gamma, WL, WR, d, Fc);
+    if (c.flags & F_RUSANOV_NN) rusanov_nn_flux(c.gamma, WL, WR, d, nn_weights<R>(), Fc);
+    else if (c.flags & F_RUSANOV) rusanov_flux(c.gamma, WL, WR, d, Fc);
     else hllc_flux(c.gamma, WL, WR, d, Fc);
   }
   R Fd[5] = {R(0.0), R(0.0), R(0.0), R(0.0), R(0.0)};
@@ -695,8 +759,36 @@ static int check_cfg(const oracle_cfg* c) {
       return -1;
   }
   if (c->nh < 3 || !(c->gamma > 1.0) || !(c->mu >= 0.0) || !(c->prandtl > 0.0)) return -1;
+  // the Rusanov-NN flux needs weights (oracle_set_nn) and is not a flux splitting
+  if ((c->flags & F_RUSANOV_NN) && (!nn_weights<double>() || (c->flags & F_ROE))) return -1;
   return 0;
 }
+
+// Weights of the Rusanov-NN flux for the entry points below (copied).
+static std::vector<double>& nn_store() {
+  static std::vector<double> w;
+  return w;
+}
+
+// Taped copies of the network weights: leaves on the active tape while one of
+// the reverse-mode entry points runs with the Rusanov-NN flux.
+struct NNLeaves {
+  std::vector<TVar> th;
+  std::vector<int32_t> id;
+  explicit NNLeaves(bool on) {
+    if (!on) return;
+    const std::vector<double>& w = nn_store();
+    th.resize(w.size());
+    id.resize(w.size());
+    for (size_t p = 0; p < w.size(); ++p) { th[p] = TVar::leaf(w[p]); id[p] = th[p].id; }
+    nn_weights<TVar>() = th.data();
+  }
+  ~NNLeaves() { nn_weights<TVar>() = nullptr; }
+  void read(const std::vector<double>& adj, double* theta_bar) const {
+    if (!theta_bar) return;
+    for (size_t p = 0; p < id.size(); ++p) theta_bar[p] = adj[id[p]];
+  }
+};
 
 extern "C" {
 
@@ -809,10 +901,37 @@ void oracle_rusanov(double gamma, const double* WL, const double* WR, int d, dou
 // Euler flux along axis d of one primitive state.
 void oracle_euler_flux(double gamma, const double* w, int d, double* F) { euler_flux(gamma, w, d, F); }
 
+// Rusanov-NN weights (2305 values, copied) for every entry point that takes a
+// configuration with the Rusanov-NN flux; NULL clears them. Returns the count.
+int oracle_set_nn(const double* theta) {
+  if (!theta) {
+    nn_store().clear();
+    nn_weights<double>() = nullptr;
+    return NN_PARAMS;
+  }
+  nn_store().assign(theta, theta + NN_PARAMS);
+  nn_weights<double>() = nn_store().data();
+  return NN_PARAMS;
+}
+
+// Network output alpha for the feature vector f (4 values) with the weights set
+// by oracle_set_nn; negative if none are set.
+double oracle_nn_alpha(const double* f) {
+  if (!nn_weights<double>()) return -1.0;
+  return nn_alpha(nn_weights<double>(), f);
+}
+
+// Rusanov-NN face flux with the weights set by oracle_set_nn.
+int oracle_rusanov_nn(double gamma, const double* WL, const double* WR, int d, double* F) {
+  if (!nn_weights<double>()) return -1;
+  rusanov_nn_flux(gamma, WL, WR, d, nn_weights<double>(), F);
+  return 0;
+}
+
 // Operation counts of one right-hand-side evaluation of state U:
 // out = {add, mul, div, sqrt, cmp}.
 int oracle_opcount(const oracle_cfg* c, const double* U, double* out) {
-  if (check_cfg(c)) return -1;
+  if (check_cfg(c) || (c->flags & F_RUSANOV_NN)) return -1;
   Grid g(*c);
   std::vector<OpCount> u(5 * g.ncell), r;
   for (long q = 0; q < 5 * g.ncell; ++q) u[q] = OpCount(U[q]);
@@ -827,7 +946,7 @@ int oracle_opcount(const oracle_cfg* c, const double* U, double* out) {
 // evaluated on state U: out[0] primitive conversion per cell, out[1..3] one
 // face flux G normal to x, y, z at an interior face (0 for inactive axes).
 int oracle_opcount_parts(const oracle_cfg* c, const double* U, double* out) {
-  if (check_cfg(c)) return -1;
+  if (check_cfg(c) || (c->flags & F_RUSANOV_NN)) return -1;
   Grid g(*c);
   std::vector<OpCount> u(5 * g.ncell);
   for (long q = 0; q < 5 * g.ncell; ++q) u[q] = OpCount(U[q]);
@@ -858,7 +977,10 @@ int oracle_opcount_parts(const oracle_cfg* c, const double* U, double* out) {
 
 // Ubar = (dR/dU)^T Rbar for R = rhs(U). Halo entries of Ubar receive nothing:
 // the halo fill overwrites them before they are read.
-int oracle_vjp_rhs(const oracle_cfg* c, const double* U, const double* Rbar, double* Ubar) {
+// With the Rusanov-NN flux, theta_bar (2305 values, may be NULL) receives
+// (dR/dtheta)^T Rbar.
+int oracle_vjp_rhs_theta(const oracle_cfg* c, const double* U, const double* Rbar, double* Ubar,
+                         double* theta_bar) {
   if (check_cfg(c)) return -1;
   Grid g(*c);
   Tape tape;
@@ -867,19 +989,27 @@ int oracle_vjp_rhs(const oracle_cfg* c, const double* U, const double* Rbar, dou
   for (long q = 0; q < 5 * g.ncell; ++q) u[q] = TVar::leaf(U[q]);
   std::vector<int32_t> leaf(5 * g.ncell);
   for (long q = 0; q < 5 * g.ncell; ++q) leaf[q] = u[q].id;
+  NNLeaves nn(c->flags & F_RUSANOV_NN);
   rhs(*c, g, u, r);
   std::vector<double> adj(tape.nodes.size(), 0.0);
   for (long q = 0; q < 5 * g.ncell; ++q)
     if (r[q].id >= 0) adj[r[q].id] += Rbar[q];
   tape.reverse(adj);
   for (long q = 0; q < 5 * g.ncell; ++q) Ubar[q] = adj[leaf[q]];
+  nn.read(adj, theta_bar);
   active_tape() = nullptr;
   return 0;
 }
 
-// Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1 for one TVD-RK3 step with fixed dt.
-int oracle_vjp_rk3_step(const oracle_cfg* c, const double* Un, double dt, const double* Ubar_np1,
-                        double* Ubar_n) {
+int oracle_vjp_rhs(const oracle_cfg* c, const double* U, const double* Rbar, double* Ubar) {
+  return oracle_vjp_rhs_theta(c, U, Rbar, Ubar, nullptr);
+}
+
+// Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1 for one step (TVD-RK3, or TVD-RK2 with
+// F_RK2) with fixed dt; with the Rusanov-NN flux theta_bar (may be NULL)
+// receives (dU^{n+1}/dtheta)^T Ubar_np1.
+int oracle_vjp_step_theta(const oracle_cfg* c, const double* Un, double dt, const double* Ubar_np1,
+                          double* Ubar_n, double* theta_bar) {
   if (check_cfg(c)) return -1;
   Grid g(*c);
   Tape tape;
@@ -887,6 +1017,7 @@ int oracle_vjp_rk3_step(const oracle_cfg* c, const double* Un, double dt, const 
   std::vector<TVar> u(5 * g.ncell);
   std::vector<int32_t> leaf(5 * g.ncell);
   for (long q = 0; q < 5 * g.ncell; ++q) { u[q] = TVar::leaf(Un[q]); leaf[q] = u[q].id; }
+  NNLeaves nn(c->flags & F_RUSANOV_NN);
   rk3_step(*c, g, u, dt);
   std::vector<double> adj(tape.nodes.size(), 0.0);
   // the result's halo cells are copies of interior cells: seed interior only
@@ -899,8 +1030,14 @@ int oracle_vjp_rk3_step(const oracle_cfg* c, const double* Un, double dt, const 
         }
   tape.reverse(adj);
   for (long q = 0; q < 5 * g.ncell; ++q) Ubar_n[q] = adj[leaf[q]];
+  nn.read(adj, theta_bar);
   active_tape() = nullptr;
   return 0;
+}
+
+int oracle_vjp_rk3_step(const oracle_cfg* c, const double* Un, double dt, const double* Ubar_np1,
+                        double* Ubar_n) {
+  return oracle_vjp_step_theta(c, Un, dt, Ubar_np1, Ubar_n, nullptr);
 }
 
 // Loss L = sum over interior cells of 1/2 |rho u|^2 / rho * dV after n_steps

@@ -30,6 +30,8 @@ inline double abs_(double x) { return std::fabs(x); }
 // Ties pick the first argument; the adjoint follows the same rule.
 inline double min_(double a, double b) { return (b < a) ? b : a; }
 inline double max_(double a, double b) { return (b > a) ? b : a; }
+inline double exp_(double x) { return std::exp(x); }
+inline double log_(double x) { return std::log(x); }
 
 // --------------------------------------------------------------- OpCount ---
 struct OpTally {
@@ -57,6 +59,8 @@ inline OpCount sqrt_(OpCount x) { tally().sqrt += 1; return OpCount(std::sqrt(x.
 inline OpCount abs_(OpCount x) { tally().cmp += 1; return OpCount(std::fabs(x.v)); }
 inline OpCount min_(OpCount a, OpCount b) { tally().cmp += 1; return (b.v < a.v) ? b : a; }
 inline OpCount max_(OpCount a, OpCount b) { tally().cmp += 1; return (b.v > a.v) ? b : a; }
+inline OpCount exp_(OpCount x) { tally().div += 1; return OpCount(std::exp(x.v)); }
+inline OpCount log_(OpCount x) { tally().div += 1; return OpCount(std::log(x.v)); }
 
 // ------------------------------------------------------------------ TVar ---
 // Tape entry: the value y of an operation with at most two operands x1, x2
@@ -123,6 +127,11 @@ inline TVar sqrt_(TVar x) {
 inline TVar abs_(TVar x) { return (x.v < 0.0) ? -x : x; }
 inline TVar min_(TVar a, TVar b) { return (b.v < a.v) ? b : a; }
 inline TVar max_(TVar a, TVar b) { return (b.v > a.v) ? b : a; }
+inline TVar exp_(TVar x) {
+  const double e = std::exp(x.v);
+  return TVar::make(e, x.id, e, -1, 0.0);
+}
+inline TVar log_(TVar x) { return TVar::make(std::log(x.v), x.id, 1.0 / x.v, -1, 0.0); }
 
 template <class R>
 inline R sq(R x) { return x * x; }

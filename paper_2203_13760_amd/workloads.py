@@ -26,6 +26,8 @@ ROE = 16  # flux splitting in characteristic space with Roe eigenvalues (the ROE
 WENO3 = 32
 RUSANOV = 64
 RK2 = 128
+RUSANOV_NN = 256
+NN_PARAMS = 2305  # Rusanov-NN weights: W1 (32x4), b1, W2 (32x32), b2, W3 (32x32), b3, W4 (1x32), b4
 ALL_PHYSICS = INVISCID | VISCOUS | HEAT
 
 
@@ -102,6 +104,23 @@ def implosion(n=128, nh=3, flags=INVISCID | WENO3 | RK2):
     zero = np.zeros_like(X)
     case["dt"] = 2.5e-4
     return case, _stack(rho, zero, zero, zero, p, X.shape)
+
+
+def nn_weights(seed=0, alpha0=1.0, scale=1.0):
+    """Seeded Rusanov-NN weights (§6.2 network: 4 inputs, three hidden ReLU
+    layers of 32, exp output): He-normal hidden layers with zero biases, the
+    output layer scaled by `scale` (times 1/sqrt(32)) with bias ln(alpha0), so
+    that scale = 0 gives alpha = alpha0 everywhere."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((4, 32), (32, 32), (32, 32)):
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), (fan_out, fan_in)).ravel())
+        parts.append(np.zeros(fan_out))
+    parts.append(scale * rng.normal(0.0, np.sqrt(1.0 / 32.0), 32))
+    parts.append(np.array([np.log(alpha0)]))
+    th = np.concatenate(parts)
+    assert th.size == NN_PARAMS
+    return th
 
 
 def entropy_wave(n, nh=3):

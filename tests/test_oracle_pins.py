@@ -608,6 +608,180 @@ def test_implosion_scheme_sod_and_walled_conservation():
         assert np.max(np.abs(b - a)) > 1e-3  # the state has moved
 
 
+def _nn_numpy(th, f):
+    """The §6.2 network through numpy matrix products (a second implementation
+    of the same definition: different code, same layer order)."""
+    o = 0
+
+    def take(k, shape):
+        nonlocal o
+        a = th[o:o + k].reshape(shape)
+        o += k
+        return a
+    h = np.asarray(f, dtype=np.float64)
+    for fan_in in (4, 32, 32):
+        W = take(32 * fan_in, (32, fan_in))
+        b = take(32, (32,))
+        h = np.maximum(W @ h + b, 0.0)
+    W4 = take(32, (32,))
+    b4 = take(1, ())
+    assert o == th.size
+    return float(np.exp(W4 @ h + b4))
+
+
+def _select_net(k):
+    """Weights whose output is alpha = exp(relu(f_k)): hidden unit 0 passes input
+    k through the three layers, everything else is zero."""
+    th = np.zeros(wl.NN_PARAMS)
+    th[0 * 4 + k] = 1.0                     # W1[0, k]
+    o = 128 + 32
+    th[o] = 1.0                              # W2[0, 0]
+    o += 1024 + 32
+    th[o] = 1.0                              # W3[0, 0]
+    o += 1024 + 32
+    th[o] = 1.0                              # W4[0]
+    return th
+
+
+def _const_net(alpha):
+    th = np.zeros(wl.NN_PARAMS)
+    th[-1] = math.log(alpha)
+    return th
+
+
+def test_nn_alpha_matches_matrix_form():
+    """The network of §6.2 (4 -> 32 -> 32 -> 32 -> 1, ReLU, exp output) against
+    numpy matrix products, for random weights and inputs of both signs."""
+    rng = np.random.default_rng(11)
+    try:
+        for seed in range(4):
+            th = wl.nn_weights(seed=seed, alpha0=1.3, scale=1.0)
+            th[np.r_[128:160, 1184:1216, 2240:2272]] = rng.normal(0, 0.3, 96)  # nonzero biases
+            oracle.set_nn(th)
+            for _ in range(20):
+                f = rng.normal(0, 1, 4)
+                a = oracle.nn_alpha(f)
+                assert a > 0.0
+                assert abs(a - _nn_numpy(th, f)) <= 1e-13 * a
+    finally:
+        oracle.set_nn(None)
+
+
+def test_rusanov_nn_flux_pins():
+    """Rusanov-NN (§6.2): with a constant network (alpha = exp(b4)) it is the
+    Rusanov flux of the same alpha, so a constant equal to the classical alpha
+    reproduces the classical Rusanov flux; equal states give the physical flux
+    for any weights; each input feature, selected alone, gives its closed form:
+    |u_R - u_L|, (u_L + u_R)/2, (c_L + c_R)/2 and |s_R - s_L| with
+    s = ln(p / rho^gamma)/(gamma - 1) (zero for an isentropic pair)."""
+    g = 1.4
+    wL = np.array([1.0, 0.3, -0.1, 0.2, 1.0])
+    wR = np.array([0.5, -0.2, 0.1, 0.0, 0.4])
+    try:
+        for d in range(3):
+            uL, uR = wL[1 + d], wR[1 + d]
+            cL, cR = math.sqrt(g * wL[4] / wL[0]), math.sqrt(g * wR[4] / wR[0])
+            a_cls = max(abs(uL - cL), abs(uL + cL), abs(uR - cR), abs(uR + cR))
+            oracle.set_nn(_const_net(a_cls))
+            np.testing.assert_allclose(oracle.rusanov_nn(g, wL, wR, d), oracle.rusanov(g, wL, wR, d),
+                                       rtol=1e-14, atol=1e-15)
+            oracle.set_nn(wl.nn_weights(seed=d, alpha0=2.0, scale=1.0))
+            np.testing.assert_allclose(oracle.rusanov_nn(g, wL, wL, d), oracle.euler_flux(g, wL, d),
+                                       rtol=1e-15, atol=1e-15)
+
+        def alpha_of(th, a, b, d=0):
+            # alpha recovered from the flux: F(alpha) = F(1) - (alpha - 1) (U_R - U_L) / 2
+            oracle.set_nn(th)
+            Fa = oracle.rusanov_nn(g, a, b, d)
+            oracle.set_nn(_const_net(1.0))
+            F1 = oracle.rusanov_nn(g, a, b, d)
+            oracle.set_nn(_const_net(2.0))
+            F2 = oracle.rusanov_nn(g, a, b, d)
+            return 1.0 + (Fa[0] - F1[0]) / (F2[0] - F1[0])
+
+        a = np.array([1.0, 0.3, 0.0, 0.0, 1.0])
+        b = np.array([0.5, -0.2, 0.0, 0.0, 1.0])
+        assert abs(alpha_of(_select_net(0), a, b) - math.exp(0.5)) < 1e-13
+        assert abs(alpha_of(_select_net(1), a, b) - math.exp(0.05)) < 1e-13
+        a2 = np.array([1.0, 0.0, 0.0, 0.0, 1.0 / g])      # c = 1
+        b2 = np.array([0.25, 0.0, 0.0, 0.0, 1.0 / g])     # c = 2
+        assert abs(alpha_of(_select_net(2), a2, b2) - math.exp(1.5)) < 1e-13
+        a3 = np.array([1.0, 0.0, 0.0, 0.0, 1.0])
+        b3 = np.array([1.0 + 1e-3, 0.0, 0.0, 0.0, 2.0])   # rho nearly equal, p doubled
+        ds = (math.log(2.0) - g * math.log(1.0 + 1e-3)) / (g - 1.0)
+        assert abs(alpha_of(_select_net(3), a3, b3) - math.exp(ds)) < 1e-12
+        b4 = np.array([2.0, 0.0, 0.0, 0.0, 2.0 ** g])     # isentropic: p / rho^gamma equal
+        assert abs(alpha_of(_select_net(3), a3, b4) - 1.0) < 1e-13
+        # the features do not depend on the side: swapping L and R and negating
+        # the normal velocity leaves |du|, c_M and |ds| alone and negates u_M
+        for k in (0, 2, 3):
+            m = lambda w: w * np.array([1, -1, 1, 1, 1])
+            assert abs(alpha_of(_select_net(k), a, b) - alpha_of(_select_net(k), m(b), m(a))) < 1e-13
+    finally:
+        oracle.set_nn(None)
+
+
+def _nn_case(n=10):
+    case, W = wl.implosion(n, flags=wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV_NN)
+    rng = np.random.default_rng(5)
+    W = W.copy()
+    W[0] *= 1.0 + 0.1 * rng.random(W[0].shape)
+    W[1] = 0.1 * rng.standard_normal(W[1].shape)
+    W[2] = 0.1 * rng.standard_normal(W[2].shape)
+    return case, W
+
+
+def test_rusanov_nn_taped_gradients_match_central_differences():
+    """The taped step derivative with the Rusanov-NN flux (walled implosion,
+    WENO3-JS + TVD-RK2, §6.2), with respect to the state and to the network
+    weights, against second-order central differences of the oracle step."""
+    case, W = _nn_case()
+    dt = 1e-3
+    th = wl.nn_weights(seed=3, alpha0=1.5, scale=0.5)
+    rng = np.random.default_rng(8)
+    try:
+        oracle.set_nn(th)
+        U0 = oracle.state_init(case, W)
+        Ub = np.zeros_like(U0)
+        oracle.interior(case, Ub)[...] = rng.standard_normal(oracle.interior(case, Ub).shape)
+
+        def L(U, t):
+            oracle.set_nn(t)
+            out, _ = oracle.rk3_step(case, U, dt)
+            return float(np.sum(oracle.interior(case, out) * oracle.interior(case, Ub)))
+        oracle.set_nn(th)
+        Ubar, tbar = oracle.vjp_step_theta(case, U0, dt, Ub)
+        assert np.any(tbar != 0.0)
+        for trial in range(3):
+            v = rng.standard_normal(th.size)
+            h = 1e-6  # small enough that no ReLU unit of any face changes side
+            fd = (L(U0, th + h * v) - L(U0, th - h * v)) / (2 * h)
+            ad = float(tbar @ v)
+            assert abs(fd - ad) <= 1e-6 * max(1.0, abs(ad)), (trial, fd, ad)
+        dU = np.zeros_like(U0)
+        oracle.interior(case, dU)[...] = rng.standard_normal(oracle.interior(case, dU).shape)
+        dU[0] *= 0.01
+        # A ReLU pre-activation of some face may sit within the step of zero on
+        # one side; a kink on one side spoils only that side's difference, so
+        # the central, forward or backward difference must agree.
+        h = 1e-8
+        L0 = L(U0, th)
+        Lp = L(oracle.fill_halo(case, U0 + h * dU), th)
+        Lm = L(oracle.fill_halo(case, U0 - h * dU), th)
+        ad = float(np.sum(oracle.interior(case, Ubar) * oracle.interior(case, dU)))
+        fds = ((Lp - Lm) / (2 * h), (Lp - L0) / h, (L0 - Lm) / h)
+        assert min(abs(f - ad) for f in fds) <= 1e-6 * max(1.0, abs(ad)), (fds, ad)
+    finally:
+        oracle.set_nn(None)
+
+
+def test_rusanov_nn_needs_weights():
+    case, W = _nn_case(8)
+    oracle.set_nn(None)
+    with pytest.raises(ValueError):
+        oracle.state_init(case, W)
+
+
 # ---------------------------------------------------------------- O1/O2 ----
 @pytest.mark.parametrize("bc", [wl.PERIODIC, wl.ZERO_GRADIENT])
 def test_halo_fill_matches_independent_padding(bc):
