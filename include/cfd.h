@@ -62,13 +62,24 @@ typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1, CFD_BC_REFLECT = 2
  * reconstruction of the primitives), CFD_F_RUSANOV (the Rusanov flux
  * (F_L + F_R)/2 - alpha (U_R - U_L)/2, alpha the largest |u -+ c| of the two
  * states, in place of HLLC) and CFD_F_RK2 (TVD-RK2 steps in place of TVD-RK3).
+ * CFD_F_RUSANOV_NN selects the Rusanov-NN flux of §6.2: the Rusanov form
+ * with alpha = exp(NN(|u_R - u_L|, (u_L + u_R)/2, (c_L + c_R)/2, |s_R - s_L|)),
+ * u normal to the face, c the speed of sound, s = (ln p - gamma ln rho)/
+ * (gamma - 1), NN a perceptron with three hidden ReLU layers of 32 units whose
+ * weights cfd_set_nn_weights supplies; it needs CFD_F_WENO3.
  * CFD_F_ROE combines with none of WENOZ, WENO3, RUSANOV, and CFD_F_WENOZ with
- * neither WENO3 nor RUSANOV (CFD_EINVAL). The adjoint covers the default
- * scheme only; the serving batch the default scheme with any boundaries. */
+ * neither WENO3 nor RUSANOV; CFD_F_RUSANOV_NN with none of ROE, WENOZ,
+ * RUSANOV (CFD_EINVAL). The adjoint covers the default scheme and WENO3-JS
+ * with the Rusanov-NN flux (inviscid), each with TVD-RK3 or TVD-RK2; the
+ * serving batch the default scheme with any boundaries. */
 enum {
   CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u, CFD_F_WENOZ = 8u, CFD_F_ROE = 16u, CFD_F_WENO3 = 32u,
-  CFD_F_RUSANOV = 64u, CFD_F_RK2 = 128u
+  CFD_F_RUSANOV = 64u, CFD_F_RK2 = 128u, CFD_F_RUSANOV_NN = 256u
 };
+
+/* Number of Rusanov-NN weights: W1 (32 x 4, row-major), b1 (32), W2 (32 x 32),
+ * b2, W3 (32 x 32), b3, W4 (1 x 32), b4 (1); a layer maps h -> W h + b. */
+#define CFD_NN_PARAMS 2305
 
 typedef struct {
   int32_t n[3];      /* interior cells (x,y,z); n[d] == 1 marks an inactive axis */
@@ -139,18 +150,36 @@ cfd_status cfd_advance(cfd_solver* s, double* U, int32_t n_steps, double t_end, 
  * differentiation, §4.5), graph-replayed like cfd_advance. */
 cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double dt, void* stream);
 
+/* Rusanov-NN weights (§6.2) of a solver created with CFD_F_RUSANOV_NN.
+ * theta: device memory, CFD_NN_PARAMS doubles in the order of CFD_NN_PARAMS,
+ * owned by the caller and read by every later launch of the solver (the
+ * values may change between calls; the address must stay valid while the
+ * solver may use it). theta_bar: device memory of CFD_NN_PARAMS doubles or
+ * NULL; every later adjoint call (cfd_rhs_adjoint, cfd_rk3_step_adjoint,
+ * cfd_rk3_step_adjoint_stages) adds its weight gradient to it (the caller
+ * clears it). The sum over faces runs in a fixed order, so for a given Rbar
+ * cfd_rhs_adjoint's weight gradient repeats bitwise; through a step it
+ * inherits the last-bit variation of the state adjoint's atomics.
+ * theta NULL unsets both. Solves with the flag and no weights fail with
+ * CFD_EINVAL. CFD_EINVAL for a solver without the flag. */
+cfd_status cfd_set_nn_weights(cfd_solver* s, const double* theta, double* theta_bar);
+
 /* Discrete adjoint of cfd_rhs: Ubar += (dR/dU)^T Rbar, evaluated at U
  * (interior cells of Rbar are read; its halo is ignored). The transposed halo
  * fill folds halo contributions back into their source cells, so the halo
- * entries of Ubar are left unchanged. U is not modified. CFD_EUNSUPPORTED for
- * a scheme other than the default. */
+ * entries of Ubar are left unchanged. U is not modified. With the Rusanov-NN
+ * flux, the theta_bar of cfd_set_nn_weights (if any) receives
+ * += (dR/dtheta)^T Rbar. CFD_EUNSUPPORTED for a scheme the adjoint does not
+ * cover (see the physics switches). */
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar,
                            void* stream);
 
-/* Discrete adjoint of one fixed-dt TVD-RK3 step: with U^{n+1} = S(U^n),
- * Ubar_n = (dS/dU^n)^T Ubar_np1 (interior cells; Ubar_n's halo is zeroed).
- * The stage states are recomputed from Un. Ubar_n must not alias the others.
- * CFD_EUNSUPPORTED for a scheme other than the default. */
+/* Discrete adjoint of one fixed-dt step (TVD-RK3, or TVD-RK2 with CFD_F_RK2):
+ * with U^{n+1} = S(U^n), Ubar_n = (dS/dU^n)^T Ubar_np1 (interior cells;
+ * Ubar_n's halo is zeroed); with the Rusanov-NN flux, theta_bar (see
+ * cfd_set_nn_weights) += (dS/dtheta)^T Ubar_np1. The stage states are
+ * recomputed from Un. Ubar_n must not alias the others. CFD_EUNSUPPORTED for
+ * a scheme the adjoint does not cover. */
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream);
 
@@ -168,7 +197,7 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
  * supplied (as cfd_rk3_step_stages leaves them; interior cells are read)
  * instead of recomputed: the same result up to the summation order of the
  * atomics, without the two forward stages. Ubar_n must not alias any input.
- * CFD_EUNSUPPORTED for a scheme other than the default. */
+ * CFD_EUNSUPPORTED with CFD_F_RK2 or a scheme the adjoint does not cover. */
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream);
 

@@ -18,7 +18,8 @@ LIB_PATH = os.environ.get("CFD_LIBRARY") or os.path.join(_HERE, "libcfd.so")
 CFD_OK, CFD_EINVAL, CFD_ENOMEM, CFD_EHIP, CFD_ENONFINITE, CFD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CFD_BC_PERIODIC, CFD_BC_ZERO_GRADIENT, CFD_BC_REFLECT = 0, 1, 2
 CFD_F_INVISCID, CFD_F_VISCOUS, CFD_F_HEAT, CFD_F_WENOZ, CFD_F_ROE = 1, 2, 4, 8, 16
-CFD_F_WENO3, CFD_F_RUSANOV, CFD_F_RK2 = 32, 64, 128
+CFD_F_WENO3, CFD_F_RUSANOV, CFD_F_RK2, CFD_F_RUSANOV_NN = 32, 64, 128, 256
+CFD_NN_PARAMS = 2305
 
 
 class CfdError(RuntimeError):
@@ -46,6 +47,7 @@ EXPORTS = (
     "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_fill_halo", "cfd_rhs",
     "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
     "cfd_rk3_step_adjoint", "cfd_rk3_step_stages", "cfd_rk3_step_adjoint_stages", "cfd_profile_stage", "cfd_check", "cfd_last_error",
+    "cfd_set_nn_weights",
     "cfd_batch_create", "cfd_batch_destroy", "cfd_batch_footprint", "cfd_batch_add", "cfd_batch_remove",
     "cfd_batch_state", "cfd_batch_step", "cfd_batch_finish", "cfd_batch_copy_state", "cfd_batch_count",
 )
@@ -81,6 +83,7 @@ def load():
         "cfd_rk3_step_stages": ([vp, dp, C.c_double, dp, dp, vp], st),
         "cfd_rk3_step_adjoint_stages": ([vp, dp, dp, dp, C.c_double, dp, dp, vp], st),
         "cfd_profile_stage": ([vp, dp, C.c_int32, C.POINTER(C.c_double), vp], st),
+        "cfd_set_nn_weights": ([vp, dp, dp], st),
         "cfd_check": ([vp, C.POINTER(C.c_int32)], st),
         "cfd_last_error": ([], C.c_char_p),
         "cfd_batch_create": ([C.c_int32, C.c_int64, C.POINTER(C.c_void_p)], st),
@@ -203,6 +206,12 @@ def cfd_rk3_step_stages(h, U, dt, U1_out, U2_out, stream=None):
 def cfd_rk3_step_adjoint_stages(h, Un, U1, U2, dt, Ubar_np1, Ubar_n, stream=None):
     _check(load().cfd_rk3_step_adjoint_stages(h, _ptr(Un), _ptr(U1), _ptr(U2), float(dt), _ptr(Ubar_np1),
                                               _ptr(Ubar_n), _stream(stream)))
+
+
+def cfd_set_nn_weights(h, theta, theta_bar=None):
+    """Rusanov-NN weights (device tensor of CFD_NN_PARAMS doubles, kept alive by
+    the caller) and the optional weight-gradient accumulator the adjoints add to."""
+    _check(load().cfd_set_nn_weights(h, _ptr(theta), _ptr(theta_bar)))
 
 
 def cfd_profile_stage(h, U, reps=5, stream=None):

@@ -10,6 +10,7 @@
 
 #include "../../include/cfd.h"
 #include "kernels_adj.hpp"
+#include "kernels_nn.hpp"
 #include "kernels_fwd.hpp"
 
 using namespace cfd;
@@ -70,6 +71,10 @@ struct cfd_solver {
   double* Wbar = nullptr; // 6 x padded
   double* Dbar = nullptr; // 9 x padded (viscous runs)
   double* partial = nullptr;  // CFL rate maxima slots (kCflSlots)
+  double* nna = nullptr;      // Rusanov-NN alpha per face (3 x padded)
+  double* nntape = nullptr;   // Rusanov-NN per-face records of the reverse (adjoint scratch)
+  double* nnbar = nullptr;    // caller's weight-gradient accumulator (may be NULL)
+  NNTape tape{};
   int npart = 0;
   DevCtl* ctl = nullptr;
   hipStream_t cap = nullptr;
@@ -96,7 +101,10 @@ static cfd_status validate(const cfd_config* c) {
   if (!(c->mu >= 0.0)) return fail(CFD_EINVAL, "mu must be >= 0");
   if (!(c->prandtl > 0.0)) return fail(CFD_EINVAL, "prandtl must be > 0");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return fail(CFD_EINVAL, "cfl must lie in (0, 1]");
-  if (c->flags & ~255u) return fail(CFD_EINVAL, "unknown physics flag");
+  if (c->flags & ~511u) return fail(CFD_EINVAL, "unknown physics flag");
+  if ((c->flags & CFD_F_RUSANOV_NN) &&
+      ((c->flags & (CFD_F_ROE | CFD_F_WENOZ | CFD_F_RUSANOV)) || !(c->flags & CFD_F_WENO3)))
+    return fail(CFD_EINVAL, "the Rusanov-NN flux runs with WENO3-JS (flag RUSANOV_NN needs WENO3, without ROE, WENOZ, RUSANOV)");
   if ((c->flags & CFD_F_ROE) && (c->flags & (CFD_F_WENOZ | CFD_F_WENO3 | CFD_F_RUSANOV)))
     return fail(CFD_EINVAL, "the Roe flux splitting reconstructs with WENO5-JS (flag WENOZ, WENO3 or RUSANOV with ROE)");
   if ((c->flags & CFD_F_WENOZ) && (c->flags & (CFD_F_WENO3 | CFD_F_RUSANOV)))
@@ -143,6 +151,7 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.weno3 = (c.flags & CFD_F_WENO3) ? 1 : 0;
   g.rusanov = (c.flags & CFD_F_RUSANOV) ? 1 : 0;
   g.rk2 = (c.flags & CFD_F_RK2) ? 1 : 0;
+  g.nn = (c.flags & CFD_F_RUSANOV_NN) ? 1 : 0;
   g.viscous = ((c.flags & CFD_F_VISCOUS) && c.mu > 0.0) ? 1 : 0;
   g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
 }
@@ -189,7 +198,8 @@ static void launch_sweep_r(cfd_solver* s, int mode, const double* P, const Stage
 template <int D, bool PN>
 static void launch_sweep(cfd_solver* s, int mode, const double* P, const StageIO& io, hipStream_t st) {
   const Geom& g = s->g;
-  if (g.roe) launch_sweep_r<D, PN, SCH_ROE>(s, mode, P, io, st);
+  if (g.nn) launch_sweep_r<D, PN, SCH_W3_NN>(s, mode, P, io, st);
+  else if (g.roe) launch_sweep_r<D, PN, SCH_ROE>(s, mode, P, io, st);
   else if (g.wenoz) launch_sweep_r<D, PN, SCH_Z>(s, mode, P, io, st);
   else if (g.weno3 && g.rusanov) launch_sweep_r<D, PN, SCH_W3_RUS>(s, mode, P, io, st);
   else if (g.weno3) launch_sweep_r<D, PN, SCH_W3>(s, mode, P, io, st);
@@ -219,8 +229,28 @@ static void sweep_order(const Geom& g, int& first, int& last) {
 // axis applies the stage update into io.Uout (and, with io.Pn set, stores the
 // primitives of the updated interior cells into io.Pn, whose halo is then
 // refreshed); otherwise io.R receives the full right-hand side.
+// Faces normal to axis d (interior cells of the other axes).
+static long long faces_of(const Geom& g, int d) {
+  return (long long)g.n[0] * g.n[1] * g.n[2] / g.n[d] * (g.n[d] + 1);
+}
+
+// Rusanov-NN: alpha of every face of the active axes from primitives P.
+static cfd_status enqueue_nn_alpha(cfd_solver* s, const double* P, hipStream_t st) {
+  const Geom& g = s->g;
+  if (!g.nnw) return fail(CFD_EINVAL, "Rusanov-NN weights are not set (cfd_set_nn_weights)");
+  if (g.act[0]) hipLaunchKernelGGL(k_nn_alpha<0>, dim3(grid_for(faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, g);
+  if (g.act[1]) hipLaunchKernelGGL(k_nn_alpha<1>, dim3(grid_for(faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, g);
+  if (g.act[2]) hipLaunchKernelGGL(k_nn_alpha<2>, dim3(grid_for(faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, g);
+  CFD_LAUNCHED();
+  return CFD_OK;
+}
+
 static cfd_status enqueue_fluxes(cfd_solver* s, const double* P, const StageIO& io, bool rk, hipStream_t st) {
   const Geom& g = s->g;
+  if (g.nn) {
+    cfd_status rc = enqueue_nn_alpha(s, P, st);
+    if (rc) return rc;
+  }
   int first = -1, last = -1;
   sweep_order(g, first, last);
   for (int d = 2; d >= 0; --d) {
@@ -367,13 +397,29 @@ static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   bool ok = hipMalloc(&s->A1, st) == hipSuccess && hipMalloc(&s->A2, st) == hipSuccess &&
             hipMalloc(&s->Wbar, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess;
   if (ok && s->g.viscous) ok = hipMalloc(&s->Dbar, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
+  long long F = 0;
+  if (s->g.nn) {
+    for (int d = 0; d < 3; ++d)
+      if (s->g.act[d]) F += faces_of(s->g, d);
+    ok = ok && hipMalloc(&s->nntape, sizeof(double) * kNNTapePerFace * (size_t)F) == hipSuccess;
+  }
   if (!ok) {
     (void)hipGetLastError();
-    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar};
+    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar, s->nntape};
     for (double* x : b)
       if (x) (void)hipFree(x);
-    s->A1 = s->A2 = s->Wbar = s->Dbar = nullptr;
+    s->A1 = s->A2 = s->Wbar = s->Dbar = s->nntape = nullptr;
     return fail(CFD_ENOMEM, "adjoint scratch allocation failed");
+  }
+  if (s->g.nn) {
+    NNTape& t = s->tape;
+    t.F = F;
+    for (int l = 0; l < 3; ++l) {
+      t.z[l] = s->nntape + (size_t)l * kNNH * F;
+      t.d[l] = s->nntape + (size_t)(3 + l) * kNNH * F;
+    }
+    t.f = s->nntape + (size_t)6 * kNNH * F;
+    t.d4 = t.f + (size_t)kNNIn * F;
   }
   return CFD_OK;
 }
@@ -411,10 +457,34 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
                        kGradComps * s->ncell);
     CFD_LAUNCHED();
   }
-  if (g.act[0]) launch_face_adj<0>(s, P, Rbar, rscale, st);
-  if (g.act[1]) launch_face_adj<1>(s, P, Rbar, rscale, st);
-  if (g.act[2]) launch_face_adj<2>(s, P, Rbar, rscale, st);
-  CFD_LAUNCHED();
+  if (g.nn) {
+    // Rusanov-NN faces (one lane per face), then the weight gradient
+    if (!g.nnw) return fail(CFD_EINVAL, "Rusanov-NN weights are not set (cfd_set_nn_weights)");
+    long long off = 0;
+    if (g.act[0]) {
+      hipLaunchKernelGGL(k_face_adj_nn<0>, dim3(grid_for(faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
+                         rscale, s->Wbar, g, s->tape, off);
+      off += faces_of(g, 0);
+    }
+    if (g.act[1]) {
+      hipLaunchKernelGGL(k_face_adj_nn<1>, dim3(grid_for(faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
+                         rscale, s->Wbar, g, s->tape, off);
+      off += faces_of(g, 1);
+    }
+    if (g.act[2])
+      hipLaunchKernelGGL(k_face_adj_nn<2>, dim3(grid_for(faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
+                         rscale, s->Wbar, g, s->tape, off);
+    CFD_LAUNCHED();
+    if (s->nnbar) {
+      hipLaunchKernelGGL(k_nn_wgrad, dim3(kNNRows), dim3(kBlock), 0, st, s->tape, s->nnbar);
+      CFD_LAUNCHED();
+    }
+  } else {
+    if (g.act[0]) launch_face_adj<0>(s, P, Rbar, rscale, st);
+    if (g.act[1]) launch_face_adj<1>(s, P, Rbar, rscale, st);
+    if (g.act[2]) launch_face_adj<2>(s, P, Rbar, rscale, st);
+    CFD_LAUNCHED();
+  }
   if (g.viscous) {
     hipLaunchKernelGGL(k_adj_dbar, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->Dbar, s->Wbar, g);
     CFD_LAUNCHED();
@@ -426,12 +496,15 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
   return CFD_OK;
 }
 
-// The adjoint covers the default scheme (WENO5-JS, HLLC, TVD-RK3), with any
-// boundaries.
+// The adjoint covers WENO5-JS with HLLC (any physics), and WENO3-JS with the
+// Rusanov-NN flux (inviscid), with TVD-RK3 or TVD-RK2 and any boundaries.
 static bool adjoint_supported(const cfd_solver* s) {
   const Geom& g = s->g;
-  return !(g.wenoz || g.roe || g.weno3 || g.rusanov || g.rk2);
+  if (g.wenoz || g.roe || g.rusanov) return false;
+  if (g.nn) return !g.viscous && !g.heat;
+  return !g.weno3;
 }
+#define CFD_ADJ_SCOPE "the adjoint covers WENO5-JS + HLLC and WENO3-JS + Rusanov-NN (inviscid)"
 
 // ===========================================================================
 extern "C" {
@@ -459,6 +532,11 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
   s->P = s->Pb[0];
   s->npart = kCflSlots;
   ok = ok && hipMalloc(&s->partial, sizeof(double) * (size_t)s->npart) == hipSuccess;
+  if (s->g.nn) {
+    ok = ok && hipMalloc(&s->nna, sizeof(double) * 3 * (size_t)s->ncell) == hipSuccess &&
+         hipMemset(s->nna, 0, sizeof(double) * 3 * (size_t)s->ncell) == hipSuccess;
+    s->g.nna = s->nna;
+  }
   if (!ok) {
     (void)hipGetLastError();
     cfd_destroy(s);
@@ -480,7 +558,8 @@ void cfd_destroy(cfd_solver* s) {
   (void)hipDeviceSynchronize();
   if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
-  double* bufs[] = {s->U1, s->U2, s->Pb[0], s->Pb[1], s->Pb[2], s->Racc, s->A1, s->A2, s->A3, s->Wbar, s->Dbar, s->partial};
+  double* bufs[] = {s->U1, s->U2,   s->Pb[0], s->Pb[1], s->Pb[2], s->Racc,    s->A1,
+                    s->A2, s->A3,   s->Wbar,  s->Dbar,  s->partial, s->nna, s->nntape};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (s->ctl) (void)hipFree(s->ctl);
@@ -650,7 +729,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
 
 cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, double* Ubar, void* stream) {
   if (!s || !U || !Rbar || !Ubar) return fail(CFD_EINVAL, "NULL argument");
-  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC and TVD-RK3 only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, CFD_ADJ_SCOPE);
   if (Ubar == U || Ubar == Rbar) return fail(CFD_EINVAL, "Ubar must not alias U or Rbar");
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
@@ -662,7 +741,7 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
                                 double* Ubar_n, void* stream) {
   if (!s || !Un || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
-  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC and TVD-RK3 only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, CFD_ADJ_SCOPE);
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == Ubar_np1) return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
   cfd_status rc = ensure_adjoint_scratch(s);
@@ -689,6 +768,19 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   io.Pn = s->Pb[1];
   if ((rc = enqueue_prim(s, Un, 0, dtp, st))) return rc;
   if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
+  if (g.rk2) {
+    // TVD-RK2:  U2 = 1/2 Un + 1/2 (U1 + dt R(U1)),  U1 = Un + dt R(Un)
+    // A1 = Ubar_1 = 1/2 Ubar_2 + (dR/dU(U1))^T (1/2 dt Ubar_2)
+    hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.5, Ubar_np1, 0.0,
+                       (const double*)nullptr, 0.0, (const double*)nullptr, g);
+    CFD_LAUNCHED();
+    if ((rc = enqueue_rhs_adjoint(s, s->U1, s->Pb[1], Ubar_np1, 0.5 * dt, s->A1, st))) return rc;
+    // Ubar_n = 1/2 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
+    hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 0.5, Ubar_np1, 1.0,
+                       (const double*)s->A1, 0.0, (const double*)nullptr, g);
+    CFD_LAUNCHED();
+    return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
+  }
   io.Uk = s->U1;
   io.Uout = s->U2;
   io.a = 0.75;
@@ -714,6 +806,19 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
 }
 
+cfd_status cfd_set_nn_weights(cfd_solver* s, const double* theta, double* theta_bar) {
+  if (!s) return fail(CFD_EINVAL, "NULL argument");
+  if (!s->g.nn) return fail(CFD_EINVAL, "the solver was not created with the Rusanov-NN flux");
+  s->g.nnw = theta;
+  s->nnbar = theta ? theta_bar : nullptr;
+  // a captured step holds the old weight address
+  if (s->graph.exec) {
+    CFD_HIP(hipGraphExecDestroy(s->graph.exec));
+    s->graph.exec = nullptr;
+  }
+  return CFD_OK;
+}
+
 cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_out, double* U2_out, void* stream) {
   if (!s || !U || !U1_out || !U2_out) return fail(CFD_EINVAL, "NULL argument");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
@@ -729,10 +834,11 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream) {
   if (!s || !Un || !U1 || !U2 || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
-  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, "the adjoint covers WENO5-JS, HLLC and TVD-RK3 only");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, CFD_ADJ_SCOPE);
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
   if (Ubar_n == Un || Ubar_n == U1 || Ubar_n == U2 || Ubar_n == Ubar_np1)
     return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
+  if (s->g.rk2) return fail(CFD_EUNSUPPORTED, "the stages kept are those of TVD-RK3");
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;

@@ -554,6 +554,7 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
       const double t0 = lane_shr1(t1);
       tf[v] = rc4(t0, t1, t2, d[v]);
     }
+    if constexpr (SCH == SCH_W3_NN) w.a = g.nna[c0 + 2];  // alpha of face f (left cell f-1)
     double G[5];
     face_flux_tf<0, SCH>(g, w, tf, G);
     double Gm[5];
@@ -655,6 +656,7 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
       }
     }
     if (kDeferTg) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (SCH == SCH_W3_NN) w.a = g.nna[AX * g.vs + c + 2 * st];  // face f+1/2, left cell f
     double G[5];
     face_flux<AX, SCH>(g, w, G);
     if (f >= s0 && in) {

@@ -1,0 +1,338 @@
+// Rusanov-NN flux of §6.2 on gfx950: the Rusanov flux whose dissipation alpha
+// is the output of a small network of four face features.
+//
+//   forward:  k_nn_alpha<D> evaluates the network once per face normal to D
+//             from the WENO3-JS face states and stores alpha at the face's
+//             left cell (Geom::nna); the sweeps (scheme SCH_W3_NN) read it.
+//   reverse:  k_face_adj_nn<D>, one lane per face, recomputes the face (states,
+//             features, network), reverses the flux with alpha held, the
+//             network (output adjoint -> input adjoint) and the features, then
+//             the WENO3-JS stencils into Wbar with atomics, as the other face
+//             reverses do. It records the network's pre-activations and their
+//             adjoints per face; k_nn_wgrad forms the weight gradient from the
+//             records as the sums over faces of (delta_l h_{l-1}^T), one block
+//             per output row, in a fixed order (bitwise repeatable for given
+//             face adjoints).
+#pragma once
+#include "kernels_adj.hpp"
+
+namespace cfd {
+
+// Network of §6.2: 4 inputs, three hidden layers of 32 units with ReLU, one
+// output through exp (alpha >= 0). Weights in the order W1 (32 x 4,
+// row-major), b1, W2 (32 x 32), b2, W3 (32 x 32), b3, W4 (1 x 32), b4; a layer
+// maps h -> W h + b.
+constexpr int kNNH = 32, kNNIn = 4;
+constexpr int kNNb1 = kNNH * kNNIn, kNNW2 = kNNb1 + kNNH, kNNb2 = kNNW2 + kNNH * kNNH, kNNW3 = kNNb2 + kNNH,
+              kNNb3 = kNNW3 + kNNH * kNNH, kNNW4 = kNNb3 + kNNH, kNNb4 = kNNW4 + kNNH, kNNParams = kNNb4 + 1;
+static_assert(kNNParams == 2305, "network size");
+
+// Per-face records of one right-hand-side reverse, written by k_face_adj_nn
+// and read by k_nn_wgrad: pre-activations z1..z3 and their adjoints d1..d3
+// ([F][32] each), the inputs ([F][4]) and the output pre-activation's adjoint
+// ([F]); F counts the faces of all active axes.
+struct NNTape {
+  double* z[3];
+  double* d[3];
+  double* f;
+  double* d4;
+  long long F;
+};
+constexpr int kNNTapePerFace = 6 * kNNH + kNNIn + 1;
+constexpr int kNNRows = 3 * kNNH + 1;  // output rows of the four layers
+
+__device__ __forceinline__ double relu(double z) { return z > 0.0 ? z : 0.0; }
+
+// WENO3-JS states across the face whose left cell is cl (padded index),
+// normal to D, from cells cl-1 .. cl+2, as in the sweeps.
+template <int D>
+__device__ __forceinline__ void nn_face_states(const Geom& g, const double* __restrict__ P, long long cl, double* WL,
+                                               double* WR) {
+  const long long st = g.s[D];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double* q = P + v * g.vs + cl;
+    const double a = q[-st], b = q[0], c = q[st], d = q[2 * st];
+    WL[v] = weno3(a, b, c);
+    WR[v] = weno3(d, c, b);
+  }
+}
+
+// Inputs of the network: |u_R - u_L|, (u_L + u_R)/2, (c_L + c_R)/2 and
+// |s_R - s_L|, u normal to the face, c = sqrt(gamma p / rho), the entropy
+// s = (ln p - gamma ln rho)/(gamma - 1).
+template <int D>
+__device__ __forceinline__ void nn_features(const Geom& g, const double* WL, const double* WR, double* f) {
+  const double uL = WL[1 + D], uR = WR[1 + D];
+  const double cL = sqrt(div_nr(g.gamma * WL[4], WL[0])), cR = sqrt(div_nr(g.gamma * WR[4], WR[0]));
+  const double sL = (log(WL[4]) - g.gamma * log(WL[0])) * g.gm1i;
+  const double sR = (log(WR[4]) - g.gamma * log(WR[0])) * g.gm1i;
+  f[0] = fabs(uR - uL);
+  f[1] = 0.5 * (uL + uR);
+  f[2] = 0.5 * (cL + cR);
+  f[3] = fabs(sR - sL);
+}
+
+// Hidden layer: zo = W relu(zi) + b (zi of the first layer are the inputs
+// themselves, passed through unchanged by the caller).
+template <int NIN, bool ACT>
+__device__ __forceinline__ void nn_layer(const double* __restrict__ W, const double* __restrict__ b, const double* zi,
+                                         double* zo) {
+#pragma unroll
+  for (int o = 0; o < kNNH; ++o) {
+    double s = b[o];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) s = fma(W[o * NIN + i], ACT ? relu(zi[i]) : zi[i], s);
+    zo[o] = s;
+  }
+}
+
+// Forward pass: the hidden pre-activations into z1..z3; returns the output
+// pre-activation (alpha = exp of it). Every lane reads the same weight
+// addresses, so the loads are scalar.
+__device__ __forceinline__ double nn_forward(const double* __restrict__ th, const double* f, double* z1, double* z2,
+                                             double* z3) {
+  nn_layer<kNNIn, false>(th, th + kNNb1, f, z1);
+  nn_layer<kNNH, true>(th + kNNW2, th + kNNb2, z1, z2);
+  nn_layer<kNNH, true>(th + kNNW3, th + kNNb3, z2, z3);
+  double s = th[kNNb4];
+#pragma unroll
+  for (int i = 0; i < kNNH; ++i) s = fma(th[kNNW4 + i], relu(z3[i]), s);
+  return s;
+}
+
+// Transposed layer: di = (W^T dout) masked by the ReLU of zi (a pre-activation
+// of exactly zero passes, as max(z, 0) taking z there).
+__device__ __forceinline__ void nn_layer_rev(const double* __restrict__ W, const double* dout, const double* zi,
+                                             double* di) {
+#pragma unroll
+  for (int i = 0; i < kNNH; ++i) {
+    double s = 0.0;
+#pragma unroll
+    for (int o = 0; o < kNNH; ++o) s = fma(W[o * kNNH + i], dout[o], s);
+    di[i] = zi[i] >= 0.0 ? s : 0.0;
+  }
+}
+
+// Primitive adjoint of one side's physical flux F(W) and conservative state
+// U(W) along D: Wb += (dF/dW)^T Fb + (dU/dW)^T Ub.
+template <int D>
+__device__ __forceinline__ void euler_state_rev(double gm1i, const double* W, const double* Fb, const double* Ub,
+                                                double* Wb) {
+  const double rho = W[0], p = W[4], un = W[1 + D];
+  const double q2 = W[1] * W[1] + W[2] * W[2] + W[3] * W[3];
+  const double E = p * gm1i + 0.5 * rho * q2;
+  const double m = rho * un;
+  // F0 = m, F_{1+a} = m u_a + [a == D] p, F4 = un (E + p)
+  double mb = Fb[0];
+  double Eb = Fb[4] * un + Ub[4];
+  double unb = Fb[4] * (E + p);
+  double pb = Fb[4] * un + Fb[1 + D];
+  double rb = Ub[0];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mb += Fb[1 + a] * W[1 + a];
+    Wb[1 + a] += Fb[1 + a] * m + Ub[1 + a] * rho;  // also U_{1+a} = rho u_a
+    rb += Ub[1 + a] * W[1 + a];
+  }
+  // m = rho un
+  rb += mb * un;
+  unb += mb * rho;
+  // E = p/(gamma-1) + rho |u|^2 / 2
+  pb += Eb * gm1i;
+  rb += Eb * 0.5 * q2;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) Wb[1 + a] += Eb * rho * W[1 + a];
+  Wb[1 + D] += unb;
+  Wb[0] += rb;
+  Wb[4] += pb;
+}
+
+// Reverse of G = (F_L + F_R)/2 - alpha (U_R - U_L)/2 with alpha held:
+// WLb, WRb += the state adjoints; returns alpha's adjoint.
+template <int D>
+__device__ __forceinline__ double rusanov_given_rev(double gm1i, const double* WL, const double* WR, double alpha,
+                                                    const double* Gb, double* WLb, double* WRb) {
+  double Fb[5], ULb[5], URb[5];
+  double ab = 0.0;
+  const double qL = WL[1] * WL[1] + WL[2] * WL[2] + WL[3] * WL[3];
+  const double qR = WR[1] * WR[1] + WR[2] * WR[2] + WR[3] * WR[3];
+  const double UL[5] = {WL[0], WL[0] * WL[1], WL[0] * WL[2], WL[0] * WL[3], WL[4] * gm1i + 0.5 * WL[0] * qL};
+  const double UR[5] = {WR[0], WR[0] * WR[1], WR[0] * WR[2], WR[0] * WR[3], WR[4] * gm1i + 0.5 * WR[0] * qR};
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    Fb[v] = 0.5 * Gb[v];
+    ULb[v] = 0.5 * alpha * Gb[v];
+    URb[v] = -0.5 * alpha * Gb[v];
+    ab -= 0.5 * Gb[v] * (UR[v] - UL[v]);
+  }
+  euler_state_rev<D>(gm1i, WL, Fb, ULb, WLb);
+  euler_state_rev<D>(gm1i, WR, Fb, URb, WRb);
+  return ab;
+}
+
+// Reverse of nn_features: WLb, WRb += (df/dW)^T fb. |x| takes the slope +1 at
+// x = 0, as the comparison x < 0 selects -x.
+template <int D>
+__device__ __forceinline__ void nn_features_rev(const Geom& g, const double* WL, const double* WR, const double* fb,
+                                                double* WLb, double* WRb) {
+  const double uL = WL[1 + D], uR = WR[1 + D];
+  const double du = uR - uL;
+  const double sg0 = du < 0.0 ? -1.0 : 1.0;
+  WRb[1 + D] += fb[0] * sg0 + 0.5 * fb[1];
+  WLb[1 + D] += -fb[0] * sg0 + 0.5 * fb[1];
+  // c = sqrt(gamma p / rho): dc/dp = c/(2p), dc/drho = -c/(2 rho)
+  const double cL = sqrt(div_nr(g.gamma * WL[4], WL[0])), cR = sqrt(div_nr(g.gamma * WR[4], WR[0]));
+  const double cb = 0.5 * fb[2];
+  WLb[4] += cb * cL / (2.0 * WL[4]);
+  WLb[0] -= cb * cL / (2.0 * WL[0]);
+  WRb[4] += cb * cR / (2.0 * WR[4]);
+  WRb[0] -= cb * cR / (2.0 * WR[0]);
+  // s = (ln p - gamma ln rho)/(gamma - 1)
+  const double sL = (log(WL[4]) - g.gamma * log(WL[0])) * g.gm1i;
+  const double sR = (log(WR[4]) - g.gamma * log(WR[0])) * g.gm1i;
+  const double sg3 = (sR - sL) < 0.0 ? -1.0 : 1.0;
+  const double sRb = fb[3] * sg3, sLb = -fb[3] * sg3;
+  WLb[4] += sLb * g.gm1i / WL[4];
+  WLb[0] -= sLb * g.gamma * g.gm1i / WL[0];
+  WRb[4] += sRb * g.gm1i / WR[4];
+  WRb[0] -= sRb * g.gamma * g.gm1i / WR[0];
+}
+
+// alpha of every face normal to D (one lane per face, numbered as in the face
+// reverses), stored at the face's left cell.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_nn_alpha(const double* __restrict__ P, Geom g) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = 0, j = 0, k = 0, f = 0, col = 0;
+  if (!face_coords<D>(g, t, i, j, k, f, col)) return;
+  const long long cl = cell_at(g, i, j, k) - g.s[D];  // cell f-1
+  double WL[5], WR[5], ft[kNNIn], z1[kNNH], z2[kNNH], z3[kNNH];
+  nn_face_states<D>(g, P, cl, WL, WR);
+  nn_features<D>(g, WL, WR, ft);
+  g.nna[D * g.vs + cl] = exp(nn_forward(g.nnw, ft, z1, z2, z3));
+}
+
+// Face reverse of the Rusanov-NN flux (inviscid), faces normal to D; the
+// records of face t go to slot off + t of the tape.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_face_adj_nn(const double* __restrict__ P, const double* __restrict__ Rbar,
+                                                        double rscale, double* Wbar, Geom g, NNTape tp, long long off) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int i = 0, j = 0, k = 0, f = 0, col = 0;
+  if (!face_coords<D>(g, t, i, j, k, f, col)) return;
+  const long long st = g.s[D];
+  const long long cf = cell_at(g, i, j, k), cl = cf - st;
+  const long long e = off + t;
+  double Gb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  face_gbar<D>(g, Rbar, rscale, cf, f, Gb);
+  double WL[5], WR[5], ft[kNNIn], z1[kNNH], z2[kNNH], z3[kNNH];
+  nn_face_states<D>(g, P, cl, WL, WR);
+  nn_features<D>(g, WL, WR, ft);
+  const double* __restrict__ th = g.nnw;
+  const double alpha = exp(nn_forward(th, ft, z1, z2, z3));
+  // records for the weight gradient; the reverse reads the pre-activations
+  // back from them rather than keeping 96 values live across it
+  double* rz1 = tp.z[0] + e * kNNH;
+  double* rz2 = tp.z[1] + e * kNNH;
+  double* rz3 = tp.z[2] + e * kNNH;
+#pragma unroll
+  for (int o = 0; o < kNNH; ++o) {
+    rz1[o] = z1[o];
+    rz2[o] = z2[o];
+    rz3[o] = z3[o];
+  }
+#pragma unroll
+  for (int m = 0; m < kNNIn; ++m) tp.f[e * kNNIn + m] = ft[m];
+  asm volatile("" ::: "memory");
+  double WLb[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WRb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const double ab = rusanov_given_rev<D>(g.gm1i, WL, WR, alpha, Gb, WLb, WRb);
+  // network reverse: output through exp, then the layers
+  const double d4 = ab * alpha;
+  tp.d4[e] = d4;
+  double da[kNNH], db[kNNH];
+#pragma unroll
+  for (int o = 0; o < kNNH; ++o) da[o] = rz3[o] >= 0.0 ? th[kNNW4 + o] * d4 : 0.0;  // d3
+#pragma unroll
+  for (int o = 0; o < kNNH; ++o) tp.d[2][e * kNNH + o] = da[o];
+  nn_layer_rev(th + kNNW3, da, rz2, db);  // d2
+#pragma unroll
+  for (int o = 0; o < kNNH; ++o) tp.d[1][e * kNNH + o] = db[o];
+  nn_layer_rev(th + kNNW2, db, rz1, da);  // d1
+#pragma unroll
+  for (int o = 0; o < kNNH; ++o) tp.d[0][e * kNNH + o] = da[o];
+  double fb[kNNIn];
+#pragma unroll
+  for (int m = 0; m < kNNIn; ++m) {
+    double s = 0.0;
+#pragma unroll
+    for (int o = 0; o < kNNH; ++o) s = fma(th[o * kNNIn + m], da[o], s);
+    fb[m] = s;
+  }
+  nn_features_rev<D>(g, WL, WR, fb, WLb, WRb);
+  // WENO3-JS reverse into the stencil cells cl-1 .. cl+2
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double* w = Wbar + v * g.vs + cl;
+    const double* q = P + v * g.vs + cl;
+    const double a = q[-st], b = q[0], c = q[st], d = q[2 * st];
+    double gs[4] = {0.0, 0.0, 0.0, 0.0};
+    weno3_rev(a, b, c, WLb[v], gs);
+    double gr[3] = {0.0, 0.0, 0.0};
+    weno3_rev(d, c, b, WRb[v], gr);
+    gs[3] += gr[0];
+    gs[2] += gr[1];
+    gs[1] += gr[2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) atomic_add(w + (m - 1) * st, gs[m]);
+  }
+}
+
+// Weight gradient from the records: thb += sum over faces. Block r owns output
+// row r: rows 0..31 of (W1 | b1), 32..63 of (W2 | b2), 64..95 of (W3 | b3), 96
+// the output layer (W4 | b4). Each lane sums a fixed stride of the faces for
+// the row's weights and bias; the wavefronts reduce by shuffles and the four
+// partial sums are added in a fixed order.
+__global__ void __launch_bounds__(kBlock) k_nn_wgrad(NNTape tp, double* __restrict__ thb) {
+  const int r = blockIdx.x;
+  const int layer = r / kNNH, o = r - layer * kNNH;
+  const double* hs = layer == 0 ? tp.f : tp.z[layer - 1];
+  double acc[kNNH + 1];
+#pragma unroll
+  for (int m = 0; m <= kNNH; ++m) acc[m] = 0.0;
+  for (long long e = threadIdx.x; e < tp.F; e += kBlock) {
+    const double dd = layer < 3 ? tp.d[layer][e * kNNH + o] : tp.d4[e];
+    acc[kNNH] += dd;
+    if (layer == 0) {
+#pragma unroll
+      for (int m = 0; m < kNNIn; ++m) acc[m] = fma(dd, hs[e * kNNIn + m], acc[m]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < kNNH; ++m) acc[m] = fma(dd, relu(hs[e * kNNH + m]), acc[m]);
+    }
+  }
+  __shared__ double part[kBlock / 64][kNNH + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 0; m <= kNNH; ++m) {
+    double v = acc[m];
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) v += __shfl_xor(v, sft, 64);
+    if (lane == 0) part[wave][m] = v;
+  }
+  __syncthreads();
+  const int m = threadIdx.x;
+  const int nin = layer == 0 ? kNNIn : kNNH;
+  if (m > kNNH || (m < kNNH && m >= nin)) return;
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) s += part[w][m];
+  long long idx;
+  if (layer == 0) idx = m < kNNH ? o * kNNIn + m : kNNb1 + o;
+  else if (layer == 1) idx = m < kNNH ? kNNW2 + o * kNNH + m : kNNb2 + o;
+  else if (layer == 2) idx = m < kNNH ? kNNW3 + o * kNNH + m : kNNb3 + o;
+  else idx = m < kNNH ? kNNW4 + m : kNNb4;
+  thb[idx] += s;
+}
+
+}  // namespace cfd

@@ -34,6 +34,9 @@ struct Geom {
   int weno3;       // WENO3-JS instead of WENO5
   int rusanov;     // Rusanov flux instead of HLLC
   int rk2;         // TVD-RK2 instead of TVD-RK3
+  int nn;          // Rusanov-NN flux (with WENO3-JS): alpha per face from nna
+  const double* nnw;  // Rusanov-NN network weights (device, 2305 values)
+  double* nna;        // Rusanov-NN alpha per face, [3][padded cells] at the face's left cell
 };
 
 // Convective schemes of the sweeps, a compile-time parameter: WENO5-JS or
@@ -44,8 +47,13 @@ constexpr int SCH_JS = 0, SCH_Z = 1, SCH_ROE = 2;
 // and the schemes of the implosion of §6.2: WENO3-JS with HLLC, WENO3-JS or
 // WENO5-JS with the Rusanov flux
 constexpr int SCH_W3 = 3, SCH_JS_RUS = 4, SCH_W3_RUS = 5;
-__host__ __device__ constexpr bool sch_weno3(int sch) { return sch == SCH_W3 || sch == SCH_W3_RUS; }
-__host__ __device__ constexpr bool sch_rusanov(int sch) { return sch == SCH_JS_RUS || sch == SCH_W3_RUS; }
+// and the Rusanov-NN flux of §6.2 (WENO3-JS, Rusanov with the dissipation of a
+// network, evaluated per face beforehand into Geom::nna)
+constexpr int SCH_W3_NN = 6;
+__host__ __device__ constexpr bool sch_weno3(int sch) { return sch == SCH_W3 || sch == SCH_W3_RUS || sch == SCH_W3_NN; }
+__host__ __device__ constexpr bool sch_rusanov(int sch) {
+  return sch == SCH_JS_RUS || sch == SCH_W3_RUS || sch == SCH_W3_NN;
+}
 
 __host__ __device__ __forceinline__ double sq(double x) { return x * x; }
 
@@ -152,17 +160,21 @@ __host__ __device__ __forceinline__ double weno3(double a, double b, double c) {
 
 // Rusanov (local Lax-Friedrichs) flux of §6.2 across a face normal to axis D
 // from reconstructed primitive states: (F_L + F_R)/2 - alpha (U_R - U_L)/2 with
-// alpha the largest |u -+ c| of the two states (u normal to the face).
-template <int D>
+// alpha the largest |u -+ c| of the two states (u normal to the face), or the
+// given alpha_in (GIVEN: the Rusanov-NN flux).
+template <int D, bool GIVEN = false>
 __host__ __device__ __forceinline__ void rusanov(double gamma, double gm1i, const double* WL, const double* WR,
-                                                 double* F) {
+                                                 double* F, double alpha_in = 0.0) {
   const double rL = WL[0], pL = WL[4], rR = WR[0], pR = WR[4];
   const double uL = WL[1 + D], uR = WR[1 + D];
   const double kL = 0.5 * rL * (WL[1] * WL[1] + WL[2] * WL[2] + WL[3] * WL[3]);
   const double kR = 0.5 * rR * (WR[1] * WR[1] + WR[2] * WR[2] + WR[3] * WR[3]);
   const double EL = pL * gm1i + kL, ER = pR * gm1i + kR;
-  const double cL = sqrt(div_nr(gamma * pL, rL)), cR = sqrt(div_nr(gamma * pR, rR));
-  const double alpha = fmax(fmax(fabs(uL - cL), fabs(uL + cL)), fmax(fabs(uR - cR), fabs(uR + cR)));
+  double alpha = alpha_in;
+  if constexpr (!GIVEN) {
+    const double cL = sqrt(div_nr(gamma * pL, rL)), cR = sqrt(div_nr(gamma * pR, rR));
+    alpha = fmax(fmax(fabs(uL - cL), fabs(uL + cL)), fmax(fabs(uR - cR), fabs(uR + cR)));
+  }
   const double UL[5] = {rL, rL * WL[1], rL * WL[2], rL * WL[3], EL};
   const double UR[5] = {rR, rR * WR[1], rR * WR[2], rR * WR[3], ER};
   double FL[5], FR[5];
@@ -247,6 +259,7 @@ struct FaceWindow {
   double q[6][5];
   double T[4];
   double tg[4][4];
+  double a;  // Rusanov-NN: the face's alpha
 };
 
 // Fourth-order central interpolation to the face between b and c (§3.4).
@@ -303,12 +316,13 @@ __host__ __device__ __forceinline__ void sub_dissipative(const Geom& g, const Fa
   }
 }
 
-template <int D, bool RUS = false>
+template <int D, bool RUS = false, bool NN = false>
 __host__ __device__ __forceinline__ void face_flux_lr(const Geom& g, const double* WL, const double* WR,
                                                       const FaceWindow& w, const double* tf, double* G) {
   double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (g.inviscid) {
-    if constexpr (RUS) rusanov<D>(g.gamma, g.gm1i, WL, WR, F);
+    if constexpr (NN) rusanov<D, true>(g.gamma, g.gm1i, WL, WR, F, w.a);
+    else if constexpr (RUS) rusanov<D>(g.gamma, g.gm1i, WL, WR, F);
     else hllc<D>(g.gamma, g.gm1i, WL, WR, F);
   }
   sub_dissipative<D>(g, w, tf, F);
@@ -434,7 +448,7 @@ __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceW
       }
     }
   }
-  face_flux_lr<D, sch_rusanov(SCH)>(g, WL, WR, w, tf, G);
+  face_flux_lr<D, sch_rusanov(SCH), SCH == SCH_W3_NN>(g, WL, WR, w, tf, G);
 }
 
 // Numerical flux G = F - F^d across the face (§3.3, §3.4) from a full window.

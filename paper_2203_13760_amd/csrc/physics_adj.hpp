@@ -8,6 +8,28 @@
 
 namespace cfd {
 
+// q = weno3(a,b,c); g[0..2] += (dq/d(a,b,c)) * qbar.
+__host__ __device__ __forceinline__ void weno3_rev(double a, double b, double c, double qbar, double* g) {
+  constexpr double eps = 1.0e-6;
+  const double d0 = b - a, d1 = c - b;
+  const double e0 = eps + d0 * d0, e1 = eps + d1 * d1;
+  const double s0 = e0 * e0, s1 = e1 * e1;
+  const double w0 = s1, w1 = 2.0 * s0;
+  const double A = 3.0 * b - a, B = b + c;
+  const double iD = 1.0 / (2.0 * (w0 + w1));
+  const double q = (w0 * A + w1 * B) * iD;
+  // reverse
+  const double Nb = qbar * iD;
+  const double Db = -qbar * q * iD;
+  const double w0b = Nb * A + 2.0 * Db, w1b = Nb * B + 2.0 * Db;
+  const double Ab = Nb * w0, Bb = Nb * w1;
+  const double e0b = 2.0 * e0 * (2.0 * w1b), e1b = 2.0 * e1 * w0b;
+  const double d0b = 2.0 * d0 * e0b, d1b = 2.0 * d1 * e1b;
+  g[0] += -Ab - d0b;
+  g[1] += 3.0 * Ab + Bb + d0b - d1b;
+  g[2] += Bb + d1b;
+}
+
 // q = weno5(a,b,c,d,e); g[0..4] += (dq/d(a..e)) * qbar.
 __host__ __device__ __forceinline__ void weno5_rev(double a, double b, double c, double d, double e,
                                                     double qbar, double* g) {

@@ -107,5 +107,16 @@ class Solver:
         cfd.cfd_rk3_step_adjoint_stages(self.h, Un, U1, U2, float(dt), Ubar_np1, Ubar_n)
         return Ubar_n
 
+    def set_nn_weights(self, theta, theta_bar=None):
+        """Rusanov-NN weights (a device float64 tensor of cfd.CFD_NN_PARAMS values,
+        read at every launch, so it may be updated in place) and an optional
+        accumulator that every later adjoint call adds the weight gradient to.
+        The solver keeps references to both."""
+        for t in (theta, theta_bar):
+            if t is not None:
+                assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == cfd.CFD_NN_PARAMS
+        cfd.cfd_set_nn_weights(self.h, theta, theta_bar)
+        self._nn = (theta, theta_bar)
+
     def check(self):
         return cfd.cfd_check(self.h)

@@ -69,7 +69,10 @@ BAD_CONFIGS = [
     ("prandtl", dict(prandtl=0.0), "prandtl"),
     ("cfl zero", dict(cfl=0.0), "cfl"),
     ("cfl above one", dict(cfl=1.5), "cfl"),
-    ("unknown flag", dict(flags=256), "flag"),
+    ("unknown flag", dict(flags=512), "flag"),
+    ("rusanov-nn without weno3", dict(flags=1 | 256), "Rusanov-NN"),
+    ("rusanov-nn with rusanov", dict(flags=1 | 32 | 64 | 256), "Rusanov-NN"),
+    ("rusanov-nn with roe", dict(flags=1 | 16 | 32 | 256), "Rusanov-NN"),
     ("roe with wenoz", dict(flags=1 | 8 | 16), "WENO5-JS"),
     ("roe with rusanov", dict(flags=1 | 16 | 64), "WENO5-JS"),
     ("wenoz with weno3", dict(flags=1 | 8 | 32), "WENO5-Z"),
@@ -117,6 +120,7 @@ def test_entry_points_reject_null_arguments():
                        ("cfd_rk3_step_stages", (null, null, ctypes.c_double(1e-3), null, null, null)),
                        ("cfd_rk3_step_adjoint_stages", (null, null, null, null, ctypes.c_double(1e-3), null, null,
                                                         null)),
+                       ("cfd_set_nn_weights", (null, null, null)),
                        ("cfd_state_init", (null, null, null, null))]:
         assert getattr(lib, name)(*args) == cfd.CFD_EINVAL, name
         assert cfd.cfd_last_error() != ""

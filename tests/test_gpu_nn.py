@@ -1,0 +1,267 @@
+"""The Rusanov-NN flux of §6.2 on the HIP path (WENO3-JS, TVD-RK2, reflecting
+walls) against the oracle: the right-hand side, one step and 100 steps of the
+forward path, and the discrete adjoint with respect to the state and to the
+network weights against the oracle's taped reverse mode.
+
+Tolerances as for the other schemes: the right-hand side to 1e-12 normwise or
+the rounding bound of its flux differences, one step to 1e-12, 100 steps to
+1e-10; adjoints (state and weights) to 1e-10 normwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2203_13760_amd import workloads as wl
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NN_FLAGS = wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV_NN
+
+
+def normwise(a, b):
+    err = 0.0
+    for v in range(a.shape[0]):
+        den = float(np.max(np.abs(b[v])))
+        num = float(np.max(np.abs(a[v] - b[v])))
+        if num == 0.0:
+            continue
+        err = max(err, num / den if den > 0 else math.inf)
+    return err
+
+
+def vecwise(a, b):
+    den = float(np.max(np.abs(b)))
+    num = float(np.max(np.abs(a - b)))
+    return 0.0 if num == 0.0 else (num / den if den > 0 else math.inf)
+
+
+@pytest.fixture(scope="module")
+def Solver():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_13760_amd.solver import Solver as S
+    return S
+
+
+@pytest.fixture(autouse=True)
+def _clear_oracle_weights():
+    yield
+    oracle.set_nn(None)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _perturbed(n, seed=5):
+    """The implosion with a density perturbation and random velocities, so that
+    every feature of the network varies from face to face."""
+    case, W = wl.implosion(n, flags=NN_FLAGS)
+    rng = np.random.default_rng(seed)
+    W = W.copy()
+    W[0] *= 1.0 + 0.1 * rng.random(W[0].shape)
+    W[1] = 0.1 * rng.standard_normal(W[1].shape)
+    W[2] = 0.1 * rng.standard_normal(W[2].shape)
+    return case, W
+
+
+THETAS = {
+    "near_const": wl.nn_weights(seed=3, alpha0=1.5, scale=0.5),
+    "wide": wl.nn_weights(seed=4, alpha0=0.8, scale=1.0),
+}
+
+CASES = {
+    "implosion24": wl.implosion(24, flags=NN_FLAGS),
+    "perturbed20x20": _perturbed(20),
+    "perturbed_x_only": (lambda c: (dict(c[0], n=(37, 1, 1), bc=(wl.REFLECT,) * 2 + (wl.PERIODIC,) * 4),
+                                    np.ascontiguousarray(c[1][:, :, :1, :])))(_perturbed(37)),
+}
+
+
+def _solver(Solver, case, theta, with_bar=False):
+    s = Solver(case)
+    th = torch.from_numpy(theta).cuda()
+    tb = torch.zeros_like(th) if with_bar else None
+    s.set_nn_weights(th, tb)
+    oracle.set_nn(theta)
+    return s, th, tb
+
+
+@pytest.mark.parametrize("tname", sorted(THETAS))
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_nn_rhs_and_step_match_oracle(Solver, name, tname):
+    case, W = CASES[name]
+    _say(f"Rusanov-NN rhs + step parity: {name} / {tname}")
+    s, th, _ = _solver(Solver, case, THETAS[tname])
+    U = s.init(W)
+    R = s.rhs(U).cpu().numpy()
+    Uo = oracle.state_init(case, W)
+    Ro = oracle.rhs(case, Uo)
+    bound = oracle.rhs_rounding_bound(case, Uo)
+    for v in range(5):
+        err = float(np.max(np.abs(R[v] - Ro[v])))
+        assert err <= max(1e-12 * float(np.max(np.abs(Ro[v]))), bound[v]), (name, v, err, bound[v])
+    s.step(U, 1e-3)
+    Uo1, _ = oracle.rk3_step(case, Uo, 1e-3)
+    e = normwise(U.cpu().numpy(), Uo1)
+    s.close()
+    assert e <= 1e-12, (name, tname, e)
+
+
+@pytest.mark.parametrize("name", ["implosion24", "perturbed20x20"])
+def test_nn_100_fixed_steps_match_oracle(Solver, name):
+    """100 fixed steps of the coarse step 1e-3 of §6.2 (graph-replayed)."""
+    case, W = CASES[name]
+    _say(f"Rusanov-NN 100-step parity: {name}")
+    s, th, _ = _solver(Solver, case, THETAS["wide"])
+    U = s.init(W)
+    s.advance_fixed(U, 100, 1e-3)
+    Uo, _, _ = oracle.advance(case, oracle.state_init(case, W), 100, fixed_dt=1e-3)
+    e = normwise(U.cpu().numpy(), Uo)
+    s.close()
+    assert e <= 1e-10, (name, e)
+
+
+def _interior_noise(case, shape, seed):
+    rng = np.random.default_rng(seed)
+    m = np.zeros(shape)
+    oracle.interior(case, m)[...] = rng.standard_normal(oracle.interior(case, m).shape)
+    return m
+
+
+@pytest.mark.parametrize("tname", sorted(THETAS))
+@pytest.mark.parametrize("name", ["perturbed20x20", "perturbed_x_only", "implosion24"])
+def test_nn_rhs_adjoint_matches_oracle_tape(Solver, name, tname):
+    case, W = CASES[name]
+    _say(f"Rusanov-NN rhs adjoint parity: {name} / {tname}")
+    if name == "implosion24":
+        # after 30 steps the shock has reached the corner walls
+        oracle.set_nn(THETAS[tname])
+        W0 = W
+        U0, _, _ = oracle.advance(case, oracle.state_init(case, W0), 30, fixed_dt=1e-3)
+    s, th, tb = _solver(Solver, case, THETAS[tname], with_bar=True)
+    U = s.init(W)
+    if name == "implosion24":
+        s.advance_fixed(U, 30, 1e-3)
+        Uo = U0
+    else:
+        Uo = oracle.state_init(case, W)
+    Rb = _interior_noise(case, Uo.shape, 7)
+    want_u, want_t = oracle.vjp_rhs_theta(case, Uo, Rb)
+    got_u = s.rhs_adjoint(U, torch.from_numpy(Rb).cuda()).cpu().numpy()
+    got_t = tb.cpu().numpy()
+    s.close()
+    assert normwise(got_u, want_u) <= 1e-10, (name, tname, normwise(got_u, want_u))
+    assert np.any(want_t != 0.0)
+    assert vecwise(got_t, want_t) <= 1e-10, (name, tname, vecwise(got_t, want_t))
+
+
+@pytest.mark.parametrize("tname", sorted(THETAS))
+@pytest.mark.parametrize("name", ["perturbed20x20", "perturbed_x_only"])
+def test_nn_step_adjoint_matches_oracle_tape(Solver, name, tname):
+    """TVD-RK2 step adjoint: the state adjoint and the weight gradient."""
+    case, W = CASES[name]
+    _say(f"Rusanov-NN step adjoint parity: {name} / {tname}")
+    s, th, tb = _solver(Solver, case, THETAS[tname], with_bar=True)
+    U = s.init(W)
+    Uo = oracle.state_init(case, W)
+    Ub = _interior_noise(case, Uo.shape, 8)
+    want_u, want_t = oracle.vjp_step_theta(case, Uo, 1e-3, Ub)
+    got_u = s.step_adjoint(U, 1e-3, torch.from_numpy(Ub).cuda()).cpu().numpy()
+    got_t = tb.cpu().numpy()
+    s.close()
+    assert normwise(got_u, want_u) <= 1e-10, (name, tname, normwise(got_u, want_u))
+    assert vecwise(got_t, want_t) <= 1e-10, (name, tname, vecwise(got_t, want_t))
+
+
+def test_nn_weight_gradient_is_repeatable_and_accumulates(Solver):
+    """For a given Rbar the right-hand side's weight gradient is summed over the
+    faces in a fixed order: a second identical call adds exactly the same
+    values (the accumulator then holds twice the first). (Through a step the
+    second stage's Rbar is a state adjoint summed with atomics, so there the
+    weight gradient varies in its last bits like the state adjoint.)"""
+    case, W = CASES["perturbed20x20"]
+    _say("Rusanov-NN weight gradient repeatability")
+    s, th, tb = _solver(Solver, case, THETAS["wide"], with_bar=True)
+    U = s.init(W)
+    Rb = torch.from_numpy(_interior_noise(case, tuple(U.shape), 9)).cuda()
+    s.rhs_adjoint(U, Rb)
+    first = tb.clone()
+    s.rhs_adjoint(U, Rb)
+    torch.cuda.synchronize()
+    s.close()
+    assert torch.any(first != 0)
+    assert torch.equal(tb, 2.0 * first)
+
+
+def test_nn_weights_update_in_place(Solver):
+    """The weights are read at every launch: changing them in place changes the
+    next step (captured steps included) as the oracle with the new weights."""
+    case, W = CASES["perturbed20x20"]
+    _say("Rusanov-NN in-place weight update")
+    s, th, _ = _solver(Solver, case, THETAS["wide"])
+    U = s.init(W)
+    s.advance_fixed(U, 3, 1e-3)
+    th.copy_(torch.from_numpy(THETAS["near_const"]))
+    s.advance_fixed(U, 3, 1e-3)
+    oracle.set_nn(THETAS["wide"])
+    Uo, _, _ = oracle.advance(case, oracle.state_init(case, W), 3, fixed_dt=1e-3)
+    oracle.set_nn(THETAS["near_const"])
+    Uo, _, _ = oracle.advance(case, Uo, 3, fixed_dt=1e-3)
+    e = normwise(U.cpu().numpy(), Uo)
+    s.close()
+    assert e <= 1e-12, e
+
+
+def test_default_scheme_rk2_step_adjoint_matches_oracle_tape(Solver):
+    """TVD-RK2 in the step adjoint also with the default scheme (WENO5-JS, HLLC)."""
+    case, W = wl.random_smooth((14, 11, 9), seed=3, mu=0.02, flags=wl.ALL_PHYSICS | wl.RK2)
+    _say("default scheme RK2 step adjoint")
+    s = Solver(case)
+    U = s.init(W)
+    Uo = oracle.state_init(case, W)
+    dt = 0.5 * oracle.cfl_dt(case, Uo)
+    Ub = _interior_noise(case, Uo.shape, 10)
+    want = oracle.vjp_rk3_step(case, Uo, dt, Ub)
+    got = s.step_adjoint(U, dt, torch.from_numpy(Ub).cuda()).cpu().numpy()
+    s.close()
+    assert normwise(got, want) <= 1e-10, normwise(got, want)
+
+
+def test_nn_configuration_errors(Solver):
+    from paper_2203_13760_amd import cfd
+    case, W = CASES["perturbed20x20"]
+    s = Solver(case)
+    U = s.init(W)
+    with pytest.raises(cfd.CfdError) as e:  # no weights yet
+        s.rhs(U)
+    assert e.value.code == cfd.CFD_EINVAL
+    s.close()
+    for bad in (wl.INVISCID | wl.RUSANOV_NN, NN_FLAGS | wl.RUSANOV, NN_FLAGS | wl.WENOZ, NN_FLAGS | wl.ROE):
+        with pytest.raises(cfd.CfdError) as e:
+            Solver(dict(case, flags=bad))
+        assert e.value.code == cfd.CFD_EINVAL
+    plain = Solver(dict(case, flags=wl.INVISCID | wl.WENO3 | wl.RK2))
+    with pytest.raises(cfd.CfdError) as e:
+        plain.set_nn_weights(torch.zeros(cfd.CFD_NN_PARAMS, dtype=torch.float64, device="cuda"))
+    assert e.value.code == cfd.CFD_EINVAL
+    plain.close()
+    visc = Solver(dict(case, flags=NN_FLAGS | wl.VISCOUS, mu=0.01))
+    th = torch.from_numpy(THETAS["wide"]).cuda()
+    visc.set_nn_weights(th)
+    U = visc.init(W)
+    with pytest.raises(cfd.CfdError) as e:
+        visc.step_adjoint(U, 1e-3, torch.ones_like(U))
+    assert e.value.code == cfd.CFD_EUNSUPPORTED
+    visc.close()
+    b = cfd.cfd_batch_create(4, 1 << 26)
+    try:
+        with pytest.raises(cfd.CfdError) as e:
+            cfd.cfd_batch_add(b, case, torch.from_numpy(W).cuda())
+        assert e.value.code == cfd.CFD_EUNSUPPORTED
+    finally:
+        torch.cuda.synchronize()
+        cfd.cfd_batch_destroy(b)
