@@ -2,8 +2,8 @@
 gradients (§6.1, "Validation of Automatic Differentiation Gradients"),
 single-phase case, on the discrete adjoint; and the implosion of §6.2 that
 the Rusanov-NN flux is trained on, with the classical Rusanov flux and HLLC
-on the coarse grid against the coarse-grained ground truth (the network and its
-training are not part of this library).
+on the coarse grid against the coarse-grained ground truth, and the supervised
+training of the Rusanov-NN dissipation through the discrete adjoint.
 
 Gradient validation:
 
@@ -184,3 +184,217 @@ def implosion_trajectories(n_fine=128, n_cg=32, dt=2.5e-4, dt_cg=1e-3, n_cg_step
         fine.close()
         for s in coarse.values():
             s.close()
+
+
+# ---------------------------------------------------------------------------
+# Rusanov-NN training (§6.2)
+
+NN_FLAGS = wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV_NN
+
+
+def cg_trajectory(n_fine=128, n_cg=32, dt=2.5e-4, dt_cg=1e-3, n_cg_steps=1000):
+    """The coarse-grained ground truth of §6.2: the n_fine^2 implosion (WENO3-JS,
+    TVD-RK2, HLLC, fixed dt) block-averaged onto n_cg^2 every dt_cg. Returns a
+    device tensor (n_cg_steps + 1, 5, 1, n_cg, n_cg) of interior conservative
+    states, snapshot 0 the initial state."""
+    case_f, W = wl.implosion(n_fine)
+    fine = Solver(case_f)
+    try:
+        Uf = fine.init(W)
+        r = int(round(dt_cg / dt))
+        out = torch.empty((n_cg_steps + 1, 5, 1, n_cg, n_cg), dtype=torch.float64, device=Uf.device)
+        out[0] = coarse_grain(Uf, case_f, n_cg)
+        for k in range(1, n_cg_steps + 1):
+            fine.advance_fixed(Uf, r, dt)
+            out[k] = coarse_grain(Uf, case_f, n_cg)
+        if fine.check() != 0:
+            raise RuntimeError("ground-truth run left the admissible states")
+        return out
+    finally:
+        fine.close()
+
+
+def primitives_2d(Ui, gamma):
+    """(rho, u, v, p) of interior conservative states (5, ...): the primitive
+    state vector W of the §6.2 loss (the flow is two-dimensional)."""
+    rho = Ui[0]
+    u = Ui[1] / rho
+    v = Ui[2] / rho
+    p = (gamma - 1.0) * (Ui[4] - 0.5 * (Ui[1] * u + Ui[2] * v + Ui[3] * Ui[3] / rho))
+    return torch.stack((rho, u, v, p))
+
+
+class RusanovNNTrainer:
+    """Supervised training of the Rusanov-NN dissipation on a coarse-grained
+    trajectory (§6.2): from snapshot s the coarse solver (WENO3-JS, TVD-RK2,
+    Rusanov-NN, fixed dt_cg) is unrolled for n_unroll steps; the loss is the
+    mean over the unrolled steps of the mean squared error between predicted
+    and coarse-grained primitive states (rho, u, v, p); its gradient with
+    respect to the network weights comes from the step adjoints of the library
+    (the state adjoint pulled back step by step, the weight gradient
+    accumulated by the library), and Adam updates the weights in place on the
+    device, where every later launch reads them."""
+
+    def __init__(self, traj, theta0, dt_cg=1e-3, n_unroll=15, lr=5e-4, betas=(0.9, 0.999), eps=1e-8):
+        n_cg = traj.shape[-1]
+        self.case, _ = wl.implosion(n_cg, flags=NN_FLAGS)
+        self.gamma = float(self.case["gamma"])
+        self.solver = Solver(self.case)
+        self.traj = traj
+        self.dt = float(dt_cg)
+        self.n_unroll = int(n_unroll)
+        self.theta = torch.as_tensor(theta0, dtype=torch.float64).to(traj.device).contiguous()
+        self.theta_bar = torch.zeros_like(self.theta)
+        self.solver.set_nn_weights(self.theta, self.theta_bar)
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.m = torch.zeros_like(self.theta)
+        self.v = torch.zeros_like(self.theta)
+        self.t = 0
+        self.states = [self.solver.empty_state() for _ in range(self.n_unroll + 1)]
+        self.ubar = [self.solver.empty_state() for _ in range(2)]
+
+    def close(self):
+        self.solver.close()
+
+    def _window(self, s0, scale):
+        """Loss of the window from snapshot s0, times `scale`; adds its weight
+        gradient (times `scale`) to theta_bar."""
+        sv, case = self.solver, self.case
+        U = self.states[0]
+        U.zero_()
+        interior(case, U).copy_(self.traj[s0])
+        sv.fill_halo(U)
+        for k in range(1, self.n_unroll + 1):
+            self.states[k].copy_(self.states[k - 1])
+            sv.step(self.states[k], self.dt)
+        total = torch.zeros((), dtype=torch.float64, device=U.device)
+        ub, ub_prev = self.ubar
+        ub.zero_()
+        for k in range(self.n_unroll, 0, -1):
+            Ui = interior(case, self.states[k]).detach().requires_grad_(True)
+            Wp = primitives_2d(Ui, self.gamma)
+            Wt = primitives_2d(self.traj[s0 + k], self.gamma)
+            loss = torch.mean((Wp - Wt) ** 2) * (scale / self.n_unroll)
+            (g,) = torch.autograd.grad(loss, Ui)
+            interior(case, ub).add_(g)
+            total += loss.detach()
+            sv.step_adjoint(self.states[k - 1], self.dt, ub, ub_prev)
+            ub, ub_prev = ub_prev, ub
+        return float(total)
+
+    def train_batch(self, starts):
+        """One Adam step on the mean loss of the windows from `starts`; returns
+        that loss."""
+        self.theta_bar.zero_()
+        scale = 1.0 / len(starts)
+        loss = sum(self._window(int(s0), scale) for s0 in starts)
+        g = self.theta_bar
+        b1, b2 = self.betas
+        self.t += 1
+        self.m.mul_(b1).add_(g, alpha=1.0 - b1)
+        self.v.mul_(b2).addcmul_(g, g, value=1.0 - b2)
+        mh = self.m / (1.0 - b1 ** self.t)
+        vh = self.v / (1.0 - b2 ** self.t)
+        self.theta.sub_(self.lr * mh / (vh.sqrt() + self.eps))
+        return loss
+
+    def rollout_errors(self, traj_eval, every=100):
+        """Relative L1 errors of density and pressure of the coarse Rusanov-NN
+        solver run from snapshot 0 over the whole of traj_eval (the quantity of
+        the paper's error figure)."""
+        sv, case = self.solver, self.case
+        U = sv.empty_state()
+        interior(case, U).copy_(traj_eval[0])
+        sv.fill_halo(U)
+        out = {"step": [], "rho": [], "p": []}
+        n = traj_eval.shape[0] - 1
+        for k in range(1, n + 1):
+            sv.advance_fixed(U, 1, self.dt)
+            if k % every == 0 or k == n:
+                rho, p = _rho_p(interior(case, U), self.gamma)
+                rho_t, p_t = _rho_p(traj_eval[k], self.gamma)
+                out["step"].append(k)
+                out["rho"].append(float((rho - rho_t).abs().sum() / rho_t.abs().sum()))
+                out["p"].append(float((p - p_t).abs().sum() / p_t.abs().sum()))
+        out["health"] = sv.check()
+        return out
+
+
+def train_rusanov_nn(epochs=1, n_train=1000, n_unroll=15, batch=20, lr=5e-4, seed=0, n_eval=2500, every=100,
+                     theta0=None, log=print):
+    """The §6.2 training on one GPU: ground truth (128^2 -> 32^2, n_eval coarse
+    steps), training windows from the first n_train coarse steps, unroll
+    n_unroll, batches of `batch` windows, Adam with learning rate lr, `epochs`
+    passes (the paper: 200), then the trained coarse solver and the classical
+    Rusanov flux evaluated over the whole trajectory. Returns the loss per
+    epoch, the errors and the timings."""
+    t0 = time.perf_counter()
+    traj = cg_trajectory(n_cg_steps=max(n_eval, n_train))
+    torch.cuda.synchronize()
+    t_truth = time.perf_counter() - t0
+    th0 = wl.nn_weights(seed=seed, alpha0=1.2, scale=0.1) if theta0 is None else theta0
+    tr = RusanovNNTrainer(traj, th0, n_unroll=n_unroll, lr=lr)
+    g = torch.Generator().manual_seed(seed)
+    starts = torch.arange(0, n_train - n_unroll + 1)
+    out = {"epochs": epochs, "n_train": n_train, "n_unroll": n_unroll, "batch": batch, "lr": lr,
+           "truth_seconds": t_truth, "epoch_loss": [], "batches": 0}
+    try:
+        out["before"] = tr.rollout_errors(traj[: n_eval + 1], every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for ep in range(epochs):
+            perm = starts[torch.randperm(len(starts), generator=g)]
+            tot, nb = 0.0, 0
+            for b in range(0, len(perm), batch):
+                tot += tr.train_batch(perm[b:b + batch].tolist())
+                nb += 1
+            out["epoch_loss"].append(tot / nb)
+            out["batches"] += nb
+            if log:
+                log(f"epoch {ep + 1}/{epochs}: loss {tot / nb:.6e}")
+        torch.cuda.synchronize()
+        out["train_seconds"] = time.perf_counter() - t1
+        out["seconds_per_batch"] = out["train_seconds"] / max(out["batches"], 1)
+        out["after"] = tr.rollout_errors(traj[: n_eval + 1], every)
+        out["theta"] = tr.theta.cpu().numpy().tolist()
+    finally:
+        tr.close()
+    # the classical Rusanov flux from the same coarse-grained initial state
+    case_r, _ = wl.implosion(traj.shape[-1], flags=wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV)
+    sr = Solver(case_r)
+    try:
+        U = sr.empty_state()
+        interior(case_r, U).copy_(traj[0])
+        sr.fill_halo(U)
+        rus = {"step": [], "rho": [], "p": []}
+        gmm = float(case_r["gamma"])
+        for k in range(1, n_eval + 1):
+            sr.advance_fixed(U, 1, 1e-3)
+            if k % every == 0 or k == n_eval:
+                rho, p = _rho_p(interior(case_r, U), gmm)
+                rho_t, p_t = _rho_p(traj[k], gmm)
+                rus["step"].append(k)
+                rus["rho"].append(float((rho - rho_t).abs().sum() / rho_t.abs().sum()))
+                rus["p"].append(float((p - p_t).abs().sum() / p_t.abs().sum()))
+        out["rusanov"] = rus
+    finally:
+        sr.close()
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="Rusanov-NN training on the implosion of §6.2")
+    ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--n-eval", type=int, default=2500)
+    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args()
+    res = train_rusanov_nn(epochs=a.epochs, n_eval=a.n_eval, lr=a.lr, log=lambda m: print(m, flush=True))
+    summary = {k: v for k, v in res.items() if k != "theta"}
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f)

@@ -265,3 +265,37 @@ def test_nn_configuration_errors(Solver):
     finally:
         torch.cuda.synchronize()
         cfd.cfd_batch_destroy(b)
+
+
+def test_training_gradient_matches_central_differences(Solver):
+    """The §6.2 training loss of a window (unrolled coarse steps against a
+    coarse-grained truth) and its weight gradient from the step adjoints,
+    against central differences of the loss along random weight directions (a
+    one-sided difference where a ReLU unit of some face changes side within
+    the step)."""
+    from paper_2203_13760_amd.experiments import RusanovNNTrainer, cg_trajectory
+    _say("Rusanov-NN training gradient vs central differences")
+    traj = cg_trajectory(n_fine=64, n_cg=16, n_cg_steps=12)
+    th0 = wl.nn_weights(seed=2, alpha0=1.2, scale=0.5)
+    tr = RusanovNNTrainer(traj, th0, n_unroll=4)
+    try:
+        tr.theta_bar.zero_()
+        L0 = tr._window(3, 1.0) + tr._window(7, 1.0)
+        g = tr.theta_bar.clone()
+        assert torch.any(g != 0)
+        rng = np.random.default_rng(4)
+        base = tr.theta.clone()
+        for trial in range(3):
+            v = torch.from_numpy(rng.standard_normal(base.numel())).cuda()
+            h = 1e-6
+
+            def L(t):
+                tr.theta.copy_(t)
+                return tr._window(3, 1.0) + tr._window(7, 1.0)
+            Lp, Lm = L(base + h * v), L(base - h * v)
+            tr.theta.copy_(base)
+            ad = float(g @ v)
+            fds = ((Lp - Lm) / (2 * h), (Lp - L0) / h, (L0 - Lm) / h)
+            assert min(abs(f - ad) for f in fds) <= 1e-6 * max(abs(ad), 1e-3 * abs(L0)), (trial, fds, ad)
+    finally:
+        tr.close()
