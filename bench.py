@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--adj-steps", type=int, default=200)
     ap.add_argument("--no-roe", action="store_true", help="skip the ROE setup and WENO5-Z legs")
     ap.add_argument("--no-implosion", action="store_true", help="skip the implosion (Rusanov vs HLLC) leg")
+    ap.add_argument("--nn-epochs", type=int, default=1,
+                    help="epochs of the Rusanov-NN training in the implosion leg (0 skips it)")
     ap.add_argument("--roe-steps", type=int, default=10)
     ap.add_argument("--serving", action="store_true",
                     help="run the serving benchmark (batched vs one at a time) instead")
@@ -205,7 +207,7 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
             "loss": float(L.item()), "grad_norm": gnorm, "shock_gradient": sg}
 
 
-def implosion_leg():
+def implosion_leg(nn_epochs=1):
     """The implosion of §6.2 (the Rusanov-NN experiment's data): the 128^2
     ground truth (WENO3-JS, TVD-RK2, HLLC, dt 2.5e-4) coarse-grained onto 32^2
     every 1e-3, against the 32^2 solvers with the classical Rusanov flux and
@@ -219,11 +221,28 @@ def implosion_leg():
     for t in (0.1, 1.0, 2.5):
         i = int(np.argmin(np.abs(np.array(out["t"]) - t)))
         pick[f"t={t}"] = {k: out[k][i] for k in keys}
-    return {"workload": "implosion of §6.2 as printed, 128^2 truth coarse-grained to 32^2, 2500 coarse steps",
-            "coarse_steps": 2500, "seconds": out["seconds"], "health": out["health"],
-            "mean": {k: float(np.mean(out[k])) for k in keys}, "at": pick,
-            "note": "the Rusanov-NN network and its training are not built; the classical Rusanov flux and "
-                    "HLLC on the coarse grid bracket what it is trained to improve"}
+    res = {"workload": "implosion of §6.2 as printed, 128^2 truth coarse-grained to 32^2, 2500 coarse steps",
+           "coarse_steps": 2500, "seconds": out["seconds"], "health": out["health"],
+           "mean": {k: float(np.mean(out[k])) for k in keys}, "at": pick}
+    if nn_epochs > 0:
+        # the Rusanov-NN flux trained on the first 1000 coarse steps (windows of 15
+        # steps, batches of 20, Adam 5e-4; the paper trains 200 epochs)
+        from paper_2203_13760_amd.experiments import train_rusanov_nn
+        nn = train_rusanov_nn(epochs=nn_epochs, n_eval=2500, every=100, log=None)
+        at = {}
+        for t in (0.1, 1.0, 2.5):
+            i = int(np.argmin(np.abs(np.array(nn["after"]["step"]) * 1e-3 - t)))
+            at[f"t={t}"] = {"nn_rho": nn["after"]["rho"][i], "nn_p": nn["after"]["p"][i],
+                            "rusanov_rho": nn["rusanov"]["rho"][i], "rusanov_p": nn["rusanov"]["p"][i]}
+        res["rusanov_nn"] = {
+            "epochs": nn_epochs, "batches": nn["batches"], "train_seconds": nn["train_seconds"],
+            "seconds_per_batch": nn["seconds_per_batch"], "epoch_loss": nn["epoch_loss"],
+            "at": at, "health": nn["after"]["health"],
+            "mean": {"nn_rho": float(np.mean(nn["after"]["rho"])), "nn_p": float(np.mean(nn["after"]["p"])),
+                     "untrained_rho": float(np.mean(nn["before"]["rho"])),
+                     "rusanov_rho": float(np.mean(nn["rusanov"]["rho"])),
+                     "rusanov_p": float(np.mean(nn["rusanov"]["p"]))}}
+    return res
 
 
 def scheme_leg(case, W, steps, reps, hllc_ms_per_step, flag):
@@ -404,10 +423,15 @@ def main():
 
     implosion = None
     if not args.no_implosion:
-        implosion = implosion_leg()
+        implosion = implosion_leg(args.nn_epochs)
         print(f"bench: implosion 128^2 -> 32^2 over {implosion['coarse_steps']} coarse steps in "
               f"{implosion['seconds']:.1f} s; mean relative L1 density error Rusanov "
               f"{implosion['mean']['rusanov_rho']:.4f}, HLLC {implosion['mean']['hllc_rho']:.4f}", flush=True)
+        if "rusanov_nn" in implosion:
+            r = implosion["rusanov_nn"]
+            print(f"bench: Rusanov-NN trained {r['epochs']} epoch(s), {r['batches']} batches at "
+                  f"{r['seconds_per_batch']:.3f} s/batch; mean relative L1 density error "
+                  f"{r['mean']['nn_rho']:.4f} (classical Rusanov {r['mean']['rusanov_rho']:.4f})", flush=True)
         torch.cuda.empty_cache()
 
     adjoint = None

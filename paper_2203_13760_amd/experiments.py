@@ -389,10 +389,12 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="Rusanov-NN training on the implosion of §6.2")
     ap.add_argument("--epochs", type=int, default=1)
     ap.add_argument("--n-eval", type=int, default=2500)
+    ap.add_argument("--n-train", type=int, default=1000)
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--out", default="")
     a = ap.parse_args()
-    res = train_rusanov_nn(epochs=a.epochs, n_eval=a.n_eval, lr=a.lr, log=lambda m: print(m, flush=True))
+    res = train_rusanov_nn(epochs=a.epochs, n_train=a.n_train, n_eval=a.n_eval, lr=a.lr,
+                           log=lambda m: print(m, flush=True))
     summary = {k: v for k, v in res.items() if k != "theta"}
     print(json.dumps(summary), flush=True)
     if a.out:
