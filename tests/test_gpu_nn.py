@@ -299,3 +299,83 @@ def test_training_gradient_matches_central_differences(Solver):
             assert min(abs(f - ad) for f in fds) <= 1e-6 * max(abs(ad), 1e-3 * abs(L0)), (trial, fds, ad)
     finally:
         tr.close()
+
+
+def _random_nn_config(rng):
+    """A small Rusanov-NN configuration: 1-3 active ragged axes of 3..16 cells
+    (3D included, so every axis's network kernels run), per-axis periodic,
+    zero-gradient, wall or mixed boundaries, TVD-RK2 or RK3, smooth seeded data
+    with 1 % seeded cell noise, seeded weights. (A smooth field whose velocity
+    does not vary along an axis has |u_R - u_L| = 0 at every face of that axis,
+    the kink of |x|: there the oracle sees an exact zero and the device, whose
+    u = m (1/rho) rounds differently from m / rho, a jump of an ulp of either
+    sign, so the two take different one-sided derivatives. The noise keeps
+    every face off the kink.)"""
+    while True:
+        n = [int(rng.integers(3, 17)) if rng.random() < 0.8 else 1 for _ in range(3)]
+        if any(x > 1 for x in n):
+            break
+    bc = []
+    for d in range(3):
+        bc += [[wl.PERIODIC] * 2, [wl.ZERO_GRADIENT] * 2, [wl.REFLECT] * 2,
+               [wl.ZERO_GRADIENT, wl.REFLECT]][int(rng.integers(0, 4))]
+    flags = wl.INVISCID | wl.WENO3 | wl.RUSANOV_NN | (wl.RK2 if rng.random() < 0.5 else 0)
+    case, W = wl.random_smooth(tuple(n), seed=int(rng.integers(1 << 30)), mu=0.0, flags=flags, bc=tuple(bc))
+    W = W * (1.0 + 0.01 * rng.standard_normal(W.shape))
+    theta = wl.nn_weights(seed=int(rng.integers(1 << 30)), alpha0=float(rng.uniform(0.6, 2.0)),
+                          scale=float(rng.uniform(0.2, 1.0)))
+    return case, W, theta
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_nn_random_configurations_match_oracle(Solver, k):
+    """Seeded random Rusanov-NN configurations: the right-hand side, one fixed
+    step, and the step adjoint (state and weights) against the oracle."""
+    rng = np.random.default_rng(20230 + k)
+    case, W, theta = _random_nn_config(rng)
+    _say(f"Rusanov-NN random configuration {k}: n={case['n']} bc={case['bc']} flags={case['flags']}")
+    s, th, tb = _solver(Solver, case, theta, with_bar=True)
+    U = s.init(W)
+    Uo = oracle.state_init(case, W)
+    R = s.rhs(U).cpu().numpy()
+    Ro = oracle.rhs(case, Uo)
+    bound = oracle.rhs_rounding_bound(case, Uo)
+    for v in range(5):
+        err = float(np.max(np.abs(R[v] - Ro[v])))
+        assert err <= max(1e-12 * float(np.max(np.abs(Ro[v]))), bound[v]), (k, v, err, bound[v])
+    dt = 0.5 * oracle.cfl_dt(case, Uo)
+    Ub = _interior_noise(case, Uo.shape, 30 + k)
+    want_u, want_t = oracle.vjp_step_theta(case, Uo, dt, Ub)
+    got_u = s.step_adjoint(U, dt, torch.from_numpy(Ub).cuda()).cpu().numpy()
+    got_t = tb.cpu().numpy()
+    assert normwise(got_u, want_u) <= 1e-10, (k, normwise(got_u, want_u))
+    assert vecwise(got_t, want_t) <= 1e-10, (k, vecwise(got_t, want_t))
+    s.step(U, dt)
+    Uo1, _ = oracle.rk3_step(case, Uo, dt)
+    e = normwise(U.cpu().numpy(), Uo1)
+    s.close()
+    assert e <= 1e-12, (k, e)
+
+
+def test_nn_rk3_kept_stages_adjoint_matches_oracle_tape(Solver):
+    """The Rusanov-NN flux with TVD-RK3: the kept-stage step and its adjoint
+    (state and weights) against the oracle."""
+    case, W = wl.random_smooth((13, 11, 7), seed=21, mu=0.0, flags=wl.INVISCID | wl.WENO3 | wl.RUSANOV_NN,
+                               bc=(wl.REFLECT,) * 2 + (wl.PERIODIC,) * 2 + (wl.ZERO_GRADIENT,) * 2)
+    _say("Rusanov-NN RK3 kept stages adjoint")
+    s, th, tb = _solver(Solver, case, THETAS["wide"], with_bar=True)
+    U = s.init(W)
+    Uo = oracle.state_init(case, W)
+    dt = 0.5 * oracle.cfl_dt(case, Uo)
+    Un = U.clone()
+    U1, U2 = torch.empty_like(U), torch.empty_like(U)
+    s.step_stages(U, dt, U1, U2)
+    Uo1, _ = oracle.rk3_step(case, Uo, dt)
+    assert normwise(U.cpu().numpy(), Uo1) <= 1e-12
+    Ub = _interior_noise(case, Uo.shape, 40)
+    want_u, want_t = oracle.vjp_step_theta(case, Uo, dt, Ub)
+    got_u = s.step_adjoint_stages(Un, U1, U2, dt, torch.from_numpy(Ub).cuda()).cpu().numpy()
+    got_t = tb.cpu().numpy()
+    s.close()
+    assert normwise(got_u, want_u) <= 1e-10, normwise(got_u, want_u)
+    assert vecwise(got_t, want_t) <= 1e-10, vecwise(got_t, want_t)
