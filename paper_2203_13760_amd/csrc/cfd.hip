@@ -117,6 +117,8 @@ static cfd_status validate(const cfd_config* c) {
     // (the x sweep numbers its faces with 3 extra slots per row)
     long long faces = (long long)c->n[0] * c->n[1] * c->n[2] / c->n[d] * (c->n[d] + (d == 0 ? 4 : 1));
     if (faces >= (1LL << 31)) return fail(CFD_EINVAL, "grid too large: faces per axis must fit in 31 bits");
+    if ((c->flags & CFD_F_RUSANOV_NN) && faces >= (1LL << 29))
+      return fail(CFD_EINVAL, "grid too large: the Rusanov-NN kernels run four lanes per face (faces per axis < 2^29)");
   }
   if (N[0] * N[1] >= (1LL << 31) || N[2] > 65535) return fail(CFD_EINVAL, "grid too large for the launch shape");
   return CFD_OK;
@@ -234,13 +236,14 @@ static long long faces_of(const Geom& g, int d) {
   return (long long)g.n[0] * g.n[1] * g.n[2] / g.n[d] * (g.n[d] + 1);
 }
 
-// Rusanov-NN: alpha of every face of the active axes from primitives P.
+// Rusanov-NN: alpha of every face of the active axes from primitives P (the
+// network kernels run four lanes per face).
 static cfd_status enqueue_nn_alpha(cfd_solver* s, const double* P, hipStream_t st) {
   const Geom& g = s->g;
   if (!g.nnw) return fail(CFD_EINVAL, "Rusanov-NN weights are not set (cfd_set_nn_weights)");
-  if (g.act[0]) hipLaunchKernelGGL(k_nn_alpha<0>, dim3(grid_for(faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, g);
-  if (g.act[1]) hipLaunchKernelGGL(k_nn_alpha<1>, dim3(grid_for(faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, g);
-  if (g.act[2]) hipLaunchKernelGGL(k_nn_alpha<2>, dim3(grid_for(faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, g);
+  if (g.act[0]) hipLaunchKernelGGL(k_nn_alpha<0>, dim3(grid_for(4 * faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, g);
+  if (g.act[1]) hipLaunchKernelGGL(k_nn_alpha<1>, dim3(grid_for(4 * faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, g);
+  if (g.act[2]) hipLaunchKernelGGL(k_nn_alpha<2>, dim3(grid_for(4 * faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, g);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -462,17 +465,17 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
     if (!g.nnw) return fail(CFD_EINVAL, "Rusanov-NN weights are not set (cfd_set_nn_weights)");
     long long off = 0;
     if (g.act[0]) {
-      hipLaunchKernelGGL(k_face_adj_nn<0>, dim3(grid_for(faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
+      hipLaunchKernelGGL(k_face_adj_nn<0>, dim3(grid_for(4 * faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
                          rscale, s->Wbar, g, s->tape, off);
       off += faces_of(g, 0);
     }
     if (g.act[1]) {
-      hipLaunchKernelGGL(k_face_adj_nn<1>, dim3(grid_for(faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
+      hipLaunchKernelGGL(k_face_adj_nn<1>, dim3(grid_for(4 * faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
                          rscale, s->Wbar, g, s->tape, off);
       off += faces_of(g, 1);
     }
     if (g.act[2])
-      hipLaunchKernelGGL(k_face_adj_nn<2>, dim3(grid_for(faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
+      hipLaunchKernelGGL(k_face_adj_nn<2>, dim3(grid_for(4 * faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
                          rscale, s->Wbar, g, s->tape, off);
     CFD_LAUNCHED();
     if (s->nnbar) {

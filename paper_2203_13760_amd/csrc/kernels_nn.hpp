@@ -1,18 +1,22 @@
 // Rusanov-NN flux of §6.2 on gfx950: the Rusanov flux whose dissipation alpha
 // is the output of a small network of four face features.
 //
-//   forward:  k_nn_alpha<D> evaluates the network once per face normal to D
+//   forward:  k_nn_alpha<D> evaluates the network for every face normal to D
 //             from the WENO3-JS face states and stores alpha at the face's
 //             left cell (Geom::nna); the sweeps (scheme SCH_W3_NN) read it.
-//   reverse:  k_face_adj_nn<D>, one lane per face, recomputes the face (states,
-//             features, network), reverses the flux with alpha held, the
-//             network (output adjoint -> input adjoint) and the features, then
-//             the WENO3-JS stencils into Wbar with atomics, as the other face
+//   reverse:  k_face_adj_nn<D> recomputes the face (states, features,
+//             network), reverses the flux with alpha held, the network
+//             (output adjoint -> input adjoint) and the features, then the
+//             WENO3-JS stencils into Wbar with atomics, as the other face
 //             reverses do. It records the network's pre-activations and their
 //             adjoints per face; k_nn_wgrad forms the weight gradient from the
 //             records as the sums over faces of (delta_l h_{l-1}^T), one block
 //             per output row, in a fixed order (bitwise repeatable for given
 //             face adjoints).
+//
+// The layers are FP64 matrix products on the matrix cores: a wavefront takes 16
+// faces, four lanes per face, and a layer of 32 units is two 16 x 16 result
+// tiles, each a chain of 16x16x4 products over the layer's inputs.
 #pragma once
 #include "kernels_adj.hpp"
 
@@ -73,45 +77,95 @@ __device__ __forceinline__ void nn_features(const Geom& g, const double* WL, con
   f[3] = fabs(sR - sL);
 }
 
-// Hidden layer: zo = W relu(zi) + b (zi of the first layer are the inputs
-// themselves, passed through unchanged by the caller).
-template <int NIN, bool ACT>
-__device__ __forceinline__ void nn_layer(const double* __restrict__ W, const double* __restrict__ b, const double* zi,
-                                         double* zo) {
+typedef double nn_v4 __attribute__((ext_vector_type(4)));
+
+// Matrix layout. The 16x16x4 product D = A B + C takes A[i][k] from lane
+// i + 16k, B[k][j] from lane j + 16k, and leaves D[4r + k][j] in item r of lane
+// j + 16k. A wavefront holds 16 faces: lane (f, q) = f + 16q works on face f
+// (f = lane % 16) in quarter q (= lane / 16). A layer's 32 units x 16 faces
+// are two tiles t of 16 units; lane (f, q) holds units 16t + 4r + q, r = 0..3,
+// of face f (NNTile). The next layer's B operand in its k-step s (s = 0..7)
+// is then the lane's own item r = s % 4 of tile t = s / 4, input unit
+// nn_unit(s, q): a layer needs no exchange between lanes.
+struct NNTile {
+  nn_v4 t[2];
+};
+
+__device__ __forceinline__ int nn_unit(int s, int q) { return 16 * (s >> 2) + 4 * (s & 3) + q; }
+
+__device__ __forceinline__ nn_v4 nn_mfma(double a, double b, nn_v4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// First layer: z = W1 f + b1; lane (f, q) supplies input feature q of its face.
+__device__ __forceinline__ void nn_layer1(const double* __restrict__ th, double fq, int f, int q, NNTile& z) {
 #pragma unroll
-  for (int o = 0; o < kNNH; ++o) {
-    double s = b[o];
+  for (int t = 0; t < 2; ++t) {
+    nn_v4 c;
 #pragma unroll
-    for (int i = 0; i < NIN; ++i) s = fma(W[o * NIN + i], ACT ? relu(zi[i]) : zi[i], s);
-    zo[o] = s;
+    for (int r = 0; r < 4; ++r) c[r] = th[kNNb1 + 16 * t + 4 * r + q];
+    z.t[t] = nn_mfma(th[(16 * t + f) * kNNIn + q], fq, c);
   }
 }
 
-// Forward pass: the hidden pre-activations into z1..z3; returns the output
-// pre-activation (alpha = exp of it). Every lane reads the same weight
-// addresses, so the loads are scalar.
-__device__ __forceinline__ double nn_forward(const double* __restrict__ th, const double* f, double* z1, double* z2,
-                                             double* z3) {
-  nn_layer<kNNIn, false>(th, th + kNNb1, f, z1);
-  nn_layer<kNNH, true>(th + kNNW2, th + kNNb2, z1, z2);
-  nn_layer<kNNH, true>(th + kNNW3, th + kNNb3, z2, z3);
-  double s = th[kNNb4];
+// Hidden layer: z = W relu(h) + b (W row-major 32 x 32).
+__device__ __forceinline__ void nn_layer(const double* __restrict__ W, const double* __restrict__ b, const NNTile& h,
+                                         int f, int q, NNTile& z) {
 #pragma unroll
-  for (int i = 0; i < kNNH; ++i) s = fma(th[kNNW4 + i], relu(z3[i]), s);
-  return s;
+  for (int t = 0; t < 2; ++t) {
+    nn_v4 c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c[r] = b[16 * t + 4 * r + q];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) c = nn_mfma(W[(16 * t + f) * kNNH + nn_unit(s, q)], relu(h.t[s >> 2][s & 3]), c);
+    z.t[t] = c;
+  }
+}
+
+// Output pre-activation of the lane's face: W4 relu(z3) + b4, the four
+// quarters' partial sums added across lanes (every lane of the face gets it).
+__device__ __forceinline__ double nn_output(const double* __restrict__ th, const NNTile& z3, int q) {
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s = fma(th[kNNW4 + 16 * t + 4 * r + q], relu(z3.t[t][r]), s);
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  return s + th[kNNb4];
+}
+
+// Forward pass of the lane's face; returns the output pre-activation.
+__device__ __forceinline__ double nn_forward(const double* __restrict__ th, double fq, int f, int q, NNTile& z1,
+                                             NNTile& z2, NNTile& z3) {
+  nn_layer1(th, fq, f, q, z1);
+  nn_layer(th + kNNW2, th + kNNb2, z1, f, q, z2);
+  nn_layer(th + kNNW3, th + kNNb3, z2, f, q, z3);
+  return nn_output(th, z3, q);
 }
 
 // Transposed layer: di = (W^T dout) masked by the ReLU of zi (a pre-activation
 // of exactly zero passes, as max(z, 0) taking z there).
-__device__ __forceinline__ void nn_layer_rev(const double* __restrict__ W, const double* dout, const double* zi,
-                                             double* di) {
+__device__ __forceinline__ void nn_layer_rev(const double* __restrict__ W, const NNTile& dout, const NNTile& zi,
+                                             int f, int q, NNTile& di) {
 #pragma unroll
-  for (int i = 0; i < kNNH; ++i) {
-    double s = 0.0;
+  for (int t = 0; t < 2; ++t) {
+    nn_v4 c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int o = 0; o < kNNH; ++o) s = fma(W[o * kNNH + i], dout[o], s);
-    di[i] = zi[i] >= 0.0 ? s : 0.0;
+    for (int s = 0; s < 8; ++s) c = nn_mfma(W[nn_unit(s, q) * kNNH + 16 * t + f], dout.t[s >> 2][s & 3], c);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c[r] = zi.t[t][r] >= 0.0 ? c[r] : 0.0;
+    di.t[t] = c;
   }
+}
+
+// Input adjoint of the first layer: W1^T d1, one tile whose rows 0..3 are the
+// four inputs; lane (f, q) receives input q's adjoint of its face.
+__device__ __forceinline__ double nn_input_rev(const double* __restrict__ th, const NNTile& d1, int f, int q) {
+  nn_v4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) c = nn_mfma(f < kNNIn ? th[nn_unit(s, q) * kNNIn + f] : 0.0, d1.t[s >> 2][s & 3], c);
+  return c[0];
 }
 
 // Primitive adjoint of one side's physical flux F(W) and conservative state
@@ -199,83 +253,99 @@ __device__ __forceinline__ void nn_features_rev(const Geom& g, const double* WL,
   WRb[0] -= sRb * g.gamma * g.gm1i / WR[0];
 }
 
-// alpha of every face normal to D (one lane per face, numbered as in the face
-// reverses), stored at the face's left cell.
+// Face and lane of a network kernel: 16 faces per wavefront, numbered as in
+// the face reverses. Lanes beyond the last face take face 0 (valid addresses)
+// and keep to the matrix products, which need the whole wavefront.
+template <int D>
+__device__ __forceinline__ bool nn_face(const Geom& g, int& t, int& i, int& j, int& k, int& f, int& q) {
+  const int lane = threadIdx.x & 63;
+  f = lane & 15;
+  q = lane >> 4;
+  t = ((blockIdx.x * blockDim.x + (int)threadIdx.x) >> 6) * 16 + f;
+  int fc = 0, col = 0;
+  const bool has = face_coords<D>(g, t, i, j, k, fc, col);
+  if (!has) face_coords<D>(g, 0, i, j, k, fc, col);
+  return has;
+}
+
+// alpha of every face normal to D, stored at the face's left cell.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_nn_alpha(const double* __restrict__ P, Geom g) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i = 0, j = 0, k = 0, f = 0, col = 0;
-  if (!face_coords<D>(g, t, i, j, k, f, col)) return;
-  const long long cl = cell_at(g, i, j, k) - g.s[D];  // cell f-1
-  double WL[5], WR[5], ft[kNNIn], z1[kNNH], z2[kNNH], z3[kNNH];
+  int t, i, j, k, f, q;
+  const bool has = nn_face<D>(g, t, i, j, k, f, q);
+  const long long cl = cell_at(g, i, j, k) - g.s[D];  // cell f-1 of the face
+  double WL[5], WR[5], ft[kNNIn];
   nn_face_states<D>(g, P, cl, WL, WR);
   nn_features<D>(g, WL, WR, ft);
-  g.nna[D * g.vs + cl] = exp(nn_forward(g.nnw, ft, z1, z2, z3));
+  const double fq = q == 0 ? ft[0] : q == 1 ? ft[1] : q == 2 ? ft[2] : ft[3];
+  NNTile z1, z2, z3;
+  const double out = nn_forward(g.nnw, fq, f, q, z1, z2, z3);
+  if (has && q == 0) g.nna[D * g.vs + cl] = exp(out);
 }
 
 // Face reverse of the Rusanov-NN flux (inviscid), faces normal to D; the
-// records of face t go to slot off + t of the tape.
+// records of face t go to slot off + t of the tape. The four lanes of a face
+// share the network's products; the flux reverse is the same in each, and the
+// stencil reverse is split by variable (quarter q takes the variables
+// v = q mod 4).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_face_adj_nn(const double* __restrict__ P, const double* __restrict__ Rbar,
                                                         double rscale, double* Wbar, Geom g, NNTape tp, long long off) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i = 0, j = 0, k = 0, f = 0, col = 0;
-  if (!face_coords<D>(g, t, i, j, k, f, col)) return;
+  int t, i, j, k, f, q;
+  const bool has = nn_face<D>(g, t, i, j, k, f, q);
   const long long st = g.s[D];
   const long long cf = cell_at(g, i, j, k), cl = cf - st;
   const long long e = off + t;
   double Gb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  face_gbar<D>(g, Rbar, rscale, cf, f, Gb);
-  double WL[5], WR[5], ft[kNNIn], z1[kNNH], z2[kNNH], z3[kNNH];
+  if (has) face_gbar<D>(g, Rbar, rscale, cf, D == 0 ? i : D == 1 ? j : k, Gb);  // face index along D
+  double WL[5], WR[5], ft[kNNIn];
   nn_face_states<D>(g, P, cl, WL, WR);
   nn_features<D>(g, WL, WR, ft);
+  const double fq = q == 0 ? ft[0] : q == 1 ? ft[1] : q == 2 ? ft[2] : ft[3];
   const double* __restrict__ th = g.nnw;
-  const double alpha = exp(nn_forward(th, ft, z1, z2, z3));
-  // records for the weight gradient; the reverse reads the pre-activations
-  // back from them rather than keeping 96 values live across it
-  double* rz1 = tp.z[0] + e * kNNH;
-  double* rz2 = tp.z[1] + e * kNNH;
-  double* rz3 = tp.z[2] + e * kNNH;
-#pragma unroll
-  for (int o = 0; o < kNNH; ++o) {
-    rz1[o] = z1[o];
-    rz2[o] = z2[o];
-    rz3[o] = z3[o];
-  }
-#pragma unroll
-  for (int m = 0; m < kNNIn; ++m) tp.f[e * kNNIn + m] = ft[m];
-  asm volatile("" ::: "memory");
+  NNTile z1, z2, z3;
+  const double alpha = exp(nn_forward(th, fq, f, q, z1, z2, z3));
   double WLb[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WRb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const double ab = rusanov_given_rev<D>(g.gm1i, WL, WR, alpha, Gb, WLb, WRb);
   // network reverse: output through exp, then the layers
   const double d4 = ab * alpha;
-  tp.d4[e] = d4;
-  double da[kNNH], db[kNNH];
+  NNTile d3, d2, d1;
 #pragma unroll
-  for (int o = 0; o < kNNH; ++o) da[o] = rz3[o] >= 0.0 ? th[kNNW4 + o] * d4 : 0.0;  // d3
+  for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
-  for (int o = 0; o < kNNH; ++o) tp.d[2][e * kNNH + o] = da[o];
-  nn_layer_rev(th + kNNW3, da, rz2, db);  // d2
-#pragma unroll
-  for (int o = 0; o < kNNH; ++o) tp.d[1][e * kNNH + o] = db[o];
-  nn_layer_rev(th + kNNW2, db, rz1, da);  // d1
-#pragma unroll
-  for (int o = 0; o < kNNH; ++o) tp.d[0][e * kNNH + o] = da[o];
+    for (int r = 0; r < 4; ++r) d3.t[tt][r] = z3.t[tt][r] >= 0.0 ? th[kNNW4 + 16 * tt + 4 * r + q] * d4 : 0.0;
+  nn_layer_rev(th + kNNW3, d3, z2, f, q, d2);
+  nn_layer_rev(th + kNNW2, d2, z1, f, q, d1);
+  const double fbq = nn_input_rev(th, d1, f, q);
   double fb[kNNIn];
 #pragma unroll
-  for (int m = 0; m < kNNIn; ++m) {
-    double s = 0.0;
+  for (int m = 0; m < kNNIn; ++m) fb[m] = __shfl(fbq, f + 16 * m, 64);
+  if (has) {
+    // records for the weight gradient
 #pragma unroll
-    for (int o = 0; o < kNNH; ++o) s = fma(th[o * kNNIn + m], da[o], s);
-    fb[m] = s;
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long long u = e * kNNH + 16 * tt + 4 * r + q;
+        tp.z[0][u] = z1.t[tt][r];
+        tp.z[1][u] = z2.t[tt][r];
+        tp.z[2][u] = z3.t[tt][r];
+        tp.d[0][u] = d1.t[tt][r];
+        tp.d[1][u] = d2.t[tt][r];
+        tp.d[2][u] = d3.t[tt][r];
+      }
+    tp.f[e * kNNIn + q] = fq;
+    if (q == 0) tp.d4[e] = d4;
   }
   nn_features_rev<D>(g, WL, WR, fb, WLb, WRb);
-  // WENO3-JS reverse into the stencil cells cl-1 .. cl+2
+  if (!has) return;
+  // WENO3-JS reverse into the stencil cells cl-1 .. cl+2, variables v = q mod 4
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
+    if ((v & 3) != q) continue;
     double* w = Wbar + v * g.vs + cl;
-    const double* q = P + v * g.vs + cl;
-    const double a = q[-st], b = q[0], c = q[st], d = q[2 * st];
+    const double* qv = P + v * g.vs + cl;
+    const double a = qv[-st], b = qv[0], c = qv[st], d = qv[2 * st];
     double gs[4] = {0.0, 0.0, 0.0, 0.0};
     weno3_rev(a, b, c, WLb[v], gs);
     double gr[3] = {0.0, 0.0, 0.0};
