@@ -224,6 +224,31 @@ def primitives_2d(Ui, gamma):
     return torch.stack((rho, u, v, p))
 
 
+def _interior_slices(case):
+    """Slices of the interior cells over the last three (z, y, x) dimensions."""
+    nh = int(case.get("nh", 3))
+    return tuple(slice(nh, nh + int(case["n"][d])) if int(case["n"][d]) > 1 else slice(0, 1) for d in (2, 1, 0))
+
+
+def primitive_mse_grad(Ui, Wt, gamma, scale):
+    """Gradient with respect to interior conservative states Ui (5, ...) of
+    scale * mean((W(Ui) - Wt)^2), W = (rho, u, v, p) as in primitives_2d and Wt
+    the target primitives (4, ...), written out by the chain rule (elementwise,
+    so it can be captured in a graph without reductions)."""
+    rho = Ui[0]
+    ir = 1.0 / rho
+    u, v, w = Ui[1] * ir, Ui[2] * ir, Ui[3] * ir
+    gm1 = gamma - 1.0
+    p = gm1 * (Ui[4] - 0.5 * (Ui[1] * u + Ui[2] * v + Ui[3] * w))
+    c = 2.0 * scale / (4.0 * rho.numel())
+    rr, ru, rv, rp = c * (rho - Wt[0]), c * (u - Wt[1]), c * (v - Wt[2]), c * (p - Wt[3])
+    return torch.stack((rr - (ru * u + rv * v) * ir + rp * (0.5 * gm1) * (u * u + v * v + w * w),
+                        ru * ir - rp * (gm1 * u),
+                        rv * ir - rp * (gm1 * v),
+                        -rp * (gm1 * w),
+                        rp * gm1))
+
+
 class RusanovNNTrainer:
     """Supervised training of the Rusanov-NN dissipation on a coarse-grained
     trajectory (§6.2): from snapshot s the coarse solver (WENO3-JS, TVD-RK2,
@@ -235,7 +260,7 @@ class RusanovNNTrainer:
     accumulated by the library), and Adam updates the weights in place on the
     device, where every later launch reads them."""
 
-    def __init__(self, traj, theta0, dt_cg=1e-3, n_unroll=15, lr=5e-4, betas=(0.9, 0.999), eps=1e-8):
+    def __init__(self, traj, theta0, dt_cg=1e-3, n_unroll=15, lr=5e-4, betas=(0.9, 0.999), eps=1e-8, graph=False):
         n_cg = traj.shape[-1]
         self.case, _ = wl.implosion(n_cg, flags=NN_FLAGS)
         self.gamma = float(self.case["gamma"])
@@ -250,44 +275,74 @@ class RusanovNNTrainer:
         self.m = torch.zeros_like(self.theta)
         self.v = torch.zeros_like(self.theta)
         self.t = 0
-        self.states = [self.solver.empty_state() for _ in range(self.n_unroll + 1)]
+        shape = tuple(self.solver.shape)
+        self.S = torch.zeros((self.n_unroll + 1,) + shape, dtype=torch.float64, device=traj.device)  # states
+        self.T = torch.zeros((self.n_unroll, 4) + tuple(traj.shape[2:]), dtype=torch.float64, device=traj.device)
         self.ubar = [self.solver.empty_state() for _ in range(2)]
+        self.graph = None
+        if graph:
+            self._capture()
 
     def close(self):
+        self.graph = None
         self.solver.close()
 
-    def _window(self, s0, scale):
-        """Loss of the window from snapshot s0, times `scale`; adds its weight
-        gradient (times `scale`) to theta_bar."""
+    def _body(self):
+        """The window on the static buffers: n_unroll fixed steps from S[0],
+        then the reverse, each step adjoint seeded with the loss gradient of its
+        output against the targets T; the library adds the weight gradient
+        (loss scale 1) to theta_bar. A fixed launch sequence with no host
+        synchronisation and no allocation (capturable)."""
         sv, case = self.solver, self.case
-        U = self.states[0]
-        U.zero_()
-        interior(case, U).copy_(self.traj[s0])
-        sv.fill_halo(U)
         for k in range(1, self.n_unroll + 1):
-            self.states[k].copy_(self.states[k - 1])
-            sv.step(self.states[k], self.dt)
-        total = torch.zeros((), dtype=torch.float64, device=U.device)
+            self.S[k].copy_(self.S[k - 1])
+            sv.step(self.S[k], self.dt)
         ub, ub_prev = self.ubar
         ub.zero_()
         for k in range(self.n_unroll, 0, -1):
-            Ui = interior(case, self.states[k]).detach().requires_grad_(True)
-            Wp = primitives_2d(Ui, self.gamma)
-            Wt = primitives_2d(self.traj[s0 + k], self.gamma)
-            loss = torch.mean((Wp - Wt) ** 2) * (scale / self.n_unroll)
-            (g,) = torch.autograd.grad(loss, Ui)
+            g = primitive_mse_grad(interior(case, self.S[k]), self.T[k - 1], self.gamma, 1.0 / self.n_unroll)
             interior(case, ub).add_(g)
-            total += loss.detach()
-            sv.step_adjoint(self.states[k - 1], self.dt, ub, ub_prev)
+            sv.step_adjoint(self.S[k - 1], self.dt, ub, ub_prev)
             ub, ub_prev = ub_prev, ub
-        return float(total)
+
+    def _capture(self):
+        """Record _body as one HIP graph (torch's graph capture over the
+        library's launches on the current stream). One eager run first
+        allocates the library's adjoint scratch and warms the allocator; the
+        weight gradient it adds is cleared."""
+        self._body()
+        torch.cuda.synchronize()
+        self.theta_bar.zero_()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._body()
+        torch.cuda.synchronize()
+        self.theta_bar.zero_()
+        self.graph = g
+
+    def _window(self, s0):
+        """Loss of the window from snapshot s0 (a device scalar); adds its
+        weight gradient to theta_bar."""
+        case = self.case
+        U = self.S[0]
+        interior(case, U).copy_(self.traj[s0])
+        self.solver.fill_halo(U)
+        Tc = self.traj[s0 + 1:s0 + 1 + self.n_unroll]          # (n_unroll, 5, 1, n, n)
+        self.T.copy_(primitives_2d(Tc.transpose(0, 1), self.gamma).transpose(0, 1))
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            self._body()
+        Si = self.S[1:][(Ellipsis,) + _interior_slices(case)]  # (n_unroll, 5, 1, n, n)
+        Wp = primitives_2d(Si.transpose(0, 1), self.gamma)
+        return torch.mean((Wp - self.T.transpose(0, 1)) ** 2)
 
     def train_batch(self, starts):
         """One Adam step on the mean loss of the windows from `starts`; returns
         that loss."""
         self.theta_bar.zero_()
-        scale = 1.0 / len(starts)
-        loss = sum(self._window(int(s0), scale) for s0 in starts)
+        loss = sum(self._window(int(s0)) for s0 in starts) / len(starts)
+        self.theta_bar.mul_(1.0 / len(starts))
         g = self.theta_bar
         b1, b2 = self.betas
         self.t += 1
@@ -296,7 +351,7 @@ class RusanovNNTrainer:
         mh = self.m / (1.0 - b1 ** self.t)
         vh = self.v / (1.0 - b2 ** self.t)
         self.theta.sub_(self.lr * mh / (vh.sqrt() + self.eps))
-        return loss
+        return float(loss)
 
     def rollout_errors(self, traj_eval, every=100):
         """Relative L1 errors of density and pressure of the coarse Rusanov-NN
@@ -321,22 +376,23 @@ class RusanovNNTrainer:
 
 
 def train_rusanov_nn(epochs=1, n_train=1000, n_unroll=15, batch=20, lr=5e-4, seed=0, n_eval=2500, every=100,
-                     theta0=None, log=print):
+                     theta0=None, log=print, graph=True):
     """The §6.2 training on one GPU: ground truth (128^2 -> 32^2, n_eval coarse
     steps), training windows from the first n_train coarse steps, unroll
     n_unroll, batches of `batch` windows, Adam with learning rate lr, `epochs`
     passes (the paper: 200), then the trained coarse solver and the classical
-    Rusanov flux evaluated over the whole trajectory. Returns the loss per
-    epoch, the errors and the timings."""
+    Rusanov flux evaluated over the whole trajectory. With graph set, each
+    window replays one captured HIP graph. Returns the loss per epoch, the
+    errors and the timings."""
     t0 = time.perf_counter()
     traj = cg_trajectory(n_cg_steps=max(n_eval, n_train))
     torch.cuda.synchronize()
     t_truth = time.perf_counter() - t0
     th0 = wl.nn_weights(seed=seed, alpha0=1.2, scale=0.1) if theta0 is None else theta0
-    tr = RusanovNNTrainer(traj, th0, n_unroll=n_unroll, lr=lr)
+    tr = RusanovNNTrainer(traj, th0, n_unroll=n_unroll, lr=lr, graph=graph)
     g = torch.Generator().manual_seed(seed)
     starts = torch.arange(0, n_train - n_unroll + 1)
-    out = {"epochs": epochs, "n_train": n_train, "n_unroll": n_unroll, "batch": batch, "lr": lr,
+    out = {"epochs": epochs, "n_train": n_train, "n_unroll": n_unroll, "batch": batch, "lr": lr, "graph": graph,
            "truth_seconds": t_truth, "epoch_loss": [], "batches": 0}
     try:
         out["before"] = tr.rollout_errors(traj[: n_eval + 1], every)
@@ -390,11 +446,12 @@ if __name__ == "__main__":
     ap.add_argument("--epochs", type=int, default=1)
     ap.add_argument("--n-eval", type=int, default=2500)
     ap.add_argument("--n-train", type=int, default=1000)
+    ap.add_argument("--no-graph", action="store_true", help="run each training window eagerly")
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     res = train_rusanov_nn(epochs=a.epochs, n_train=a.n_train, n_eval=a.n_eval, lr=a.lr,
-                           log=lambda m: print(m, flush=True))
+                           log=lambda m: print(m, flush=True), graph=not a.no_graph)
     summary = {k: v for k, v in res.items() if k != "theta"}
     print(json.dumps(summary), flush=True)
     if a.out:

@@ -280,7 +280,7 @@ def test_training_gradient_matches_central_differences(Solver):
     tr = RusanovNNTrainer(traj, th0, n_unroll=4)
     try:
         tr.theta_bar.zero_()
-        L0 = tr._window(3, 1.0) + tr._window(7, 1.0)
+        L0 = float(tr._window(3) + tr._window(7))
         g = tr.theta_bar.clone()
         assert torch.any(g != 0)
         rng = np.random.default_rng(4)
@@ -291,7 +291,7 @@ def test_training_gradient_matches_central_differences(Solver):
 
             def L(t):
                 tr.theta.copy_(t)
-                return tr._window(3, 1.0) + tr._window(7, 1.0)
+                return float(tr._window(3) + tr._window(7))
             Lp, Lm = L(base + h * v), L(base - h * v)
             tr.theta.copy_(base)
             ad = float(g @ v)
@@ -379,3 +379,35 @@ def test_nn_rk3_kept_stages_adjoint_matches_oracle_tape(Solver):
     s.close()
     assert normwise(got_u, want_u) <= 1e-10, normwise(got_u, want_u)
     assert vecwise(got_t, want_t) <= 1e-10, vecwise(got_t, want_t)
+
+
+def test_training_window_graph_matches_eager(Solver):
+    """The training window captured as one HIP graph (15 steps, the loss
+    gradients, 15 step adjoints) against the same window run eagerly: every
+    replay, with eager work and synchronisations between replays, gives the
+    eager loss and weight gradient (to the run-to-run rounding of the
+    adjoint's atomics), and a captured Adam batch equals an eager one."""
+    from paper_2203_13760_amd.experiments import RusanovNNTrainer, cg_trajectory
+    _say("Rusanov-NN training window: graph replays against eager")
+    traj = cg_trajectory(n_fine=64, n_cg=16, n_cg_steps=30)
+    th0 = wl.nn_weights(seed=2, alpha0=1.2, scale=0.5)
+    eager = RusanovNNTrainer(traj, th0, n_unroll=6)
+    graph = RusanovNNTrainer(traj, th0, n_unroll=6, graph=True)
+    try:
+        for s0 in (0, 9, 4, 17):
+            eager.theta_bar.zero_()
+            graph.theta_bar.zero_()
+            le = float(eager._window(s0))
+            torch.cuda.synchronize()
+            lg = float(graph._window(s0))
+            torch.cuda.synchronize()
+            assert abs(lg - le) <= 1e-12 * abs(le), (s0, lg, le)
+            assert vecwise(graph.theta_bar.cpu().numpy(), eager.theta_bar.cpu().numpy()) <= 1e-10, s0
+        for b in ([1, 5, 9], [2, 3]):
+            le = eager.train_batch(b)
+            lg = graph.train_batch(b)
+            assert abs(lg - le) <= 1e-12 * abs(le), (b, lg, le)
+            assert vecwise(graph.theta.cpu().numpy(), eager.theta.cpu().numpy()) <= 1e-12, b
+    finally:
+        eager.close()
+        graph.close()

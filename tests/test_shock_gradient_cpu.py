@@ -100,3 +100,20 @@ def test_coarse_graining_conserves_totals():
     assert torch.allclose(C.sum(dim=(1, 2, 3)) * 16, tot_f, rtol=1e-14, atol=0)
     interior(case, U).fill_(2.5)
     assert torch.all(coarse_grain(U, case, 4) == 2.5)
+
+
+def test_primitive_mse_grad_matches_autograd():
+    """The hand-written gradient of the Rusanov-NN training loss (mean squared
+    error of (rho, u, v, p)) against torch autograd, on the CPU."""
+    import torch
+    from paper_2203_13760_amd.experiments import primitive_mse_grad, primitives_2d
+    g = torch.Generator().manual_seed(3)
+    Ui = torch.rand((5, 1, 6, 7), generator=g, dtype=torch.float64)
+    Ui[0] += 0.5
+    Ui[4] += 3.0
+    Wt = torch.rand((4, 1, 6, 7), generator=g, dtype=torch.float64)
+    x = Ui.clone().requires_grad_(True)
+    loss = torch.mean((primitives_2d(x, 1.4) - Wt) ** 2) * 0.3
+    (want,) = torch.autograd.grad(loss, x)
+    got = primitive_mse_grad(Ui, Wt, 1.4, 0.3)
+    assert torch.allclose(got, want, rtol=1e-13, atol=1e-16)
