@@ -305,14 +305,27 @@ class RusanovNNTrainer:
             sv.step_adjoint(self.S[k - 1], self.dt, ub, ub_prev)
             ub, ub_prev = ub_prev, ub
 
+    def _load(self, s0):
+        """The window from snapshot s0 into the static buffers: S[0] (with its
+        halo) and the target primitives T."""
+        case = self.case
+        U = self.S[0]
+        interior(case, U).copy_(self.traj[s0])
+        self.solver.fill_halo(U)
+        Tc = self.traj[s0 + 1:s0 + 1 + self.n_unroll]          # (n_unroll, 5, 1, n, n)
+        self.T.copy_(primitives_2d(Tc.transpose(0, 1), self.gamma).transpose(0, 1))
+
     def _capture(self):
         """Record _body as one HIP graph (torch's graph capture over the
-        library's launches on the current stream). One eager run first
-        allocates the library's adjoint scratch and warms the allocator; the
-        weight gradient it adds is cleared."""
+        library's launches on the current stream). One eager run on the first
+        window first allocates the library's adjoint scratch and warms the
+        allocator; the weight gradient it adds is cleared, and so is the
+        solver's health word."""
+        self._load(0)
         self._body()
         torch.cuda.synchronize()
         self.theta_bar.zero_()
+        self.solver.check()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self._body()
@@ -324,11 +337,7 @@ class RusanovNNTrainer:
         """Loss of the window from snapshot s0 (a device scalar); adds its
         weight gradient to theta_bar."""
         case = self.case
-        U = self.S[0]
-        interior(case, U).copy_(self.traj[s0])
-        self.solver.fill_halo(U)
-        Tc = self.traj[s0 + 1:s0 + 1 + self.n_unroll]          # (n_unroll, 5, 1, n, n)
-        self.T.copy_(primitives_2d(Tc.transpose(0, 1), self.gamma).transpose(0, 1))
+        self._load(s0)
         if self.graph is not None:
             self.graph.replay()
         else:

@@ -394,6 +394,7 @@ def test_training_window_graph_matches_eager(Solver):
     eager = RusanovNNTrainer(traj, th0, n_unroll=6)
     graph = RusanovNNTrainer(traj, th0, n_unroll=6, graph=True)
     try:
+        assert graph.solver.check() == 0  # the capture leaves no bad state behind
         for s0 in (0, 9, 4, 17):
             eager.theta_bar.zero_()
             graph.theta_bar.zero_()
@@ -408,6 +409,7 @@ def test_training_window_graph_matches_eager(Solver):
             lg = graph.train_batch(b)
             assert abs(lg - le) <= 1e-12 * abs(le), (b, lg, le)
             assert vecwise(graph.theta.cpu().numpy(), eager.theta.cpu().numpy()) <= 1e-12, b
+        assert graph.solver.check() == 0 and eager.solver.check() == 0
     finally:
         eager.close()
         graph.close()
