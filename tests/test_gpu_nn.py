@@ -413,3 +413,32 @@ def test_training_window_graph_matches_eager(Solver):
     finally:
         eager.close()
         graph.close()
+
+
+def test_nn_viscous_forward_matches_oracle(Solver):
+    """The Rusanov-NN convective flux with the viscous and heat fluxes (forward
+    only; the adjoint covers the inviscid Rusanov-NN): right-hand side, one
+    CFL step and 20 fixed steps against the oracle, on a 3D walled grid."""
+    case, W = wl.random_smooth((15, 12, 10), seed=31, mu=0.02,
+                               flags=wl.ALL_PHYSICS | wl.WENO3 | wl.RUSANOV_NN | wl.RK2,
+                               bc=(wl.REFLECT,) * 2 + (wl.ZERO_GRADIENT,) * 2 + (wl.PERIODIC,) * 2)
+    W = W * (1.0 + 0.01 * np.random.default_rng(32).standard_normal(W.shape))
+    _say("Rusanov-NN viscous forward")
+    s, th, _ = _solver(Solver, case, THETAS["wide"])
+    U = s.init(W)
+    Uo = oracle.state_init(case, W)
+    R = s.rhs(U).cpu().numpy()
+    Ro = oracle.rhs(case, Uo)
+    bound = oracle.rhs_rounding_bound(case, Uo)
+    for v in range(5):
+        err = float(np.max(np.abs(R[v] - Ro[v])))
+        assert err <= max(1e-12 * float(np.max(np.abs(Ro[v]))), bound[v]), (v, err, bound[v])
+    dt = s.step(U)
+    Uo1, dto = oracle.rk3_step(case, Uo)
+    assert abs(float(dt.item()) - dto) <= 1e-14 * dto
+    assert normwise(U.cpu().numpy(), Uo1) <= 1e-12
+    s.advance_fixed(U, 20, 0.5 * dto)
+    Uo20, _, _ = oracle.advance(case, Uo1, 20, fixed_dt=0.5 * dto)
+    e = normwise(U.cpu().numpy(), Uo20)
+    s.close()
+    assert e <= 1e-10, e
