@@ -6,7 +6,9 @@ and the CPU-baseline leg of ``bench.py``. The product package never imports it.
 A case is described by a plain mapping with the keys ``n`` (3 interior extents,
 1 = inactive axis), ``nh`` (halo width), ``lo``/``hi`` (box), ``gamma``, ``mu``,
 ``prandtl``, ``cfl``, ``bc`` (6 boundary codes, 0 periodic, 1 zero gradient,
-order x-, x+, y-, y+, z-, z+) and ``flags`` (1 inviscid, 2 viscous, 4 heat).
+2 reflecting wall, order x-, x+, y-, y+, z-, z+) and ``flags`` (1 inviscid,
+2 viscous, 4 heat, 8 WENO5-Z, 16 Roe flux splitting, 32 WENO3-JS, 64 Rusanov,
+128 TVD-RK2, 256 Rusanov-NN with the weights given to ``set_nn``).
 States are float64 numpy arrays of shape (5, Z, Y, X) with halos (x fastest).
 """
 from __future__ import annotations
