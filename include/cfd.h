@@ -161,7 +161,8 @@ cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double d
  * cfd_rhs_adjoint's weight gradient repeats bitwise; through a step it
  * inherits the last-bit variation of the state adjoint's atomics.
  * theta NULL unsets both. Solves with the flag and no weights fail with
- * CFD_EINVAL. CFD_EINVAL for a solver without the flag. */
+ * CFD_EINVAL. CFD_EINVAL for a solver without the flag. Synchronises the
+ * device when the solver holds a captured step (which it then discards). */
 cfd_status cfd_set_nn_weights(cfd_solver* s, const double* theta, double* theta_bar);
 
 /* Discrete adjoint of cfd_rhs: Ubar += (dR/dU)^T Rbar, evaluated at U

@@ -814,8 +814,9 @@ cfd_status cfd_set_nn_weights(cfd_solver* s, const double* theta, double* theta_
   if (!s->g.nn) return fail(CFD_EINVAL, "the solver was not created with the Rusanov-NN flux");
   s->g.nnw = theta;
   s->nnbar = theta ? theta_bar : nullptr;
-  // a captured step holds the old weight address
+  // a captured step holds the old weight address; it may still be running
   if (s->graph.exec) {
+    CFD_HIP(hipDeviceSynchronize());
     CFD_HIP(hipGraphExecDestroy(s->graph.exec));
     s->graph.exec = nullptr;
   }
