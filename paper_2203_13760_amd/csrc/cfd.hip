@@ -236,14 +236,29 @@ static long long faces_of(const Geom& g, int d) {
   return (long long)g.n[0] * g.n[1] * g.n[2] / g.n[d] * (g.n[d] + 1);
 }
 
-// Rusanov-NN: alpha of every face of the active axes from primitives P (the
-// network kernels run four lanes per face).
+// Rusanov-NN launch split: 64 faces per block per active axis (the network
+// kernels run four lanes per face), record offsets in axis order.
+static NNAxes nn_axes(const Geom& g, long long& blocks) {
+  NNAxes a{};
+  blocks = 0;
+  long long off = 0;
+  for (int d = 0; d < 3; ++d) {
+    const long long F = g.act[d] ? faces_of(g, d) : 0;
+    a.blk[d] = (int)((F + 63) / 64);
+    a.off[d] = off;
+    off += F;
+    blocks += a.blk[d];
+  }
+  return a;
+}
+
+// Rusanov-NN: alpha of every face of the active axes from primitives P.
 static cfd_status enqueue_nn_alpha(cfd_solver* s, const double* P, hipStream_t st) {
   const Geom& g = s->g;
   if (!g.nnw) return fail(CFD_EINVAL, "Rusanov-NN weights are not set (cfd_set_nn_weights)");
-  if (g.act[0]) hipLaunchKernelGGL(k_nn_alpha<0>, dim3(grid_for(4 * faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, g);
-  if (g.act[1]) hipLaunchKernelGGL(k_nn_alpha<1>, dim3(grid_for(4 * faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, g);
-  if (g.act[2]) hipLaunchKernelGGL(k_nn_alpha<2>, dim3(grid_for(4 * faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, g);
+  long long blocks = 0;
+  const NNAxes ax = nn_axes(g, blocks);
+  hipLaunchKernelGGL(k_nn_alpha, dim3((unsigned)blocks), dim3(kBlock), 0, st, P, g, ax);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -461,22 +476,12 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
     CFD_LAUNCHED();
   }
   if (g.nn) {
-    // Rusanov-NN faces (one lane per face), then the weight gradient
+    // Rusanov-NN faces of every axis in one launch, then the weight gradient
     if (!g.nnw) return fail(CFD_EINVAL, "Rusanov-NN weights are not set (cfd_set_nn_weights)");
-    long long off = 0;
-    if (g.act[0]) {
-      hipLaunchKernelGGL(k_face_adj_nn<0>, dim3(grid_for(4 * faces_of(g, 0), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
-                         rscale, s->Wbar, g, s->tape, off);
-      off += faces_of(g, 0);
-    }
-    if (g.act[1]) {
-      hipLaunchKernelGGL(k_face_adj_nn<1>, dim3(grid_for(4 * faces_of(g, 1), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
-                         rscale, s->Wbar, g, s->tape, off);
-      off += faces_of(g, 1);
-    }
-    if (g.act[2])
-      hipLaunchKernelGGL(k_face_adj_nn<2>, dim3(grid_for(4 * faces_of(g, 2), 1LL << 31)), dim3(kBlock), 0, st, P, Rbar,
-                         rscale, s->Wbar, g, s->tape, off);
+    long long blocks = 0;
+    const NNAxes ax = nn_axes(g, blocks);
+    hipLaunchKernelGGL(k_face_adj_nn, dim3((unsigned)blocks), dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g,
+                       s->tape, ax);
     CFD_LAUNCHED();
     if (s->nnbar) {
       hipLaunchKernelGGL(k_nn_wgrad, dim3(kNNRows), dim3(kBlock), 0, st, s->tape, s->nnbar);

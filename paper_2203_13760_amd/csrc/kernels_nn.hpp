@@ -1,10 +1,10 @@
 // Rusanov-NN flux of §6.2 on gfx950: the Rusanov flux whose dissipation alpha
 // is the output of a small network of four face features.
 //
-//   forward:  k_nn_alpha<D> evaluates the network for every face normal to D
+//   forward:  k_nn_alpha evaluates the network for every face of the active axes
 //             from the WENO3-JS face states and stores alpha at the face's
 //             left cell (Geom::nna); the sweeps (scheme SCH_W3_NN) read it.
-//   reverse:  k_face_adj_nn<D> recomputes the face (states, features,
+//   reverse:  k_face_adj_nn recomputes the face (states, features,
 //             network), reverses the flux with alpha held, the network
 //             (output adjoint -> input adjoint) and the features, then the
 //             WENO3-JS stencils into Wbar with atomics, as the other face
@@ -257,22 +257,31 @@ __device__ __forceinline__ void nn_features_rev(const Geom& g, const double* WL,
 // the face reverses. Lanes beyond the last face take face 0 (valid addresses)
 // and keep to the matrix products, which need the whole wavefront.
 template <int D>
-__device__ __forceinline__ bool nn_face(const Geom& g, int& t, int& i, int& j, int& k, int& f, int& q) {
+__device__ __forceinline__ bool nn_face(const Geom& g, int bx, int& t, int& i, int& j, int& k, int& f, int& q) {
   const int lane = threadIdx.x & 63;
   f = lane & 15;
   q = lane >> 4;
-  t = ((blockIdx.x * blockDim.x + (int)threadIdx.x) >> 6) * 16 + f;
+  t = ((bx * kBlock + (int)threadIdx.x) >> 6) * 16 + f;
   int fc = 0, col = 0;
   const bool has = face_coords<D>(g, t, i, j, k, fc, col);
   if (!has) face_coords<D>(g, 0, i, j, k, fc, col);
   return has;
 }
 
+// One launch covers the faces of every active axis: blocks [0, blk[0]) take
+// x faces, the next blk[1] y faces, the last blk[2] z faces (64 faces per
+// block; 0 blocks for an inactive axis), so the axes' latencies overlap.
+// off[D]: first record slot of axis D in the reverse's tape.
+struct NNAxes {
+  int blk[3];
+  long long off[3];
+};
+
 // alpha of every face normal to D, stored at the face's left cell.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_nn_alpha(const double* __restrict__ P, Geom g) {
+__device__ __forceinline__ void nn_alpha_body(const double* __restrict__ P, const Geom& g, int bx) {
   int t, i, j, k, f, q;
-  const bool has = nn_face<D>(g, t, i, j, k, f, q);
+  const bool has = nn_face<D>(g, bx, t, i, j, k, f, q);
   const long long cl = cell_at(g, i, j, k) - g.s[D];  // cell f-1 of the face
   double WL[5], WR[5], ft[kNNIn];
   nn_face_states<D>(g, P, cl, WL, WR);
@@ -289,10 +298,11 @@ __global__ void __launch_bounds__(kBlock) k_nn_alpha(const double* __restrict__ 
 // stencil reverse is split by variable (quarter q takes the variables
 // v = q mod 4).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_adj_nn(const double* __restrict__ P, const double* __restrict__ Rbar,
-                                                        double rscale, double* Wbar, Geom g, NNTape tp, long long off) {
+__device__ __forceinline__ void face_adj_nn_body(const double* __restrict__ P, const double* __restrict__ Rbar,
+                                                 double rscale, double* Wbar, const Geom& g, const NNTape& tp,
+                                                 long long off, int bx) {
   int t, i, j, k, f, q;
-  const bool has = nn_face<D>(g, t, i, j, k, f, q);
+  const bool has = nn_face<D>(g, bx, t, i, j, k, f, q);
   const long long st = g.s[D];
   const long long cf = cell_at(g, i, j, k), cl = cf - st;
   const long long e = off + t;
@@ -356,6 +366,26 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_nn(const double* __restrict
 #pragma unroll
     for (int m = 0; m < 4; ++m) atomic_add(w + (m - 1) * st, gs[m]);
   }
+}
+
+__global__ void __launch_bounds__(kBlock) k_nn_alpha(const double* __restrict__ P, Geom g, NNAxes ax) {
+  int b = blockIdx.x;
+  if (b < ax.blk[0]) return nn_alpha_body<0>(P, g, b);
+  b -= ax.blk[0];
+  if (b < ax.blk[1]) return nn_alpha_body<1>(P, g, b);
+  b -= ax.blk[1];
+  nn_alpha_body<2>(P, g, b);
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_face_adj_nn(const double* __restrict__ P, const double* __restrict__ Rbar,
+                                                        double rscale, double* Wbar, Geom g, NNTape tp, NNAxes ax) {
+  int b = blockIdx.x;
+  if (b < ax.blk[0]) return face_adj_nn_body<0>(P, Rbar, rscale, Wbar, g, tp, ax.off[0], b);
+  b -= ax.blk[0];
+  if (b < ax.blk[1]) return face_adj_nn_body<1>(P, Rbar, rscale, Wbar, g, tp, ax.off[1], b);
+  b -= ax.blk[1];
+  face_adj_nn_body<2>(P, Rbar, rscale, Wbar, g, tp, ax.off[2], b);
 }
 
 // Weight gradient from the records: thb += sum over faces. Block r owns output
