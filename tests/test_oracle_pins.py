@@ -775,6 +775,36 @@ def test_rusanov_nn_taped_gradients_match_central_differences():
         oracle.set_nn(None)
 
 
+def test_rusanov_nn_rhs_weight_gradient_matches_central_differences():
+    """The taped right-hand-side derivative with respect to the network weights
+    (the reference the device's weight gradient is compared with) against
+    central differences of <Rbar, R(U; theta)> along random weight directions
+    (a one-sided difference where a ReLU unit of some face changes side)."""
+    case, W = _nn_case(12)
+    th = wl.nn_weights(seed=7, alpha0=1.1, scale=0.8)
+    rng = np.random.default_rng(17)
+    try:
+        oracle.set_nn(th)
+        U0 = oracle.state_init(case, W)
+        Rb = np.zeros_like(U0)
+        oracle.interior(case, Rb)[...] = rng.standard_normal(oracle.interior(case, Rb).shape)
+        _, tbar = oracle.vjp_rhs_theta(case, U0, Rb)
+
+        def L(t):
+            oracle.set_nn(t)
+            return float(np.sum(oracle.rhs(case, U0) * Rb))
+        L0 = L(th)
+        for trial in range(3):
+            v = rng.standard_normal(th.size)
+            h = 1e-7
+            Lp, Lm = L(th + h * v), L(th - h * v)
+            ad = float(tbar @ v)
+            fds = ((Lp - Lm) / (2 * h), (Lp - L0) / h, (L0 - Lm) / h)
+            assert min(abs(f - ad) for f in fds) <= 1e-6 * max(1.0, abs(ad)), (trial, fds, ad)
+    finally:
+        oracle.set_nn(None)
+
+
 def test_rusanov_nn_needs_weights():
     case, W = _nn_case(8)
     oracle.set_nn(None)
