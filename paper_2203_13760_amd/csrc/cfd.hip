@@ -153,9 +153,29 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.weno3 = (c.flags & CFD_F_WENO3) ? 1 : 0;
   g.rusanov = (c.flags & CFD_F_RUSANOV) ? 1 : 0;
   g.rk2 = (c.flags & CFD_F_RK2) ? 1 : 0;
+  g.seg = kSeg;
   g.nn = (c.flags & CFD_F_RUSANOV_NN) ? 1 : 0;
   g.viscous = ((c.flags & CFD_F_VISCOUS) && c.mu > 0.0) ? 1 : 0;
   g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
+}
+
+// March segment length of a single-grid solver: halved (down to 8 cells)
+// while a y or z march would run fewer than 1024 wavefronts, so that small
+// grids spread their marches over more lanes (each segment recomputes one
+// seed face). The serving batch keeps kSeg: it fills the chip with many grids.
+static void choose_segment(Geom& g) {
+  auto waves = [&](int seg) {
+    long long w = -1;
+    for (int ax = 1; ax < 3; ++ax) {
+      if (!g.act[ax]) continue;
+      const int ot = ax == 1 ? 2 : 1;
+      const long long v = (long long)((g.n[0] + 63) / 64) * g.n[ot] * ((g.n[ax] + seg - 1) / seg);
+      w = w < 0 ? v : std::min(w, v);
+    }
+    return w;
+  };
+  g.seg = kSeg;
+  while (g.seg > 8 && waves(g.seg) >= 0 && waves(g.seg) < 1024) g.seg /= 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -528,6 +548,7 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
   if (!s) return fail(CFD_ENOMEM, "host allocation failed");
   s->cfg = *cfg;
   make_geom(*cfg, s->g);
+  choose_segment(s->g);
   s->ncell = s->g.vs;
   s->nint = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
   const size_t st = sizeof(double) * 5 * (size_t)s->ncell;

@@ -589,9 +589,10 @@ __host__ __device__ __forceinline__ int sweep_x_blocks(const Geom& g) {
   return (int)((waves + 3) / 4);
 }
 
-// y / z sweep: one lane per (x, other) column segment of kSeg cells along the
-// axis; lanes run along x so every load is coalesced. The segment's first
-// face is computed only to seed the left flux.
+// y / z sweep: one lane per (x, other) column segment of Geom::seg cells
+// along the axis (kSeg by default; fewer on grids too small to fill the chip
+// with segments that long); lanes run along x so every load is coalesced. The
+// segment's first face is computed only to seed the left flux.
 constexpr int kSeg = 32;
 
 // y / z sweep body of one lane. Lanes beyond the grid (a partial last block)
@@ -602,7 +603,8 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
                                                  const Geom& g, int bx, int by) {
   constexpr int OT = AX == 1 ? 2 : 1;  // the other transverse axis
   const int i = bx * 64 + (threadIdx.x & 63);
-  const int nseg = (g.n[AX] + kSeg - 1) / kSeg;
+  const int sl = g.seg;
+  const int nseg = (g.n[AX] + sl - 1) / sl;
   const long long col = (long long)by * (kBlock >> 6) + (threadIdx.x >> 6);
   const bool in = i < g.n[0] && col < (long long)g.n[OT] * nseg;
   if (!PN && !in) return;
@@ -611,8 +613,8 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
   const long long colc = in ? col : 0;
   const int o = (int)(colc / nseg);
   const int seg = (int)(colc - (long long)o * nseg);
-  const int s0 = seg * kSeg;
-  const int s1 = min(s0 + kSeg, g.n[AX]);
+  const int s0 = seg * sl;
+  const int s1 = min(s0 + sl, g.n[AX]);
   const long long st = g.s[AX];
   int q3[3];
   q3[0] = in ? i : 0;
@@ -711,7 +713,7 @@ k_sweep_march(const double* __restrict__ P, StageIO io, Geom g) {
 template <int AX>
 __host__ __device__ __forceinline__ void sweep_march_blocks(const Geom& g, int& gx, int& gy) {
   constexpr int OT = AX == 1 ? 2 : 1;
-  const int nseg = (g.n[AX] + kSeg - 1) / kSeg;
+  const int nseg = (g.n[AX] + g.seg - 1) / g.seg;
   gx = (g.n[0] + 63) / 64;
   gy = (int)(((long long)g.n[OT] * nseg + 3) / 4);
 }
