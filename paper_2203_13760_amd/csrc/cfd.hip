@@ -439,7 +439,8 @@ static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   if (s->g.nn) {
     for (int d = 0; d < 3; ++d)
       if (s->g.act[d]) F += faces_of(s->g, d);
-    ok = ok && hipMalloc(&s->nntape, sizeof(double) * kNNTapePerFace * (size_t)F) == hipSuccess;
+    ok = ok && hipMalloc(&s->nntape, sizeof(double) * (kNNTapePerFace * (size_t)F + kNNChunks * kNNParams)) ==
+                   hipSuccess;
   }
   if (!ok) {
     (void)hipGetLastError();
@@ -458,6 +459,7 @@ static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
     }
     t.f = s->nntape + (size_t)6 * kNNH * F;
     t.d4 = t.f + (size_t)kNNIn * F;
+    t.part = t.d4 + F;
   }
   return CFD_OK;
 }
@@ -504,7 +506,9 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
                        s->tape, ax);
     CFD_LAUNCHED();
     if (s->nnbar) {
-      hipLaunchKernelGGL(k_nn_wgrad, dim3(kNNRows), dim3(kBlock), 0, st, s->tape, s->nnbar);
+      hipLaunchKernelGGL(k_nn_wgrad, dim3(kNNRows * kNNChunks), dim3(kBlock), 0, st, s->tape);
+      hipLaunchKernelGGL(k_nn_wgrad_sum, dim3((kNNParams + kBlock - 1) / kBlock), dim3(kBlock), 0, st,
+                         (const double*)s->tape.part, s->nnbar);
       CFD_LAUNCHED();
     }
   } else {

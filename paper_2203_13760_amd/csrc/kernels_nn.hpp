@@ -40,9 +40,11 @@ struct NNTape {
   double* d[3];
   double* f;
   double* d4;
+  double* part;  // kNNChunks partial weight gradients (kNNParams each)
   long long F;
 };
 constexpr int kNNTapePerFace = 6 * kNNH + kNNIn + 1;
+constexpr int kNNChunks = 4;  // face chunks of the weight gradient
 constexpr int kNNRows = 3 * kNNH + 1;  // output rows of the four layers
 
 __device__ __forceinline__ double relu(double z) { return z > 0.0 ? z : 0.0; }
@@ -388,19 +390,22 @@ k_face_adj_nn(const double* __restrict__ P, const double* __restrict__ Rbar,
   face_adj_nn_body<2>(P, Rbar, rscale, Wbar, g, tp, ax.off[2], b);
 }
 
-// Weight gradient from the records: thb += sum over faces. Block r owns output
-// row r: rows 0..31 of (W1 | b1), 32..63 of (W2 | b2), 64..95 of (W3 | b3), 96
-// the output layer (W4 | b4). Each lane sums a fixed stride of the faces for
-// the row's weights and bias; the wavefronts reduce by shuffles and the four
-// partial sums are added in a fixed order.
-__global__ void __launch_bounds__(kBlock) k_nn_wgrad(NNTape tp, double* __restrict__ thb) {
-  const int r = blockIdx.x;
+// Weight gradient from the records, in two launches with every sum in a fixed
+// order. k_nn_wgrad: block (r, chunk) = r + kNNRows * chunk owns output row r
+// (rows 0..31 of (W1 | b1), 32..63 of (W2 | b2), 64..95 of (W3 | b3), 96 the
+// output layer (W4 | b4)) over the faces of its chunk (faces e with
+// e / kBlock = chunk mod kNNChunks); each lane sums its faces for the row's
+// weights and bias, the wavefronts reduce by shuffles, the four partial sums
+// are added in a fixed order and stored in the chunk's partial gradient.
+// k_nn_wgrad_sum then adds the kNNChunks partials to thb.
+__global__ void __launch_bounds__(kBlock) k_nn_wgrad(NNTape tp) {
+  const int r = blockIdx.x % kNNRows, chunk = blockIdx.x / kNNRows;
   const int layer = r / kNNH, o = r - layer * kNNH;
   const double* hs = layer == 0 ? tp.f : tp.z[layer - 1];
   double acc[kNNH + 1];
 #pragma unroll
   for (int m = 0; m <= kNNH; ++m) acc[m] = 0.0;
-  for (long long e = threadIdx.x; e < tp.F; e += kBlock) {
+  for (long long e = (long long)chunk * kBlock + threadIdx.x; e < tp.F; e += (long long)kBlock * kNNChunks) {
     const double dd = layer < 3 ? tp.d[layer][e * kNNH + o] : tp.d4[e];
     acc[kNNH] += dd;
     if (layer == 0) {
@@ -432,7 +437,16 @@ __global__ void __launch_bounds__(kBlock) k_nn_wgrad(NNTape tp, double* __restri
   else if (layer == 1) idx = m < kNNH ? kNNW2 + o * kNNH + m : kNNb2 + o;
   else if (layer == 2) idx = m < kNNH ? kNNW3 + o * kNNH + m : kNNb3 + o;
   else idx = m < kNNH ? kNNW4 + m : kNNb4;
-  thb[idx] += s;
+  tp.part[(long long)chunk * kNNParams + idx] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_nn_wgrad_sum(const double* __restrict__ part, double* __restrict__ thb) {
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  if (p >= kNNParams) return;
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < kNNChunks; ++c) s += part[c * kNNParams + p];
+  thb[p] += s;
 }
 
 }  // namespace cfd
