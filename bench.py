@@ -208,7 +208,7 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
 
 
 def implosion_leg(nn_epochs=1):
-    """The implosion of §6.2 (the Rusanov-NN experiment's data): the 128^2
+    """The implosion of §7.4 (the Rusanov-NN experiment's data): the 128^2
     ground truth (WENO3-JS, TVD-RK2, HLLC, dt 2.5e-4) coarse-grained onto 32^2
     every 1e-3, against the 32^2 solvers with the classical Rusanov flux and
     with HLLC, over the paper's 2500 coarse steps: relative L1 errors of
@@ -221,7 +221,7 @@ def implosion_leg(nn_epochs=1):
     for t in (0.1, 1.0, 2.5):
         i = int(np.argmin(np.abs(np.array(out["t"]) - t)))
         pick[f"t={t}"] = {k: out[k][i] for k in keys}
-    res = {"workload": "implosion of §6.2 as printed, 128^2 truth coarse-grained to 32^2, 2500 coarse steps",
+    res = {"workload": "implosion of §7.4 as printed, 128^2 truth coarse-grained to 32^2, 2500 coarse steps",
            "coarse_steps": 2500, "seconds": out["seconds"], "health": out["health"],
            "mean": {k: float(np.mean(out[k])) for k in keys}, "at": pick}
     if nn_epochs > 0:

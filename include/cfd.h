@@ -45,7 +45,7 @@ typedef enum {
 
 /* Boundary types (§3.7): periodic (in pairs) and zero gradient, the paper's
  * "neumann" without a value; and the reflecting (slip) wall at which the
- * implosion of §6.2 reflects its shock: the halo mirrors the interior about
+ * implosion of §7.4 reflects its shock: the halo mirrors the interior about
  * the boundary face with the wall-normal momentum negated. */
 typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1, CFD_BC_REFLECT = 2 } cfd_bc;
 
@@ -58,11 +58,11 @@ typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1, CFD_BC_REFLECT = 2
  * the paper's ROE setup (§5): Roe-averaged eigen-decomposition at each face,
  * the stencil's states and fluxes projected on its characteristic fields,
  * split with the moduli of the Roe eigenvalues (no entropy fix), WENO5-JS per
- * field, transformed back. The implosion of §6.2 adds CFD_F_WENO3 (WENO3-JS
+ * field, transformed back. The implosion of §7.4 adds CFD_F_WENO3 (WENO3-JS
  * reconstruction of the primitives), CFD_F_RUSANOV (the Rusanov flux
  * (F_L + F_R)/2 - alpha (U_R - U_L)/2, alpha the largest |u -+ c| of the two
  * states, in place of HLLC) and CFD_F_RK2 (TVD-RK2 steps in place of TVD-RK3).
- * CFD_F_RUSANOV_NN selects the Rusanov-NN flux of §6.2: the Rusanov form
+ * CFD_F_RUSANOV_NN selects the Rusanov-NN flux of §7.4: the Rusanov form
  * with alpha = exp(NN(|u_R - u_L|, (u_L + u_R)/2, (c_L + c_R)/2, |s_R - s_L|)),
  * u normal to the face, c the speed of sound, s = (ln p - gamma ln rho)/
  * (gamma - 1), NN a perceptron with three hidden ReLU layers of 32 units whose
@@ -150,7 +150,7 @@ cfd_status cfd_advance(cfd_solver* s, double* U, int32_t n_steps, double t_end, 
  * differentiation, §4.5), graph-replayed like cfd_advance. */
 cfd_status cfd_advance_fixed(cfd_solver* s, double* U, int32_t n_steps, double dt, void* stream);
 
-/* Rusanov-NN weights (§6.2) of a solver created with CFD_F_RUSANOV_NN.
+/* Rusanov-NN weights (§7.4) of a solver created with CFD_F_RUSANOV_NN.
  * theta: device memory, CFD_NN_PARAMS doubles in the order of CFD_NN_PARAMS,
  * owned by the caller and read by every later launch of the solver (the
  * values may change between calls; the address must stay valid while the
@@ -226,8 +226,9 @@ const char* cfd_last_error(void);
  * Serving batch: many independent solves (mixed sizes, 2D and 3D, different
  * physics) resident on the device at once, advanced together. Each TVD-RK3
  * step is one replay of a captured HIP graph whose launches are persistent
- * kernels, one per phase of each stage (primitives, CFL step, velocity
- * gradient, x/y/z sweeps), each covering the work of every resident grid
+ * kernels, one per phase of each stage (primitives, CFL step, z/y/x
+ * sweeps, halo refresh of the next primitives), each covering the work of
+ * every resident grid
  * through a device descriptor table. Every grid keeps its own state, scratch
  * and CFL step, so its result does not depend on the other grids in the batch.
  * A batch is used from one stream at a time. */

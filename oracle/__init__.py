@@ -65,6 +65,8 @@ def _load():
     lib.oracle_weno5z.restype = d
     lib.oracle_hllc.argtypes = [d, dp, dp, C.c_int, dp]
     lib.oracle_hllc.restype = None
+    lib.oracle_einfeldt.argtypes = [d, dp, dp, C.c_int, dp]
+    lib.oracle_einfeldt.restype = None
     lib.oracle_roe_eigen.argtypes = [d, dp, dp, C.c_int, dp, dp, dp]
     lib.oracle_roe_eigen.restype = None
     lib.oracle_roe_flux.argtypes = [d, dp, C.c_int, dp]
@@ -211,6 +213,16 @@ def hllc(gamma, WL, WR, axis):
     return F
 
 
+def einfeldt(gamma, WL, WR, axis):
+    """The Einfeldt signal speeds of the HLLC flux at a face: (ubar, dbar, S_L, S_R)."""
+    lib = _load()
+    WL = np.ascontiguousarray(WL, dtype=np.float64)
+    WR = np.ascontiguousarray(WR, dtype=np.float64)
+    out = np.zeros(4)
+    lib.oracle_einfeldt(float(gamma), _ptr(WL), _ptr(WR), int(axis), _ptr(out))
+    return out
+
+
 def roe_eigen(gamma, wl, wr, axis):
     """Roe average of primitive states wl | wr along `axis`: (R, L, lam) with
     the right eigenvectors as the columns of R, L = R^-1 (by elimination)."""
@@ -338,7 +350,7 @@ def rhs_rounding_bound(case, U, k=16.0):
 
 
 # --------------------------------------------------------------------------
-# Rusanov-NN flux (§6.2): Rusanov with alpha = exp(MLP(|du|, u_M, c_M, |ds|)),
+# Rusanov-NN flux (§7.4): Rusanov with alpha = exp(MLP(|du|, u_M, c_M, |ds|)),
 # three hidden ReLU layers of 32 units; NN_PARAMS weights in the order
 # W1 (32x4), b1, W2 (32x32), b2, W3 (32x32), b3, W4 (1x32), b4.
 NN_PARAMS = 2305

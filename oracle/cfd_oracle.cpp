@@ -38,7 +38,7 @@ typedef struct {
   uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux, 8 WENO5-Z reconstruction,
                        // 16 Roe flux splitting in characteristic space (the paper's ROE setup),
                        // 32 WENO3-JS reconstruction, 64 Rusanov flux, 128 TVD-RK2 time integration,
-                       // 256 Rusanov-NN flux (Rusanov with the learned dissipation of §6.2)
+                       // 256 Rusanov-NN flux (Rusanov with the learned dissipation of §7.4)
 } oracle_cfg;
 }
 
@@ -82,7 +82,7 @@ struct Grid {
 // --------------------------------------------------------------------------
 // Boundary conditions (§3.7 and Table of numerical methods: periodic and zero
 // gradient; the setup file of Appendix A calls zero gradient "neumann" without
-// a value; the implosion of §6.2 reflects its shock at walls, read as a slip
+// a value; the implosion of §7.4 reflects its shock at walls, read as a slip
 // wall: the halo mirrors the interior about the boundary face and the momentum
 // normal to it changes sign). Halo layers are filled axis by axis, x then y
 // then z; each later axis sweeps the full extent of the earlier axes including
@@ -196,7 +196,7 @@ R weno5_z(R a, R b, R c, R d, R e) {
   return (alpha0 * p0 + alpha1 * p1 + alpha2 * p2) / (alpha0 + alpha1 + alpha2);
 }
 
-// WENO3-JS (Jiang & Shu 1996, r = 2; the implosion of §6.2 reconstructs with
+// WENO3-JS (Jiang & Shu 1996, r = 2; the implosion of §7.4 reconstructs with
 // it): value at the right face of the centre cell b of the stencil (a, b, c) =
 // (q_{i-1}, q_i, q_{i+1}): candidates p0 = (3b - a)/2 and p1 = (b + c)/2,
 // smoothness indicators (b - a)^2 and (c - b)^2, linear weights (1/3, 2/3),
@@ -214,7 +214,7 @@ R weno3_js(R a, R b, R c) {
   return (alpha0 * p0 + alpha1 * p1) / (alpha0 + alpha1);
 }
 
-// Rusanov (local Lax-Friedrichs) flux of §6.2 across a face normal to axis d
+// Rusanov (local Lax-Friedrichs) flux of §7.4 across a face normal to axis d
 // from the reconstructed primitive states WL, WR:
 //   F = (F_L + F_R)/2 - alpha (U_R - U_L)/2,
 //   alpha = max(|u_L - c_L|, |u_L + c_L|, |u_R - c_R|, |u_R + c_R|),
@@ -222,13 +222,13 @@ R weno3_js(R a, R b, R c) {
 template <class R>
 void rusanov_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]);
 
-// Rusanov-NN flux of §6.2: the Rusanov form with alpha replaced by the output
+// Rusanov-NN flux of §7.4: the Rusanov form with alpha replaced by the output
 // of a multi-layer perceptron. Inputs are the face-normal velocity jump
 // |u_R - u_L|, the mean normal velocity (u_L + u_R)/2, the mean speed of sound
 // (c_L + c_R)/2 and the entropy jump |s_R - s_L|; three hidden layers of 32
 // units with ReLU; one output through exp, so alpha >= 0. The entropy is
 // s = ln(p / rho^gamma) / (gamma - 1) (specific entropy in units of c_v, up to
-// an additive constant that the jump cancels; the same s as in §6.1).
+// an additive constant that the jump cancels; the same s as in §7.3).
 // Parameters theta, 2305 values in this order: W1 (32 x 4, row-major), b1
 // (32), W2 (32 x 32), b2, W3 (32 x 32), b3, W4 (1 x 32), b4 (1); a layer maps
 // h -> W h + b.
@@ -269,6 +269,31 @@ template <class R>
 void rusanov_nn_flux(double gamma, const R WL[5], const R WR[5], int d, const R* th, R F[5]);
 
 // --------------------------------------------------------------------------
+// Einfeldt (1988) signal speeds of the HLLC solver below (the setup file of
+// Appendix A selects "EINFELDT"; the formula is not printed, reading: the
+// Roe-averaged form with the min/max safety bounds). From the primitive
+// states left and right of a face normal to axis d, with r_K = sqrt(rho_K)
+// and the sound speeds c_K = sqrt(gamma p_K / rho_K):
+//   ubar  = (r_L u_L + r_R u_R) / (r_L + r_R)
+//   dbar2 = (r_L c_L^2 + r_R c_R^2) / (r_L + r_R) + eta2 (u_R - u_L)^2,
+//   eta2  = 1/2 r_L r_R / (r_L + r_R)^2
+//   S_L = min(u_L - c_L, ubar - dbar),  S_R = max(u_R + c_R, ubar + dbar).
+template <class R>
+void einfeldt_speeds(double gamma, const R WL[5], const R WR[5], int d, R& ubar, R& dbar, R& SL, R& SR) {
+  const R rL = WL[0], uL = WL[1 + d], pL = WL[4];
+  const R rR = WR[0], uR = WR[1 + d], pR = WR[4];
+  const R cL = sqrt_(gamma * pL / rL);
+  const R cR = sqrt_(gamma * pR / rR);
+  const R sL = sqrt_(rL), sR = sqrt_(rR);
+  ubar = (sL * uL + sR * uR) / (sL + sR);
+  const R eta2 = 0.5 * sL * sR / sq(sL + sR);
+  const R dbar2 = (sL * cL * cL + sR * cR * cR) / (sL + sR) + eta2 * sq(uR - uL);
+  dbar = sqrt_(dbar2);
+  SL = min_(uL - cL, ubar - dbar);
+  SR = max_(uR + cR, ubar + dbar);
+}
+
+// --------------------------------------------------------------------------
 // HLLC approximate Riemann solver (Toro, Spruce & Speares 1994; §3.3 step 3)
 // with the Einfeldt (1988) signal-speed estimate (the setup file of Appendix A
 // selects "HLLC" with "EINFELDT"). Inputs are the reconstructed primitive
@@ -284,20 +309,13 @@ void hllc_flux(double gamma, const R WL[5], const R WR[5], int d, R F[5]) {
   // fluxes of §2 (convective flux F, G, H rotated to the face normal)
   const R EL = pL / (gamma - 1.0) + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
   const R ER = pR / (gamma - 1.0) + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
-  const R cL = sqrt_(gamma * pL / rL);
-  const R cR = sqrt_(gamma * pR / rR);
   const R UL[5] = {rL, rL * uL, rL * aL, rL * bL, EL};
   const R UR[5] = {rR, rR * uR, rR * aR, rR * bR, ER};
   const R FL[5] = {rL * uL, rL * uL * uL + pL, rL * uL * aL, rL * uL * bL, uL * (EL + pL)};
   const R FR[5] = {rR * uR, rR * uR * uR + pR, rR * uR * aR, rR * uR * bR, uR * (ER + pR)};
   // Einfeldt: Roe-averaged normal velocity and sound-speed bound
-  const R sL = sqrt_(rL), sR = sqrt_(rR);
-  const R ubar = (sL * uL + sR * uR) / (sL + sR);
-  const R eta2 = 0.5 * sL * sR / sq(sL + sR);
-  const R dbar2 = (sL * cL * cL + sR * cR * cR) / (sL + sR) + eta2 * sq(uR - uL);
-  const R dbar = sqrt_(dbar2);
-  const R SL = min_(uL - cL, ubar - dbar);
-  const R SR = max_(uR + cR, ubar + dbar);
+  R ubar, dbar, SL, SR;
+  einfeldt_speeds(gamma, WL, WR, d, ubar, dbar, SL, SR);
   // contact wave speed
   const R Sstar = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
                   (rL * (SL - uL) - rR * (SR - uR));
@@ -692,7 +710,7 @@ inline double cfl_dt(const oracle_cfg& c, const Grid& g, const std::vector<doubl
 //   Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2))
 // dt stays fixed over the three stages. Only interior cells are updated; the
 // halos of the result are refreshed afterwards. With F_RK2 the step is the
-// second-order TVD Runge-Kutta scheme of the same paper (the implosion of §6.2
+// second-order TVD Runge-Kutta scheme of the same paper (the implosion of §7.4
 // integrates with TVD-RK2):
 //   U1   = Un + dt R(Un)
 //   Un+1 = 1/2 Un + 1/2 (U1 + dt R(U1))
@@ -879,6 +897,10 @@ double oracle_weno5z(double a, double b, double c, double d, double e) {
 }
 void oracle_hllc(double gamma, const double* WL, const double* WR, int d, double* F) {
   hllc_flux(gamma, WL, WR, d, F);
+}
+// The Einfeldt speeds HLLC uses at that face: out = (ubar, dbar, S_L, S_R).
+void oracle_einfeldt(double gamma, const double* WL, const double* WR, int d, double* out) {
+  einfeldt_speeds(gamma, WL, WR, d, out[0], out[1], out[2], out[3]);
 }
 // Roe average and eigen-decomposition between primitive states wl, wr
 // (rho, u, v, w, p) along axis d: Rm, Lm row-major 5x5, lam[5].

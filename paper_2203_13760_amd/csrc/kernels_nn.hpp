@@ -1,4 +1,4 @@
-// Rusanov-NN flux of §6.2 on gfx950: the Rusanov flux whose dissipation alpha
+// Rusanov-NN flux of §7.4 on gfx950: the Rusanov flux whose dissipation alpha
 // is the output of a small network of four face features.
 //
 //   forward:  k_nn_alpha evaluates the network for every face of the active axes
@@ -22,7 +22,7 @@
 
 namespace cfd {
 
-// Network of §6.2: 4 inputs, three hidden layers of 32 units with ReLU, one
+// Network of §7.4: 4 inputs, three hidden layers of 32 units with ReLU, one
 // output through exp (alpha >= 0). Weights in the order W1 (32 x 4,
 // row-major), b1, W2 (32 x 32), b2, W3 (32 x 32), b3, W4 (1 x 32), b4; a layer
 // maps h -> W h + b.

@@ -45,10 +45,10 @@ struct Geom {
 // the flux-splitting approach with Roe eigenvalues and WENO5-JS in
 // characteristic space (§3.3; the ROE setup of §5).
 constexpr int SCH_JS = 0, SCH_Z = 1, SCH_ROE = 2;
-// and the schemes of the implosion of §6.2: WENO3-JS with HLLC, WENO3-JS or
+// and the schemes of the implosion of §7.4: WENO3-JS with HLLC, WENO3-JS or
 // WENO5-JS with the Rusanov flux
 constexpr int SCH_W3 = 3, SCH_JS_RUS = 4, SCH_W3_RUS = 5;
-// and the Rusanov-NN flux of §6.2 (WENO3-JS, Rusanov with the dissipation of a
+// and the Rusanov-NN flux of §7.4 (WENO3-JS, Rusanov with the dissipation of a
 // network, evaluated per face beforehand into Geom::nna)
 constexpr int SCH_W3_NN = 6;
 __host__ __device__ constexpr bool sch_weno3(int sch) { return sch == SCH_W3 || sch == SCH_W3_RUS || sch == SCH_W3_NN; }
@@ -86,7 +86,7 @@ __device__ __forceinline__ long long cell_at(const Geom& g, int i, int j, int k)
 
 // Interior source coordinate of a (possibly halo) coordinate c on an axis with
 // n cells: periodic image, zero-gradient clamp (§3.7), or the mirror image
-// about a reflecting wall (the slip walls of the implosion, §6.2). Applying it
+// about a reflecting wall (the slip walls of the implosion, §7.4). Applying it
 // per axis reproduces the axis-by-axis halo fill, corners included.
 __device__ __forceinline__ int bc_source(int c, int n, int bc_lo, int bc_hi) {
   if (c < 0) return bc_lo == 0 ? c + n : (bc_lo == 2 ? -1 - c : 0);
@@ -159,7 +159,7 @@ __host__ __device__ __forceinline__ double weno3(double a, double b, double c) {
   return div_nr(w0 * (3.0 * b - a) + w1 * (b + c), 2.0 * (w0 + w1));
 }
 
-// Rusanov (local Lax-Friedrichs) flux of §6.2 across a face normal to axis D
+// Rusanov (local Lax-Friedrichs) flux of §7.4 across a face normal to axis D
 // from reconstructed primitive states: (F_L + F_R)/2 - alpha (U_R - U_L)/2 with
 // alpha the largest |u -+ c| of the two states (u normal to the face), or the
 // given alpha_in (GIVEN: the Rusanov-NN flux).

@@ -1,6 +1,6 @@
 """Two experiments of the paper on libcfd: the validation of reverse-mode
-gradients (§6.1, "Validation of Automatic Differentiation Gradients"),
-single-phase case, on the discrete adjoint; and the implosion of §6.2 that
+gradients (§7.3, "Validation of Automatic Differentiation Gradients"),
+single-phase case, on the discrete adjoint; and the implosion of §7.4 that
 the Rusanov-NN flux is trained on, with the classical Rusanov flux and HLLC
 on the coarse grid against the coarse-grained ground truth, and the supervised
 training of the Rusanov-NN dissipation through the discrete adjoint.
@@ -116,7 +116,7 @@ def shock_entropy_gradient(M0=SHOCK_M, eps=SHOCK_EPS, n=40):
         s.close()
 
 
-# ---------------------------------------------------------------- §6.2 implosion
+# ---------------------------------------------------------------- §7.4 implosion
 def coarse_grain(U_fine, case_fine, n_cg):
     """Block averages of the fine interior conservative state onto n_cg x n_cg
     cells (reading: the paper's coarse-graining of the 128^2 trajectory onto
@@ -139,7 +139,7 @@ def _rho_p(Ui, gamma):
 
 
 def implosion_trajectories(n_fine=128, n_cg=32, dt=2.5e-4, dt_cg=1e-3, n_cg_steps=2500, every=100):
-    """The implosion of §6.2: the ground truth on n_fine^2 (WENO3-JS, TVD-RK2,
+    """The implosion of §7.4: the ground truth on n_fine^2 (WENO3-JS, TVD-RK2,
     HLLC, fixed dt), coarse-grained onto n_cg^2 every dt_cg, and the coarse
     solvers with the Rusanov flux and with HLLC (WENO3-JS, TVD-RK2, dt_cg) run
     from the coarse-grained initial state. Returns the relative L1 errors of
@@ -187,13 +187,13 @@ def implosion_trajectories(n_fine=128, n_cg=32, dt=2.5e-4, dt_cg=1e-3, n_cg_step
 
 
 # ---------------------------------------------------------------------------
-# Rusanov-NN training (§6.2)
+# Rusanov-NN training (§7.4)
 
 NN_FLAGS = wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV_NN
 
 
 def cg_trajectory(n_fine=128, n_cg=32, dt=2.5e-4, dt_cg=1e-3, n_cg_steps=1000):
-    """The coarse-grained ground truth of §6.2: the n_fine^2 implosion (WENO3-JS,
+    """The coarse-grained ground truth of §7.4: the n_fine^2 implosion (WENO3-JS,
     TVD-RK2, HLLC, fixed dt) block-averaged onto n_cg^2 every dt_cg. Returns a
     device tensor (n_cg_steps + 1, 5, 1, n_cg, n_cg) of interior conservative
     states, snapshot 0 the initial state."""
@@ -216,7 +216,7 @@ def cg_trajectory(n_fine=128, n_cg=32, dt=2.5e-4, dt_cg=1e-3, n_cg_steps=1000):
 
 def primitives_2d(Ui, gamma):
     """(rho, u, v, p) of interior conservative states (5, ...): the primitive
-    state vector W of the §6.2 loss (the flow is two-dimensional)."""
+    state vector W of the §7.4 loss (the flow is two-dimensional)."""
     rho = Ui[0]
     u = Ui[1] / rho
     v = Ui[2] / rho
@@ -251,7 +251,7 @@ def primitive_mse_grad(Ui, Wt, gamma, scale):
 
 class RusanovNNTrainer:
     """Supervised training of the Rusanov-NN dissipation on a coarse-grained
-    trajectory (§6.2): from snapshot s the coarse solver (WENO3-JS, TVD-RK2,
+    trajectory (§7.4): from snapshot s the coarse solver (WENO3-JS, TVD-RK2,
     Rusanov-NN, fixed dt_cg) is unrolled for n_unroll steps; the loss is the
     mean over the unrolled steps of the mean squared error between predicted
     and coarse-grained primitive states (rho, u, v, p); its gradient with
@@ -386,7 +386,7 @@ class RusanovNNTrainer:
 
 def train_rusanov_nn(epochs=1, n_train=1000, n_unroll=15, batch=20, lr=5e-4, seed=0, n_eval=2500, every=100,
                      theta0=None, log=print, graph=True):
-    """The §6.2 training on one GPU: ground truth (128^2 -> 32^2, n_eval coarse
+    """The §7.4 training on one GPU: ground truth (128^2 -> 32^2, n_eval coarse
     steps), training windows from the first n_train coarse steps, unroll
     n_unroll, batches of `batch` windows, Adam with learning rate lr, `epochs`
     passes (the paper: 200), then the trained coarse solver and the classical
@@ -451,7 +451,7 @@ if __name__ == "__main__":
     import argparse
     import json
 
-    ap = argparse.ArgumentParser(description="Rusanov-NN training on the implosion of §6.2")
+    ap = argparse.ArgumentParser(description="Rusanov-NN training on the implosion of §7.4")
     ap.add_argument("--epochs", type=int, default=1)
     ap.add_argument("--n-eval", type=int, default=2500)
     ap.add_argument("--n-train", type=int, default=1000)

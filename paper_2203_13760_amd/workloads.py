@@ -92,7 +92,7 @@ def lax(n=100, nh=3):
 
 
 def implosion(n=128, nh=3, flags=INVISCID | WENO3 | RK2):
-    """The implosion of §6.2 as printed: (rho, u, v, p) = (0.14, 0, 0, 0.125)
+    """The implosion of §7.4 as printed: (rho, u, v, p) = (0.14, 0, 0, 0.125)
     where x + y <= 0.15 and (1, 0, 0, 1) elsewhere on [0,1]^2, reflecting walls
     on all four sides, inviscid; the paper's ground truth runs WENO3-JS, TVD-RK2
     and HLLC at 128^2 with a fixed dt = 2.5e-4."""
@@ -107,7 +107,7 @@ def implosion(n=128, nh=3, flags=INVISCID | WENO3 | RK2):
 
 
 def nn_weights(seed=0, alpha0=1.0, scale=1.0):
-    """Seeded Rusanov-NN weights (§6.2 network: 4 inputs, three hidden ReLU
+    """Seeded Rusanov-NN weights (§7.4 network: 4 inputs, three hidden ReLU
     layers of 32, exp output): He-normal hidden layers with zero biases, the
     output layer scaled by `scale` (times 1/sqrt(32)) with bias ln(alpha0), so
     that scale = 0 gives alpha = alpha0 everywhere."""

@@ -227,7 +227,7 @@ def test_gradient_of_long_rollout_matches_finite_differences(Solver):
 
 
 # ---------------------------------------------------------------- the paper's gradient check
-# §6.1 (validation of AD gradients), single phase: d(Delta S)/dM_S of a Mach 2
+# §7.3 (validation of AD gradients), single phase: d(Delta S)/dM_S of a Mach 2
 # shock after 5 steps of dt = 1e-2, by the GPU adjoint, against the oracle's
 # taped reverse mode (same discrete operator) and against central differences.
 
@@ -297,7 +297,7 @@ def test_random_configurations_adjoint_match_oracle_tape(Solver, k):
 
 
 def test_walled_implosion_adjoint_matches_oracle_tape(Solver):
-    """Reflecting walls in the adjoint (the implosion of §6.2 with the default
+    """Reflecting walls in the adjoint (the implosion of §7.4 with the default
     scheme at 12^2, after 30 steps so the shock meets the walls): the
     right-hand-side adjoint and the step adjoint against the tape."""
     case, W = wl.implosion(12, flags=wl.INVISCID)

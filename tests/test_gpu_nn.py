@@ -1,4 +1,4 @@
-"""The Rusanov-NN flux of §6.2 on the HIP path (WENO3-JS, TVD-RK2, reflecting
+"""The Rusanov-NN flux of §7.4 on the HIP path (WENO3-JS, TVD-RK2, reflecting
 walls) against the oracle: the right-hand side, one step and 100 steps of the
 forward path, and the discrete adjoint with respect to the state and to the
 network weights against the oracle's taped reverse mode.
@@ -113,7 +113,7 @@ def test_nn_rhs_and_step_match_oracle(Solver, name, tname):
 
 @pytest.mark.parametrize("name", ["implosion24", "perturbed20x20"])
 def test_nn_100_fixed_steps_match_oracle(Solver, name):
-    """100 fixed steps of the coarse step 1e-3 of §6.2 (graph-replayed)."""
+    """100 fixed steps of the coarse step 1e-3 of §7.4 (graph-replayed)."""
     case, W = CASES[name]
     _say(f"Rusanov-NN 100-step parity: {name}")
     s, th, _ = _solver(Solver, case, THETAS["wide"])
@@ -268,7 +268,7 @@ def test_nn_configuration_errors(Solver):
 
 
 def test_training_gradient_matches_central_differences(Solver):
-    """The §6.2 training loss of a window (unrolled coarse steps against a
+    """The §7.4 training loss of a window (unrolled coarse steps against a
     coarse-grained truth) and its weight gradient from the step adjoints,
     against central differences of the loss along random weight directions (a
     one-sided difference where a ReLU unit of some face changes side within

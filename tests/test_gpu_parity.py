@@ -430,7 +430,7 @@ def test_roe_is_rejected_where_unsupported(Solver):
         cfd.cfd_batch_destroy(b)
 
 
-# ---------------------------------------------------------------- implosion substrate (§6.2)
+# ---------------------------------------------------------------- implosion substrate (§7.4)
 def _walls(case_W, axes):
     case, W = case_W
     case = dict(case)
@@ -488,7 +488,7 @@ def test_implosion_substrate_rhs_and_step_match_oracle(Solver, name):
 @pytest.mark.parametrize("name", ["implosion32_hllc", "implosion32_rusanov"])
 def test_implosion_100_fixed_steps_match_oracle(Solver, name):
     """The implosion at 32^2 through 100 fixed steps of 1e-3 (the coarse step
-    of §6.2), shock reflected at the walls."""
+    of §7.4), shock reflected at the walls."""
     case, W = F3_CASES[name]
     _say(f"implosion 100-step parity: {name}")
     s = Solver(case)
@@ -555,7 +555,7 @@ def test_implosion_128_conserves_mass_and_energy_on_gpu(Solver):
 
 
 def test_implosion_coarse_errors_rusanov_above_hllc(Solver):
-    """The §6.2 setting over 200 coarse steps: the coarse-grained 128^2 truth
+    """The §7.4 setting over 200 coarse steps: the coarse-grained 128^2 truth
     against 32^2 runs; the classical Rusanov flux smears more than HLLC, the
     gap the paper's Rusanov-NN is trained to close."""
     from paper_2203_13760_amd.experiments import implosion_trajectories

@@ -41,7 +41,7 @@ def _mix():
         wl.random_smooth((33, 29, 35), seed=3, mu=0.02, bc=(P, P, Z, Z, P, P)),
         # no x axis: the primitive pass at every stage instead of the x sweep's
         wl.random_shocky((1, 26, 19), seed=5),
-        # reflecting walls (the implosion of §6.2 with the default scheme)
+        # reflecting walls (the implosion of §7.4 with the default scheme)
         wl.implosion(40, flags=wl.INVISCID),
     ]
 

@@ -475,7 +475,7 @@ def test_roe_setup_through_the_oracle():
         assert np.all(oracle.rhs(case, U) == 0.0)
 
 
-# ---------------------------------------------------------------- implosion substrate (§6.2)
+# ---------------------------------------------------------------- implosion substrate (§7.4)
 def _mirror_pair(axis, n=24, steps=30, flags=wl.INVISCID, dt=2e-3):
     """A state on [0,1] along `axis` with reflecting walls at both ends, and the
     same state mirrored onto [0,2] with periodic ends (density and pressure
@@ -517,7 +517,7 @@ def _mirror_pair(axis, n=24, steps=30, flags=wl.INVISCID, dt=2e-3):
 @pytest.mark.parametrize("axis", [0, 1])
 @pytest.mark.parametrize("flags", [wl.INVISCID, wl.INVISCID | wl.WENO3 | wl.RK2 | wl.RUSANOV])
 def test_reflecting_wall_equals_mirrored_periodic_domain(axis, flags):
-    """Reflecting walls (the implosion of §6.2): the walled run equals the
+    """Reflecting walls (the implosion of §7.4): the walled run equals the
     first half of the run on the mirrored domain twice as long, for a jump and
     a smooth profile, along x and along y (the sign flip must hit the wall's
     normal momentum and only it)."""
@@ -561,7 +561,7 @@ def test_tvd_rk2_second_order_in_time():
 
 
 def test_rusanov_flux_pins():
-    """Rusanov (§6.2): equal states give the physical flux; alpha is the
+    """Rusanov (§7.4): equal states give the physical flux; alpha is the
     largest |u -+ c| of the two states; at a stationary contact (u = 0, equal
     pressures) HLLC gives the exact flux (0, p, 0, 0, 0) and Rusanov adds the
     dissipation -alpha (U_R - U_L)/2."""
@@ -609,7 +609,7 @@ def test_implosion_scheme_sod_and_walled_conservation():
 
 
 def _nn_numpy(th, f):
-    """The §6.2 network through numpy matrix products (a second implementation
+    """The §7.4 network through numpy matrix products (a second implementation
     of the same definition: different code, same layer order)."""
     o = 0
 
@@ -650,7 +650,7 @@ def _const_net(alpha):
 
 
 def test_nn_alpha_matches_matrix_form():
-    """The network of §6.2 (4 -> 32 -> 32 -> 32 -> 1, ReLU, exp output) against
+    """The network of §7.4 (4 -> 32 -> 32 -> 32 -> 1, ReLU, exp output) against
     numpy matrix products, for random weights and inputs of both signs."""
     rng = np.random.default_rng(11)
     try:
@@ -668,7 +668,7 @@ def test_nn_alpha_matches_matrix_form():
 
 
 def test_rusanov_nn_flux_pins():
-    """Rusanov-NN (§6.2): with a constant network (alpha = exp(b4)) it is the
+    """Rusanov-NN (§7.4): with a constant network (alpha = exp(b4)) it is the
     Rusanov flux of the same alpha, so a constant equal to the classical alpha
     reproduces the classical Rusanov flux; equal states give the physical flux
     for any weights; each input feature, selected alone, gives its closed form:
@@ -733,7 +733,7 @@ def _nn_case(n=10):
 
 def test_rusanov_nn_taped_gradients_match_central_differences():
     """The taped step derivative with the Rusanov-NN flux (walled implosion,
-    WENO3-JS + TVD-RK2, §6.2), with respect to the state and to the network
+    WENO3-JS + TVD-RK2, §7.4), with respect to the state and to the network
     weights, against second-order central differences of the oracle step."""
     case, W = _nn_case()
     dt = 1e-3

@@ -1,4 +1,4 @@
-"""CPU checks of the shock-gradient experiment (§6.1, validation of AD
+"""CPU checks of the shock-gradient experiment (§7.3, validation of AD
 gradients): the Rankine-Hugoniot initial state against closed forms, and the
 oracle's taped reverse-mode gradient of the entropy increase against its own
 central differences (second order, as the paper observes)."""
