@@ -139,7 +139,8 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     every ckpt_every steps (kept stages, and recomputed stages)."""
     import torch
     from paper_2203_13760_amd import workloads as wl
-    from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
+    from paper_2203_13760_amd.autograd import rollout, state_init
+    from paper_2203_13760_amd.experiments import kinetic_energy
     from paper_2203_13760_amd.solver import Solver
     case, W = wl.taylor_green_noisy(n, sigma=1e-3, seed=4)
     s = Solver(case)
@@ -184,7 +185,7 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
         Wt = torch.from_numpy(W).cuda().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        L = kinetic_energy(s, rollout(conservative_from_primitive(s, Wt), s, dt, nsteps, ckpt_every,
+        L = kinetic_energy(s, rollout(state_init(s, Wt), s, dt, nsteps, ckpt_every,
                                       keep_stages=keep))
         L.backward()
         torch.cuda.synchronize()

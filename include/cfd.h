@@ -114,6 +114,19 @@ int64_t cfd_state_numel(const cfd_solver* s);
  * U receives the padded conservative state with its halos filled. */
 cfd_status cfd_state_init(cfd_solver* s, const double* W, double* U, void* stream);
 
+/* Discrete adjoint of cfd_state_init (§2): with U = S(W) the padded state
+ * cfd_state_init makes from W (halos filled), Wbar += (dS/dW)^T Ubar. Each
+ * halo entry of Ubar is first added to the interior cell it is an image of
+ * (the transpose of the halo fill; a reflecting wall's normal momentum with
+ * its sign), in a fixed order, then the transposed primitive-to-conservative
+ * map at W gives, per interior cell,
+ *   rho_bar += Ubar_rho + u . Ubar_m + |u|^2/2 Ubar_E,
+ *   u_bar_d += rho (Ubar_m_d + u_d Ubar_E),   p_bar += Ubar_E / (gamma - 1).
+ * W and Wbar hold 5 blocks of interior cells [nz][ny][nx] (the layout of W in
+ * cfd_state_init); Ubar is a padded state (device memory, not modified).
+ * Wbar must not alias W or Ubar (CFD_EINVAL). The result is deterministic. */
+cfd_status cfd_state_init_adjoint(cfd_solver* s, const double* W, const double* Ubar, double* Wbar, void* stream);
+
 /* Refresh the halo cells of U in place from its interior, per the boundary
  * types (§3.7): periodic images, zero-gradient copies or mirror images with
  * the wall-normal momentum negated (reflecting walls), x then y then z. */

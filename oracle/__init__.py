@@ -80,6 +80,7 @@ def _load():
     lib.oracle_opcount.argtypes = [cfgp, dp, dp]
     lib.oracle_opcount_parts.argtypes = [cfgp, dp, dp]
     lib.oracle_vjp_rhs.argtypes = [cfgp, dp, dp, dp]
+    lib.oracle_vjp_state_init.argtypes = [cfgp, dp, dp, dp]
     lib.oracle_vjp_rk3_step.argtypes = [cfgp, dp, d, dp, dp]
     lib.oracle_grad_ke.argtypes = [cfgp, dp, C.c_int, d, dp, dp]
     lib.oracle_vjp_rhs_theta.argtypes = [cfgp, dp, dp, dp, dp]
@@ -292,6 +293,17 @@ def vjp_rhs(case, U, Rbar):
     Ubar = np.zeros_like(U)
     _ok(lib.oracle_vjp_rhs(C.byref(cfg), _ptr(U), _ptr(Rbar), _ptr(Ubar)))
     return Ubar
+
+
+def vjp_state_init(case, W, Ubar):
+    """Wbar = (dU/dW)^T Ubar for U = state_init(case, W) (halo entries of Ubar count)."""
+    lib = _load()
+    cfg = make_cfg(case)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    Ubar = np.ascontiguousarray(Ubar, dtype=np.float64)
+    Wbar = np.zeros_like(W)
+    _ok(lib.oracle_vjp_state_init(C.byref(cfg), _ptr(W), _ptr(Ubar), _ptr(Wbar)))
+    return Wbar
 
 
 def vjp_rk3_step(case, Un, dt, Ubar_np1):

@@ -1023,6 +1023,27 @@ int oracle_vjp_rhs_theta(const oracle_cfg* c, const double* U, const double* Rba
   return 0;
 }
 
+// Wbar = (dU/dW)^T Ubar for U = state_init(W) (§2, halos filled): W and
+// Wbar hold 5 x interior primitives, Ubar a padded state (halo entries count).
+int oracle_vjp_state_init(const oracle_cfg* c, const double* W, const double* Ubar, double* Wbar) {
+  if (check_cfg(c)) return -1;
+  Grid g(*c);
+  const long ni = (long)g.n[0] * g.n[1] * g.n[2];
+  Tape tape;
+  active_tape() = &tape;
+  std::vector<TVar> w(5 * ni);
+  for (long q = 0; q < 5 * ni; ++q) w[q] = TVar::leaf(W[q]);
+  std::vector<TVar> u;
+  state_init(*c, g, w.data(), u);
+  std::vector<double> adj(tape.nodes.size(), 0.0);
+  for (long q = 0; q < 5 * g.ncell; ++q)
+    if (u[q].id >= 0) adj[u[q].id] += Ubar[q];
+  tape.reverse(adj);
+  for (long q = 0; q < 5 * ni; ++q) Wbar[q] = adj[w[q].id];
+  active_tape() = nullptr;
+  return 0;
+}
+
 int oracle_vjp_rhs(const oracle_cfg* c, const double* U, const double* Rbar, double* Ubar) {
   return oracle_vjp_rhs_theta(c, U, Rbar, Ubar, nullptr);
 }

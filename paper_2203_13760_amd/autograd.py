@@ -78,26 +78,29 @@ def rollout(U0, solver: Solver, dt: float, n_steps: int, ckpt_every: int = 20, k
     return RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every, keep_stages)
 
 
-def conservative_from_primitive(solver: Solver, W):
-    """Differentiable torch map from interior primitives W (5, nz, ny, nx) to a
-    padded conservative state (halos zero; the rollout refreshes them)."""
-    g = solver.case["gamma"]
-    rho, u, v, w, p = W[0], W[1], W[2], W[3], W[4]
-    Ui = torch.stack([rho, rho * u, rho * v, rho * w, p / (g - 1.0) + 0.5 * rho * (u * u + v * v + w * w)])
-    U = torch.zeros(solver.shape, dtype=W.dtype, device=W.device)
-    nh = solver.case.get("nh", 3)
-    sl = []
-    for d in (2, 1, 0):
-        n = solver.case["n"][d]
-        sl.append(slice(nh, nh + n) if n > 1 else slice(0, 1))
-    U[(slice(None),) + tuple(sl)] = Ui
-    return U
+class StateInit(torch.autograd.Function):
+    """U = S(W): the padded conservative state (halos filled) of interior
+    primitive point values W (5, nz, ny, nx), by cfd_state_init; the backward
+    pass is cfd_state_init_adjoint (the transposed halo fill and primitive map)."""
+
+    @staticmethod
+    def forward(ctx, W, solver: Solver):
+        W = W.detach().contiguous()
+        U = solver.empty_state()
+        solver.state_init(W, U)
+        ctx.solver = solver
+        ctx.save_for_backward(W)
+        return U
+
+    @staticmethod
+    def backward(ctx, Ubar):
+        (W,) = ctx.saved_tensors
+        Wbar = torch.zeros_like(W)
+        ctx.solver.state_init_adjoint(W, Ubar.contiguous(), Wbar)
+        return Wbar, None
 
 
-def kinetic_energy(solver: Solver, U):
-    """Total kinetic energy sum 1/2 |rho u|^2 / rho dV over interior cells."""
-    Ui = interior(solver.case, U)
-    dV = 1.0
-    for d in range(3):
-        dV *= (solver.case["hi"][d] - solver.case["lo"][d]) / solver.case["n"][d]
-    return (0.5 * (Ui[1] ** 2 + Ui[2] ** 2 + Ui[3] ** 2) / Ui[0]).sum() * dV
+def state_init(solver: Solver, W):
+    """Differentiable cfd_state_init: interior primitives W (5, nz, ny, nx) on
+    the solver's device to the padded conservative state."""
+    return StateInit.apply(W, solver)

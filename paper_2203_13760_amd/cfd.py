@@ -44,7 +44,7 @@ class cfd_config(C.Structure):
 
 
 EXPORTS = (
-    "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_fill_halo", "cfd_rhs",
+    "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_state_init_adjoint", "cfd_fill_halo", "cfd_rhs",
     "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
     "cfd_rk3_step_adjoint", "cfd_rk3_step_stages", "cfd_rk3_step_adjoint_stages", "cfd_profile_stage", "cfd_check", "cfd_last_error",
     "cfd_set_nn_weights",
@@ -72,6 +72,7 @@ def load():
         "cfd_destroy": ([vp], None),
         "cfd_state_numel": ([vp], C.c_int64),
         "cfd_state_init": ([vp, dp, dp, vp], st),
+        "cfd_state_init_adjoint": ([vp, dp, dp, dp, vp], st),
         "cfd_fill_halo": ([vp, dp, vp], st),
         "cfd_rhs": ([vp, dp, dp, vp], st),
         "cfd_compute_dt": ([vp, dp, dp, vp], st),
@@ -164,6 +165,10 @@ def cfd_state_numel(h):
 
 def cfd_state_init(h, W, U, stream=None):
     _check(load().cfd_state_init(h, _ptr(W), _ptr(U), _stream(stream)))
+
+
+def cfd_state_init_adjoint(h, W, Ubar, Wbar, stream=None):
+    _check(load().cfd_state_init_adjoint(h, _ptr(W), _ptr(Ubar), _ptr(Wbar), _stream(stream)))
 
 
 def cfd_fill_halo(h, U, stream=None):

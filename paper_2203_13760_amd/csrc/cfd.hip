@@ -609,6 +609,15 @@ cfd_status cfd_state_init(cfd_solver* s, const double* W, double* U, void* strea
   return enqueue_fill_halo(s, U, st);
 }
 
+cfd_status cfd_state_init_adjoint(cfd_solver* s, const double* W, const double* Ubar, double* Wbar, void* stream) {
+  if (!s || !W || !Ubar || !Wbar) return fail(CFD_EINVAL, "NULL argument");
+  if (Wbar == W || Wbar == Ubar) return fail(CFD_EINVAL, "Wbar must not alias W or Ubar");
+  hipLaunchKernelGGL(k_state_init_adj, plane_grid(s->g), dim3(kBlock), 0, (hipStream_t)stream, W, Ubar, Wbar,
+                     s->g);
+  CFD_LAUNCHED();
+  return CFD_OK;
+}
+
 cfd_status cfd_fill_halo(cfd_solver* s, double* U, void* stream) {
   if (!s || !U) return fail(CFD_EINVAL, "NULL argument");
   return enqueue_fill_halo(s, U, (hipStream_t)stream);

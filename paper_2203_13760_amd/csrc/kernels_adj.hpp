@@ -527,4 +527,65 @@ __global__ void __launch_bounds__(kBlock) k_lincomb(double* __restrict__ out, do
   }
 }
 
+// Coordinates along one axis (n cells, halo h) whose value in a state with
+// filled halos is the image of interior coordinate c: m = 0 is c itself,
+// m = 1 .. h the low halo cells -m and m = h+1 .. 2h the high halo cells
+// n-1 .. n-1+h; false when halo cell m's boundary source is not c. sg is the
+// factor the image applies to the axis's velocity (-1 through a wall).
+__device__ __forceinline__ bool halo_preimage(int c, int n, int h, int bc_lo, int bc_hi, int m, int& x, double& sg) {
+  if (m == 0) {
+    x = c;
+    sg = 1.0;
+    return true;
+  }
+  x = m <= h ? -m : n - 1 + (m - h);
+  if (bc_source(x, n, bc_lo, bc_hi) != c) return false;
+  sg = bc_sign(x, n, bc_lo, bc_hi);
+  return true;
+}
+
+// Adjoint of the initial state U = S(W) (primitive point values W, 5 x
+// interior, to the padded conservative state with filled halos): per interior
+// cell, the adjoint of the cell's conservative values gathers Ubar over the
+// cell and all its halo images (the transpose of the halo fill, in a fixed
+// order, so the result is deterministic), then the transposed map of
+// (rho, u, v, w, p) -> (rho, rho u, rho v, rho w, p/(gamma-1) + rho |u|^2/2)
+// at W is added to Wbar.
+__global__ void __launch_bounds__(kBlock) k_state_init_adj(const double* __restrict__ W,
+                                                           const double* __restrict__ Ubar,
+                                                           double* __restrict__ Wbar, Geom g) {
+  const PlaneIdx p = plane_index(g);
+  if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
+  double ub[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int a = 0; a <= 2 * g.h[0]; ++a) {
+    int x;
+    double sx;
+    if (!halo_preimage(p.i, g.n[0], g.h[0], g.bc[0], g.bc[1], a, x, sx)) continue;
+    for (int b = 0; b <= 2 * g.h[1]; ++b) {
+      int y;
+      double sy;
+      if (!halo_preimage(p.j, g.n[1], g.h[1], g.bc[2], g.bc[3], b, y, sy)) continue;
+      for (int c = 0; c <= 2 * g.h[2]; ++c) {
+        int z;
+        double sz;
+        if (!halo_preimage(p.k, g.n[2], g.h[2], g.bc[4], g.bc[5], c, z, sz)) continue;
+        const long long e = cell_at(g, x, y, z);
+        ub[0] += Ubar[e];
+        ub[1] += sx * Ubar[g.vs + e];
+        ub[2] += sy * Ubar[2 * g.vs + e];
+        ub[3] += sz * Ubar[3 * g.vs + e];
+        ub[4] += Ubar[4 * g.vs + e];
+      }
+    }
+  }
+  const long long ni = (long long)g.n[0] * g.n[1] * g.n[2];
+  const long long s = ((long long)p.k * g.n[1] + p.j) * g.n[0] + p.i;
+  const double rho = W[s], u = W[ni + s], v = W[2 * ni + s], w = W[3 * ni + s];
+  Wbar[s] += ub[0] + u * ub[1] + v * ub[2] + w * ub[3] + 0.5 * (u * u + v * v + w * w) * ub[4];
+  Wbar[ni + s] += rho * (ub[1] + u * ub[4]);
+  Wbar[2 * ni + s] += rho * (ub[2] + v * ub[4]);
+  Wbar[3 * ni + s] += rho * (ub[3] + w * ub[4]);
+  Wbar[4 * ni + s] += ub[4] * g.gm1i;
+}
+
 }  // namespace cfd

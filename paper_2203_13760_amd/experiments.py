@@ -33,7 +33,7 @@ import time
 import torch
 
 from . import workloads as wl
-from .autograd import conservative_from_primitive, rollout
+from .autograd import rollout, state_init
 from .solver import Solver, interior
 
 SHOCK_M = 2.0
@@ -70,6 +70,17 @@ def initial_W(case, M, x_shock=0.5):
     return torch.stack([rho, u, zero, zero, p]).reshape(5, 1, 1, -1)
 
 
+def kinetic_energy(solver: Solver, U):
+    """Total kinetic energy sum 1/2 |rho u|^2 / rho dV over interior cells: the
+    loss of the differentiation workload (a Taylor-Green vortex's final
+    kinetic energy as a function of its initial velocities)."""
+    Ui = interior(solver.case, U)
+    dV = 1.0
+    for d in range(3):
+        dV *= (solver.case["hi"][d] - solver.case["lo"][d]) / solver.case["n"][d]
+    return (0.5 * (Ui[1] ** 2 + Ui[2] ** 2 + Ui[3] ** 2) / Ui[0]).sum() * dV
+
+
 def integral_entropy(case, U):
     """sum_i rho_i s_i dx over the interior cells of a padded conservative state."""
     g = case["gamma"]
@@ -84,7 +95,7 @@ def integral_entropy(case, U):
 def delta_entropy(solver: Solver, M, dt=SHOCK_DT, n_steps=SHOCK_STEPS):
     """Delta S after n_steps from the shock of Mach number M (differentiable in M)."""
     case = solver.case
-    U0 = conservative_from_primitive(solver, initial_W(case, M))
+    U0 = state_init(solver, initial_W(case, M))
     Un = rollout(U0, solver, dt, n_steps, ckpt_every=n_steps)
     return integral_entropy(case, Un) - integral_entropy(case, U0)
 

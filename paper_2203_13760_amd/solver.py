@@ -56,6 +56,16 @@ class Solver:
         cfd.cfd_state_init(self.h, W, U)
         return U
 
+    def state_init(self, W, U):
+        """cfd_state_init of device primitives W (5, nz, ny, nx) into U."""
+        cfd.cfd_state_init(self.h, W, U)
+        return U
+
+    def state_init_adjoint(self, W, Ubar, Wbar):
+        """Wbar += (dU/dW)^T Ubar for U = state_init(W) (cfd_state_init_adjoint)."""
+        cfd.cfd_state_init_adjoint(self.h, W, Ubar, Wbar)
+        return Wbar
+
     def fill_halo(self, U):
         cfd.cfd_fill_halo(self.h, U)
         return U

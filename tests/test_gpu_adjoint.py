@@ -60,6 +60,55 @@ def _interior_mask(case, shape):
     return m
 
 
+STATE_INIT_CASES = {
+    "periodic3d": wl.random_smooth((7, 6, 5), seed=12, mu=0.02),
+    "mixed_bc": wl.random_smooth((9, 8, 7), seed=13, bc=(wl.PERIODIC, wl.PERIODIC, wl.ZERO_GRADIENT,
+                                                         wl.ZERO_GRADIENT, wl.REFLECT, wl.ZERO_GRADIENT)),
+    "walls2d": wl.implosion(12),
+    "sod": wl.sod(20),
+}
+
+
+@pytest.mark.parametrize("name", sorted(STATE_INIT_CASES))
+def test_state_init_adjoint_matches_oracle_tape(Solver, name):
+    """cfd_state_init_adjoint (§2 primitive-to-conservative map and the
+    transposed halo fill) against the oracle's taped reverse mode of
+    state_init, with a dense cotangent on the halo cells too."""
+    case, W = STATE_INIT_CASES[name]
+    print(f"state_init adjoint parity: {name} n={case['n']}", flush=True)
+    s = Solver(case)
+    rng = np.random.default_rng(31)
+    Ub = rng.standard_normal(oracle.padded_shape(case))
+    Wt = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    Wb = torch.zeros_like(Wt)
+    s.state_init_adjoint(Wt, torch.from_numpy(Ub).cuda(), Wb)
+    g = Wb.cpu().numpy()
+    # accumulates: a second call doubles the result
+    s.state_init_adjoint(Wt, torch.from_numpy(Ub).cuda(), Wb)
+    g2 = Wb.cpu().numpy()
+    s.close()
+    go = oracle.vjp_state_init(case, W, Ub)
+    assert normwise(g, go) <= 1e-13, normwise(g, go)
+    assert normwise(g2, 2.0 * go) <= 1e-13
+
+
+def test_state_init_autograd_function(Solver):
+    """autograd.state_init: forward equals cfd_state_init, backward equals
+    cfd_state_init_adjoint (halo cotangents folded into their sources)."""
+    from paper_2203_13760_amd.autograd import state_init
+    case, W = wl.random_smooth((8, 7, 6), seed=14, bc=(wl.ZERO_GRADIENT,) * 6)
+    s = Solver(case)
+    Wt = torch.from_numpy(W).cuda().requires_grad_(True)
+    U = state_init(s, Wt)
+    assert torch.equal(U, s.init(W))
+    rng = np.random.default_rng(32)
+    Ub = rng.standard_normal(U.shape)
+    (U * torch.from_numpy(Ub).cuda()).sum().backward()
+    g = Wt.grad.cpu().numpy()
+    s.close()
+    assert normwise(g, oracle.vjp_state_init(case, W, Ub)) <= 1e-13
+
+
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_rhs_adjoint_matches_oracle_tape(Solver, name):
     case, W = CASES[name]
@@ -155,14 +204,15 @@ def test_rhs_adjoint_dot_product_on_gpu(Solver):
 
 
 def test_gradient_through_checkpointed_rollout_matches_oracle(Solver):
-    from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
+    from paper_2203_13760_amd.autograd import rollout, state_init
+    from paper_2203_13760_amd.experiments import kinetic_energy
     case, W = wl.taylor_green_noisy(16, sigma=1e-3, seed=4)
     nsteps, every = 16, 4
     dt = oracle.cfl_dt(case, oracle.state_init(case, W))
     print(f"rollout gradient vs oracle tape: 16^3, {nsteps} steps, checkpoints every {every}", flush=True)
     s = Solver(case)
     Wt = torch.from_numpy(W).cuda().requires_grad_(True)
-    U0 = conservative_from_primitive(s, Wt)
+    U0 = state_init(s, Wt)
     L = kinetic_energy(s, rollout(U0, s, dt, nsteps, every))
     L.backward()
     g = Wt.grad[1:4].cpu().numpy()
@@ -179,7 +229,8 @@ def test_rollout_gradient_with_and_without_kept_stages(Solver):
     stages are bitwise the same, the atomic sums of the face adjoints are not
     ordered, and their rounding differences compound over the 11 step
     adjoints (about 1e-11 here), so the bar is this file's 1e-10."""
-    from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
+    from paper_2203_13760_amd.autograd import rollout, state_init
+    from paper_2203_13760_amd.experiments import kinetic_energy
     case, W = wl.taylor_green_noisy(16, sigma=1e-3, seed=4)
     dt = oracle.cfl_dt(case, oracle.state_init(case, W))
     print("rollout gradient, kept vs recomputed stages", flush=True)
@@ -187,7 +238,7 @@ def test_rollout_gradient_with_and_without_kept_stages(Solver):
     grads = []
     for keep in (True, False):
         Wt = torch.from_numpy(W).cuda().requires_grad_(True)
-        L = kinetic_energy(s, rollout(conservative_from_primitive(s, Wt), s, dt, 11, 4, keep_stages=keep))
+        L = kinetic_energy(s, rollout(state_init(s, Wt), s, dt, 11, 4, keep_stages=keep))
         L.backward()
         grads.append(Wt.grad.cpu().numpy())
     s.close()
@@ -195,7 +246,8 @@ def test_rollout_gradient_with_and_without_kept_stages(Solver):
 
 
 def test_gradient_of_long_rollout_matches_finite_differences(Solver):
-    from paper_2203_13760_amd.autograd import conservative_from_primitive, kinetic_energy, rollout
+    from paper_2203_13760_amd.autograd import rollout, state_init
+    from paper_2203_13760_amd.experiments import kinetic_energy
     case, W = wl.taylor_green_noisy(24, sigma=1e-3, seed=4)
     nsteps, every = 60, 20
     s = Solver(case)
@@ -203,7 +255,7 @@ def test_gradient_of_long_rollout_matches_finite_differences(Solver):
     dt = float(s.compute_dt(U0).item())
     print(f"rollout gradient vs central differences: 24^3, {nsteps} steps", flush=True)
     Wt = torch.from_numpy(W).cuda().requires_grad_(True)
-    L = kinetic_energy(s, rollout(conservative_from_primitive(s, Wt), s, dt, nsteps, every))
+    L = kinetic_energy(s, rollout(state_init(s, Wt), s, dt, nsteps, every))
     L.backward()
     g = Wt.grad[1:4]
     gen = torch.Generator(device="cuda").manual_seed(11)
@@ -213,7 +265,7 @@ def test_gradient_of_long_rollout_matches_finite_differences(Solver):
         Wx = Wt.detach().clone()
         Wx[1:4] += t * d
         with torch.no_grad():
-            U = conservative_from_primitive(s, Wx)
+            U = state_init(s, Wx)
             s.fill_halo(U)
             s.advance_fixed(U, nsteps, dt)
             return float(kinetic_energy(s, U).item())

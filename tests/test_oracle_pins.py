@@ -868,6 +868,31 @@ def test_taped_rhs_derivative_matches_finite_differences(kind):
     assert abs(lhs - r) <= 3e-6 * max(abs(lhs), abs(r)), (lhs, r)
 
 
+@pytest.mark.parametrize("bc", [wl.PERIODIC, wl.ZERO_GRADIENT, wl.REFLECT])
+def test_taped_state_init_derivative_matches_finite_differences(bc):
+    """The taped reverse mode of state_init (primitive point values to the
+    padded conservative state with its halos, §2, §3.7): <w, J v> by central
+    differences against <J^T w, v>; the map is at most cubic in W, so the
+    differences are exact to rounding. A cotangent on the halo cells reaches
+    their interior sources."""
+    flags = wl.INVISCID
+    case = wl.make_case((5, 4, 3), bc=(bc,) * 4 + (wl.PERIODIC,) * 2, flags=flags)
+    rng = np.random.default_rng(33)
+    W = np.stack([rng.uniform(0.5, 2, (3, 4, 5)), *rng.uniform(-1, 1, (3, 3, 4, 5)),
+                  rng.uniform(0.5, 2, (3, 4, 5))])
+    v = rng.standard_normal(W.shape)
+    w = rng.standard_normal(oracle.padded_shape(case))
+    h = 1e-5
+    fd = (oracle.state_init(case, W + h * v) - oracle.state_init(case, W - h * v)) / (2 * h)
+    lhs = float(np.sum(w * fd))
+    rhs_ = float(np.sum(oracle.vjp_state_init(case, W, w) * v))
+    assert abs(lhs - rhs_) <= 1e-9 * abs(lhs), (lhs, rhs_)
+    # a halo-only cotangent gives a nonzero gradient on the cells it mirrors
+    wh = w.copy()
+    oracle.interior(case, wh)[...] = 0.0
+    assert np.max(np.abs(oracle.vjp_state_init(case, W, wh))) > 0.1
+
+
 def test_taped_step_and_loss_gradient_match_finite_differences():
     case, W = wl.taylor_green_noisy(6, sigma=1e-3, seed=4)
     U = oracle.state_init(case, W)
