@@ -232,6 +232,24 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
  * at the start of any step since the previous cfd_check (which clears it). */
 cfd_status cfd_check(cfd_solver* s, int32_t* status_out);
 
+/* Allocation-free TVD-RK3 step, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): cfd_rk3_step of U in place for the configuration cfg,
+ * with no solver handle and no device allocation or free. Its scratch (CFL
+ * slots, control block, two stage states, the right-hand-side accumulator and
+ * three primitive buffers: 33 doubles per padded cell) is one static device
+ * array of 96 MiB, allocated with the library on every device it runs on and
+ * held until the process ends; the grid may have at most
+ * CFD_NOALLOC_MAX_PADDED_CELLS padded cells (CFD_EINVAL otherwise, before any
+ * device work). dt > 0 fixes the step, dt <= 0 takes the CFL step of U;
+ * dt_used_dev (device, nullable) receives it. The results equal
+ * cfd_rk3_step's bitwise. Every call on a device uses that device's one
+ * array: calls that overlap on one device (other streams, other threads)
+ * race and give undefined results. The Rusanov-NN flux is not taken
+ * (CFD_EUNSUPPORTED). */
+#define CFD_NOALLOC_MAX_PADDED_CELLS 381291
+cfd_status cfd_rk3_step_noalloc(const cfd_config* cfg, double* U, double dt, double* dt_used_dev, void* stream);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* cfd_last_error(void);
 

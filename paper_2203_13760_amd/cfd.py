@@ -20,6 +20,7 @@ CFD_BC_PERIODIC, CFD_BC_ZERO_GRADIENT, CFD_BC_REFLECT = 0, 1, 2
 CFD_F_INVISCID, CFD_F_VISCOUS, CFD_F_HEAT, CFD_F_WENOZ, CFD_F_ROE = 1, 2, 4, 8, 16
 CFD_F_WENO3, CFD_F_RUSANOV, CFD_F_RK2, CFD_F_RUSANOV_NN = 32, 64, 128, 256
 CFD_NN_PARAMS = 2305
+CFD_NOALLOC_MAX_PADDED_CELLS = 381291
 
 
 class CfdError(RuntimeError):
@@ -47,7 +48,7 @@ EXPORTS = (
     "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_state_init_adjoint", "cfd_fill_halo", "cfd_rhs",
     "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
     "cfd_rk3_step_adjoint", "cfd_rk3_step_stages", "cfd_rk3_step_adjoint_stages", "cfd_profile_stage", "cfd_check", "cfd_last_error",
-    "cfd_set_nn_weights",
+    "cfd_set_nn_weights", "cfd_rk3_step_noalloc",
     "cfd_batch_create", "cfd_batch_destroy", "cfd_batch_footprint", "cfd_batch_add", "cfd_batch_remove",
     "cfd_batch_state", "cfd_batch_step", "cfd_batch_finish", "cfd_batch_copy_state", "cfd_batch_count",
 )
@@ -85,6 +86,7 @@ def load():
         "cfd_rk3_step_adjoint_stages": ([vp, dp, dp, dp, C.c_double, dp, dp, vp], st),
         "cfd_profile_stage": ([vp, dp, C.c_int32, C.POINTER(C.c_double), vp], st),
         "cfd_set_nn_weights": ([vp, dp, dp], st),
+        "cfd_rk3_step_noalloc": ([cfgp, dp, C.c_double, dp, vp], st),
         "cfd_check": ([vp, C.POINTER(C.c_int32)], st),
         "cfd_last_error": ([], C.c_char_p),
         "cfd_batch_create": ([C.c_int32, C.c_int64, C.POINTER(C.c_void_p)], st),
@@ -217,6 +219,13 @@ def cfd_set_nn_weights(h, theta, theta_bar=None):
     """Rusanov-NN weights (device tensor of CFD_NN_PARAMS doubles, kept alive by
     the caller) and the optional weight-gradient accumulator the adjoints add to."""
     _check(load().cfd_set_nn_weights(h, _ptr(theta), _ptr(theta_bar)))
+
+
+def cfd_rk3_step_noalloc(case, U, dt=0.0, dt_used_dev=None, stream=None):
+    """Allocation-free TVD-RK3 step of U in place (no solver handle; the
+    library's static device scratch, grids up to CFD_NOALLOC_MAX_PADDED_CELLS)."""
+    cfg = make_config(case)
+    _check(load().cfd_rk3_step_noalloc(C.byref(cfg), _ptr(U), float(dt), _ptr(dt_used_dev), _stream(stream)))
 
 
 def cfd_profile_stage(h, U, reps=5, stream=None):

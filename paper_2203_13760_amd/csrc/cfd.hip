@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -906,6 +907,85 @@ cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const do
                      (const double*)s->A2, 1.0, (const double*)s->A1, g);
   CFD_LAUNCHED();
   return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free TVD-RK3 step. Its scratch (CFL slots, control block, two
+// stage states, the right-hand-side accumulator and three primitive buffers)
+// lives in one file-scope device array, present on every device the library
+// runs on until the process ends. Host code never passes the array's name to
+// a kernel (on the host it is only a stand-in symbol): the device address of
+// each device's copy is looked up once, on that device's first call, with
+// hipGetSymbolAddress and kept per device.
+constexpr long long kNoAllocDoubles = 96LL << 17;  // 96 MiB of FP64
+constexpr long long kNoAllocHead = kCflSlots + 32;  // CFL slots, then the control block (256 B aligned)
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// Padded cells of cfg that fit the scratch array: 33 doubles per padded cell
+// (U1, U2, R: 5 each; three primitive buffers: 6 each) after the head.
+static constexpr long long noalloc_max_cells() { return (kNoAllocDoubles - kNoAllocHead) / 33; }
+static_assert(noalloc_max_cells() == CFD_NOALLOC_MAX_PADDED_CELLS, "header limit out of date");
+
+static cfd_status noalloc_scratch(double** out) {
+  int dev = -1;
+  CFD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(CFD_EUNSUPPORTED, "device index beyond the supported range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CFD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return CFD_OK;
+}
+
+extern "C" {
+
+cfd_status cfd_rk3_step_noalloc(const cfd_config* cfg, double* U, double dt, double* dt_used_dev, void* stream) {
+  if (!U) return fail(CFD_EINVAL, "NULL argument");
+  cfd_status rc = validate(cfg);
+  if (rc) return rc;
+  if (!std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be finite");
+  if (cfg->flags & CFD_F_RUSANOV_NN)
+    return fail(CFD_EUNSUPPORTED, "the allocation-free step does not take the Rusanov-NN flux (it needs weights)");
+  cfd_solver s{};
+  s.cfg = *cfg;
+  make_geom(*cfg, s.g);
+  choose_segment(s.g);
+  s.ncell = s.g.vs;
+  s.nint = (long long)cfg->n[0] * cfg->n[1] * cfg->n[2];
+  if (s.ncell > noalloc_max_cells())
+    return fail(CFD_EINVAL, "grid too large for the allocation-free step: " + std::to_string(s.ncell) +
+                                " padded cells, at most " + std::to_string(noalloc_max_cells()));
+  double* base = nullptr;
+  if ((rc = noalloc_scratch(&base))) return rc;
+  const long long nc = s.ncell;
+  s.partial = base;
+  s.npart = kCflSlots;
+  s.ctl = reinterpret_cast<DevCtl*>(base + kCflSlots);
+  double* b = base + kNoAllocHead;
+  s.U1 = b;
+  s.U2 = b + 5 * nc;
+  s.Racc = b + 10 * nc;
+  for (int k = 0; k < 3; ++k) s.Pb[k] = b + (15 + 6 * k) * nc;
+  s.P = s.Pb[0];
+  hipStream_t st = (hipStream_t)stream;
+  // the control block (step size, health bits) starts clear on every call;
+  // the CFL slots are cleared by the prologue of a CFL step
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlock), 0, st, base + kCflSlots, 32LL);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_step_prologue(&s, U, !(dt > 0.0), st))) return rc;
+  if ((rc = enqueue_step(&s, U, dt > 0.0 ? dt : 0.0, 0.0, nullptr, dt_used_dev, st))) return rc;
+  return enqueue_fill_halo(&s, U, st);
 }
 
 }  // extern "C"

@@ -124,3 +124,20 @@ def test_entry_points_reject_null_arguments():
                        ("cfd_state_init", (null, null, null, null))]:
         assert getattr(lib, name)(*args) == cfd.CFD_EINVAL, name
         assert cfd.cfd_last_error() != ""
+
+
+def test_noalloc_step_rejects_before_device_work():
+    """The allocation-free step validates its configuration, and the grid
+    against its static scratch, before any HIP call."""
+    _lib_or_skip()
+    fake = ctypes.c_void_p(8)  # never dereferenced: every case fails validation first
+    lib = cfd.load()
+    for kw, msg in [(dict(nh=2), "nh"), (dict(n=(78, 78, 78)), "too large"), (dict(flags=1 | 32 | 256), "Rusanov-NN")]:
+        cfg = cfd.make_config(_case(**kw))
+        rc = lib.cfd_rk3_step_noalloc(ctypes.byref(cfg), fake, ctypes.c_double(0.0), ctypes.c_void_p(0),
+                                      ctypes.c_void_p(0))
+        assert rc in (cfd.CFD_EINVAL, cfd.CFD_EUNSUPPORTED), kw
+        assert msg in cfd.cfd_last_error(), (kw, cfd.cfd_last_error())
+    assert lib.cfd_rk3_step_noalloc(ctypes.byref(cfd.make_config(_case())), ctypes.c_void_p(0), ctypes.c_double(0.0),
+                                    ctypes.c_void_p(0), ctypes.c_void_p(0)) == cfd.CFD_EINVAL
+    assert cfd.CFD_NOALLOC_MAX_PADDED_CELLS == 381291
