@@ -509,9 +509,9 @@ __device__ __forceinline__ double lane_shr1(double x) {
 constexpr int kXCtx = 3;
 constexpr int kXFaces = 64 - (kXCtx + 1);  // faces a wavefront emits
 
-template <int MODE, bool PN = false, int SCH = SCH_JS>
-__device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const StageIO& io, const Geom& g,
-                                             int bx) {
+template <int MODE, bool PN, int SCH>
+__device__ __forceinline__ void sweep_x_body_face(const double* __restrict__ P, const StageIO& io, const Geom& g,
+                                                  int bx) {
   // slot numbering fits in 32 bits (checked when the solver is created)
   const int lane = threadIdx.x & 63;
   const int wave = (bx * kBlock + (int)threadIdx.x) >> 6;
@@ -573,6 +573,89 @@ __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const
   if (PN) finish_prims(io, smax, bad);
 }
 
+// The same for the cell-centred schemes: the lane of face f reconstructs at
+// both faces of cell f (window cells f-2 .. f+2, one smoothness evaluation
+// for the two faces) and takes the left state of face f from the lane below,
+// which reconstructed cell f-1.
+template <int MODE, bool PN, int SCH>
+__device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, const StageIO& io, const Geom& g,
+                                                  int bx) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (bx * kBlock + (int)threadIdx.x) >> 6;
+  const int S = g.n[0] + 1 + kXCtx;
+  const int total = S * g.n[1] * g.n[2];
+  const int first = wave * kXFaces;
+  double smax = 0.0;
+  int bad = 0;
+  if (first < total) {  // uniform per wavefront
+    const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
+    const int gs = first - (kXCtx + 1) + lane;
+    const bool inrange = gs >= 0 && gs < total;
+    int f = 0, j = 0, k = 0;
+    if (inrange) {
+      const int row = gs / S;
+      f = gs - row * S - kXCtx;
+      k = row / g.n[1];
+      j = row - k * g.n[1];
+    }
+    const bool valid = inrange && f >= 0 && gs >= first - 1;  // lanes whose face flux is used
+    // every lane loads a window inside the padded block and computes a flux:
+    // the context slots before a row's first face reconstruct cell -1 (the
+    // left state of face 0 comes from the slot below it), lanes past the end
+    // take face 0 of the first row
+    const int fl = f < -1 ? -1 : f;
+    const long long c0 = cell_at(g, fl - 2, j, k);  // cells f-2 .. f+2
+    double q[5][5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) load_prims(P, g.vs, c0 + m, q[m]);
+    double T[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) T[m] = P[5 * g.vs + c0 + m];  // cells f-2 .. f+1; unused without heat flux
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    if (g.viscous) tangential_at_flat<0>(g, P, cell_at(g, f + 1, j, k), d);
+    // face values of the derivatives from cells f-2..f+1 (lanes - 3 .. lane)
+    double tf[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double t2 = lane_shr1(d[v]);
+      const double t1 = lane_shr1(t2);
+      const double t0 = lane_shr1(t1);
+      tf[v] = rc4(t0, t1, t2, d[v]);
+    }
+    double WL[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WR[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (g.inviscid) {
+      double qr[5];
+      recon_pair<SCH>(q, qr, WR);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) WL[v] = lane_shr1(qr[v]);
+    }
+    double alpha = 0.0;
+    if constexpr (SCH == SCH_W3_NN) alpha = g.nna[c0 + 1];  // alpha of face f (left cell f-1)
+    double G[5];
+    face_flux_states<0, SCH>(g, WL, WR, q, T, tf, alpha, G);
+    double Gm[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Gm[v] = lane_shr1(G[v]);
+    if (valid && gs >= first && f >= 1) {
+      double D[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[0];
+      const long long ce = cell_at(g, f - 1, j, k);
+      EmitIn ein;
+      emit_fetch<MODE>(io, g.vs, ce, ein);
+      emit_put<MODE, PN>(io, g, ce, D, ein, dt, smax, bad);
+    }
+  }
+  if (PN) finish_prims(io, smax, bad);
+}
+
+template <int MODE, bool PN = false, int SCH = SCH_JS>
+__device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const StageIO& io, const Geom& g,
+                                             int bx) {
+  if constexpr (SCH == SCH_ROE) sweep_x_body_face<MODE, PN, SCH>(P, io, g, bx);
+  else sweep_x_body_pair<MODE, PN, SCH>(P, io, g, bx);
+}
+
 // Blocks are taken in XCD-major order, so that the neighbouring rows and
 // planes whose velocities the derivative stencils read are being processed in
 // the same XCD and stay in its L2.
@@ -598,9 +681,9 @@ constexpr int kSeg = 32;
 // y / z sweep body of one lane. Lanes beyond the grid (a partial last block)
 // march a valid column too but store nothing, so that every lane reaches the
 // block-wide CFL reduction of a sweep that stores next-stage primitives.
-template <int AX, int MODE, bool PN = false, int SCH = SCH_JS>
-__device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const StageIO& io,
-                                                 const Geom& g, int bx, int by) {
+template <int AX, int MODE, bool PN, int SCH>
+__device__ __forceinline__ void sweep_march_body_face(const double* __restrict__ P, const StageIO& io,
+                                                      const Geom& g, int bx, int by) {
   constexpr int OT = AX == 1 ? 2 : 1;  // the other transverse axis
   const int i = bx * 64 + (threadIdx.x & 63);
   const int sl = g.seg;
@@ -693,6 +776,141 @@ __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, c
     }
   }
   if (PN) finish_prims(io, smax, bad);
+}
+
+// The same for the cell-centred schemes: the lane carries the left state of
+// the next face, reconstructed with the right state of the current face from
+// the cell between them (one smoothness evaluation for the two faces), so the
+// window holds five cells, f-1 .. f+3 for face f+1/2. The segment starts with
+// the reconstruction of cell s0-1, for the left state of its first face.
+template <int AX, int MODE, bool PN, int SCH>
+__device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__ P, const StageIO& io,
+                                                      const Geom& g, int bx, int by) {
+  constexpr int OT = AX == 1 ? 2 : 1;  // the other transverse axis
+  const int i = bx * 64 + (threadIdx.x & 63);
+  const int sl = g.seg;
+  const int nseg = (g.n[AX] + sl - 1) / sl;
+  const long long col = (long long)by * (kBlock >> 6) + (threadIdx.x >> 6);
+  const bool in = i < g.n[0] && col < (long long)g.n[OT] * nseg;
+  if (!PN && !in) return;
+  double smax = 0.0;
+  int bad = 0;
+  const long long colc = in ? col : 0;
+  const int o = (int)(colc / nseg);
+  const int seg = (int)(colc - (long long)o * nseg);
+  const int s0 = seg * sl;
+  const int s1 = min(s0 + sl, g.n[AX]);
+  const long long st = g.s[AX];
+  int q3[3];
+  q3[0] = in ? i : 0;
+  q3[OT] = o;
+  q3[AX] = s0 - 3;
+  long long c = cell_at(g, q3[0], q3[1], q3[2]);  // cell s0-3
+  const bool dis = g.viscous || g.heat;
+  double q[5][5];   // window: cells f-1 .. f+3 for face f+1/2
+  double WLc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // left state of face f+1/2
+  {
+    double s[5][5];  // cells s0-3 .. s0+1
+#pragma unroll
+    for (int m = 0; m < 5; ++m) load_prims(P, g.vs, c + m * st, s[m]);
+    load_prims(P, g.vs, c + 5 * st, q[4]);
+    if (g.inviscid) {
+      double unused[5];
+      recon_pair<SCH>(s, WLc, unused);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) q[m][v] = s[m + 1][v];
+  }
+  c += st;  // window cell 0: cell f-1 for the first face f = s0-1
+  double T[4] = {0.0, 0.0, 0.0, 0.0}, tg[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tg[m][v] = 0.0;
+  if (dis) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      T[m] = P[5 * g.vs + c + m * st];
+      if (g.viscous) tangential_at<AX>(g, P, c + m * st, tg[m]);
+    }
+  }
+  double Gm[5];
+  const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
+  for (int f = s0 - 1; f < s1; ++f) {
+    // issue the loads of the cell entering the window at the next face, and
+    // those of this face's cell update, before this face's arithmetic, so
+    // their latency overlaps it
+    const bool more = f + 1 < s1;
+    EmitIn ein;
+    if (f >= s0 && in) emit_fetch<MODE>(io, g.vs, c + st, ein);  // window cell 1 is cell f
+    constexpr bool kDeferTg = MODE == MODE_WRITE;
+    double nq[5], nT = 0.0, ntr[4][4], ntg[4] = {0.0, 0.0, 0.0, 0.0};
+    if (more) {
+      load_prims(P, g.vs, c + 5 * st, nq);
+      if (dis) {
+        nT = P[5 * g.vs + c + 4 * st];
+        if (g.viscous) {
+          if (kDeferTg) tangential_load<AX>(g, P, c + 4 * st, ntr);
+          else tangential_at<AX>(g, P, c + 4 * st, ntg);
+        }
+      }
+    }
+    if (kDeferTg) __builtin_amdgcn_sched_barrier(0);
+    double alpha = 0.0;
+    if constexpr (SCH == SCH_W3_NN) alpha = g.nna[AX * g.vs + c + st];  // face f+1/2, left cell f
+    double WR[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, qr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (g.inviscid) recon_pair<SCH>(q, qr, WR);  // cell f+1: left state of face f+3/2, right state of f+1/2
+    double tf[4] = {0.0, 0.0, 0.0, 0.0};
+    if (g.viscous) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tf[v] = rc4(tg[0][v], tg[1][v], tg[2][v], tg[3][v]);
+    }
+    double G[5];
+    face_flux_states<AX, SCH>(g, WLc, WR, q, T, tf, alpha, G);
+    if (f >= s0 && in) {
+      double D[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[AX];
+      emit_put<MODE, PN>(io, g, c + st, D, ein, dt, smax, bad);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      Gm[v] = G[v];
+      WLc[v] = qr[v];
+    }
+    if (more) {
+      // shift the window by one cell along the axis
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[m][v] = q[m + 1][v];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) q[4][v] = nq[v];
+      c += st;
+      if (dis) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          T[m] = T[m + 1];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) tg[m][v] = tg[m + 1][v];
+        }
+        T[3] = nT;
+        if (kDeferTg && g.viscous) tangential_combine<AX>(g, ntr, ntg);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tg[3][v] = ntg[v];
+      }
+    }
+  }
+  if (PN) finish_prims(io, smax, bad);
+}
+
+template <int AX, int MODE, bool PN = false, int SCH = SCH_JS>
+__device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const StageIO& io,
+                                                 const Geom& g, int bx, int by) {
+  if constexpr (SCH == SCH_ROE) sweep_march_body_face<AX, MODE, PN, SCH>(P, io, g, bx, by);
+  else sweep_march_body_pair<AX, MODE, PN, SCH>(P, io, g, bx, by);
 }
 
 // The Roe flux splitting does not fit the marching window in the register

@@ -148,6 +148,75 @@ __host__ __device__ __forceinline__ double weno5z(double a, double b, double c, 
   return (w0 * P0 + w1 * P1 + w2 * P2) / (6.0 * (w0 + w1 + w2));
 }
 
+// WENO5-JS at both faces of the centre cell c of the stencil (a, b, c, d, e) =
+// q_{i-2} .. q_{i+2}: qr at the right face i+1/2 (the left state there) and
+// ql at the left face i-1/2 (the right state there). The two reconstructions
+// share their three smoothness indicators in mirrored roles - the indicator
+// of cells i-2..i is beta_0 of qr and beta_2 of ql - so each is formed once
+// per cell, from the second differences Db, Dc, Dd centred at b, c, d and the
+// first differences dm = c - b, dp = d - c:
+//   beta_L = 13/12 Db^2 + 1/4 (Db + 2 dm)^2     (a - 4b + 3c = Db + 2 dm)
+//   beta_C = 13/12 Dc^2 + 1/4 (dm + dp)^2       (b - d = -(dm + dp))
+//   beta_R = 13/12 Dd^2 + 1/4 (Dd - 2 dp)^2     (3c - 4d + e = Dd - 2 dp).
+// With s_k = (1e-6 + beta_k)^2 the weights of qr are proportional to
+// (0.1 s_C s_R, 0.6 s_L s_R, 0.3 s_L s_C) on the candidates
+// (2a - 7b + 11c, -b + 5c + 2d, 2c + 5d - e)/6, those of ql to
+// (0.1 s_L s_C, 0.6 s_L s_R, 0.3 s_C s_R) on the mirrored candidates
+// (2e - 7d + 11c, -d + 5c + 2b, 2c + 5b - a)/6: the pairwise products are
+// shared too. Both quotients come from one reciprocal of the product of the
+// two normalisers (in range for |beta| below ~1e38).
+__host__ __device__ __forceinline__ void weno5_pair(double a, double b, double c, double d, double e, double& qr,
+                                                   double& ql) {
+  constexpr double k13 = 13.0 / 12.0;
+  constexpr double eps = 1.0e-6;
+  const double Db = a - 2.0 * b + c, Dc = b - 2.0 * c + d, Dd = c - 2.0 * d + e;
+  const double dm = c - b, dp = d - c;
+  const double tL = Db + 2.0 * dm, tC = dm + dp, tR = Dd - 2.0 * dp;
+  const double sL = sq(eps + (k13 * Db * Db + 0.25 * tL * tL));
+  const double sC = sq(eps + (k13 * Dc * Dc + 0.25 * tC * tC));
+  const double sR = sq(eps + (k13 * Dd * Dd + 0.25 * tR * tR));
+  const double pCR = sC * sR, pLR = sL * sR, pLC = sL * sC;
+  const double nr = 0.1 * pCR * (2.0 * a - 7.0 * b + 11.0 * c) + 0.6 * pLR * (-b + 5.0 * c + 2.0 * d) +
+                    0.3 * pLC * (2.0 * c + 5.0 * d - e);
+  const double nl = 0.1 * pLC * (2.0 * e - 7.0 * d + 11.0 * c) + 0.6 * pLR * (-d + 5.0 * c + 2.0 * b) +
+                    0.3 * pCR * (2.0 * c + 5.0 * b - a);
+  const double dr = 0.1 * pCR + 0.6 * pLR + 0.3 * pLC;
+  const double dl = 0.1 * pLC + 0.6 * pLR + 0.3 * pCR;
+  const double r = div_nr(1.0, 6.0 * (dr * dl));
+  qr = nr * dl * r;
+  ql = nl * dr * r;
+}
+
+// WENO5-Z at both faces of the centre cell (as weno5_pair): the indicators
+// beta_L, beta_C, beta_R in mirrored roles, tau5 = |beta_L - beta_R| for both
+// faces, e_k = beta_k + 1e-40; the weights of qr are proportional to
+// (0.1 (e_L + tau) e_C e_R, 0.6 (e_C + tau) e_L e_R, 0.3 (e_R + tau) e_L e_C),
+// those of ql to (0.1 (e_R + tau) e_C e_L, 0.6 (e_C + tau) e_L e_R,
+// 0.3 (e_L + tau) e_C e_R).
+__host__ __device__ __forceinline__ void weno5z_pair(double a, double b, double c, double d, double e, double& qr,
+                                                    double& ql) {
+  constexpr double k13 = 13.0 / 12.0;
+  constexpr double eps = 1.0e-40;
+  const double Db = a - 2.0 * b + c, Dc = b - 2.0 * c + d, Dd = c - 2.0 * d + e;
+  const double dm = c - b, dp = d - c;
+  const double tL = Db + 2.0 * dm, tC = dm + dp, tR = Dd - 2.0 * dp;
+  const double bL = k13 * Db * Db + 0.25 * tL * tL;
+  const double bC = k13 * Dc * Dc + 0.25 * tC * tC;
+  const double bR = k13 * Dd * Dd + 0.25 * tR * tR;
+  const double tau = fabs(bL - bR);
+  const double eL = bL + eps, eC = bC + eps, eR = bR + eps;
+  const double pCR = eC * eR, pLR = eL * eR, pLC = eL * eC;
+  const double wLr = 0.1 * (eL + tau) * pCR, wC = 0.6 * (eC + tau) * pLR, wRr = 0.3 * (eR + tau) * pLC;
+  const double wRl = 0.1 * (eR + tau) * pLC, wLl = 0.3 * (eL + tau) * pCR;
+  const double nr = wLr * (2.0 * a - 7.0 * b + 11.0 * c) + wC * (-b + 5.0 * c + 2.0 * d) + wRr * (2.0 * c + 5.0 * d - e);
+  const double nl = wRl * (2.0 * e - 7.0 * d + 11.0 * c) + wC * (-d + 5.0 * c + 2.0 * b) + wLl * (2.0 * c + 5.0 * b - a);
+  const double dr = wLr + wC + wRr;
+  const double dl = wRl + wC + wLl;
+  const double r = div_nr(1.0, 6.0 * (dr * dl));
+  qr = nr * dl * r;
+  ql = nl * dr * r;
+}
+
 // WENO3-JS (Jiang & Shu 1996, r = 2) value at the right face of the centre
 // cell b of the stencil (a, b, c): candidates (3b - a)/2 and (b + c)/2,
 // smoothness indicators (b - a)^2 and (c - b)^2, linear weights (1/3, 2/3),
@@ -157,6 +226,22 @@ __host__ __device__ __forceinline__ double weno3(double a, double b, double c) {
   const double s0 = sq(eps + sq(b - a)), s1 = sq(eps + sq(c - b));
   const double w0 = s1, w1 = 2.0 * s0;  // (1/3)/s0 : (2/3)/s1, times 3 s0 s1
   return div_nr(w0 * (3.0 * b - a) + w1 * (b + c), 2.0 * (w0 + w1));
+}
+
+// WENO3-JS at both faces of the centre cell b of (a, b, c): qr = weno3(a, b, c)
+// at the right face and ql = weno3(c, b, a) at the left face, sharing the two
+// indicators: s0 = (1e-6 + (b - a)^2)^2 and s1 = (1e-6 + (c - b)^2)^2 weigh
+// the candidates (3b - a, b + c)/2 of qr as (s1, 2 s0) and (3b - c, b + a)/2
+// of ql as (s0, 2 s1).
+__host__ __device__ __forceinline__ void weno3_pair(double a, double b, double c, double& qr, double& ql) {
+  constexpr double eps = 1.0e-6;
+  const double s0 = sq(eps + sq(b - a)), s1 = sq(eps + sq(c - b));
+  const double nr = s1 * (3.0 * b - a) + 2.0 * s0 * (b + c);
+  const double nl = s0 * (3.0 * b - c) + 2.0 * s1 * (b + a);
+  const double dr = s1 + 2.0 * s0, dl = s0 + 2.0 * s1;
+  const double r = div_nr(1.0, 2.0 * (dr * dl));
+  qr = nr * dl * r;
+  ql = nl * dr * r;
 }
 
 // Rusanov (local Lax-Friedrichs) flux of §7.4 across a face normal to axis D
@@ -283,9 +368,11 @@ __host__ __device__ __forceinline__ void face_tangential(const FaceWindow& w, do
 // window's cells 1..4 (velocities and T~ for the fourth-order normal
 // derivatives and the face velocities) and the face values tf of the
 // tangential derivatives.
+// The same from the primitives q[0..3] and T~[0..3] of the four cells i-1 ..
+// i+2 around the face i+1/2.
 template <int D>
-__host__ __device__ __forceinline__ void sub_dissipative(const Geom& g, const FaceWindow& w, const double* tf,
-                                                         double* F) {
+__host__ __device__ __forceinline__ void sub_dissipative_q(const Geom& g, const double (*q)[5], const double* T,
+                                                           const double* tf, double* F) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   if (g.viscous || g.heat) {
     const double i24 = g.idx[D] / 24.0;
@@ -293,28 +380,34 @@ __host__ __device__ __forceinline__ void sub_dissipative(const Geom& g, const Fa
     double Fd1 = 0.0, Fd2 = 0.0, Fd3 = 0.0, Fd4 = 0.0;  // slots D, T1, T2 momentum; energy
     if (g.viscous) {
       // normal derivatives of the three velocity components
-      const double dD = dn(w.q[1][1 + D], w.q[2][1 + D], w.q[3][1 + D], w.q[4][1 + D]);
-      const double d1 = dn(w.q[1][1 + T1], w.q[2][1 + T1], w.q[3][1 + T1], w.q[4][1 + T1]);
-      const double d2 = dn(w.q[1][1 + T2], w.q[2][1 + T2], w.q[3][1 + T2], w.q[4][1 + T2]);
+      const double dD = dn(q[0][1 + D], q[1][1 + D], q[2][1 + D], q[3][1 + D]);
+      const double d1 = dn(q[0][1 + T1], q[1][1 + T1], q[2][1 + T1], q[3][1 + T1]);
+      const double d2 = dn(q[0][1 + T2], q[1][1 + T2], q[2][1 + T2], q[3][1 + T2]);
       const double uD_t1 = tf[0], u1_t1 = tf[1], uD_t2 = tf[2], u2_t2 = tf[3];
       const double div = dD + u1_t1 + u2_t2;
       const double tDD = g.mu * (dD + dD) - (2.0 / 3.0) * g.mu * div;
       const double tD1 = g.mu * (uD_t1 + d1);
       const double tD2 = g.mu * (uD_t2 + d2);
-      const double ufD = rc4(w.q[1][1 + D], w.q[2][1 + D], w.q[3][1 + D], w.q[4][1 + D]);
-      const double uf1 = rc4(w.q[1][1 + T1], w.q[2][1 + T1], w.q[3][1 + T1], w.q[4][1 + T1]);
-      const double uf2 = rc4(w.q[1][1 + T2], w.q[2][1 + T2], w.q[3][1 + T2], w.q[4][1 + T2]);
+      const double ufD = rc4(q[0][1 + D], q[1][1 + D], q[2][1 + D], q[3][1 + D]);
+      const double uf1 = rc4(q[0][1 + T1], q[1][1 + T1], q[2][1 + T1], q[3][1 + T1]);
+      const double uf2 = rc4(q[0][1 + T2], q[1][1 + T2], q[2][1 + T2], q[3][1 + T2]);
       Fd1 = tDD;
       Fd2 = tD1;
       Fd3 = tD2;
       Fd4 = ufD * tDD + uf1 * tD1 + uf2 * tD2;
     }
-    if (g.heat) Fd4 += g.kappa * dn(w.T[0], w.T[1], w.T[2], w.T[3]);
+    if (g.heat) Fd4 += g.kappa * dn(T[0], T[1], T[2], T[3]);
     F[1 + D] -= Fd1;
     F[1 + T1] -= Fd2;
     F[1 + T2] -= Fd3;
     F[4] -= Fd4;
   }
+}
+
+template <int D>
+__host__ __device__ __forceinline__ void sub_dissipative(const Geom& g, const FaceWindow& w, const double* tf,
+                                                         double* F) {
+  sub_dissipative_q<D>(g, w.q + 1, w.T, tf, F);
 }
 
 template <int D, bool RUS = false, bool NN = false>
@@ -450,6 +543,39 @@ __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceW
     }
   }
   face_flux_lr<D, sch_rusanov(SCH), SCH == SCH_W3_NN>(g, WL, WR, w, tf, G);
+}
+
+// Reconstructed states of the cell-centred schemes (every scheme but the Roe
+// flux splitting, whose projection depends on the face): from the primitives
+// q[0..4] of cells i-2 .. i+2, the left state of face i+1/2 (qr) and the right
+// state of face i-1/2 (ql), per variable.
+template <int SCH>
+__host__ __device__ __forceinline__ void recon_pair(const double (*q)[5], double* qr, double* ql) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    if constexpr (sch_weno3(SCH)) weno3_pair(q[1][v], q[2][v], q[3][v], qr[v], ql[v]);
+    else if constexpr (SCH == SCH_Z) weno5z_pair(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], qr[v], ql[v]);
+    else weno5_pair(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], qr[v], ql[v]);
+  }
+}
+
+// Numerical flux G = F - F^d across face i+1/2 (§3.3, §3.4) from its
+// reconstructed states WL, WR, the primitives q[0..3] and T~[0..3] of cells
+// i-1 .. i+2, the face values tf of the tangential derivatives and, for the
+// Rusanov-NN flux, the face's alpha.
+template <int D, int SCH>
+__host__ __device__ __forceinline__ void face_flux_states(const Geom& g, const double* WL, const double* WR,
+                                                          const double (*q)[5], const double* T, const double* tf,
+                                                          double alpha, double* G) {
+  double F[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (g.inviscid) {
+    if constexpr (SCH == SCH_W3_NN) rusanov<D, true>(g.gamma, g.gm1i, WL, WR, F, alpha);
+    else if constexpr (sch_rusanov(SCH)) rusanov<D>(g.gamma, g.gm1i, WL, WR, F);
+    else hllc<D>(g.gamma, g.gm1i, WL, WR, F);
+  }
+  sub_dissipative_q<D>(g, q, T, tf, F);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) G[v] = F[v];
 }
 
 // Numerical flux G = F - F^d across the face (§3.3, §3.4) from a full window.
