@@ -69,12 +69,19 @@ typedef enum { CFD_BC_PERIODIC = 0, CFD_BC_ZERO_GRADIENT = 1, CFD_BC_REFLECT = 2
  * weights cfd_set_nn_weights supplies; it needs CFD_F_WENO3.
  * CFD_F_ROE combines with none of WENOZ, WENO3, RUSANOV, and CFD_F_WENOZ with
  * neither WENO3 nor RUSANOV; CFD_F_RUSANOV_NN with none of ROE, WENOZ,
- * RUSANOV (CFD_EINVAL). The adjoint covers the default scheme and WENO3-JS
- * with the Rusanov-NN flux (inviscid), each with TVD-RK3 or TVD-RK2; the
- * serving batch the default scheme with any boundaries. */
+ * RUSANOV (CFD_EINVAL). CFD_F_SAFE_RECON is the safe reconstruction the
+ * paper's setup file switches on (Appendix A, is_safe_reconstruction; not
+ * defined in the paper; reading): at a face where a reconstructed state has
+ * rho <= 0 or p <= 0, both states take the values of the two cells next to the
+ * face (first order); not with ROE (CFD_EINVAL). Without the flag such faces
+ * keep their states (the Riemann solver's sound speed is then undefined);
+ * either way cfd_check reports them. The adjoint covers the default scheme
+ * and WENO3-JS with the Rusanov-NN flux (inviscid), each with TVD-RK3 or
+ * TVD-RK2, without safe reconstruction; the serving batch the default scheme
+ * with any boundaries. */
 enum {
   CFD_F_INVISCID = 1u, CFD_F_VISCOUS = 2u, CFD_F_HEAT = 4u, CFD_F_WENOZ = 8u, CFD_F_ROE = 16u, CFD_F_WENO3 = 32u,
-  CFD_F_RUSANOV = 64u, CFD_F_RK2 = 128u, CFD_F_RUSANOV_NN = 256u
+  CFD_F_RUSANOV = 64u, CFD_F_RK2 = 128u, CFD_F_RUSANOV_NN = 256u, CFD_F_SAFE_RECON = 512u
 };
 
 /* Number of Rusanov-NN weights: W1 (32 x 4, row-major), b1 (32), W2 (32 x 32),
@@ -227,9 +234,12 @@ cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const do
  * Within a run of steps the primitive pass runs once, before the first step. */
 cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, double* ms_out, void* stream);
 
-/* Synchronise the solver's last stream use and report its health word:
- * bit 0 a non-finite conservative value, bit 1 rho <= 0, bit 2 p <= 0, seen
- * at the start of any step since the previous cfd_check (which clears it). */
+/* Synchronise the solver's last stream use and report its health word since
+ * the previous cfd_check (which clears it): bit 0 a non-finite conservative
+ * value, bit 1 rho <= 0, bit 2 p <= 0, in a state a step started from or
+ * produced (its stage states included); bit 3 a face whose reconstructed
+ * state had rho <= 0 or p <= 0 (any step or right-hand side; the Roe flux
+ * splitting reconstructs characteristic fields and reports none). */
 cfd_status cfd_check(cfd_solver* s, int32_t* status_out);
 
 /* Allocation-free TVD-RK3 step, for callers that cannot allocate device

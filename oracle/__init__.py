@@ -80,6 +80,8 @@ def _load():
     lib.oracle_opcount.argtypes = [cfgp, dp, dp]
     lib.oracle_opcount_parts.argtypes = [cfgp, dp, dp]
     lib.oracle_vjp_rhs.argtypes = [cfgp, dp, dp, dp]
+    lib.oracle_status.argtypes = [C.c_int]
+    lib.oracle_status.restype = C.c_int
     lib.oracle_vjp_state_init.argtypes = [cfgp, dp, dp, dp]
     lib.oracle_vjp_rk3_step.argtypes = [cfgp, dp, d, dp, dp]
     lib.oracle_grad_ke.argtypes = [cfgp, dp, C.c_int, d, dp, dp]
@@ -195,6 +197,14 @@ def advance(case, U, n_steps, t_end=0.0, fixed_dt=0.0, t=0.0):
     if n < 0:
         raise ValueError("oracle rejected the configuration")
     return U, tt.value, int(n)
+
+
+def status(clear=True):
+    """Health word of the calling thread since the last clear: bit 0 a
+    non-finite conservative value, bit 1 rho <= 0, bit 2 p <= 0 in a step's
+    input, stage or output state; bit 3 a reconstructed face state with
+    rho <= 0 or p <= 0."""
+    return int(_load().oracle_status(1 if clear else 0))
 
 
 def weno5(a, b, c, d, e):

@@ -38,7 +38,9 @@ typedef struct {
   uint32_t flags;      // 1 inviscid flux, 2 viscous flux, 4 heat flux, 8 WENO5-Z reconstruction,
                        // 16 Roe flux splitting in characteristic space (the paper's ROE setup),
                        // 32 WENO3-JS reconstruction, 64 Rusanov flux, 128 TVD-RK2 time integration,
-                       // 256 Rusanov-NN flux (Rusanov with the learned dissipation of §7.4)
+                       // 256 Rusanov-NN flux (Rusanov with the learned dissipation of §7.4),
+                       // 512 safe reconstruction (first-order states at faces whose
+                       // reconstructed rho or p is not positive)
 } oracle_cfg;
 }
 
@@ -47,7 +49,7 @@ namespace oracle {
 enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_REFLECT = 2 };
 enum : uint32_t {
   F_INVISCID = 1u, F_VISCOUS = 2u, F_HEAT = 4u, F_WENOZ = 8u, F_ROE = 16u, F_WENO3 = 32u, F_RUSANOV = 64u,
-  F_RK2 = 128u, F_RUSANOV_NN = 256u
+  F_RK2 = 128u, F_RUSANOV_NN = 256u, F_SAFE_RECON = 512u
 };
 
 // --------------------------------------------------------------------------
@@ -119,6 +121,19 @@ void fill_halo(const oracle_cfg& c, const Grid& g, std::vector<R>& U) {
           }
         }
   }
+}
+
+// --------------------------------------------------------------------------
+// Health word of the calling thread, OR-accumulated by the solver and read
+// (and cleared) through oracle_status: bit 0 a non-finite conservative value,
+// bit 1 rho <= 0, bit 2 p <= 0, in a state a step starts from or produces
+// (stage states included); bit 3 a reconstructed face state with rho <= 0 or
+// p <= 0, where the Riemann solver's sound speed is undefined. Appendix A
+// names an "is_safe_reconstruction" switch for this situation without
+// defining it; the reading here flags such faces and repairs nothing.
+inline int& health_word() {
+  static thread_local int h = 0;
+  return h;
 }
 
 // --------------------------------------------------------------------------
@@ -261,7 +276,7 @@ R nn_alpha(const R* th, const R f[NN_IN]) {
 // evaluate the Rusanov-NN flux (the taped entry points hold them as leaves).
 template <class R>
 const R*& nn_weights() {
-  static const R* w = nullptr;
+  static thread_local const R* w = nullptr;
   return w;
 }
 
@@ -611,6 +626,18 @@ void face_flux(const oracle_cfg& c, const Grid& g, const Prims<R>& W, int d, con
         WR[v] = weno5_js(at(3), at(2), at(1), at(0), at(-1));
       }
     }
+    if (!(val(WL[0]) > 0.0) || !(val(WL[4]) > 0.0) || !(val(WR[0]) > 0.0) || !(val(WR[4]) > 0.0)) {
+      health_word() |= 8;
+      // safe reconstruction (Appendix A's is_safe_reconstruction; reading:
+      // both states of the face fall back to the values of the two cells next
+      // to it, the first-order reconstruction)
+      if (c.flags & F_SAFE_RECON)
+        for (int v = 0; v < 5; ++v) {
+          const std::vector<R>& s = *q[v];
+          WL[v] = s[g.shift(d, a[0], a[1], a[2], 0)];
+          WR[v] = s[g.shift(d, a[0], a[1], a[2], 1)];
+        }
+    }
     if (c.flags & F_RUSANOV_NN) rusanov_nn_flux(c.gamma, WL, WR, d, nn_weights<R>(), Fc);
     else if (c.flags & F_RUSANOV) rusanov_flux(c.gamma, WL, WR, d, Fc);
     else hllc_flux(c.gamma, WL, WR, d, Fc);
@@ -714,6 +741,26 @@ inline double cfl_dt(const oracle_cfg& c, const Grid& g, const std::vector<doubl
 // integrates with TVD-RK2):
 //   U1   = Un + dt R(Un)
 //   Un+1 = 1/2 Un + 1/2 (U1 + dt R(U1))
+// Bits 0-2 of the health word for the interior cells of a state.
+template <class R>
+void note_health(const oracle_cfg& c, const Grid& g, const std::vector<R>& U) {
+  int bad = 0;
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        const long q = g.at(i, j, k);
+        double u[5];
+        for (int v = 0; v < 5; ++v) u[v] = val(U[(long)v * g.ncell + q]);
+        if (!std::isfinite(u[0]) || !std::isfinite(u[1]) || !std::isfinite(u[2]) || !std::isfinite(u[3]) ||
+            !std::isfinite(u[4]))
+          bad |= 1;
+        if (!(u[0] > 0.0)) bad |= 2;
+        const double kin = 0.5 * (u[1] * (u[1] / u[0]) + u[2] * (u[2] / u[0]) + u[3] * (u[3] / u[0]));
+        if (!((c.gamma - 1.0) * (u[4] - kin) > 0.0)) bad |= 4;
+      }
+  health_word() |= bad;
+}
+
 template <class R>
 void rk3_step(const oracle_cfg& c, const Grid& g, std::vector<R>& U, double dt) {
   std::vector<R> Un = U, U1 = U, U2 = U, Rh;
@@ -723,18 +770,23 @@ void rk3_step(const oracle_cfg& c, const Grid& g, std::vector<R>& U, double dt) 
         for (int j = 0; j < g.n[1]; ++j)
           for (int i = 0; i < g.n[0]; ++i) body((long)v * g.ncell + g.at(i, j, k));
   };
+  note_health(c, g, Un);
   rhs(c, g, Un, Rh);
   interior([&](long q) { U1[q] = Un[q] + dt * Rh[q]; });
+  note_health(c, g, U1);
   if (c.flags & F_RK2) {
     rhs(c, g, U1, Rh);
     interior([&](long q) { U[q] = 0.5 * Un[q] + 0.5 * (U1[q] + dt * Rh[q]); });
+    note_health(c, g, U);
     fill_halo(c, g, U);
     return;
   }
   rhs(c, g, U1, Rh);
   interior([&](long q) { U2[q] = 0.75 * Un[q] + 0.25 * (U1[q] + dt * Rh[q]); });
+  note_health(c, g, U2);
   rhs(c, g, U2, Rh);
   interior([&](long q) { U[q] = (1.0 / 3.0) * Un[q] + (2.0 / 3.0) * (U2[q] + dt * Rh[q]); });
+  note_health(c, g, U);
   fill_halo(c, g, U);
 }
 
@@ -886,6 +938,13 @@ int oracle_advance(const oracle_cfg* c, double* U, int n_steps, double t_end, do
   std::memcpy(U, u.data(), sizeof(double) * u.size());
   if (t) *t = time;
   return taken;
+}
+
+// The calling thread's health word (see health_word); clear != 0 resets it.
+int oracle_status(int clear) {
+  const int h = health_word();
+  if (clear) health_word() = 0;
+  return h;
 }
 
 // Single-face building blocks, for unit tests of the method's pieces.

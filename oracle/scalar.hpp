@@ -38,7 +38,7 @@ struct OpTally {
   double add = 0, mul = 0, div = 0, sqrt = 0, cmp = 0;
 };
 inline OpTally& tally() {
-  static OpTally t;
+  static thread_local OpTally t;
   return t;
 }
 
@@ -89,7 +89,7 @@ struct Tape {
   }
 };
 inline Tape*& active_tape() {
-  static Tape* t = nullptr;
+  static thread_local Tape* t = nullptr;
   return t;
 }
 

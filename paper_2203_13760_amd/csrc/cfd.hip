@@ -102,7 +102,9 @@ static cfd_status validate(const cfd_config* c) {
   if (!(c->mu >= 0.0)) return fail(CFD_EINVAL, "mu must be >= 0");
   if (!(c->prandtl > 0.0)) return fail(CFD_EINVAL, "prandtl must be > 0");
   if (!(c->cfl > 0.0 && c->cfl <= 1.0)) return fail(CFD_EINVAL, "cfl must lie in (0, 1]");
-  if (c->flags & ~511u) return fail(CFD_EINVAL, "unknown physics flag");
+  if (c->flags & ~1023u) return fail(CFD_EINVAL, "unknown physics flag");
+  if ((c->flags & CFD_F_SAFE_RECON) && (c->flags & CFD_F_ROE))
+    return fail(CFD_EINVAL, "safe reconstruction applies to reconstructed primitives (flag SAFE_RECON with ROE)");
   if ((c->flags & CFD_F_RUSANOV_NN) &&
       ((c->flags & (CFD_F_ROE | CFD_F_WENOZ | CFD_F_RUSANOV)) || !(c->flags & CFD_F_WENO3)))
     return fail(CFD_EINVAL, "the Rusanov-NN flux runs with WENO3-JS (flag RUSANOV_NN needs WENO3, without ROE, WENOZ, RUSANOV)");
@@ -156,6 +158,7 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.rk2 = (c.flags & CFD_F_RK2) ? 1 : 0;
   g.seg = kSeg;
   g.nn = (c.flags & CFD_F_RUSANOV_NN) ? 1 : 0;
+  g.safe = (c.flags & CFD_F_SAFE_RECON) ? 1 : 0;
   g.viscous = ((c.flags & CFD_F_VISCOUS) && c.mu > 0.0) ? 1 : 0;
   g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
 }
@@ -356,7 +359,7 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   io.a = 0.0;
   io.b = 1.0;
   io.Pn = s->Pb[1];
-  io.what = 0;
+  io.what = PRIM_HEALTH;  // health bits of every stage state
   if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
   if (s->g.rk2) {
     // TVD-RK2, second stage: Un+1 = 1/2 Un + 1/2 (U1 + dt R(U1)), in place on U
@@ -533,11 +536,11 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
 // Rusanov-NN flux (inviscid), with TVD-RK3 or TVD-RK2 and any boundaries.
 static bool adjoint_supported(const cfd_solver* s) {
   const Geom& g = s->g;
-  if (g.wenoz || g.roe || g.rusanov) return false;
+  if (g.wenoz || g.roe || g.rusanov || g.safe) return false;
   if (g.nn) return !g.viscous && !g.heat;
   return !g.weno3;
 }
-#define CFD_ADJ_SCOPE "the adjoint covers WENO5-JS + HLLC and WENO3-JS + Rusanov-NN (inviscid)"
+#define CFD_ADJ_SCOPE "the adjoint covers WENO5-JS + HLLC and WENO3-JS + Rusanov-NN (inviscid), without safe reconstruction"
 
 // ===========================================================================
 extern "C" {
@@ -636,6 +639,7 @@ cfd_status cfd_rhs(cfd_solver* s, double* U, double* R, void* stream) {
   StageIO io{};
   io.R = R;
   io.dtp = nullptr;
+  io.ctl = s->ctl;  // faces with non-positive reconstructed states
   return enqueue_fluxes(s, s->P, io, false, st);
 }
 

@@ -111,7 +111,7 @@ __device__ __forceinline__ void batch_item(const BatchTable* __restrict__ tab, i
     io.Pn = w.Pb[STAGE % 3];
     io.partial = w.partial;
     io.ctl = w.ctl;
-    io.what = STAGE == 3 ? (PRIM_HEALTH | PRIM_CFL) : 0;
+    io.what = STAGE == 3 ? (PRIM_HEALTH | PRIM_CFL) : PRIM_HEALTH;
     const double* P = w.Pb[STAGE - 1];
     if (PHASE == PH_PRIM) {
       const int by = local / w.pgx;

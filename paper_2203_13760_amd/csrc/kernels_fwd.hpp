@@ -252,6 +252,29 @@ __device__ __forceinline__ void cons_to_prim(const Geom& g, const double* q, dou
   w[5] = w[4] * ir;
 }
 
+// Health bits of a cell: 1 non-finite conservative value, 2 rho <= 0, 4 p <= 0;
+// and of a face: 8 a reconstructed state with rho <= 0 or p <= 0.
+constexpr int kBadFace = 8;
+
+// Face check of the cell-centred schemes: a reconstructed state of the face
+// with a non-positive (or non-finite) density or pressure sets kBadFace in
+// bad; with safe reconstruction both states then take the values of the two
+// cells next to the face (qa left, qb right: the first-order reconstruction).
+__device__ __forceinline__ void check_face_states(const Geom& g, bool use, double* WL, double* WR,
+                                                  const double* qa, const double* qb, int& bad) {
+  const bool ok = WL[0] > 0.0 && WL[4] > 0.0 && WR[0] > 0.0 && WR[4] > 0.0;
+  if (use && !ok) {
+    bad |= kBadFace;
+    if (g.safe) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        WL[v] = qa[v];
+        WR[v] = qb[v];
+      }
+    }
+  }
+}
+
 // Health bits of a cell: 1 non-finite conservative value, 2 rho <= 0, 4 p <= 0.
 __device__ __forceinline__ int health_bits(const double* q, double p) {
   int bad = 0;
@@ -628,6 +651,7 @@ __device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, 
       recon_pair<SCH>(q, qr, WR);
 #pragma unroll
       for (int v = 0; v < 5; ++v) WL[v] = lane_shr1(qr[v]);
+      check_face_states(g, valid, WL, WR, q[1], q[2], bad);
     }
     double alpha = 0.0;
     if constexpr (SCH == SCH_W3_NN) alpha = g.nna[c0 + 1];  // alpha of face f (left cell f-1)
@@ -647,6 +671,7 @@ __device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, 
     }
   }
   if (PN) finish_prims(io, smax, bad);
+  else if (bad && io.ctl) atomicOr(&io.ctl->status, bad);
 }
 
 template <int MODE, bool PN = false, int SCH = SCH_JS>
@@ -861,14 +886,20 @@ __device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__
     double alpha = 0.0;
     if constexpr (SCH == SCH_W3_NN) alpha = g.nna[AX * g.vs + c + st];  // face f+1/2, left cell f
     double WR[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, qr[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (g.inviscid) recon_pair<SCH>(q, qr, WR);  // cell f+1: left state of face f+3/2, right state of f+1/2
+    double WL[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) WL[v] = WLc[v];
+    if (g.inviscid) {
+      recon_pair<SCH>(q, qr, WR);  // cell f+1: left state of face f+3/2, right state of f+1/2
+      check_face_states(g, true, WL, WR, q[1], q[2], bad);
+    }
     double tf[4] = {0.0, 0.0, 0.0, 0.0};
     if (g.viscous) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) tf[v] = rc4(tg[0][v], tg[1][v], tg[2][v], tg[3][v]);
     }
     double G[5];
-    face_flux_states<AX, SCH>(g, WLc, WR, q, T, tf, alpha, G);
+    face_flux_states<AX, SCH>(g, WL, WR, q, T, tf, alpha, G);
     if (f >= s0 && in) {
       double D[5];
 #pragma unroll
@@ -904,6 +935,7 @@ __device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__
     }
   }
   if (PN) finish_prims(io, smax, bad);
+  else if (bad && io.ctl) atomicOr(&io.ctl->status, bad);
 }
 
 template <int AX, int MODE, bool PN = false, int SCH = SCH_JS>

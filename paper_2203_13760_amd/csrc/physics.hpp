@@ -36,6 +36,7 @@ struct Geom {
   int rk2;         // TVD-RK2 instead of TVD-RK3
   int seg;         // cells per lane of the y / z marches
   int nn;          // Rusanov-NN flux (with WENO3-JS): alpha per face from nna
+  int safe;        // safe reconstruction: first-order states at faces with a non-positive rho or p
   const double* nnw;  // Rusanov-NN network weights (device, 2305 values)
   double* nna;        // Rusanov-NN alpha per face, [3][padded cells] at the face's left cell
 };

@@ -27,6 +27,7 @@ WENO3 = 32
 RUSANOV = 64
 RK2 = 128
 RUSANOV_NN = 256
+SAFE_RECON = 512  # first-order states at faces whose reconstructed rho or p is not positive
 NN_PARAMS = 2305  # Rusanov-NN weights: W1 (32x4), b1, W2 (32x32), b2, W3 (32x32), b3, W4 (1x32), b4
 ALL_PHYSICS = INVISCID | VISCOUS | HEAT
 

@@ -69,7 +69,8 @@ BAD_CONFIGS = [
     ("prandtl", dict(prandtl=0.0), "prandtl"),
     ("cfl zero", dict(cfl=0.0), "cfl"),
     ("cfl above one", dict(cfl=1.5), "cfl"),
-    ("unknown flag", dict(flags=512), "flag"),
+    ("unknown flag", dict(flags=1024), "flag"),
+    ("safe reconstruction with roe", dict(flags=1 | 16 | 512), "SAFE_RECON"),
     ("rusanov-nn without weno3", dict(flags=1 | 256), "Rusanov-NN"),
     ("rusanov-nn with rusanov", dict(flags=1 | 32 | 64 | 256), "Rusanov-NN"),
     ("rusanov-nn with roe", dict(flags=1 | 16 | 32 | 256), "Rusanov-NN"),

@@ -651,3 +651,84 @@ def test_random_configurations_match_oracle(Solver, k):
         e = normwise(U.cpu().numpy(), Uo1)
         s.close()
         assert e <= TOL_ONE, (k, t, case, e)
+
+
+# ---------------------------------------------------------------- non-positive reconstructed states
+# Random blocks against reflecting walls: next to a wall WENO5-JS reconstructs
+# negative pressures at some faces. Both sides report such faces (health bit
+# 3); without safe reconstruction the flux there is undefined (the oracle and
+# the device resolve the undefined sound speed differently), with it (flag
+# 512, Appendix A's is_safe_reconstruction, reading: first-order states at
+# those faces) the results are defined and match.
+def _walled_blocks(flags):
+    case, W = wl.random_shocky((21, 19, 17), seed=13)
+    case = dict(case)
+    case["bc"] = (wl.PERIODIC, wl.PERIODIC) + (wl.REFLECT,) * 4
+    case["flags"] = flags
+    return case, W
+
+
+def test_nonpositive_reconstruction_is_reported_on_both_sides(Solver):
+    case, W = _walled_blocks(wl.INVISCID)
+    _say("non-positive reconstructed states: reported, random blocks at walls")
+    s = Solver(case)
+    U = s.init(W)
+    s.rhs(U)
+    st_rhs = s.check()
+    s.step(U)
+    st_step = s.check()
+    s.close()
+    oracle.status()
+    oracle.rhs(case, oracle.state_init(case, W))
+    so_rhs = oracle.status()
+    oracle.rk3_step(case, oracle.state_init(case, W))
+    so_step = oracle.status()
+    assert st_rhs & 8 and so_rhs & 8, (st_rhs, so_rhs)
+    assert st_step & 8 and so_step & 8, (st_step, so_step)
+
+
+def test_safe_reconstruction_matches_oracle(Solver):
+    case, W = _walled_blocks(wl.INVISCID | wl.SAFE_RECON)
+    _say("safe reconstruction: rhs, one step and 10 steps, random blocks at walls")
+    s = Solver(case)
+    U = s.init(W)
+    R = s.rhs(U).cpu().numpy()
+    assert s.check() & 8
+    Uo = oracle.state_init(case, W)
+    oracle.status()
+    Ro = oracle.rhs(case, Uo)
+    assert oracle.status() & 8
+    bound = oracle.rhs_rounding_bound(case, Uo)
+    for v in range(5):
+        err = float(np.max(np.abs(R[v] - Ro[v])))
+        assert err <= max(TOL_ONE * float(np.max(np.abs(Ro[v]))), bound[v]), (v, err, bound[v])
+    dt = s.step(U)
+    Uo1, dto = oracle.rk3_step(case, Uo)
+    assert abs(float(dt.item()) - dto) <= 1e-14 * dto
+    assert normwise(U.cpu().numpy(), Uo1) <= TOL_ONE
+    s.advance(U, 9)
+    st = s.check()
+    s.close()
+    oracle.status()
+    Uo10, _, _ = oracle.advance(case, Uo1, 9)
+    so = oracle.status()
+    # first-order states at the flagged faces keep every stage state physical
+    assert st & 7 == 0 and so & 7 == 0, (st, so)
+    assert normwise(U.cpu().numpy(), Uo10) <= TOL_100
+
+
+def test_roe_negative_stage_pressure_is_reported_on_both_sides(Solver):
+    """The Roe flux splitting has no positivity guarantee: on random blocks of
+    an x-z grid its first stage leaves a negative pressure. The health word of
+    both sides covers the stage states and reports it (bit 2)."""
+    case, W = _roe(CASES["shocky_xz"])
+    _say("ROE on random blocks: negative stage pressure reported")
+    s = Solver(case)
+    U = s.init(W)
+    s.step(U)
+    st = s.check()
+    s.close()
+    oracle.status()
+    oracle.rk3_step(case, oracle.state_init(case, W))
+    so = oracle.status()
+    assert st & 4 and so & 4, (st, so)

@@ -378,3 +378,69 @@ def test_cfl_step_3d_hand_values():
     assert abs(run(W3, 5.0, 0.72, wl.HEAT | wl.INVISCID) - 0.5 / sv3) <= 1e-15
     # below the crossover the convective rate decides
     assert abs(run(W, 0.01, 0.72, wl.ALL_PHYSICS) - 0.5 / s) <= 1e-15
+
+
+# ------------------------------------------------------ safe reconstruction -
+def _pocket_case(flags):
+    """1D periodic pressure pocket: p = 3 with two cells at 0.1, rho = 1,
+    u = 0.2. WENO5-JS across the pocket reconstructs a negative pressure
+    (the stencil (3, 3, 0.1, 0.1, 3) gives about -0.42 at the right face of
+    its centre cell)."""
+    n = 16
+    case = wl.make_case((n, 1, 1), flags=flags)
+    W = np.zeros((5, 1, 1, n))
+    W[0] = 1.0
+    W[1] = 0.2
+    W[4] = 3.0
+    W[4, 0, 0, 6:8] = 0.1
+    return case, W
+
+
+def test_safe_reconstruction_first_order_at_flagged_faces():
+    """Reading of Appendix A's is_safe_reconstruction (flag 512): at a face
+    whose WENO5-JS states have rho <= 0 or p <= 0, both states fall back to
+    the two adjacent cell values; the health word's bit 3 records such faces
+    with or without the flag. The right-hand side is rebuilt here face by
+    face from the pinned WENO5-JS value and HLLC flux."""
+    case, W = _pocket_case(wl.INVISCID | 512)
+    n, g = case["n"][0], case["gamma"]
+    dx = 1.0 / n
+    U = oracle.state_init(case, W)
+    oracle.status()
+    R = oracle.interior(case, oracle.rhs(case, U)).reshape(5, n)
+    assert oracle.status() & 8
+    q = W.reshape(5, n)
+    F = np.zeros((n, 5))  # F[i]: flux at the face between cells i and i+1 (periodic)
+    flagged = 0
+    for i in range(n):
+        st = [q[:, (i + o) % n] for o in (-2, -1, 0, 1, 2, 3)]
+        WL = np.array([oracle.weno5(*[s[v] for s in st[0:5]]) for v in range(5)])
+        WR = np.array([oracle.weno5(*[s[v] for s in st[5:0:-1]]) for v in range(5)])
+        if min(WL[0], WL[4], WR[0], WR[4]) <= 0.0:
+            WL, WR = st[2].copy(), st[3].copy()
+            flagged += 1
+        F[i] = oracle.hllc(g, WL, WR, 0)
+    assert flagged >= 1
+    want = -(F - np.roll(F, 1, axis=0)).T / dx
+    np.testing.assert_allclose(R, want, rtol=0, atol=1e-12 * np.max(np.abs(want)))
+    # without the flag the flagged faces keep their non-physical states: the
+    # health word still reports them and the result differs there
+    case0, _ = _pocket_case(wl.INVISCID)
+    oracle.status()
+    R0 = oracle.interior(case0, oracle.rhs(case0, oracle.state_init(case0, W))).reshape(5, n)
+    assert oracle.status() & 8
+    assert np.max(np.abs(R0 - R)) > 1e-3
+
+
+def test_health_word_of_stage_states():
+    """Bits 0-2 of the health word cover every state of a step (input, stages,
+    output): a state with a negative pressure in one cell is reported by the
+    step that starts from it, and a clean run reports nothing."""
+    case, W = wl.sod(50)
+    oracle.status()
+    oracle.rk3_step(case, oracle.state_init(case, W))
+    assert oracle.status() == 0
+    W2 = W.copy()
+    W2[4, 0, 0, 10] = -0.5
+    oracle.rk3_step(case, oracle.state_init(case, W2))
+    assert oracle.status() & 4
