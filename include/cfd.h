@@ -246,9 +246,9 @@ cfd_status cfd_check(cfd_solver* s, int32_t* status_out);
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation): cfd_rk3_step of U in place for the configuration cfg,
  * with no solver handle and no device allocation or free. Its scratch (CFL
- * slots, control block, two stage states, the right-hand-side accumulator and
- * three primitive buffers: 33 doubles per padded cell) is one static device
- * array of 96 MiB, allocated with the library on every device it runs on and
+ * slots, control block, two stage states, two right-hand-side accumulators and
+ * three primitive buffers: 38 doubles per padded cell) is one static device
+ * array of 112 MiB, allocated with the library on every device it runs on and
  * held until the process ends; the grid may have at most
  * CFD_NOALLOC_MAX_PADDED_CELLS padded cells (CFD_EINVAL otherwise, before any
  * device work). dt > 0 fixes the step, dt <= 0 takes the CFL step of U;
@@ -257,7 +257,7 @@ cfd_status cfd_check(cfd_solver* s, int32_t* status_out);
  * array: calls that overlap on one device (other streams, other threads)
  * race and give undefined results. The Rusanov-NN flux is not taken
  * (CFD_EUNSUPPORTED). */
-#define CFD_NOALLOC_MAX_PADDED_CELLS 381291
+#define CFD_NOALLOC_MAX_PADDED_CELLS 386309
 cfd_status cfd_rk3_step_noalloc(const cfd_config* cfg, double* U, double dt, double* dt_used_dev, void* stream);
 
 /* Message of the last failure on this thread ("" if none). */

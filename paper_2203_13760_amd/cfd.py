@@ -20,7 +20,7 @@ CFD_BC_PERIODIC, CFD_BC_ZERO_GRADIENT, CFD_BC_REFLECT = 0, 1, 2
 CFD_F_INVISCID, CFD_F_VISCOUS, CFD_F_HEAT, CFD_F_WENOZ, CFD_F_ROE = 1, 2, 4, 8, 16
 CFD_F_WENO3, CFD_F_RUSANOV, CFD_F_RK2, CFD_F_RUSANOV_NN, CFD_F_SAFE_RECON = 32, 64, 128, 256, 512
 CFD_NN_PARAMS = 2305
-CFD_NOALLOC_MAX_PADDED_CELLS = 381291
+CFD_NOALLOC_MAX_PADDED_CELLS = 386309
 
 
 class CfdError(RuntimeError):

@@ -66,6 +66,7 @@ struct cfd_solver {
   double* P = nullptr;    // 6 x padded (= Pb[0])
   double* Pb[3] = {nullptr, nullptr, nullptr};  // primitives of the stage inputs of a step
   double* Racc = nullptr; // 5 x padded
+  double* Racc2 = nullptr; // 5 x padded: the second march's accumulator (grids with three active axes)
   double* A1 = nullptr;   // adjoint scratch (allocated on the first adjoint call)
   double* A2 = nullptr;
   double* A3 = nullptr;
@@ -202,6 +203,7 @@ static void launch_sweep_r(cfd_solver* s, int mode, const double* P, const Stage
       case MODE_WRITE: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE, false, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
       case MODE_ACC: hipLaunchKernelGGL((k_sweep_x<MODE_ACC, false, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
       case MODE_ACC_RK: hipLaunchKernelGGL((k_sweep_x<MODE_ACC_RK, PN, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
+      case MODE_ACC2_RK: hipLaunchKernelGGL((k_sweep_x<MODE_ACC2_RK, PN, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
       default: hipLaunchKernelGGL((k_sweep_x<MODE_WRITE_RK, PN, SCH>), grid, dim3(kBlock), 0, st, P, io, g); break;
     }
   } else {
@@ -240,11 +242,14 @@ static void launch_sweep_axis(cfd_solver* s, int d, int mode, const double* P, c
   else launch_sweep<2, PN>(s, mode, P, io, st);
 }
 
-// Sweeps run z, y, x (active axes only): the x sweep, the lightest in
-// registers, takes the stage update and the next-stage primitives.
+// A stage of a grid with three active axes splits its accumulator: the y and
+// z marches write R and R2, the x sweep reads both (MODE_ACC2_RK).
+static bool stage_split(const Geom& g) { return g.act[0] && g.act[1] && g.act[2]; }
+
+// The first and last active axes in sweep order (kSweepAxes).
 static void sweep_order(const Geom& g, int& first, int& last) {
   first = last = -1;
-  for (int d = 2; d >= 0; --d)
+  for (int d : kSweepAxes)
     if (g.act[d]) {
       if (first < 0) first = d;
       last = d;
@@ -295,13 +300,21 @@ static cfd_status enqueue_fluxes(cfd_solver* s, const double* P, const StageIO& 
   }
   int first = -1, last = -1;
   sweep_order(g, first, last);
-  for (int d = 2; d >= 0; --d) {
+  for (int d : kSweepAxes) {
     if (!g.act[d]) continue;
     int mode;
-    if (d == last && rk) mode = d == first ? MODE_WRITE_RK : MODE_ACC_RK;
-    else mode = d == first ? MODE_WRITE : MODE_ACC;
-    if (d == last && rk && io.Pn) launch_sweep_axis<true>(s, d, mode, P, io, st);
-    else launch_sweep_axis<false>(s, d, mode, P, io, st);
+    StageIO iod = io;
+    if (d == last && rk) {
+      mode = d == first ? MODE_WRITE_RK : (stage_split(g) && d == 0 ? MODE_ACC2_RK : MODE_ACC_RK);
+    } else if (rk && stage_split(g)) {
+      // the marches before the x sweep each write their own accumulator
+      mode = MODE_WRITE;
+      if (d != first) iod.R = const_cast<double*>(io.R2);
+    } else {
+      mode = d == first ? MODE_WRITE : MODE_ACC;
+    }
+    if (d == last && rk && io.Pn) launch_sweep_axis<true>(s, d, mode, P, iod, st);
+    else launch_sweep_axis<false>(s, d, mode, P, iod, st);
     CFD_LAUNCHED();
   }
   if (rk && io.Pn) {
@@ -348,6 +361,7 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   CFD_LAUNCHED();
   StageIO io{};
   io.R = s->Racc;
+  io.R2 = s->Racc2;
   io.Un = U;
   io.dtp = dtp;
   io.partial = s->partial;
@@ -562,6 +576,7 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
   const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
   bool ok = hipMalloc(&s->U1, st) == hipSuccess && hipMalloc(&s->U2, st) == hipSuccess &&
             hipMalloc(&s->Racc, st) == hipSuccess &&
+            (!stage_split(s->g) || hipMalloc(&s->Racc2, st) == hipSuccess) &&
             hipMalloc(&s->Pb[0], sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
             hipMalloc(&s->Pb[1], sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
             hipMalloc(&s->Pb[2], sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
@@ -595,7 +610,7 @@ void cfd_destroy(cfd_solver* s) {
   (void)hipDeviceSynchronize();
   if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
-  double* bufs[] = {s->U1, s->U2,   s->Pb[0], s->Pb[1], s->Pb[2], s->Racc,    s->A1,
+  double* bufs[] = {s->U1, s->U2,   s->Pb[0], s->Pb[1], s->Pb[2], s->Racc,    s->Racc2, s->A1,
                     s->A2, s->A3,   s->Wbar,  s->Dbar,  s->partial, s->nna, s->nntape};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
@@ -727,6 +742,7 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
     const int stage = r % 3;
     StageIO io{};
     io.R = s->Racc;
+    io.R2 = s->Racc2;
     io.Un = U;
     io.Uk = U;
     io.Uout = s->U2;
@@ -744,11 +760,20 @@ cfd_status cfd_profile_stage(cfd_solver* s, const double* U, int32_t reps, doubl
     hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, U, s->P, g, s->ctl, 0, io.dtp, s->partial);
     sl[n] = 0;
     (void)hipEventRecord(e[++n], st);
-    for (int d = 2; d >= 0; --d) {
+    for (int d : kSweepAxes) {
       if (!g.act[d]) continue;
-      int mode = d == last ? (d == first ? MODE_WRITE_RK : MODE_ACC_RK) : (d == first ? MODE_WRITE : MODE_ACC);
-      if (d == last) launch_sweep_axis<true>(s, d, mode, s->P, io, st);
-      else launch_sweep_axis<false>(s, d, mode, s->P, io, st);
+      int mode;
+      StageIO iod = io;
+      if (d == last) {
+        mode = d == first ? MODE_WRITE_RK : (stage_split(g) && d == 0 ? MODE_ACC2_RK : MODE_ACC_RK);
+      } else if (stage_split(g)) {
+        mode = MODE_WRITE;
+        if (d != first) iod.R = const_cast<double*>(io.R2);
+      } else {
+        mode = d == first ? MODE_WRITE : MODE_ACC;
+      }
+      if (d == last) launch_sweep_axis<true>(s, d, mode, s->P, iod, st);
+      else launch_sweep_axis<false>(s, d, mode, s->P, iod, st);
       sl[n] = 1 + d;
       (void)hipEventRecord(e[++n], st);
     }
@@ -803,6 +828,7 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   const double* dtp = &s->ctl->dt;
   StageIO io{};
   io.R = s->Racc;
+  io.R2 = s->Racc2;
   io.Un = Un;
   io.dtp = dtp;
   io.partial = s->partial;
@@ -923,7 +949,7 @@ cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const do
 // a kernel (on the host it is only a stand-in symbol): the device address of
 // each device's copy is looked up once, on that device's first call, with
 // hipGetSymbolAddress and kept per device.
-constexpr long long kNoAllocDoubles = 96LL << 17;  // 96 MiB of FP64
+constexpr long long kNoAllocDoubles = 112LL << 17;  // 112 MiB of FP64
 constexpr long long kNoAllocHead = kCflSlots + 32;  // CFL slots, then the control block (256 B aligned)
 constexpr int kNoAllocMaxDevices = 64;
 static __device__ __align__(256) double scratch[kNoAllocDoubles];
@@ -931,9 +957,10 @@ static __device__ __align__(256) double scratch[kNoAllocDoubles];
 static std::mutex g_noalloc_mu;
 static double* g_noalloc_ptr[kNoAllocMaxDevices] = {};
 
-// Padded cells of cfg that fit the scratch array: 33 doubles per padded cell
-// (U1, U2, R: 5 each; three primitive buffers: 6 each) after the head.
-static constexpr long long noalloc_max_cells() { return (kNoAllocDoubles - kNoAllocHead) / 33; }
+// Padded cells of cfg that fit the scratch array: 38 doubles per padded cell
+// (U1, U2 and the two accumulators: 5 each; three primitive buffers: 6 each)
+// after the head.
+static constexpr long long noalloc_max_cells() { return (kNoAllocDoubles - kNoAllocHead) / 38; }
 static_assert(noalloc_max_cells() == CFD_NOALLOC_MAX_PADDED_CELLS, "header limit out of date");
 
 static cfd_status noalloc_scratch(double** out) {
@@ -980,7 +1007,8 @@ cfd_status cfd_rk3_step_noalloc(const cfd_config* cfg, double* U, double dt, dou
   s.U1 = b;
   s.U2 = b + 5 * nc;
   s.Racc = b + 10 * nc;
-  for (int k = 0; k < 3; ++k) s.Pb[k] = b + (15 + 6 * k) * nc;
+  s.Racc2 = b + 15 * nc;
+  for (int k = 0; k < 3; ++k) s.Pb[k] = b + (20 + 6 * k) * nc;
   s.P = s.Pb[0];
   hipStream_t st = (hipStream_t)stream;
   // the control block (step size, health bits) starts clear on every call;

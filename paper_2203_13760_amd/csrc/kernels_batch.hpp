@@ -31,6 +31,7 @@ struct GridWork {
   double* U2;
   double* Pb[3];   // primitives (6 x padded) of the stage inputs: stage s reads Pb[s-1]
   double* R;       // 5 x padded
+  double* R2;      // 5 x padded: the second march's accumulator (grids with three active axes)
   double* partial; // CFL rate slots
   DevCtl* ctl;
   int npart;
@@ -102,6 +103,7 @@ __device__ __forceinline__ void batch_item(const BatchTable* __restrict__ tab, i
     const Geom& g = w.g;
     StageIO io;
     io.R = w.R;
+    io.R2 = w.R2;
     io.Un = w.U;
     io.dtp = &w.ctl->dt;
     io.Uk = STAGE == 1 ? w.U : (STAGE == 2 ? w.U1 : w.U2);
@@ -126,15 +128,20 @@ __device__ __forceinline__ void batch_item(const BatchTable* __restrict__ tab, i
     } else {
       const int axis = PHASE - PH_SX;
       const bool last = axis == w.last_axis, first = axis == w.first_axis;
+      const bool split = g.act[0] && g.act[1] && g.act[2];  // y and z marches write R and R2
       if (last) {
         // the last axis is x whenever x is active
         if (axis == 0) {
           if (first) batch_sweep<MODE_WRITE_RK, true>(axis, w, P, io, local);
+          else if (split) batch_sweep<MODE_ACC2_RK, true>(axis, w, P, io, local);
           else batch_sweep<MODE_ACC_RK, true>(axis, w, P, io, local);
         } else {
           if (first) batch_sweep<MODE_WRITE_RK, false>(axis, w, P, io, local);
           else batch_sweep<MODE_ACC_RK, false>(axis, w, P, io, local);
         }
+      } else if (split) {
+        if (!first) io.R = w.R2;
+        batch_sweep<MODE_WRITE, false>(axis, w, P, io, local);
       } else {
         if (first) batch_sweep<MODE_WRITE, false>(axis, w, P, io, local);
         else batch_sweep<MODE_ACC, false>(axis, w, P, io, local);

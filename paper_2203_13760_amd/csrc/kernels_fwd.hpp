@@ -30,10 +30,18 @@ struct DevCtl {
 constexpr int kBlock = 256;
 constexpr int kGradComps = 9;  // adjoint of d u_a / d x_b accumulated at component a*3+b
 
-enum SweepMode { MODE_WRITE = 0, MODE_ACC = 1, MODE_ACC_RK = 2, MODE_WRITE_RK = 3 };
+// What a sweep does with the divergence D of its axis: MODE_WRITE stores
+// R = -D, MODE_ACC R -= D; the RK modes apply the stage update with
+// R = -D (MODE_WRITE_RK), R - D (MODE_ACC_RK) or R + R2 - D (MODE_ACC2_RK:
+// the two marches before it each wrote their own accumulator, which spares
+// the second one a read-modify-write of R).
+enum SweepMode { MODE_WRITE = 0, MODE_ACC = 1, MODE_ACC_RK = 2, MODE_WRITE_RK = 3, MODE_ACC2_RK = 4 };
+__host__ __device__ constexpr bool mode_rk(int m) { return m == MODE_ACC_RK || m == MODE_WRITE_RK || m == MODE_ACC2_RK; }
+__host__ __device__ constexpr bool mode_reads_r(int m) { return m == MODE_ACC || m == MODE_ACC_RK || m == MODE_ACC2_RK; }
 
 struct StageIO {
   double* R;         // right-hand-side accumulator (padded layout)
+  const double* R2;  // second accumulator (MODE_ACC2_RK)
   const double* Un;  // state at the start of the step
   const double* Uk;  // stage input state
   double* Uout;      // stage output state (may alias Un in the last stage)
@@ -470,7 +478,8 @@ __device__ __forceinline__ void emit_fetch(const StageIO& io, long long vs, long
   for (int v = 0; v < 5; ++v) {
     const long long e = v * vs + c;
     if (MODE == MODE_ACC || MODE == MODE_ACC_RK) in.r[v] = io.R[e];
-    if (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) {
+    if (MODE == MODE_ACC2_RK) in.r[v] = io.R[e] + io.R2[e];
+    if (mode_rk(MODE)) {
       in.un[v] = io.Un[e];
       in.uk[v] = io.Uk[e];
     }
@@ -492,7 +501,7 @@ __device__ __forceinline__ void emit_put(const StageIO& io, const Geom& g, long 
       io.Uout[e] = uo[v];
     }
   }
-  if constexpr (PN && (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK)) {
+  if constexpr (PN && mode_rk(MODE)) {
     double w[6];
     cons_to_prim(g, uo, w);
 #pragma unroll
@@ -544,7 +553,7 @@ __device__ __forceinline__ void sweep_x_body_face(const double* __restrict__ P, 
   double smax = 0.0;
   int bad = 0;
   if (first < total) {  // uniform per wavefront
-    const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
+    const double dt = mode_rk(MODE) ? *io.dtp : 0.0;
     const int gs = first - (kXCtx + 1) + lane;
     const bool inrange = gs >= 0 && gs < total;
     int f = 0, j = 0, k = 0;
@@ -611,7 +620,7 @@ __device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, 
   double smax = 0.0;
   int bad = 0;
   if (first < total) {  // uniform per wavefront
-    const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
+    const double dt = mode_rk(MODE) ? *io.dtp : 0.0;
     const int gs = first - (kXCtx + 1) + lane;
     const bool inrange = gs >= 0 && gs < total;
     int f = 0, j = 0, k = 0;
@@ -677,7 +686,7 @@ __device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, 
 template <int MODE, bool PN = false, int SCH = SCH_JS>
 __device__ __forceinline__ void sweep_x_body(const double* __restrict__ P, const StageIO& io, const Geom& g,
                                              int bx) {
-  if constexpr (SCH == SCH_ROE) sweep_x_body_face<MODE, PN, SCH>(P, io, g, bx);
+  if constexpr (SCH == SCH_ROE || SCH == SCH_Z) sweep_x_body_face<MODE, PN, SCH>(P, io, g, bx);
   else sweep_x_body_pair<MODE, PN, SCH>(P, io, g, bx);
 }
 
@@ -741,7 +750,7 @@ __device__ __forceinline__ void sweep_march_body_face(const double* __restrict__
     }
   }
   double Gm[5];
-  const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
+  const double dt = mode_rk(MODE) ? *io.dtp : 0.0;
   for (int f = s0 - 1; f < s1; ++f) {
     // issue the loads of the cell entering the window at the next face, and
     // those of this face's cell update, before this face's arithmetic, so
@@ -862,7 +871,7 @@ __device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__
     }
   }
   double Gm[5];
-  const double dt = (MODE == MODE_ACC_RK || MODE == MODE_WRITE_RK) ? *io.dtp : 0.0;
+  const double dt = mode_rk(MODE) ? *io.dtp : 0.0;
   for (int f = s0 - 1; f < s1; ++f) {
     // issue the loads of the cell entering the window at the next face, and
     // those of this face's cell update, before this face's arithmetic, so
@@ -941,7 +950,7 @@ __device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__
 template <int AX, int MODE, bool PN = false, int SCH = SCH_JS>
 __device__ __forceinline__ void sweep_march_body(const double* __restrict__ P, const StageIO& io,
                                                  const Geom& g, int bx, int by) {
-  if constexpr (SCH == SCH_ROE) sweep_march_body_face<AX, MODE, PN, SCH>(P, io, g, bx, by);
+  if constexpr (SCH == SCH_ROE || SCH == SCH_Z) sweep_march_body_face<AX, MODE, PN, SCH>(P, io, g, bx, by);
   else sweep_march_body_pair<AX, MODE, PN, SCH>(P, io, g, bx, by);
 }
 
@@ -967,6 +976,14 @@ __host__ __device__ __forceinline__ void sweep_march_blocks(const Geom& g, int& 
   gx = (g.n[0] + 63) / 64;
   gy = (int)(((long long)g.n[OT] * nseg + 3) / 4);
 }
+
+// Order of the per-axis sweeps of a stage: y, z, x over the active axes. The
+// first writes the right-hand side, the later ones accumulate into it, and x,
+// the last whenever it is active, applies the stage update and stores the next
+// primitives. The y march goes first because it writes without reading the
+// accumulator, which leaves it the registers to hold the loads of its
+// tangential stencil (whose z neighbours lie a plane apart) across a face.
+constexpr int kSweepAxes[3] = {1, 2, 0};
 
 // Zero a buffer (graph-safe replacement for a memset node).
 __global__ void __launch_bounds__(kBlock) k_zero(double* x, long long n) {

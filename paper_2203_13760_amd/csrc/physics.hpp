@@ -188,36 +188,6 @@ __host__ __device__ __forceinline__ void weno5_pair(double a, double b, double c
   ql = nl * dr * r;
 }
 
-// WENO5-Z at both faces of the centre cell (as weno5_pair): the indicators
-// beta_L, beta_C, beta_R in mirrored roles, tau5 = |beta_L - beta_R| for both
-// faces, e_k = beta_k + 1e-40; the weights of qr are proportional to
-// (0.1 (e_L + tau) e_C e_R, 0.6 (e_C + tau) e_L e_R, 0.3 (e_R + tau) e_L e_C),
-// those of ql to (0.1 (e_R + tau) e_C e_L, 0.6 (e_C + tau) e_L e_R,
-// 0.3 (e_L + tau) e_C e_R).
-__host__ __device__ __forceinline__ void weno5z_pair(double a, double b, double c, double d, double e, double& qr,
-                                                    double& ql) {
-  constexpr double k13 = 13.0 / 12.0;
-  constexpr double eps = 1.0e-40;
-  const double Db = a - 2.0 * b + c, Dc = b - 2.0 * c + d, Dd = c - 2.0 * d + e;
-  const double dm = c - b, dp = d - c;
-  const double tL = Db + 2.0 * dm, tC = dm + dp, tR = Dd - 2.0 * dp;
-  const double bL = k13 * Db * Db + 0.25 * tL * tL;
-  const double bC = k13 * Dc * Dc + 0.25 * tC * tC;
-  const double bR = k13 * Dd * Dd + 0.25 * tR * tR;
-  const double tau = fabs(bL - bR);
-  const double eL = bL + eps, eC = bC + eps, eR = bR + eps;
-  const double pCR = eC * eR, pLR = eL * eR, pLC = eL * eC;
-  const double wLr = 0.1 * (eL + tau) * pCR, wC = 0.6 * (eC + tau) * pLR, wRr = 0.3 * (eR + tau) * pLC;
-  const double wRl = 0.1 * (eR + tau) * pLC, wLl = 0.3 * (eL + tau) * pCR;
-  const double nr = wLr * (2.0 * a - 7.0 * b + 11.0 * c) + wC * (-b + 5.0 * c + 2.0 * d) + wRr * (2.0 * c + 5.0 * d - e);
-  const double nl = wRl * (2.0 * e - 7.0 * d + 11.0 * c) + wC * (-d + 5.0 * c + 2.0 * b) + wLl * (2.0 * c + 5.0 * b - a);
-  const double dr = wLr + wC + wRr;
-  const double dl = wRl + wC + wLl;
-  const double r = div_nr(1.0, 6.0 * (dr * dl));
-  qr = nr * dl * r;
-  ql = nl * dr * r;
-}
-
 // WENO3-JS (Jiang & Shu 1996, r = 2) value at the right face of the centre
 // cell b of the stencil (a, b, c): candidates (3b - a)/2 and (b + c)/2,
 // smoothness indicators (b - a)^2 and (c - b)^2, linear weights (1/3, 2/3),
@@ -546,16 +516,18 @@ __host__ __device__ __forceinline__ void face_flux_tf(const Geom& g, const FaceW
   face_flux_lr<D, sch_rusanov(SCH), SCH == SCH_W3_NN>(g, WL, WR, w, tf, G);
 }
 
-// Reconstructed states of the cell-centred schemes (every scheme but the Roe
-// flux splitting, whose projection depends on the face): from the primitives
-// q[0..4] of cells i-2 .. i+2, the left state of face i+1/2 (qr) and the right
-// state of face i-1/2 (ql), per variable.
+// Reconstructed states of the cell-centred schemes (WENO5-JS and WENO3-JS on
+// the primitives; the Roe flux splitting projects per face, and WENO5-Z's
+// per-cell form needs more registers than the marches hold, so both stay
+// face by face): from the primitives q[0..4] of cells i-2 .. i+2, the left
+// state of face i+1/2 (qr) and the right state of face i-1/2 (ql), per
+// variable.
 template <int SCH>
 __host__ __device__ __forceinline__ void recon_pair(const double (*q)[5], double* qr, double* ql) {
+  static_assert(SCH != SCH_ROE && SCH != SCH_Z, "face-by-face schemes");
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     if constexpr (sch_weno3(SCH)) weno3_pair(q[1][v], q[2][v], q[3][v], qr[v], ql[v]);
-    else if constexpr (SCH == SCH_Z) weno5z_pair(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], qr[v], ql[v]);
     else weno5_pair(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], qr[v], ql[v]);
   }
 }

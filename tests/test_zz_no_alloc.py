@@ -55,7 +55,7 @@ def test_noalloc_step_equals_solver_step():
 def test_noalloc_step_rejects_grids_beyond_its_scratch():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    case, W = wl.taylor_green(0, shape=(72, 72, 72))  # 78^3 padded cells > 381291
+    case, W = wl.taylor_green(0, shape=(72, 72, 72))  # 78^3 padded cells > 386309
     U = torch.zeros((5, 78, 78, 78), dtype=torch.float64, device="cuda")
     with pytest.raises(cfd.CfdError) as e:
         cfd.cfd_rk3_step_noalloc(case, U, 0.0)
