@@ -85,6 +85,7 @@ def parse():
     ap.add_argument("--nn-epochs", type=int, default=1,
                     help="epochs of the Rusanov-NN training in the implosion leg (0 skips it)")
     ap.add_argument("--roe-steps", type=int, default=10)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg (batched vs one at a time)")
     ap.add_argument("--serving", action="store_true",
                     help="run the serving benchmark (batched vs one at a time) instead")
     ap.add_argument("--serving-requests", type=int, default=400)
@@ -295,6 +296,26 @@ def roe_leg(case, W, steps, reps, hllc_ms_per_step):
     return out
 
 
+def serving_leg(requests, rate, steps):
+    """The serving workload (seeded Poisson arrivals of mixed 2D Kelvin-Helmholtz /
+    3D Taylor-Green solves): continuous batching against the same server with
+    one resident solve at a time; p50/p99 time to solution and throughput."""
+    from paper_2203_13760_amd import serving
+    srv = serving.BatchServer(max_grids=256, arena_bytes=96 << 30)
+    try:
+        srv.run(serving.mixed_workload(8, 1000.0, seed=99, steps=3, kh_range=(64, 96), tgv_range=(32, 40)))
+        mk = lambda: serving.mixed_workload(requests, rate, seed=3, steps=steps)
+        batched = srv.run(mk())
+        single = srv.run(mk(), max_resident=1)
+    finally:
+        srv.close()
+    return {"workload": f"{requests} requests, Poisson {rate}/s (seed 3), 60% KH 2D n in [64,1024], "
+                        f"40% TGV 3D n in [32,128], {steps} TVD-RK3 CFL steps each",
+            "p50_s": batched["p50_s"], "p99_s": batched["p99_s"],
+            "throughput_ratio": batched["throughput_req_s"] / single["throughput_req_s"],
+            "batched": batched, "one_at_a_time": single}
+
+
 def serving_bench(args):
     """Continuous-batching serving of mixed 2D Kelvin-Helmholtz / 3D Taylor-Green
     solves (seeded Poisson arrivals): batched persistent launches vs the same
@@ -454,6 +475,14 @@ def main():
               f"gradient through {args.adj_steps} steps in {adjoint['gradient_s']:.2f} s", flush=True)
         torch.cuda.empty_cache()
 
+    serving_out = None
+    if not args.no_serving:
+        serving_out = serving_leg(args.serving_requests, args.serving_rate, args.serving_steps)
+        print(f"bench: serving p50 {serving_out['p50_s']:.2f} s, p99 {serving_out['p99_s']:.2f} s, batched "
+              f"{serving_out['batched']['throughput_req_s']:.1f} req/s = {serving_out['throughput_ratio']:.2f} x "
+              f"one at a time", flush=True)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case, W, args.cpu_slab)
@@ -481,6 +510,8 @@ def main():
         "step_tflops": step_flops * cells * args.steps / sec / 1e12,
         "fused_min_traffic_GBps": 320.0 * value * 1e6 / 1e9,
         "cpu_baseline": cpu,
+        "p99_solve_latency_s": serving_out["p99_s"] if serving_out else None,
+        "serving": serving_out,
         "differentiation": adjoint,
         "roe_setup": roe,
         "wenoz": wenoz,

@@ -842,6 +842,9 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   if ((rc = enqueue_prim(s, Un, 0, dtp, st))) return rc;
   if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
   if (g.rk2) {
+    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->U1, s->Pb[1], g, s->ctl, 0,
+                       (const double*)nullptr, s->partial);
+    CFD_LAUNCHED();
     // TVD-RK2:  U2 = 1/2 Un + 1/2 (U1 + dt R(U1)),  U1 = Un + dt R(Un)
     // A1 = Ubar_1 = 1/2 Ubar_2 + (dR/dU(U1))^T (1/2 dt Ubar_2)
     hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.5, Ubar_np1, 0.0,
@@ -860,6 +863,13 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   io.b = 0.25;
   io.Pn = s->Pb[2];
   if ((rc = enqueue_fluxes(s, s->Pb[1], io, true, st))) return rc;
+  // the stage updates store no T~ with the next primitives: the primitive
+  // passes of U1, U2 complete P for the face reverses
+  for (int k = 1; k < 3; ++k) {
+    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, (const double*)(k == 1 ? s->U1 : s->U2), s->Pb[k],
+                       g, s->ctl, 0, (const double*)nullptr, s->partial);
+    CFD_LAUNCHED();
+  }
   // reverse:  U3 = 1/3 Un + 2/3 (U2 + dt R(U2)),  U2 = 3/4 Un + 1/4 (U1 + dt R(U1)),
   //           U1 = Un + dt R(Un)
   // A2 = Ubar_2 = 2/3 Ubar_3 + (dR/dU(U2))^T (2/3 dt Ubar_3)

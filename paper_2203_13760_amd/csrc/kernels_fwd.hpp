@@ -486,7 +486,9 @@ __device__ __forceinline__ void emit_fetch(const StageIO& io, long long vs, long
   }
 }
 
-template <int MODE, bool PN = false>
+// STORE_T: also store T~ = p/rho with the next primitives (the face-by-face
+// sweeps read it from P; the cell-centred ones form it from rho and p).
+template <int MODE, bool PN = false, bool STORE_T = true>
 __device__ __forceinline__ void emit_put(const StageIO& io, const Geom& g, long long c, const double* D,
                                          const EmitIn& in, double dt, double& smax, int& bad) {
   double uo[5];
@@ -505,7 +507,7 @@ __device__ __forceinline__ void emit_put(const StageIO& io, const Geom& g, long 
     double w[6];
     cons_to_prim(g, uo, w);
 #pragma unroll
-    for (int v = 0; v < 6; ++v) io.Pn[v * g.vs + c] = w[v];
+    for (int v = 0; v < (STORE_T ? 6 : 5); ++v) io.Pn[v * g.vs + c] = w[v];
     if (io.what & PRIM_CFL) smax = fmax(smax, cfl_rate(g, w[0], w + 1, w[4]));
     if (io.what & PRIM_HEALTH) bad |= health_bits(uo, w[4]);
   }
@@ -541,6 +543,26 @@ __device__ __forceinline__ double lane_shr1(double x) {
 constexpr int kXCtx = 3;
 constexpr int kXFaces = 64 - (kXCtx + 1);  // faces a wavefront emits
 
+// Interior row `row` (a line of cells along x) of an x sweep in band-major
+// order: bands of kXBand consecutive y rows, within a band z outer and y
+// inner. The blocks one XCD runs at a time then cover a few planes of a
+// narrow band, so the y and z neighbours the tangential stencils read are
+// mostly still in that XCD's L2.
+constexpr int kXBand = 16;
+
+__device__ __forceinline__ void x_row(const Geom& g, int row, int& j, int& k) {
+  const int full = g.n[1] / kXBand;
+  const int band_rows = kXBand * g.n[2];
+  int band = row / band_rows, h = kXBand;
+  if (band >= full) {
+    band = full;
+    h = g.n[1] - full * kXBand;
+  }
+  const int r = row - band * band_rows;
+  k = r / h;
+  j = band * kXBand + (r - k * h);
+}
+
 template <int MODE, bool PN, int SCH>
 __device__ __forceinline__ void sweep_x_body_face(const double* __restrict__ P, const StageIO& io, const Geom& g,
                                                   int bx) {
@@ -560,8 +582,7 @@ __device__ __forceinline__ void sweep_x_body_face(const double* __restrict__ P, 
     if (inrange) {
       const int row = gs / S;
       f = gs - row * S - kXCtx;
-      k = row / g.n[1];
-      j = row - k * g.n[1];
+      x_row(g, row, j, k);
     }
     const bool valid = inrange && f >= 0 && gs >= first - 1;  // lanes whose face flux is used
     // Every lane loads a window inside the padded block (context slots and
@@ -627,8 +648,7 @@ __device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, 
     if (inrange) {
       const int row = gs / S;
       f = gs - row * S - kXCtx;
-      k = row / g.n[1];
-      j = row - k * g.n[1];
+      x_row(g, row, j, k);
     }
     const bool valid = inrange && f >= 0 && gs >= first - 1;  // lanes whose face flux is used
     // every lane loads a window inside the padded block and computes a flux:
@@ -640,11 +660,14 @@ __device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, 
     double q[5][5];
 #pragma unroll
     for (int m = 0; m < 5; ++m) load_prims(P, g.vs, c0 + m, q[m]);
-    double T[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) T[m] = P[5 * g.vs + c0 + m];  // cells f-2 .. f+1; unused without heat flux
     double d[4] = {0.0, 0.0, 0.0, 0.0};
     if (g.viscous) tangential_at_flat<0>(g, P, cell_at(g, f + 1, j, k), d);
+    // T~ = p/rho of cells f-2 .. f+1 (heat flux only), from the window
+    double T[4] = {0.0, 0.0, 0.0, 0.0};
+    if (g.heat) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) T[m] = div_nr(q[m][4], q[m][0]);
+    }
     // face values of the derivatives from cells f-2..f+1 (lanes - 3 .. lane)
     double tf[4];
 #pragma unroll
@@ -676,7 +699,7 @@ __device__ __forceinline__ void sweep_x_body_pair(const double* __restrict__ P, 
       const long long ce = cell_at(g, f - 1, j, k);
       EmitIn ein;
       emit_fetch<MODE>(io, g.vs, ce, ein);
-      emit_put<MODE, PN>(io, g, ce, D, ein, dt, smax, bad);
+      emit_put<MODE, PN, false>(io, g, ce, D, ein, dt, smax, bad);
     }
   }
   if (PN) finish_prims(io, smax, bad);
@@ -866,7 +889,7 @@ __device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__
   if (dis) {
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      T[m] = P[5 * g.vs + c + m * st];
+      if (g.heat) T[m] = div_nr(q[m][4], q[m][0]);  // T~ = p/rho from the window
       if (g.viscous) tangential_at<AX>(g, P, c + m * st, tg[m]);
     }
   }
@@ -884,7 +907,7 @@ __device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__
     if (more) {
       load_prims(P, g.vs, c + 5 * st, nq);
       if (dis) {
-        nT = P[5 * g.vs + c + 4 * st];
+        if (g.heat) nT = div_nr(q[4][4], q[4][0]);  // cell f+3, window cell 4
         if (g.viscous) {
           if (kDeferTg) tangential_load<AX>(g, P, c + 4 * st, ntr);
           else tangential_at<AX>(g, P, c + 4 * st, ntg);
@@ -913,7 +936,7 @@ __device__ __forceinline__ void sweep_march_body_pair(const double* __restrict__
       double D[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) D[v] = (G[v] - Gm[v]) * g.idx[AX];
-      emit_put<MODE, PN>(io, g, c + st, D, ein, dt, smax, bad);
+      emit_put<MODE, PN, false>(io, g, c + st, D, ein, dt, smax, bad);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
