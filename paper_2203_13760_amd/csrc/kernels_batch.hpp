@@ -20,7 +20,12 @@
 
 namespace cfd {
 
-enum BatchPhase { PH_PRIM = 0, PH_DT, PH_SX, PH_SY, PH_SZ, PH_HALO, PH_COUNT };
+// PH_SX/SY/SZ: the sweep of that axis where it does not apply the stage
+// update except the x sweep (which applies it whenever x is active);
+// PH_SLAST: the last march of grids without an x axis, which applies the
+// update. Keeping those rare updating marches in a phase of their own keeps
+// the y and z phases to one sweep mode and within the register file.
+enum BatchPhase { PH_PRIM = 0, PH_DT, PH_SX, PH_SY, PH_SZ, PH_SLAST, PH_HALO, PH_COUNT };
 
 constexpr int kBatchMaxGrids = 512;
 
@@ -125,27 +130,22 @@ __device__ __forceinline__ void batch_item(const BatchTable* __restrict__ tab, i
       dt_body(w.ctl, g.cfl, 0.0, 0.0, nullptr, nullptr, w.partial, w.npart);
     } else if (PHASE == PH_HALO) {
       prim_halo_body(io.Pn, g, (long long)local * kBlock + threadIdx.x);
+    } else if (PHASE == PH_SX) {
+      // x is the last axis whenever it is active: the stage update
+      const bool split = g.act[1] && g.act[2];  // y and z marches wrote R and R2
+      if (w.first_axis == 0) batch_sweep<MODE_WRITE_RK, true>(0, w, P, io, local);
+      else if (split) batch_sweep<MODE_ACC2_RK, true>(0, w, P, io, local);
+      else batch_sweep<MODE_ACC_RK, true>(0, w, P, io, local);
+    } else if (PHASE == PH_SLAST) {
+      // the last march of a grid without an x axis
+      if (w.last_axis == w.first_axis) batch_sweep<MODE_WRITE_RK, false>(w.last_axis, w, P, io, local);
+      else batch_sweep<MODE_ACC_RK, false>(w.last_axis, w, P, io, local);
     } else {
-      const int axis = PHASE - PH_SX;
-      const bool last = axis == w.last_axis, first = axis == w.first_axis;
-      const bool split = g.act[0] && g.act[1] && g.act[2];  // y and z marches write R and R2
-      if (last) {
-        // the last axis is x whenever x is active
-        if (axis == 0) {
-          if (first) batch_sweep<MODE_WRITE_RK, true>(axis, w, P, io, local);
-          else if (split) batch_sweep<MODE_ACC2_RK, true>(axis, w, P, io, local);
-          else batch_sweep<MODE_ACC_RK, true>(axis, w, P, io, local);
-        } else {
-          if (first) batch_sweep<MODE_WRITE_RK, false>(axis, w, P, io, local);
-          else batch_sweep<MODE_ACC_RK, false>(axis, w, P, io, local);
-        }
-      } else if (split) {
-        if (!first) io.R = w.R2;
-        batch_sweep<MODE_WRITE, false>(axis, w, P, io, local);
-      } else {
-        if (first) batch_sweep<MODE_WRITE, false>(axis, w, P, io, local);
-        else batch_sweep<MODE_ACC, false>(axis, w, P, io, local);
-      }
+      // a march before the update: the first writes R, a second (only with
+      // x active) its own accumulator R2
+      constexpr int axis = PHASE == PH_SY ? 1 : 2;
+      if (axis != w.first_axis) io.R = w.R2;
+      batch_sweep<MODE_WRITE, false>(axis, w, P, io, local);
     }
   }
 }
