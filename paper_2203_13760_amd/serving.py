@@ -121,36 +121,59 @@ class BatchServer:
 
     def run(self, requests, max_resident=None, realtime=True, keep_results=False, log=None):
         """Serve `requests` (sorted by arrival); returns per-request records and totals.
-        realtime=False admits every request at time 0 (closed-loop throughput)."""
+        realtime=False admits every request at time 0 (closed-loop throughput).
+
+        Continuous batching: requests that arrive while a step runs are
+        admitted on a side stream during that step (initial field, state and
+        primitives of the new grid, in arena space no running step touches)
+        and join at the next step; the step stream waits for the admissions
+        before the next step uploads the grid table. With one resident grid at
+        most, a request is admitted only once the previous one has left."""
         max_resident = max_resident or self.max_grids
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue = collections.deque()
         resident = []
         stream = torch.cuda.current_stream()
+        side = torch.cuda.Stream()  # default priority, like every stream here
         done = []
         ticks = 0
         cell_updates = 0
         t0 = time.perf_counter()
         last_log = t0
-        while pending or queue or resident:
+
+        def arrivals():
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 queue.append(pending.popleft())
-            while queue and len(resident) < max_resident:
+
+        def admit(limit):
+            out = []
+            while queue and limit(len(out)):
                 r = queue[0]
-                W = r.make_W()
-                slot = cfd.cfd_batch_add(self.b, r.case, W)
+                with torch.cuda.stream(side):
+                    W = r.make_W()
+                    slot = cfd.cfd_batch_add(self.b, r.case, W, stream=side)
+                    del W
                 if slot is None:
                     break  # wait for memory to free up
-                del W
                 r.slot = slot
                 r.admitted = time.perf_counter() - t0
-                resident.append(queue.popleft())
+                out.append(queue.popleft())
+            return out
+
+        while pending or queue or resident:
+            arrivals()
             if not resident:
-                if pending:
-                    time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.01)))
-                continue
+                resident = admit(lambda k: k < max_resident)
+                stream.wait_stream(side)
+                if not resident:
+                    if pending:
+                        time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.01)))
+                    continue
             cfd.cfd_batch_step(self.b)
+            # admissions overlap the running step; they start at the next one
+            arrivals()
+            joining = admit(lambda k: len(resident) + k < max_resident)
             stream.synchronize()
             ticks += 1
             tnow = time.perf_counter() - t0
@@ -167,7 +190,8 @@ class BatchServer:
                     done.append(r)
                 else:
                     still.append(r)
-            resident = still
+            resident = still + joining
+            stream.wait_stream(side)
             if log and time.perf_counter() - last_log > 5.0:
                 last_log = time.perf_counter()
                 log(f"serving: t={tnow:.1f}s done={len(done)} resident={len(resident)} queued={len(queue)} "
