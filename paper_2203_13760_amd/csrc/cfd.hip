@@ -80,6 +80,8 @@ struct cfd_solver {
   int npart = 0;
   DevCtl* ctl = nullptr;
   hipStream_t cap = nullptr;
+  hipStream_t side = nullptr;  // the dissipative face reverses run here, beside the inviscid ones
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   GraphCache graph;
 };
 
@@ -482,8 +484,10 @@ static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   return CFD_OK;
 }
 
+// The face reverses of axis D: the inviscid part on st, the dissipative part on sd.
 template <int D>
-static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, double rscale, hipStream_t st) {
+static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, double rscale, hipStream_t st,
+                            hipStream_t sd) {
   const Geom& g = s->g;
   if constexpr (D == 0) {
     long long faces = (long long)g.n[0] * g.n[1] * g.n[2] / g.n[D] * (g.n[D] + 1);
@@ -491,14 +495,14 @@ static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, 
     if (g.inviscid)
       hipLaunchKernelGGL(k_face_adj_inv<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
     if (g.viscous || g.heat)
-      hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar, g);
+      hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, sd, P, Rbar, rscale, s->Wbar, s->Dbar, g);
   } else {
-    const dim3 grid_inv = face_adj_tile_grid<D, kAdjTileFacesInv>(g);
-    const dim3 grid_dis = face_adj_tile_grid<D, kAdjTileFacesDis>(g);
+    int gx = 0, gy = 0;
+    sweep_march_blocks<D>(g, gx, gy);
     if (g.inviscid)
-      hipLaunchKernelGGL(k_face_adj_inv_tiled<D>, grid_inv, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
+      hipLaunchKernelGGL(k_march_adj_inv<D>, dim3(gx, gy), dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
     if (g.viscous || g.heat)
-      hipLaunchKernelGGL(k_face_adj_dis_tiled<D>, grid_dis, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, s->Dbar,
+      hipLaunchKernelGGL(k_march_adj_dis<D>, dim3(gx, gy), dim3(kBlock), 0, sd, P, Rbar, rscale, s->Wbar, s->Dbar,
                          g);
   }
 }
@@ -530,10 +534,24 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
       CFD_LAUNCHED();
     }
   } else {
-    if (g.act[0]) launch_face_adj<0>(s, P, Rbar, rscale, st);
-    if (g.act[1]) launch_face_adj<1>(s, P, Rbar, rscale, st);
-    if (g.act[2]) launch_face_adj<2>(s, P, Rbar, rscale, st);
+    // the inviscid reverses (FP64-bound) and the dissipative ones (bound by
+    // their stencil loads) add to disjoint or commuting entries of Wbar and
+    // Dbar: they run side by side on two streams
+    const bool fork = g.inviscid && (g.viscous || g.heat);
+    hipStream_t sd = st;
+    if (fork) {
+      CFD_HIP(hipEventRecord(s->ev_fork, st));
+      CFD_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+      sd = s->side;
+    }
+    if (g.act[0]) launch_face_adj<0>(s, P, Rbar, rscale, st, sd);
+    if (g.act[1]) launch_face_adj<1>(s, P, Rbar, rscale, st, sd);
+    if (g.act[2]) launch_face_adj<2>(s, P, Rbar, rscale, st, sd);
     CFD_LAUNCHED();
+    if (fork) {
+      CFD_HIP(hipEventRecord(s->ev_join, s->side));
+      CFD_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+    }
   }
   if (g.viscous) {
     hipLaunchKernelGGL(k_adj_dbar, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->Dbar, s->Wbar, g);
@@ -597,6 +615,9 @@ cfd_status cfd_create(const cfd_config* cfg, cfd_solver** out) {
   if (hipMemset(s->ctl, 0, sizeof(DevCtl)) != hipSuccess ||
       hipMemset(s->partial, 0, sizeof(double) * (size_t)s->npart) != hipSuccess ||
       hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     cfd_destroy(s);
     return fail(CFD_EHIP, "solver initialisation failed");
@@ -610,6 +631,9 @@ void cfd_destroy(cfd_solver* s) {
   (void)hipDeviceSynchronize();
   if (s->graph.exec) (void)hipGraphExecDestroy(s->graph.exec);
   if (s->cap) (void)hipStreamDestroy(s->cap);
+  if (s->side) (void)hipStreamDestroy(s->side);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   double* bufs[] = {s->U1, s->U2,   s->Pb[0], s->Pb[1], s->Pb[2], s->Racc,    s->Racc2, s->A1,
                     s->A2, s->A3,   s->Wbar,  s->Dbar,  s->partial, s->nna, s->nntape};
   for (double* b : bufs)

@@ -2,16 +2,17 @@
 //
 //   1. the primitives P at the state (the forward kernels, or the buffers a
 //      forward recompute of the stages leaves);
-//   2. k_face_adj<D>: one lane per face normal to D. The face flux adjoint
-//      follows from Rbar (R_i = -(G_{i+1/2} - G_{i-1/2})/dx gives
-//      Gbar_{i+1/2} = (Rbar_{i+1} - Rbar_i)/dx), the face recomputes its
-//      forward flux and reverses it (physics_adj.hpp), and its contributions
-//      go to Wbar (rho,u,v,w,p,T~ of the stencil cells) and Dbar (the adjoints
-//      of the centred derivatives) with hardware FP64 atomics. For x faces
-//      the lanes of a wavefront hold consecutive faces of a row and the
-//      contributions are first summed per cell by shuffles (one atomic per
-//      cell and variable); y and z faces keep x-consecutive lanes, whose
-//      loads coalesce, and add every contribution directly;
+//   2. the face reverses: the face flux adjoint follows from Rbar
+//      (R_i = -(G_{i+1/2} - G_{i-1/2})/dx gives Gbar_{i+1/2} =
+//      (Rbar_{i+1} - Rbar_i)/dx); each face recomputes its forward flux and
+//      reverses it (physics_adj.hpp), and its contributions go to Wbar
+//      (rho,u,v,w,p,T~ of the stencil cells) and Dbar (the adjoints of the
+//      centred derivatives) with hardware FP64 atomics. x faces
+//      (k_face_adj_inv/dis<0>): one lane per face, the lanes of a wavefront
+//      holding consecutive faces of a row, contributions summed per cell by
+//      shuffles (one atomic per cell and variable). y and z faces
+//      (k_march_adj_inv/dis): marching wavefronts, the reverse of the forward
+//      marches. The inviscid and dissipative reverses run on two streams;
 //   3. k_adj_dbar (viscous): the transposed centred differences of Dbar,
 //      added to Wbar at every padded cell;
 //   4. k_adj_halo: the transposed halo fill, every halo cell's Wbar added to
@@ -247,168 +248,260 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restric
   }
 }
 
-// y and z faces, tiled: a block takes 64 consecutive x (one per lane) and
-// TF consecutive faces along D at one coordinate of the other transverse
-// axis, each wavefront TF / 4 of those faces in turn.
-// The contributions of the block's faces are added into an LDS tile of the
-// cells they touch (LDS FP64 atomics), and the tile is then added to memory,
-// one global atomic per nonzero tile entry: about four times fewer global
-// atomics than adding each face's contributions directly, with the loads
-// still coalesced along x.
-// Faces per tile along D: the inviscid kernel's tile holds 5 components, the
-// dissipative kernel's 8, so the dissipative tile stays short to keep its
-// LDS within three workgroups per CU.
-constexpr int kAdjTileFacesInv = 8;
-constexpr int kAdjTileFacesDis = 8;
+// ---------------------------------------------------------------------------
+// Marching face reverses along y and z (AX = 1, 2), the reverse counterparts
+// of the forward marches: a wavefront holds 64 consecutive x of one column
+// (other transverse coordinate, segment of g.seg cells along AX) and walks
+// its faces in order, keeping the stencil window in registers, so every cell
+// of the column is loaded once per segment instead of once per face that
+// touches it, and a cell's adjoint is added to memory once, when the last
+// face of the segment that touches it is done (one atomic per cell and
+// variable; a cell near a segment end gets a share from each of the two
+// segments). Launch shape: sweep_march_blocks<AX>.
 
-template <int D, int TF>
-__host__ __device__ __forceinline__ dim3 face_adj_tile_grid(const Geom& g) {
-  constexpr int OT = D == 1 ? 2 : 1;
-  const int nfc = (g.n[D] + 1 + TF - 1) / TF;
-  return dim3((unsigned)((g.n[0] + 63) / 64), (unsigned)(nfc * g.n[OT]));
+// Column, segment and first/last face of the marching wavefront; false for a
+// lane without a column. The segment of cells [s0, s1) owns faces s0 .. s1-1,
+// and the last segment also face n (the upper boundary).
+template <int AX>
+__device__ __forceinline__ bool march_adj_column(const Geom& g, int& i, int& o, int& s0, int& fe) {
+  constexpr int OT = AX == 1 ? 2 : 1;
+  const int logical = xcd_major_block(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int by = logical / gridDim.x, bx = logical - by * gridDim.x;
+  i = bx * 64 + (threadIdx.x & 63);
+  const int sl = g.seg;
+  const int nseg = (g.n[AX] + sl - 1) / sl;
+  const long long col = (long long)by * (kBlock >> 6) + (threadIdx.x >> 6);
+  if (i >= g.n[0] || col >= (long long)g.n[OT] * nseg) return false;
+  o = (int)(col / nseg);
+  const int seg = (int)(col - (long long)o * nseg);
+  s0 = seg * sl;
+  const int s1 = min(s0 + sl, g.n[AX]);
+  fe = s1 == g.n[AX] ? s1 : s1 - 1;
+  return true;
 }
 
-// Lane, x, first face of the tile, other-axis coordinate of a tiled launch.
-template <int D, int TF>
-__device__ __forceinline__ void face_adj_tile(const Geom& g, int& lane, int& x, int& f0, int& o) {
-  const int nfc = (g.n[D] + 1 + TF - 1) / TF;
-  lane = threadIdx.x & 63;
-  x = blockIdx.x * 64 + lane;
-  o = blockIdx.y / nfc;
-  f0 = (blockIdx.y - o * nfc) * TF;
+template <int AX>
+__device__ __forceinline__ long long march_adj_cell(const Geom& g, int i, int o, int a) {
+  return AX == 1 ? cell_at(g, i, a, o) : cell_at(g, i, o, a);
 }
 
-template <int D>
-__device__ __forceinline__ long long tile_cell(const Geom& g, int x, int c, int o) {
-  return D == 1 ? cell_at(g, x, c, o) : cell_at(g, x, o, c);
-}
+// Inviscid part. Face f (between cells f-1 and f) takes its left state from
+// the reconstruction pair of cell f-1 and its right state from that of cell
+// f (§3.3): the wavefront computes the pair of cell f at face f, reverses the
+// HLLC flux of face f, and then reverses the pair of cell f-1, whose two
+// cotangents (from faces f-1 and f) are both known, into cells f-3 .. f+1.
+// The window holds cells f-3 .. f+2; the per-cell adjoint sums of the five
+// cells a pair reverse touches live in a lane-private LDS ring (the register
+// file holds the window and the HLLC reverse). A pair shared with the
+// neighbouring segment is reversed in both, each with its own face's share of
+// the cotangent (the reverse is linear in it). The window, the HLLC reverse
+// and the carried states need about 380 registers: the kernel runs one
+// wavefront per SIMD (at two it spills, and ran 1.8x slower).
+constexpr int kMarchRing = 5;
 
-// Zero an LDS tile of nv components.
-__device__ __forceinline__ void tile_zero(double* tile, int n) {
-  for (int e = threadIdx.x; e < n; e += kBlock) tile[e] = 0.0;
-  __syncthreads();
-}
-
-// Add the LDS tile (component v at base[v], rows of cells f0-3+r, TF + 5
-// rows) to memory.
-template <int D, int TF>
-__device__ __forceinline__ void tile_flush(const Geom& g, const double* tile, int nv, double* const* base, int f0,
-                                           int o) {
-  constexpr int rows = TF + 5;
-  __syncthreads();
-  const int x0 = blockIdx.x * 64;
-  for (int e = threadIdx.x; e < nv * rows * 64; e += kBlock) {
-    const double val = tile[e];
-    if (val == 0.0) continue;  // only cells a face of the tile touched are nonzero
-    const int l = e & 63;
-    const int r = (e >> 6) % rows;
-    const int v = (e >> 6) / rows;
-    unsafeAtomicAdd(base[v] + tile_cell<D>(g, x0 + l, f0 - 3 + r, o), val);
+template <int AX>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1)))
+k_march_adj_inv(const double* __restrict__ P, const double* __restrict__ Rbar, double rscale, double* Wbar,
+                Geom g) {
+  __shared__ double ring[kMarchRing * 5 * kBlock];
+  int i, o, s0, fe;
+  if (!march_adj_column<AX>(g, i, o, s0, fe)) return;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int e = 0; e < kMarchRing * 5; ++e) ring[e * kBlock + tid] = 0.0;
+  const long long st = g.s[AX], vs = g.vs;
+  const int n = g.n[AX];
+  const double gs_scale = rscale * g.idx[AX];
+  long long c = march_adj_cell<AX>(g, i, o, s0 - 3);  // window cell 0: cell f-3 of face f = s0
+  double w[6][5];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) load_prims(P, vs, c + m * st, w[m]);
+  double WLc[5], WRbc[5], rl[5];
+  {
+    double unused[5];
+    double q[5][5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) q[m][v] = w[m][v];
+    recon_pair<SCH_JS>(q, WLc, unused);  // cell s0-1: left state of face s0
   }
-}
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_adj_inv_tiled(const double* P, const double* __restrict__ Rbar,
-                                                               double rscale, double* Wbar, Geom g) {
-  constexpr int TF = kAdjTileFacesInv, rows = TF + 5;
-  __shared__ double tile[5 * rows * 64];
-  int lane, x, f0, o;
-  face_adj_tile<D, TF>(g, lane, x, f0, o);
-  tile_zero(tile, 5 * rows * 64);
-  const int w = threadIdx.x >> 6;
-  constexpr int per_wave = TF / (kBlock / 64);
-  const long long st = g.s[D];
-  for (int it = 0; it < per_wave; ++it) {
-    const int fl = w * per_wave + it;  // face of the tile, 0 .. TF-1
-    const int f = f0 + fl;
-    if (x >= g.n[0] || f > g.n[D]) continue;
-    const long long cf = tile_cell<D>(g, x, f, o);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    WRbc[v] = 0.0;  // face s0-1 belongs to the previous segment
+    rl[v] = s0 >= 1 ? Rbar[v * vs + c + 2 * st] : 0.0;
+  }
+  int r0 = 0;  // ring slot of window cell 0
+  for (int f = s0; f <= fe; ++f) {
+    const bool more = f < fe;
+    double nq[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, rr[5];
+    if (more) load_prims(P, vs, c + 6 * st, nq);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) rr[v] = f < n ? Rbar[v * vs + c + 3 * st] : 0.0;
     double Gb[5];
-    if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) continue;
-    const long long c0 = cf - 3 * st;
-    double WL[5], WR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Gb[v] = gs_scale * (rr[v] - rl[v]);
+    // pair of cell f (window cells 1..5): left state of face f+1, right state of face f
+    double nWL[5], WR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) weno5_pair(w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], nWL[v], WR[v]);
+    double WLb[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WRb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    hllc_rev<AX>(g.gamma, g.gm1i, WLc, WR, Gb, WLb, WRb);
+    // pair of cell f-1 (window cells 0..4) with the cotangents of faces f and f-1
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double* q = P + v * g.vs + c0;
-      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
-      WL[v] = weno5(q0, q1, q2, q3, q4);
-      WR[v] = weno5(q5, q4, q3, q2, q1);
+      double gq[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      weno5_pair_rev(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], WLb[v], WRbc[v], gq);
+#pragma unroll
+      for (int m = 0; m < 5; ++m) {
+        const int slot = r0 + m < kMarchRing ? r0 + m : r0 + m - kMarchRing;
+        ring[(slot * 5 + v) * kBlock + tid] += gq[m];
+      }
     }
-    double WLb[5] = {0, 0, 0, 0, 0}, WRb[5] = {0, 0, 0, 0, 0};
-    hllc_rev<D>(g.gamma, g.gm1i, WL, WR, Gb, WLb, WRb);
-    asm volatile("" ::: "memory");  // reload the stencils below instead of keeping them live
+    // cell f-3 is complete for this segment
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double* q = P + v * g.vs + c0;
-      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
-      double gs[6] = {0, 0, 0, 0, 0, 0};
-      weno5_rev(q0, q1, q2, q3, q4, WLb[v], gs);
-      double gr[5] = {0, 0, 0, 0, 0};
-      weno5_rev(q5, q4, q3, q2, q1, WRb[v], gr);
+      double& a = ring[(r0 * 5 + v) * kBlock + tid];
+      atomic_add(Wbar + v * vs + c, a);
+      a = 0.0;
+    }
+    r0 = r0 + 1 < kMarchRing ? r0 + 1 : 0;
 #pragma unroll
-      for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
+    for (int v = 0; v < 5; ++v) {
 #pragma unroll
-      for (int m = 0; m < 6; ++m) atomicAdd(&tile[(v * rows + fl + m) * 64 + lane], gs[m]);
+      for (int m = 0; m < 5; ++m) w[m][v] = w[m + 1][v];
+      w[5][v] = nq[v];
+      WLc[v] = nWL[v];
+      WRbc[v] = WRb[v];
+      rl[v] = rr[v];
+    }
+    c += st;
+  }
+  // the pair of cell fe (window cells 0..4) with the cotangent of face fe only
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double gq[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    weno5_pair_rev(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], 0.0, WRbc[v], gq);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const int slot = r0 + m < kMarchRing ? r0 + m : r0 + m - kMarchRing;
+      atomic_add(Wbar + v * vs + c + m * st, ring[(slot * 5 + v) * kBlock + tid] + gq[m]);
     }
   }
-  double* base[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) base[v] = Wbar + v * g.vs;
-  tile_flush<D, TF>(g, tile, 5, base, f0, o);
 }
 
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_adj_dis_tiled(const double* __restrict__ P,
-                                                               const double* __restrict__ Rbar, double rscale,
-                                                               double* Wbar, double* Dbar, Geom g) {
-  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  // components: u, v, w, T~ of Wbar, then the four derivative inputs of Dbar
-  constexpr int TF = kAdjTileFacesDis, rows = TF + 5;
-  __shared__ double tile[8 * rows * 64];
-  int lane, x, f0, o;
-  face_adj_tile<D, TF>(g, lane, x, f0, o);
-  tile_zero(tile, 8 * rows * 64);
-  const int w = threadIdx.x >> 6;
-  constexpr int per_wave = TF / (kBlock / 64);
-  const long long st = g.s[D];
-  for (int it = 0; it < per_wave; ++it) {
-    const int fl = w * per_wave + it;
-    const int f = f0 + fl;
-    if (x >= g.n[0] || f > g.n[D]) continue;
-    const long long cf = tile_cell<D>(g, x, f, o);
-    double Gb[5];
-    if (!face_gbar<D>(g, Rbar, rscale, cf, f, Gb)) continue;
-    const long long c0 = cf - 3 * st;
-    FaceWindow win;
+// Dissipative part (viscous and heat flux). Face f reads window cells
+// f-2 .. f+1 (u, v, w, T~ and the four tangential-derivative inputs of each,
+// formed from P as in the forward marches); the adjoints of those inputs
+// (Wbar u, v, w, T~ and Dbar) are summed in registers and cell f-2 is added
+// to memory after face f.
+template <int AX>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k_march_adj_dis(const double* __restrict__ P, const double* __restrict__ Rbar, double rscale, double* Wbar,
+                double* Dbar, Geom g) {
+  constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
+  int i, o, s0, fe;
+  if (!march_adj_column<AX>(g, i, o, s0, fe)) return;
+  const long long st = g.s[AX], vs = g.vs;
+  const int n = g.n[AX];
+  const double gs_scale = rscale * g.idx[AX];
+  Geom gd = g;
+  gd.inviscid = 0;  // the inviscid part is k_march_adj_inv
+  long long c = march_adj_cell<AX>(g, i, o, s0 - 2);  // window cell 0: cell f-2 of face f = s0
+  // q[1..4] (u, v, w) and tg[0..3]: cells f-2 .. f+1. The heat flux is
+  // linear in T~, so its reverse needs no T~ values.
+  FaceWindow win;
 #pragma unroll
-    for (int m = 1; m < 5; ++m)
+  for (int m = 0; m < 6; ++m)
 #pragma unroll
-      for (int v = 1; v < 4; ++v) win.q[m][v] = P[v * g.vs + c0 + m * st];
+    for (int v = 0; v < 5; ++v) win.q[m][v] = 0.0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      win.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
-      if (g.viscous) tangential_at<D>(g, P, c0 + (1 + m) * st, win.tg[m]);
-    }
-    Geom gd = g;
-    gd.inviscid = 0;  // the inviscid part is k_face_adj_inv_tiled
-    struct TileSink {
-      double* tile;
-      int fl, lane;
-      bool act[4];
-      __device__ void q(int m, int v, double val) {
-        const int c = v == 5 ? 3 : v - 1;  // u, v, w, T~
-        atomicAdd(&tile[(c * rows + fl + m) * 64 + lane], val);
-      }
-      __device__ void tg(int m, int k, double val) {
-        if (act[k]) atomicAdd(&tile[((4 + k) * rows + fl + m) * 64 + lane], val);
-      }
-    } sink{tile, fl, lane, {g.act[T1] != 0, g.act[T1] != 0, g.act[T2] != 0, g.act[T2] != 0}};
-    face_flux_rev<D>(gd, win, Gb, sink);
+  for (int m = 0; m < 4; ++m) {
+    win.T[m] = 0.0;
+#pragma unroll
+    for (int v = 1; v < 4; ++v) win.q[1 + m][v] = g.viscous ? P[v * vs + c + m * st] : 0.0;
+    if (g.viscous) tangential_at<AX>(g, P, c + m * st, win.tg[m]);
+    else
+#pragma unroll
+      for (int k = 0; k < 4; ++k) win.tg[m][k] = 0.0;
   }
-  const int comp[4] = {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2};
-  double* base[8] = {Wbar + 1 * g.vs, Wbar + 2 * g.vs, Wbar + 3 * g.vs, Wbar + 5 * g.vs,
-                     Dbar + comp[0] * g.vs, Dbar + comp[1] * g.vs, Dbar + comp[2] * g.vs, Dbar + comp[3] * g.vs};
-  tile_flush<D, TF>(g, tile, 8, base, f0, o);
+  struct RegSink {
+    double qb[4][4];   // window cells 0..3: u, v, w, T~
+    double tgb[4][4];  // window cells 0..3: derivative inputs
+    __device__ void q(int m, int v, double x) { qb[m - 1][v == 5 ? 3 : v - 1] += x; }
+    __device__ void tg(int m, int k, double x) { tgb[m - 1][k] += x; }
+  } sink;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sink.qb[m][v] = sink.tgb[m][v] = 0.0;
+  double rl[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) rl[v] = s0 >= 1 ? Rbar[v * vs + c + st] : 0.0;
+  const int wslot[4] = {1, 2, 3, 5};  // u, v, w, T~ in Wbar
+  const int comp[4] = {AX * 3 + T1, T1 * 3 + T1, AX * 3 + T2, T2 * 3 + T2};
+  const bool tact[4] = {g.act[T1] != 0, g.act[T1] != 0, g.act[T2] != 0, g.act[T2] != 0};
+  for (int f = s0; f <= fe; ++f) {
+    const bool more = f < fe;
+    double nq[3] = {0.0, 0.0, 0.0}, ntr[4][4], rr[5];
+    if (more && g.viscous) {
+#pragma unroll
+      for (int v = 1; v < 4; ++v) nq[v - 1] = P[v * vs + c + 4 * st];
+      tangential_load<AX>(g, P, c + 4 * st, ntr);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) rr[v] = f < n ? Rbar[v * vs + c + 2 * st] : 0.0;
+    double Gb[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Gb[v] = gs_scale * (rr[v] - rl[v]);
+    face_flux_rev<AX>(gd, win, Gb, sink);
+    // cell f-2 is complete for this segment
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (v == 3 ? g.heat : g.viscous) atomic_add(Wbar + wslot[v] * vs + c, sink.qb[0][v]);
+    }
+    if (g.viscous) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (tact[k]) atomic_add(Dbar + comp[k] * vs + c, sink.tgb[0][k]);
+    }
+    double ntg[4] = {0.0, 0.0, 0.0, 0.0};
+    if (more && g.viscous) tangential_combine<AX>(g, ntr, ntg);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sink.qb[m][v] = sink.qb[m + 1][v];
+        sink.tgb[m][v] = sink.tgb[m + 1][v];
+        win.tg[m][v] = win.tg[m + 1][v];
+      }
+#pragma unroll
+      for (int v = 1; v < 4; ++v) win.q[1 + m][v] = win.q[2 + m][v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      sink.qb[3][v] = sink.tgb[3][v] = 0.0;
+      win.tg[3][v] = ntg[v];
+    }
+#pragma unroll
+    for (int v = 1; v < 4; ++v) win.q[4][v] = nq[v - 1];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) rl[v] = rr[v];
+    c += st;
+  }
+  // cells fe-1 .. fe+1 (window cells 0..2) hold the rest of this segment's sums
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (v == 3 ? g.heat : g.viscous) atomic_add(Wbar + wslot[v] * vs + c + m * st, sink.qb[m][v]);
+    }
+    if (g.viscous) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (tact[k]) atomic_add(Dbar + comp[k] * vs + c + m * st, sink.tgb[m][k]);
+    }
+  }
 }
 
 // Transposed centred differences of Dbar at padded cell cc (coordinates q),

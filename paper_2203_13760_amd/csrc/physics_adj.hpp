@@ -68,6 +68,55 @@ __host__ __device__ __forceinline__ void weno5_rev(double a, double b, double c,
   g[4] += t2b + u2b - P2b;
 }
 
+// Reverse of weno5_pair (both face values of the centre cell c of the stencil
+// a..e, sharing the three smoothness indicators): given the adjoints qrb of
+// the right-face value qr and qlb of the left-face value ql, g[0..4] +=
+// (d qr/d(a..e)) qrb + (d ql/d(a..e)) qlb. With qr = nr / (6 dr) and
+// ql = nl / (6 dl), one reciprocal 1/(6 dr dl) serves both, as in the forward.
+__host__ __device__ __forceinline__ void weno5_pair_rev(double a, double b, double c, double d, double e,
+                                                         double qrb, double qlb, double* g) {
+  constexpr double k13 = 13.0 / 12.0;
+  constexpr double eps = 1.0e-6;
+  // ---- forward recompute (same expressions as weno5_pair)
+  const double Db = a - 2.0 * b + c, Dc = b - 2.0 * c + d, Dd = c - 2.0 * d + e;
+  const double dm = c - b, dp = d - c;
+  const double tL = Db + 2.0 * dm, tC = dm + dp, tR = Dd - 2.0 * dp;
+  const double eL = eps + (k13 * Db * Db + 0.25 * tL * tL);
+  const double eC = eps + (k13 * Dc * Dc + 0.25 * tC * tC);
+  const double eR = eps + (k13 * Dd * Dd + 0.25 * tR * tR);
+  const double sL = eL * eL, sC = eC * eC, sR = eR * eR;
+  const double pCR = sC * sR, pLR = sL * sR, pLC = sL * sC;
+  const double PR0 = 2.0 * a - 7.0 * b + 11.0 * c, PR1 = -b + 5.0 * c + 2.0 * d, PR2 = 2.0 * c + 5.0 * d - e;
+  const double PL0 = 2.0 * e - 7.0 * d + 11.0 * c, PL1 = -d + 5.0 * c + 2.0 * b, PL2 = 2.0 * c + 5.0 * b - a;
+  const double nr = 0.1 * pCR * PR0 + 0.6 * pLR * PR1 + 0.3 * pLC * PR2;
+  const double nl = 0.1 * pLC * PL0 + 0.6 * pLR * PL1 + 0.3 * pCR * PL2;
+  const double dr = 0.1 * pCR + 0.6 * pLR + 0.3 * pLC;
+  const double dl = 0.1 * pLC + 0.6 * pLR + 0.3 * pCR;
+  const double r = div_nr(1.0, 6.0 * (dr * dl));
+  const double ir = dl * r, il = dr * r;  // 1/(6 dr), 1/(6 dl)
+  // ---- reverse
+  const double nrb = qrb * ir, nlb = qlb * il;
+  const double drb = -6.0 * (nr * ir) * nrb, dlb = -6.0 * (nl * il) * nlb;  // d(n/(6d))/dd = -q/d
+  const double pCRb = 0.1 * PR0 * nrb + 0.3 * PL2 * nlb + 0.1 * drb + 0.3 * dlb;
+  const double pLRb = 0.6 * (PR1 * nrb + PL1 * nlb + drb + dlb);
+  const double pLCb = 0.3 * PR2 * nrb + 0.1 * PL0 * nlb + 0.3 * drb + 0.1 * dlb;
+  const double PR0b = 0.1 * pCR * nrb, PR1b = 0.6 * pLR * nrb, PR2b = 0.3 * pLC * nrb;
+  const double PL0b = 0.1 * pLC * nlb, PL1b = 0.6 * pLR * nlb, PL2b = 0.3 * pCR * nlb;
+  const double sLb = pLRb * sR + pLCb * sC, sCb = pCRb * sR + pLCb * sL, sRb = pCRb * sC + pLRb * sL;
+  const double eLb = 2.0 * eL * sLb, eCb = 2.0 * eC * sCb, eRb = 2.0 * eR * sRb;
+  const double tLb = 0.5 * tL * eLb, tCb = 0.5 * tC * eCb, tRb = 0.5 * tR * eRb;
+  const double Dbb = 2.0 * k13 * Db * eLb + tLb;
+  const double Dcb = 2.0 * k13 * Dc * eCb;
+  const double Ddb = 2.0 * k13 * Dd * eRb + tRb;
+  const double dmb = 2.0 * tLb + tCb, dpb = tCb - 2.0 * tRb;
+  g[0] += Dbb + 2.0 * PR0b - PL2b;
+  g[1] += -2.0 * Dbb + Dcb - dmb - 7.0 * PR0b - PR1b + 2.0 * PL1b + 5.0 * PL2b;
+  g[2] += Dbb - 2.0 * Dcb + Ddb + dmb - dpb + 11.0 * PR0b + 5.0 * PR1b + 2.0 * PR2b + 11.0 * PL0b + 5.0 * PL1b +
+          2.0 * PL2b;
+  g[3] += Dcb - 2.0 * Ddb + dpb + 2.0 * PR1b + 5.0 * PR2b - 7.0 * PL0b - PL1b;
+  g[4] += Ddb - PR2b + 2.0 * PL0b;
+}
+
 // Reverse of hllc<D>: given Fbar (physical slot order) accumulate WLb, WRb
 // (physical slot order).
 template <int D>
