@@ -490,12 +490,17 @@ static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, 
                             hipStream_t sd) {
   const Geom& g = s->g;
   if constexpr (D == 0) {
-    long long faces = (long long)g.n[0] * g.n[1] * g.n[2] / g.n[D] * (g.n[D] + 1);
-    const dim3 grid(grid_for(faces, 1LL << 31));
+    const long long rows = (long long)g.n[1] * g.n[2];
+    auto blocks = [&](long long slots, int per_wave) {
+      const long long waves = (slots + per_wave - 1) / per_wave;
+      return dim3((unsigned)((waves + (kBlock / 64) - 1) / (kBlock / 64)));
+    };
     if (g.inviscid)
-      hipLaunchKernelGGL(k_face_adj_inv<D>, grid, dim3(kBlock), 0, st, P, Rbar, rscale, s->Wbar, g);
+      hipLaunchKernelGGL(k_xadj_inv, blocks((g.n[0] + 6) * rows, kXInvNew), dim3(kBlock), 0, st, P, Rbar, rscale,
+                         s->Wbar, g);
     if (g.viscous || g.heat)
-      hipLaunchKernelGGL(k_face_adj_dis<D>, grid, dim3(kBlock), 0, sd, P, Rbar, rscale, s->Wbar, s->Dbar, g);
+      hipLaunchKernelGGL(k_xadj_dis, blocks((g.n[0] + 1 + kXDisCtx) * rows, kXDisNew), dim3(kBlock), 0, sd, P,
+                         Rbar, rscale, s->Wbar, s->Dbar, g);
   } else {
     int gx = 0, gy = 0;
     sweep_march_blocks<D>(g, gx, gy);

@@ -8,9 +8,9 @@
 //      reverses it (physics_adj.hpp), and its contributions go to Wbar
 //      (rho,u,v,w,p,T~ of the stencil cells) and Dbar (the adjoints of the
 //      centred derivatives) with hardware FP64 atomics. x faces
-//      (k_face_adj_inv/dis<0>): one lane per face, the lanes of a wavefront
-//      holding consecutive faces of a row, contributions summed per cell by
-//      shuffles (one atomic per cell and variable). y and z faces
+//      (k_xadj_inv/dis): one lane per cell or face of a row, inputs passed
+//      between lanes and contributions summed per cell by wavefront shifts
+//      (one atomic per cell and variable). y and z faces
 //      (k_march_adj_inv/dis): marching wavefronts, the reverse of the forward
 //      marches. The inviscid and dissipative reverses run on two streams;
 //   3. k_adj_dbar (viscous): the transposed centred differences of Dbar,
@@ -66,46 +66,6 @@ __device__ __forceinline__ bool face_coords(const Geom& g, int t, int& i, int& j
   }
 }
 
-// Summation across a wavefront whose lanes hold consecutive faces of rows.
-// A lane's contribution to cell f + d of its row (d in -3..2) belongs to the
-// lane holding face f + d of the same row (the cell's "owner"); the owner adds
-// up what it receives and adds the total to memory with one atomic. A
-// contribution whose owner is not in the wavefront (row ends, wavefront edges,
-// halo cells) is added to memory by its lane directly.
-struct LaneSum {
-  int lane;
-  int key;            // column of a lane with a face, -2 without a face
-  bool sent[6];       // offset d = idx - 3: the owner lane + d exists
-  bool got[6];        //                     the lane - d exists (sends to me)
-
-  // has: the lane holds a face; col: its column, or -1 when the lanes of the
-  // wavefront hold faces of different columns (every contribution but the
-  // lane's own cell is then added directly)
-  __device__ __forceinline__ void init(int lane_, bool has, int col) {
-    lane = lane_;
-    key = has ? col : -2;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      const int d = e - 3;
-      const int dst = lane + d, src = lane - d;
-      const int kd = __shfl(key, dst & 63, 64), ks = __shfl(key, src & 63, 64);
-      if (d == 0) {
-        sent[e] = got[e] = has;
-      } else {
-        sent[e] = has && col >= 0 && dst >= 0 && dst < 64 && kd == key;
-        got[e] = has && col >= 0 && src >= 0 && src < 64 && ks == key;
-      }
-    }
-  }
-  // Contribution x to cell f + d (address addr): returns the share this lane
-  // collects as owner from lane - d; adds x to memory when no owner exists.
-  __device__ __forceinline__ double pass(double x, int d, double* addr) const {
-    const int e = d + 3;
-    const double y = __shfl(x, (lane - d) & 63, 64);
-    if (key != -2 && !sent[e]) atomic_add(addr, x);
-    return got[e] ? y : 0.0;
-  }
-};
 // Face adjoint Gbar from Rbar (read as rscale * Rbar, interior cells only).
 template <int D>
 __device__ __forceinline__ bool face_gbar(const Geom& g, const double* __restrict__ Rbar, double rscale, long long cf,
@@ -123,82 +83,134 @@ __device__ __forceinline__ bool face_gbar(const Geom& g, const double* __restric
   return any != 0.0;
 }
 
-// Inviscid part of the face adjoint: WENO5-JS forward, HLLC reverse, then the
-// WENO reverse one variable at a time with that variable's stencil reloaded,
-// so the window is not held in registers across the HLLC reverse. Every lane
-// takes part in the shuffles; lanes without a face (or with a zero face
-// adjoint) contribute zeros.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_adj_inv(const double* P, const double* __restrict__ Rbar,
-                                                         double rscale, double* Wbar, Geom g) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i = 0, j = 0, k = 0, f = 0, col = 0;
-  const bool has = face_coords<D>(g, t, i, j, k, f, col);
-  if (!has) i = j = k = f = 0;  // a valid cell for the (unused) address arithmetic
-  LaneSum ls;
-  ls.init(threadIdx.x & 63, has, col);
-  const long long st = g.s[D];
-  const long long cf = cell_at(g, i, j, k);  // cell f: the face lies between f-1 and f
-  const long long c0 = cf - 3 * st;          // window cell 0 = cell f-3
-  double Gb[5] = {0, 0, 0, 0, 0};
-  const bool active = has && face_gbar<D>(g, Rbar, rscale, cf, f, Gb);
-  double WLb[5] = {0, 0, 0, 0, 0}, WRb[5] = {0, 0, 0, 0, 0};
-  if (active) {
-    double WL[5], WR[5];
+// ---------------------------------------------------------------------------
+// x faces: one lane per slot of a row, as in the forward x sweep; the
+// neighbouring cells of a row are neighbouring lanes, so a cell's inputs are
+// loaded once and passed to the faces that use them, and the contributions to
+// a cell are summed across lanes into the lane that owns it (DPP wavefront
+// shifts, no LDS), which adds the sum to memory with one atomic per variable.
+// Rows are taken in the band-major order of the forward x sweep.
+
+// Inviscid part: the slots of a row are its cells -3 .. n+2 (every cell a
+// reconstruction reaches). The lane of cell x forms the reconstruction pair
+// of x (cells x-1 .. n have one, §3.3), reverses the HLLC flux of face x
+// (between x-1 and x; its left state is the pair of x-1, one lane below), and
+// then reverses the pair of x with the cotangents of its faces x (own) and
+// x+1 (one lane above), into cells x-2 .. x+2 (lanes -2 .. +2). A wavefront
+// takes 64 consecutive slots of which the middle kXInvNew reverse their
+// pairs; two slots at each end overlap the neighbouring wavefronts and only
+// supply shuffles and collect sums.
+constexpr int kXInvNew = 60;
+
+__global__ void __launch_bounds__(kBlock) k_xadj_inv(const double* P, const double* __restrict__ Rbar,
+                                                     double rscale, double* Wbar, Geom g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (xcd_major_block(blockIdx.x, gridDim.x) * kBlock + (int)threadIdx.x) >> 6;
+  const int n = g.n[0];
+  const int S = n + 6;
+  const int total = S * g.n[1] * g.n[2];
+  const int first = wave * kXInvNew;
+  if (first >= total) return;  // uniform per wavefront
+  const int gs = first - 2 + lane;
+  const bool inrange = gs >= 0 && gs < total;
+  int x = 0, j = 0, k = 0;
+  if (inrange) {
+    const int row = gs / S;
+    x = gs - row * S - 3;
+    x_row(g, row, j, k);
+  }
+  const bool pair = inrange && x >= -1 && x <= n;     // cell x has a reconstruction pair
+  const bool face = inrange && x >= 0 && x <= n && lane >= 1;  // face x, with its left cell in the wavefront
+  const bool rev = pair && lane >= 2 && lane < 2 + kXInvNew;
+  const long long cx = cell_at(g, x, j, k);
+  const long long c0 = cell_at(g, (pair ? x : 0) - 2, j, k);  // window: cells x-2 .. x+2
+  const double gsc = rscale * g.idx[0];
+  double WLb[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, WRb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  {
+    double q[5][5];
+#pragma unroll
+    for (int m = 0; m < 5; ++m) load_prims(P, g.vs, c0 + m, q[m]);
+    double qr[5], ql[5];
+    recon_pair<SCH_JS>(q, qr, ql);  // right face of x (left state of face x+1), left face of x
+    double WL[5], Gb[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double* q = P + v * g.vs + c0;
-      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
-      WL[v] = weno5(q0, q1, q2, q3, q4);
-      WR[v] = weno5(q5, q4, q3, q2, q1);
+      const double r = inrange && x >= 0 && x < n ? Rbar[v * g.vs + cx] : 0.0;
+      Gb[v] = gsc * (r - lane_shr1(r));  // (Rbar_x - Rbar_{x-1}) / dx
+      WL[v] = lane_shr1(qr[v]);
     }
-    hllc_rev<D>(g.gamma, g.gm1i, WL, WR, Gb, WLb, WRb);
+    if (face) hllc_rev<0>(g.gamma, g.gm1i, WL, ql, Gb, WLb, WRb);
   }
-  asm volatile("" ::: "memory");  // reload the stencils below instead of keeping them live
+  asm volatile("" ::: "memory");  // reload the window below instead of keeping it live
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    double gs[6] = {0, 0, 0, 0, 0, 0};
-    if (active) {
+    const double qrb = lane_shl1(WLb[v]);  // face x+1: cotangent of the right-face value of x
+    double gq[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (rev) {
       const double* q = P + v * g.vs + c0;
-      const double q0 = q[0], q1 = q[st], q2 = q[2 * st], q3 = q[3 * st], q4 = q[4 * st], q5 = q[5 * st];
-      weno5_rev(q0, q1, q2, q3, q4, WLb[v], gs);
-      double gr[5] = {0, 0, 0, 0, 0};
-      weno5_rev(q5, q4, q3, q2, q1, WRb[v], gr);
-#pragma unroll
-      for (int m = 0; m < 5; ++m) gs[5 - m] += gr[m];
+      weno5_pair_rev(q[0], q[1], q[2], q[3], q[4], qrb, WRb[v], gq);
     }
-    double* wv = Wbar + v * g.vs + c0;
-    double own = 0.0;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) own += ls.pass(gs[m], m - 3, wv + m * st);
-    if (has) atomic_add(wv + 3 * st, own);
+    // cell x receives gq[4] from lane - 2, gq[3] from lane - 1, gq[2] from
+    // itself, gq[1] from lane + 1 and gq[0] from lane + 2
+    const double up = lane_shr1(lane_shr1(gq[4]) + gq[3]);
+    const double down = lane_shl1(lane_shl1(gq[0]) + gq[1]);
+    if (inrange) atomic_add(Wbar + v * g.vs + cx, up + gq[2] + down);
   }
 }
 
-// Dissipative part of the face adjoint (viscous and heat flux).
-// The cell-centred tangential derivatives are formed from P as in the forward
-// sweeps; their adjoints go to Dbar and are transposed in k_adj_fold. The
-// window's adjoints (cells 1..4: u, v, w, T~ and the four derivative inputs)
-// are collected in registers, then summed across the wavefront.
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restrict__ P,
-                                                         const double* __restrict__ Rbar, double rscale,
-                                                         double* Wbar, double* Dbar, Geom g) {
-  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int i = 0, j = 0, k = 0, f = 0, col = 0;
-  const bool has = face_coords<D>(g, t, i, j, k, f, col);
-  if (!has) i = j = k = f = 0;
-  LaneSum ls;
-  ls.init(threadIdx.x & 63, has, col);
-  const long long st = g.s[D];
-  const long long cf = cell_at(g, i, j, k);
-  const long long c0 = cf - 3 * st;
-  double Gb[5] = {0, 0, 0, 0, 0};
-  const bool active = has && face_gbar<D>(g, Rbar, rscale, cf, f, Gb);
+// Dissipative part: slot s of a row is face f = s - 3 (f = -3 .. n), and its
+// lane loads the inputs of cell f+1 (u, v, w and the four tangential
+// derivatives). Face f takes those of cells f-2 .. f+1 from itself and the
+// three lanes below, and its contributions to those cells flow back down to
+// them. A wavefront takes 64 consecutive slots; the first three overlap its
+// predecessor and only supply inputs and collect sums. The heat flux is
+// linear in T~, so its reverse needs no T~ values.
+constexpr int kXDisCtx = 3;
+constexpr int kXDisNew = 64 - kXDisCtx;
+
+__global__ void __launch_bounds__(kBlock) k_xadj_dis(const double* __restrict__ P, const double* __restrict__ Rbar,
+                                                     double rscale, double* Wbar, double* Dbar, Geom g) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (xcd_major_block(blockIdx.x, gridDim.x) * kBlock + (int)threadIdx.x) >> 6;
+  const int n = g.n[0];
+  const int S = n + 1 + kXDisCtx;
+  const int total = S * g.n[1] * g.n[2];
+  const int first = wave * kXDisNew;
+  if (first >= total) return;  // uniform per wavefront
+  const int gs = first - kXDisCtx + lane;
+  const bool inrange = gs >= 0 && gs < total;
+  int f = 0, j = 0, k = 0;
+  if (inrange) {
+    const int row = gs / S;
+    f = gs - row * S - kXDisCtx;
+    x_row(g, row, j, k);
+  }
+  const bool face = inrange && f >= 0 && lane >= kXDisCtx;
+  const long long co = cell_at(g, inrange ? f + 1 : 0, j, k);  // the lane's cell f+1
+  // inputs of cell f+1, then of cells f, f-1, f-2 from the lanes below
+  double u[4][3], d[4][4], r[3][5];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) u[3][v] = g.viscous ? P[(1 + v) * g.vs + co] : 0.0;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) d[3][kk] = 0.0;
+  if (g.viscous) tangential_at_flat<0>(g, P, co, d[3]);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) r[0][v] = inrange && f + 1 >= 0 && f + 1 < n ? Rbar[v * g.vs + co] : 0.0;
+#pragma unroll
+  for (int m = 2; m >= 0; --m) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) u[m][v] = lane_shr1(u[m + 1][v]);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) d[m][kk] = lane_shr1(d[m + 1][kk]);
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    r[1][v] = lane_shr1(r[0][v]);  // cell f
+    r[2][v] = lane_shr1(r[1][v]);  // cell f-1
+  }
   struct RegSink {
-    double qb[4][4];   // window cells 1..4: u, v, w, T~
-    double tgb[4][4];  // window cells 1..4: derivative inputs
+    double qb[4][4];   // cells f-2 .. f+1: u, v, w, T~
+    double tgb[4][4];  // cells f-2 .. f+1: derivative inputs
     __device__ void q(int m, int v, double x) { qb[m - 1][v == 5 ? 3 : v - 1] += x; }
     __device__ void tg(int m, int kk, double x) { tgb[m - 1][kk] += x; }
   } sink;
@@ -206,44 +218,55 @@ __global__ void __launch_bounds__(kBlock) k_face_adj_dis(const double* __restric
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int v = 0; v < 4; ++v) sink.qb[m][v] = sink.tgb[m][v] = 0.0;
-  if (active) {
+  if (face) {
     FaceWindow w;
 #pragma unroll
-    for (int m = 1; m < 5; ++m)
+    for (int m = 0; m < 6; ++m)
 #pragma unroll
-      for (int v = 1; v < 4; ++v) w.q[m][v] = P[v * g.vs + c0 + m * st];
+      for (int v = 0; v < 5; ++v) w.q[m][v] = 0.0;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      w.T[m] = P[5 * g.vs + c0 + (1 + m) * st];
-      if (g.viscous) tangential_at<D>(g, P, c0 + (1 + m) * st, w.tg[m]);
+      w.T[m] = 0.0;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) w.q[1 + m][1 + v] = u[m][v];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) w.tg[m][kk] = d[m][kk];
     }
+    const double gsc = rscale * g.idx[0];
+    double Gb[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) Gb[v] = gsc * (r[1][v] - r[2][v]);
     Geom gd = g;
-    gd.inviscid = 0;  // the inviscid part is k_face_adj_inv
-    face_flux_rev<D>(gd, w, Gb, sink);
+    gd.inviscid = 0;  // the inviscid part is k_xadj_inv
+    face_flux_rev<0>(gd, w, Gb, sink);
   }
-  // window cell m (1..4) is cell f + (m - 3)
+  // cell f+1 collects its share from faces f, f+1, f+2, f+3 (this lane and
+  // the three above), up to the end of its row
+  const bool above = inrange && f < n;
+  auto gather = [&](const double (&c)[4][4], int v) {
+    double a = c[0][v];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) {
+      const double b = lane_shl1(a);  // every lane takes part in the shift
+      a = (above ? b : 0.0) + c[m][v];
+    }
+    return a;
+  };
   const int wslot[4] = {1, 2, 3, 5};  // u, v, w, T~ in Wbar
+  const int comp[4] = {0 * 3 + 1, 1 * 3 + 1, 0 * 3 + 2, 2 * 3 + 2};
+  const bool tact[4] = {g.act[1] != 0, g.act[1] != 0, g.act[2] != 0, g.act[2] != 0};
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    if (v == 3 && !g.heat) continue;
-    if (v < 3 && !g.viscous) continue;
-    double* wv = Wbar + wslot[v] * g.vs + c0;
-    double own = 0.0;
-#pragma unroll
-    for (int m = 1; m < 5; ++m) own += ls.pass(sink.qb[m - 1][v], m - 3, wv + m * st);
-    if (has) atomic_add(wv + 3 * st, own);
+    if (v == 3 ? !g.heat : !g.viscous) continue;
+    const double t = gather(sink.qb, v);
+    if (inrange) atomic_add(Wbar + wslot[v] * g.vs + co, t);
   }
   if (g.viscous) {
-    const int comp[4] = {D * 3 + T1, T1 * 3 + T1, D * 3 + T2, T2 * 3 + T2};
-    const bool act[4] = {g.act[T1] != 0, g.act[T1] != 0, g.act[T2] != 0, g.act[T2] != 0};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      if (!act[kk]) continue;
-      double* dv = Dbar + comp[kk] * g.vs + c0;
-      double own = 0.0;
-#pragma unroll
-      for (int m = 1; m < 5; ++m) own += ls.pass(sink.tgb[m - 1][kk], m - 3, dv + m * st);
-      if (has) atomic_add(dv + 3 * st, own);
+      if (!tact[kk]) continue;
+      const double t = gather(sink.tgb, kk);
+      if (inrange) atomic_add(Dbar + comp[kk] * g.vs + co, t);
     }
   }
 }

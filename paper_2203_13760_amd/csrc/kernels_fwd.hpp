@@ -530,6 +530,14 @@ __device__ __forceinline__ double lane_shr1(double x) {
   return __hiloint2double(hi, lo);
 }
 
+// Value of x in the lane above (lane + 1), wavefront shift left by one lane;
+// lane 63 receives 0.
+__device__ __forceinline__ double lane_shl1(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // x sweep: every interior row holds kXCtx context slots followed by its nx+1
 // faces, and the slots of all rows are numbered row-major; slot s of a row is
 // face f = s - kXCtx, lying between cells f-1 and f. A wavefront takes 64
