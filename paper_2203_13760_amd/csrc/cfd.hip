@@ -120,8 +120,9 @@ static cfd_status validate(const cfd_config* c) {
   long long N[3];
   for (int d = 0; d < 3; ++d) N[d] = c->n[d] > 1 ? c->n[d] + 2LL * c->nh : 1;
   for (int d = 0; d < 3; ++d) {
-    // (the x sweep numbers its faces with 3 extra slots per row)
-    long long faces = (long long)c->n[0] * c->n[1] * c->n[2] / c->n[d] * (c->n[d] + (d == 0 ? 4 : 1));
+    // (the x sweep numbers its faces with 3 extra slots per row, the x
+    // adjoint its cells with 6)
+    long long faces = (long long)c->n[0] * c->n[1] * c->n[2] / c->n[d] * (c->n[d] + (d == 0 ? 6 : 1));
     if (faces >= (1LL << 31)) return fail(CFD_EINVAL, "grid too large: faces per axis must fit in 31 bits");
     if ((c->flags & CFD_F_RUSANOV_NN) && faces >= (1LL << 29))
       return fail(CFD_EINVAL, "grid too large: the Rusanov-NN kernels run four lanes per face (faces per axis < 2^29)");
@@ -451,6 +452,8 @@ static cfd_status run_graph(cfd_solver* s, double* U, int mode, double fixed_dt,
 // derivative-adjoint accumulators. Allocated on the first adjoint call.
 static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   if (s->A1) return CFD_OK;
+  // the marching face reverses address cells with 32-bit offsets
+  if (s->ncell >= (1LL << 31)) return fail(CFD_EINVAL, "grid too large for the adjoint (2^31 padded cells or more)");
   const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
   bool ok = hipMalloc(&s->A1, st) == hipSuccess && hipMalloc(&s->A2, st) == hipSuccess &&
             hipMalloc(&s->Wbar, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess;

@@ -313,13 +313,16 @@ __device__ __forceinline__ long long march_adj_cell(const Geom& g, int i, int o,
 // f (§3.3): the wavefront computes the pair of cell f at face f, reverses the
 // HLLC flux of face f, and then reverses the pair of cell f-1, whose two
 // cotangents (from faces f-1 and f) are both known, into cells f-3 .. f+1.
-// The window holds cells f-3 .. f+2; the per-cell adjoint sums of the five
-// cells a pair reverse touches live in a lane-private LDS ring (the register
-// file holds the window and the HLLC reverse). A pair shared with the
-// neighbouring segment is reversed in both, each with its own face's share of
-// the cotangent (the reverse is linear in it). The window, the HLLC reverse
-// and the carried states need about 380 registers: the kernel runs one
-// wavefront per SIMD (at two it spills, and ran 1.8x slower).
+// A pair shared with the neighbouring segment is reversed in both, each with
+// its own face's share of the cotangent (the reverse is linear in it).
+// The window holds cells f-3 .. f+2 in registers, and the per-cell sums of
+// the five cells a pair reverse touches live in a lane-private LDS ring.
+// Cell offsets are 32-bit (the adjoint requires fewer than 2^31 padded
+// cells): one address register per cell instead of one per cell and
+// variable. The window, the HLLC reverse and the carried states still need
+// about 380 registers, so the kernel runs one wavefront per SIMD; at two it
+// spills, and reloading the window at every face instead (which fits two)
+// ran 1.3x slower, the reloads' latency exposed.
 constexpr int kMarchRing = 5;
 
 template <int AX>
@@ -332,10 +335,11 @@ k_march_adj_inv(const double* __restrict__ P, const double* __restrict__ Rbar, d
   const int tid = threadIdx.x;
 #pragma unroll
   for (int e = 0; e < kMarchRing * 5; ++e) ring[e * kBlock + tid] = 0.0;
-  const long long st = g.s[AX], vs = g.vs;
+  const int st = (int)g.s[AX];
+  const long long vs = g.vs;
   const int n = g.n[AX];
   const double gs_scale = rscale * g.idx[AX];
-  long long c = march_adj_cell<AX>(g, i, o, s0 - 3);  // window cell 0: cell f-3 of face f = s0
+  int c = (int)march_adj_cell<AX>(g, i, o, s0 - 3);  // window cell 0: cell f-3 of face f = s0
   double w[6][5];
 #pragma unroll
   for (int m = 0; m < 6; ++m) load_prims(P, vs, c + m * st, w[m]);
@@ -425,12 +429,13 @@ k_march_adj_dis(const double* __restrict__ P, const double* __restrict__ Rbar, d
   constexpr int T1 = (AX + 1) % 3, T2 = (AX + 2) % 3;
   int i, o, s0, fe;
   if (!march_adj_column<AX>(g, i, o, s0, fe)) return;
-  const long long st = g.s[AX], vs = g.vs;
+  const int st = (int)g.s[AX];  // 32-bit cell offsets, as in k_march_adj_inv
+  const long long vs = g.vs;
   const int n = g.n[AX];
   const double gs_scale = rscale * g.idx[AX];
   Geom gd = g;
   gd.inviscid = 0;  // the inviscid part is k_march_adj_inv
-  long long c = march_adj_cell<AX>(g, i, o, s0 - 2);  // window cell 0: cell f-2 of face f = s0
+  int c = (int)march_adj_cell<AX>(g, i, o, s0 - 2);  // window cell 0: cell f-2 of face f = s0
   // q[1..4] (u, v, w) and tg[0..3]: cells f-2 .. f+1. The heat flux is
   // linear in T~, so its reverse needs no T~ values.
   FaceWindow win;

@@ -128,10 +128,10 @@ __host__ __device__ __forceinline__ void hllc_rev(double gamma, double gm1i, con
   const double rR = WR[0], uR = WR[1 + D], aR = WR[1 + T1], bR = WR[1 + T2], pR = WR[4];
   const double EL = pL * gm1i + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
   const double ER = pR * gm1i + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
-  const double c2L = gamma * pL / rL, c2R = gamma * pR / rR;
+  const double c2L = div_nr(gamma * pL, rL), c2R = div_nr(gamma * pR, rR);
   const double cL = sqrt(c2L), cR = sqrt(c2R);
   const double sL = sqrt(rL), sR = sqrt(rR);
-  const double isum = 1.0 / (sL + sR);
+  const double isum = div_nr(1.0, sL + sR);
   const double ubar = (sL * uL + sR * uR) * isum;
   const double eta2 = 0.5 * sL * sR * isum * isum;
   const double Hs = sL * c2L + sR * c2R;
@@ -145,7 +145,7 @@ __host__ __device__ __forceinline__ void hllc_rev(double gamma, double gm1i, con
   const double SR = firstR ? candR1 : candR2;
   const double mL = rL * (SL - uL), mR = rR * (SR - uR);
   const double den = mL - mR;
-  const double Ss = (pR - pL + uL * mL - uR * mR) / den;
+  const double Ss = div_nr(pR - pL + uL * mL - uR * mR, den);
   const bool useL = 0.0 <= SL;
   const bool useSL = !useL && 0.0 <= Ss;
   const bool useSR = !useL && !useSL && 0.0 < SR;
@@ -156,122 +156,81 @@ __host__ __device__ __forceinline__ void hllc_rev(double gamma, double gm1i, con
   double rLb = 0, uLb = 0, aLb = 0, bLb = 0, pLb = 0, ELb = 0;
   double rRb = 0, uRb = 0, aRb = 0, bRb = 0, pRb = 0, ERb = 0;
   double SLb = 0, SRb = 0, Ssb = 0, mLb = 0, mRb = 0;
-  double FLb[5] = {0, 0, 0, 0, 0}, FRb[5] = {0, 0, 0, 0, 0};
-
-  if (useL) {
-    for (int v = 0; v < 5; ++v) FLb[v] = Fb[v];
-  } else if (useR) {
-    for (int v = 0; v < 5; ++v) FRb[v] = Fb[v];
-  } else if (useSL) {
-    // F = FL + SL (UsL - UL)
-    const double iL = 1.0 / (SL - Ss);
-    const double fL = mL * iL;
-    const double A = SL - uL, C = Ss - uL, B = fL * Ss + pL * iL;
-    const double eL = A * iL * EL + C * B;
-    const double UsL[5] = {fL, fL * Ss, fL * aL, fL * bL, eL};
-    const double UL[5] = {rL, rL * uL, rL * aL, rL * bL, EL};
-    double Usb[5], Ulb[5];
-    for (int v = 0; v < 5; ++v) {
-      FLb[v] = Fb[v];
-      SLb += Fb[v] * (UsL[v] - UL[v]);
-      Usb[v] = SL * Fb[v];
-      Ulb[v] = -SL * Fb[v];
-    }
-    double fLb = Usb[0] + Usb[1] * Ss + Usb[2] * aL + Usb[3] * bL;
-    Ssb += Usb[1] * fL;
-    aLb += Usb[2] * fL;
-    bLb += Usb[3] * fL;
-    const double eLb = Usb[4];
-    const double Ab = eLb * iL * EL;
-    double iLb = eLb * A * EL;
-    ELb += eLb * A * iL;
-    const double Cb = eLb * B, Bb = eLb * C;
-    fLb += Bb * Ss;
-    Ssb += Bb * fL;
-    pLb += Bb * iL;
-    iLb += Bb * pL;
-    SLb += Ab;
-    uLb -= Ab;
-    Ssb += Cb;
-    uLb -= Cb;
-    rLb += Ulb[0] + Ulb[1] * uL + Ulb[2] * aL + Ulb[3] * bL;
-    uLb += Ulb[1] * rL;
-    aLb += Ulb[2] * rL;
-    bLb += Ulb[3] * rL;
-    ELb += Ulb[4];
-    mLb += fLb * iL;
-    iLb += fLb * mL;
-    SLb -= iLb * iL * iL;
-    Ssb += iLb * iL * iL;
-  } else {
-    // useSR: F = FR + SR (UsR - UR)
-    const double iR = 1.0 / (SR - Ss);
-    const double fR = mR * iR;
-    const double A = SR - uR, C = Ss - uR, B = fR * Ss + pR * iR;
-    const double eR = A * iR * ER + C * B;
-    const double UsR[5] = {fR, fR * Ss, fR * aR, fR * bR, eR};
-    const double UR[5] = {rR, rR * uR, rR * aR, rR * bR, ER};
-    double Usb[5], Urb[5];
-    for (int v = 0; v < 5; ++v) {
-      FRb[v] = Fb[v];
-      SRb += Fb[v] * (UsR[v] - UR[v]);
-      Usb[v] = SR * Fb[v];
-      Urb[v] = -SR * Fb[v];
-    }
-    double fRb = Usb[0] + Usb[1] * Ss + Usb[2] * aR + Usb[3] * bR;
-    Ssb += Usb[1] * fR;
-    aRb += Usb[2] * fR;
-    bRb += Usb[3] * fR;
-    const double eRb = Usb[4];
-    const double Ab = eRb * iR * ER;
-    double iRb = eRb * A * ER;
-    ERb += eRb * A * iR;
-    const double Cb = eRb * B, Bb = eRb * C;
-    fRb += Bb * Ss;
-    Ssb += Bb * fR;
-    pRb += Bb * iR;
-    iRb += Bb * pR;
-    SRb += Ab;
-    uRb -= Ab;
-    Ssb += Cb;
-    uRb -= Cb;
-    rRb += Urb[0] + Urb[1] * uR + Urb[2] * aR + Urb[3] * bR;
-    uRb += Urb[1] * rR;
-    aRb += Urb[2] * rR;
-    bRb += Urb[3] * rR;
-    ERb += Urb[4];
-    mRb += fRb * iR;
-    iRb += fRb * mR;
-    SRb -= iRb * iR * iR;
-    Ssb += iRb * iR * iR;
-  }
-  // physical fluxes FL, FR
   {
-    const double F0 = rL * uL;
-    const double F0b = FLb[0] + FLb[1] * uL + FLb[2] * aL + FLb[3] * bL;
-    uLb += FLb[1] * F0 + FLb[4] * (EL + pL);
-    aLb += FLb[2] * F0;
-    bLb += FLb[3] * F0;
-    pLb += FLb[1] + FLb[4] * uL;
-    ELb += FLb[4] * uL;
-    rLb += F0b * uL;
-    uLb += F0b * rL;
-  }
-  {
-    const double F0 = rR * uR;
-    const double F0b = FRb[0] + FRb[1] * uR + FRb[2] * aR + FRb[3] * bR;
-    uRb += FRb[1] * F0 + FRb[4] * (ER + pR);
-    aRb += FRb[2] * F0;
-    bRb += FRb[3] * F0;
-    pRb += FRb[1] + FRb[4] * uR;
-    ERb += FRb[4] * uR;
-    rRb += F0b * uR;
-    uRb += F0b * rR;
+    // The flux takes one side K: F = F_K (supersonic) or F_K + S_K (U*_K - U_K)
+    // (star region). The side's inputs are selected first, so that a
+    // wavefront whose faces take different sides runs one reverse, not two.
+    const bool left = useL || useSL;
+    const bool star = useSL || useSR;
+    const double rK = left ? rL : rR, uK = left ? uL : uR, aK = left ? aL : aR, bK = left ? bL : bR;
+    const double pK = left ? pL : pR, EK = left ? EL : ER, SK = left ? SL : SR, mK = left ? mL : mR;
+    double rKb = 0, uKb = 0, aKb = 0, bKb = 0, pKb = 0, EKb = 0, SKb = 0, mKb = 0;
+    double FKb[5];
+    for (int v = 0; v < 5; ++v) FKb[v] = Fb[v];
+    if (star) {
+      const double iK = div_nr(1.0, SK - Ss);
+      const double fK = mK * iK;
+      const double A = SK - uK, C = Ss - uK, B = fK * Ss + pK * iK;
+      const double eK = A * iK * EK + C * B;
+      const double UsK[5] = {fK, fK * Ss, fK * aK, fK * bK, eK};
+      const double UK[5] = {rK, rK * uK, rK * aK, rK * bK, EK};
+      double Usb[5], Ukb[5];
+      for (int v = 0; v < 5; ++v) {
+        SKb += Fb[v] * (UsK[v] - UK[v]);
+        Usb[v] = SK * Fb[v];
+        Ukb[v] = -SK * Fb[v];
+      }
+      double fKb = Usb[0] + Usb[1] * Ss + Usb[2] * aK + Usb[3] * bK;
+      Ssb += Usb[1] * fK;
+      aKb += Usb[2] * fK;
+      bKb += Usb[3] * fK;
+      const double eKb = Usb[4];
+      const double Ab = eKb * iK * EK;
+      double iKb = eKb * A * EK;
+      EKb += eKb * A * iK;
+      const double Cb = eKb * B, Bb = eKb * C;
+      fKb += Bb * Ss;
+      Ssb += Bb * fK;
+      pKb += Bb * iK;
+      iKb += Bb * pK;
+      SKb += Ab;
+      uKb -= Ab;
+      Ssb += Cb;
+      uKb -= Cb;
+      rKb += Ukb[0] + Ukb[1] * uK + Ukb[2] * aK + Ukb[3] * bK;
+      uKb += Ukb[1] * rK;
+      aKb += Ukb[2] * rK;
+      bKb += Ukb[3] * rK;
+      EKb += Ukb[4];
+      mKb += fKb * iK;
+      iKb += fKb * mK;
+      SKb -= iKb * iK * iK;
+      Ssb += iKb * iK * iK;
+    }
+    // physical flux F_K
+    {
+      const double F0 = rK * uK;
+      const double F0b = FKb[0] + FKb[1] * uK + FKb[2] * aK + FKb[3] * bK;
+      uKb += FKb[1] * F0 + FKb[4] * (EK + pK);
+      aKb += FKb[2] * F0;
+      bKb += FKb[3] * F0;
+      pKb += FKb[1] + FKb[4] * uK;
+      EKb += FKb[4] * uK;
+      rKb += F0b * uK;
+      uKb += F0b * rK;
+    }
+    // back to the side's own adjoints
+    if (left) {
+      rLb = rKb; uLb = uKb; aLb = aKb; bLb = bKb; pLb = pKb; ELb = EKb; SLb = SKb; mLb = mKb;
+    } else {
+      rRb = rKb; uRb = uKb; aRb = aKb; bRb = bKb; pRb = pKb; ERb = EKb; SRb = SKb; mRb = mKb;
+    }
   }
   if (!useL && !useR) {
     // contact speed S* = num / den
-    const double numb = Ssb / den;
-    const double denb = -Ssb * Ss / den;
+    const double iden = div_nr(1.0, den);
+    const double numb = Ssb * iden;
+    const double denb = -Ssb * Ss * iden;
     pRb += numb;
     pLb -= numb;
     uLb += numb * mL;
@@ -289,7 +248,7 @@ __host__ __device__ __forceinline__ void hllc_rev(double gamma, double gm1i, con
     double cLb = 0, cRb = 0, ubarb = 0, dbarb = 0;
     if (firstL) { uLb += SLb; cLb -= SLb; } else { ubarb += SLb; dbarb -= SLb; }
     if (firstR) { uRb += SRb; cRb += SRb; } else { ubarb += SRb; dbarb += SRb; }
-    const double dbar2b = dbarb * 0.5 / dbar;
+    const double dbar2b = div_nr(0.5 * dbarb, dbar);
     const double Hsb = dbar2b * isum;
     double isumb = dbar2b * Hs;
     const double eta2b = dbar2b * du * du;
@@ -311,14 +270,17 @@ __host__ __device__ __forceinline__ void hllc_rev(double gamma, double gm1i, con
     const double sumb = -isumb * isum * isum;
     sLb += sumb;
     sRb += sumb;
-    rLb += sLb * 0.5 / sL;
-    rRb += sRb * 0.5 / sR;
-    c2Lb += cLb * 0.5 / cL;
-    c2Rb += cRb * 0.5 / cR;
-    pLb += c2Lb * gamma / rL;
-    rLb -= c2Lb * c2L / rL;
-    pRb += c2Rb * gamma / rR;
-    rRb -= c2Rb * c2R / rR;
+    // 1/sqrt(r) = sqrt(r)/r: one reciprocal of rho per side serves the
+    // square-root and sound-speed terms
+    const double irL = div_nr(1.0, rL), irR = div_nr(1.0, rR);
+    rLb += 0.5 * sLb * sL * irL;
+    rRb += 0.5 * sRb * sR * irR;
+    c2Lb += div_nr(0.5 * cLb, cL);
+    c2Rb += div_nr(0.5 * cRb, cR);
+    pLb += c2Lb * gamma * irL;
+    rLb -= c2Lb * c2L * irL;
+    pRb += c2Rb * gamma * irR;
+    rRb -= c2Rb * c2R * irR;
   }
   // total energies
   pLb += ELb * gm1i;
