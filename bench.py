@@ -144,7 +144,8 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     """Cost of the discrete adjoint on the Taylor-Green vortex with seeded noise
     (sigma 1e-3) at n^3: one fixed-dt TVD-RK3 step vs one step adjoint applied
     to a seeded Gaussian cotangent, the adjoint either recomputing its two
-    inner stages or taking them from a step that kept them, each timed with
+    inner stages or taking the primitives of its three stage inputs from a
+    step that kept them (cfd_rk3_step_prims), each timed with
     torch events on the stream the library launches on; and the full gradient
     of the final kinetic energy through an n_steps rollout with checkpoints
     every ckpt_every steps (kept stages, and recomputed stages)."""
@@ -157,8 +158,7 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     s = Solver(case)
     U = s.init(W)
     dt = float(s.compute_dt(U).item())
-    # a dense seeded cotangent: a uniform one has zero face differences, so the
-    # face adjoints would skip their work
+    # a dense seeded cotangent (a uniform one has zero face differences)
     gen = torch.Generator(device="cuda").manual_seed(4)
     Ub = torch.randn(U.shape, generator=gen, dtype=torch.float64, device="cuda")
     out = torch.empty_like(U)
@@ -176,21 +176,22 @@ def differentiation(n, nsteps, ckpt_every=20, reps=5):
     torch.cuda.synchronize()
     fwd = ev[0].elapsed_time(ev[1]) / reps
     adj = ev[1].elapsed_time(ev[2]) / reps
-    U1, U2 = torch.empty_like(U), torch.empty_like(U)
-    s.step_stages(U, dt, U1, U2)
-    s.step_adjoint_stages(U, U1, U2, dt, Ub, out)
+    # the rollout's kept stages: the primitives of the three stage inputs
+    Pk = s.empty_stage_prims()
+    s.step_prims(U, dt, Pk)
+    s.step_adjoint_prims(Pk, dt, Ub, out)
     torch.cuda.synchronize()
     ev[0].record()
     for _ in range(reps):
-        s.step_stages(U, dt, U1, U2)
+        s.step_prims(U, dt, Pk)
     ev[1].record()
     for _ in range(reps):
-        s.step_adjoint_stages(U, U1, U2, dt, Ub, out)
+        s.step_adjoint_prims(Pk, dt, Ub, out)
     ev[2].record()
     torch.cuda.synchronize()
     fwd_keep = ev[0].elapsed_time(ev[1]) / reps
     adj_kept = ev[1].elapsed_time(ev[2]) / reps
-    del U1, U2
+    del Pk
     tgrad = {}
     for keep in (True, False):
         Wt = torch.from_numpy(W).cuda().requires_grad_(True)

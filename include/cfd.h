@@ -222,6 +222,29 @@ cfd_status cfd_rk3_step_stages(cfd_solver* s, double* U, double dt, double* U1_o
 cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const double* U1, const double* U2, double dt,
                                        const double* Ubar_np1, double* Ubar_n, void* stream);
 
+/* One fixed-dt TVD-RK3 step on U in place (§3.2; as cfd_rk3_step with dt > 0)
+ * that also leaves the primitive states of its three stage inputs Un, U1, U2
+ * in P_out: a caller-owned device buffer of 3 * 6 * cfd_state_numel / 5
+ * doubles, not aliasing U, holding three primitive blocks (P of Un, U1, U2 in
+ * turn) of six components (rho, u, v, w, p, T~; component stride the padded
+ * cell count) each. rho, u, v, w, p are written at every padded cell (halos
+ * through the boundary map); T~ is written for Un only. These are everything
+ * cfd_rk3_step_adjoint_prims needs: the stage passes write the primitives of
+ * their outputs anyway, so keeping them costs no extra pass. For checkpointed
+ * reverse passes (§4.5) that keep a recomputed segment. CFD_EUNSUPPORTED with
+ * CFD_F_RK2. */
+cfd_status cfd_rk3_step_prims(cfd_solver* s, double* U, double dt, double* P_out, void* stream);
+
+/* cfd_rk3_step_adjoint of the step whose stage primitives P (as
+ * cfd_rk3_step_prims leaves them) are supplied: Ubar_n = (dU^{n+1}/dU^n)^T
+ * Ubar_np1 (interior cells; halo entries zero), the same result as
+ * cfd_rk3_step_adjoint up to the summation order of the atomics, without the
+ * forward stages and without primitive passes. Ubar_n must not alias P or
+ * Ubar_np1. CFD_EUNSUPPORTED with CFD_F_RK2 or a scheme the adjoint does not
+ * cover. */
+cfd_status cfd_rk3_step_adjoint_prims(cfd_solver* s, const double* P, double dt, const double* Ubar_np1,
+                                      double* Ubar_n, void* stream);
+
 /* Measurement aid: enqueue the kernels of TVD-RK3 stages on U as a run of
  * steps runs them (stage r % 3 + 1 in repetition r, with dt = 1e-12, written to
  * solver scratch, so U is not modified; the third stage also forms the CFL

@@ -6,11 +6,12 @@ RK3Rollout.apply(U0, solver, dt, n_steps, ckpt_every, keep_stages) returns
 U_N; its backward pass walks the rollout in reverse segment by segment: the
 segment's states are recomputed from its checkpoint (kept every `ckpt_every`
 steps in the forward pass), then the step adjoint maps the adjoint back one
-step at a time. With keep_stages (the default) the recompute keeps each step's
-two stage states (cfd_rk3_step_stages) and cfd_rk3_step_adjoint_stages uses
-them; otherwise cfd_rk3_step_adjoint recomputes them in every step adjoint.
-Memory: the checkpoints plus one segment of states (three per step with
-keep_stages). Gradients flow to the interior cells of U0; halo entries of the
+step at a time. With keep_stages (the default) the recompute keeps the
+primitives of each step's three stage inputs (cfd_rk3_step_prims) and
+cfd_rk3_step_adjoint_prims uses them; otherwise cfd_rk3_step_adjoint
+recomputes the stages in every step adjoint. Memory: the checkpoints plus one
+segment of states (with keep_stages, 18 components per padded cell and step
+instead of 5). Gradients flow to the interior cells of U0; halo entries of the
 returned gradient are zero.
 """
 from __future__ import annotations
@@ -51,25 +52,26 @@ class RK3Rollout(torch.autograd.Function):
         scratch = torch.empty_like(Ub)
         for start, ck in reversed(ctx.ckpts):
             k = min(ctx.ckpt_every, ctx.n_steps - start)
-            states = [ck]
-            stages = []
             U = ck.clone()
-            for i in range(k - 1 if not ctx.keep_stages else k):
-                if ctx.keep_stages:
-                    U1, U2 = torch.empty_like(U), torch.empty_like(U)
-                    solver.step_stages(U, dt, U1, U2)
-                    stages.append((U1, U2))
-                else:
+            if ctx.keep_stages:
+                prims = []
+                for i in range(k):
+                    P = solver.empty_stage_prims()
+                    solver.step_prims(U, dt, P)
+                    prims.append(P)
+                for s in reversed(range(k)):
+                    solver.step_adjoint_prims(prims[s], dt, Ub, scratch)
+                    Ub, scratch = scratch, Ub
+                del prims
+            else:
+                states = [ck]
+                for i in range(k - 1):
                     solver.advance_fixed(U, 1, dt)
-                if i < k - 1:
                     states.append(U.clone())
-            for s in reversed(range(k)):
-                if ctx.keep_stages:
-                    solver.step_adjoint_stages(states[s], stages[s][0], stages[s][1], dt, Ub, scratch)
-                else:
+                for s in reversed(range(k)):
                     solver.step_adjoint(states[s], dt, Ub, scratch)
-                Ub, scratch = scratch, Ub
-            del states, stages
+                    Ub, scratch = scratch, Ub
+                del states
         ctx.ckpts = None
         return Ub, None, None, None, None, None
 

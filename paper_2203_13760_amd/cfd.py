@@ -47,7 +47,8 @@ class cfd_config(C.Structure):
 EXPORTS = (
     "cfd_create", "cfd_destroy", "cfd_state_numel", "cfd_state_init", "cfd_state_init_adjoint", "cfd_fill_halo", "cfd_rhs",
     "cfd_compute_dt", "cfd_rk3_step", "cfd_advance", "cfd_advance_fixed", "cfd_rhs_adjoint",
-    "cfd_rk3_step_adjoint", "cfd_rk3_step_stages", "cfd_rk3_step_adjoint_stages", "cfd_profile_stage", "cfd_check", "cfd_last_error",
+    "cfd_rk3_step_adjoint", "cfd_rk3_step_stages", "cfd_rk3_step_adjoint_stages", "cfd_rk3_step_prims",
+    "cfd_rk3_step_adjoint_prims", "cfd_profile_stage", "cfd_check", "cfd_last_error",
     "cfd_set_nn_weights", "cfd_rk3_step_noalloc",
     "cfd_batch_create", "cfd_batch_destroy", "cfd_batch_footprint", "cfd_batch_add", "cfd_batch_remove",
     "cfd_batch_state", "cfd_batch_step", "cfd_batch_finish", "cfd_batch_copy_state", "cfd_batch_count",
@@ -84,6 +85,8 @@ def load():
         "cfd_rk3_step_adjoint": ([vp, dp, C.c_double, dp, dp, vp], st),
         "cfd_rk3_step_stages": ([vp, dp, C.c_double, dp, dp, vp], st),
         "cfd_rk3_step_adjoint_stages": ([vp, dp, dp, dp, C.c_double, dp, dp, vp], st),
+        "cfd_rk3_step_prims": ([vp, dp, C.c_double, dp, vp], st),
+        "cfd_rk3_step_adjoint_prims": ([vp, dp, C.c_double, dp, dp, vp], st),
         "cfd_profile_stage": ([vp, dp, C.c_int32, C.POINTER(C.c_double), vp], st),
         "cfd_set_nn_weights": ([vp, dp, dp], st),
         "cfd_rk3_step_noalloc": ([cfgp, dp, C.c_double, dp, vp], st),
@@ -213,6 +216,15 @@ def cfd_rk3_step_stages(h, U, dt, U1_out, U2_out, stream=None):
 def cfd_rk3_step_adjoint_stages(h, Un, U1, U2, dt, Ubar_np1, Ubar_n, stream=None):
     _check(load().cfd_rk3_step_adjoint_stages(h, _ptr(Un), _ptr(U1), _ptr(U2), float(dt), _ptr(Ubar_np1),
                                               _ptr(Ubar_n), _stream(stream)))
+
+
+def cfd_rk3_step_prims(h, U, dt, P_out, stream=None):
+    _check(load().cfd_rk3_step_prims(h, _ptr(U), float(dt), _ptr(P_out), _stream(stream)))
+
+
+def cfd_rk3_step_adjoint_prims(h, P, dt, Ubar_np1, Ubar_n, stream=None):
+    _check(load().cfd_rk3_step_adjoint_prims(h, _ptr(P), float(dt), _ptr(Ubar_np1), _ptr(Ubar_n),
+                                             _stream(stream)))
 
 
 def cfd_set_nn_weights(h, theta, theta_bar=None):

@@ -56,6 +56,9 @@ struct GraphCache {
   int mode = -1;
 };
 
+// Components of a primitive buffer (rho, u, v, w, p, T~) per padded cell.
+constexpr int kPrimComps = 6;
+
 struct cfd_solver {
   cfd_config cfg;
   Geom g;
@@ -353,10 +356,17 @@ static cfd_status enqueue_step_prologue(cfd_solver* s, const double* U, bool cfl
 // primitives of its output for the next stage (Pb[0] -> Pb[1] -> Pb[2] ->
 // Pb[0]); the third also the health bits of U^{n+1} and, for CFL steps, its
 // CFL rate maxima, so consecutive steps need no separate primitive pass.
+// Pst (nullable): the primitives of the three stage inputs are read from and
+// written to Pst[0] (which must hold those of Un), Pst[1] and Pst[2] instead
+// of the solver's ring; the third stage still writes Pb[0].
 static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double t_end, double* t_dev,
-                               double* dt_out, hipStream_t st, double* U1 = nullptr, double* U2 = nullptr) {
+                               double* dt_out, hipStream_t st, double* U1 = nullptr, double* U2 = nullptr,
+                               double* const* Pst = nullptr) {
   if (!U1) U1 = s->U1;
   if (!U2) U2 = s->U2;
+  double* const P0 = Pst ? Pst[0] : s->Pb[0];
+  double* const P1 = Pst ? Pst[1] : s->Pb[1];
+  double* const P2 = Pst ? Pst[2] : s->Pb[2];
   const double* dtp = &s->ctl->dt;
   const bool cfl = !(fixed_dt > 0.0);
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, s->g.cfl, fixed_dt, t_end, t_dev, dt_out,
@@ -375,9 +385,9 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   io.Uout = U1;
   io.a = 0.0;
   io.b = 1.0;
-  io.Pn = s->Pb[1];
+  io.Pn = P1;
   io.what = PRIM_HEALTH;  // health bits of every stage state
-  if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
+  if ((rc = enqueue_fluxes(s, P0, io, true, st))) return rc;
   if (s->g.rk2) {
     // TVD-RK2, second stage: Un+1 = 1/2 Un + 1/2 (U1 + dt R(U1)), in place on U
     io.Uk = U1;
@@ -386,15 +396,15 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
     io.b = 0.5;
     io.Pn = s->Pb[0];
     io.what = PRIM_HEALTH | (cfl ? PRIM_CFL : 0);
-    return enqueue_fluxes(s, s->Pb[1], io, true, st);
+    return enqueue_fluxes(s, P1, io, true, st);
   }
   // stage 2: U2 = 3/4 Un + 1/4 (U1 + dt R(U1))
   io.Uk = U1;
   io.Uout = U2;
   io.a = 0.75;
   io.b = 0.25;
-  io.Pn = s->Pb[2];
-  if ((rc = enqueue_fluxes(s, s->Pb[1], io, true, st))) return rc;
+  io.Pn = P2;
+  if ((rc = enqueue_fluxes(s, P1, io, true, st))) return rc;
   // stage 3: Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2)), in place on U
   io.Uk = U2;
   io.Uout = U;
@@ -402,7 +412,7 @@ static cfd_status enqueue_step(cfd_solver* s, double* U, double fixed_dt, double
   io.b = 2.0 / 3.0;
   io.Pn = s->Pb[0];
   io.what = PRIM_HEALTH | (cfl ? PRIM_CFL : 0);
-  return enqueue_fluxes(s, s->Pb[2], io, true, st);
+  return enqueue_fluxes(s, P2, io, true, st);
 }
 
 static cfd_status enqueue_fill_halo(cfd_solver* s, double* U, hipStream_t st) {
@@ -515,9 +525,9 @@ static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, 
   }
 }
 
-// Ubar += (dR/dU(U))^T (rscale Rbar), interior cells; P holds the primitives
-// of U (padded, halos included).
-static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const double* P, const double* Rbar,
+// Ubar += (dR/dU(U))^T (rscale Rbar), interior cells, with U given by its
+// primitives P (padded, halos included; rho, u, v, w, p are read).
+static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const double* Rbar,
                                       double rscale, double* Ubar, hipStream_t st) {
   const Geom& g = s->g;
   hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * s->ncell)), dim3(kBlock), 0, st, s->Wbar, 6 * s->ncell);
@@ -567,7 +577,7 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* U, const doub
   }
   hipLaunchKernelGGL(k_adj_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, s->Wbar, g);
   CFD_LAUNCHED();
-  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, U, (const double*)s->Wbar, Ubar, g);
+  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, P, (const double*)s->Wbar, Ubar, g);
   CFD_LAUNCHED();
   return CFD_OK;
 }
@@ -839,7 +849,7 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if ((rc = enqueue_prim(s, U, 0, nullptr, st))) return rc;
-  return enqueue_rhs_adjoint(s, U, s->P, Rbar, 1.0, Ubar, st);
+  return enqueue_rhs_adjoint(s, s->P, Rbar, 1.0, Ubar, st);
 }
 
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
@@ -854,6 +864,7 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   const Geom& g = s->g;
   // forward recompute of the stage states U1, U2 with the fixed step; the
   // stage updates leave the primitives of Un, U1, U2 in Pb[0], Pb[1], Pb[2]
+  // (rho, u, v, w, p with halos: all the face reverses and the fold read)
   hipLaunchKernelGGL(k_dt, dim3(1), dim3(kBlock), 0, st, s->ctl, g.cfl, dt, 0.0, (double*)nullptr,
                      (double*)nullptr, s->partial, s->npart);
   CFD_LAUNCHED();
@@ -874,20 +885,17 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   if ((rc = enqueue_prim(s, Un, 0, dtp, st))) return rc;
   if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
   if (g.rk2) {
-    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->U1, s->Pb[1], g, s->ctl, 0,
-                       (const double*)nullptr, s->partial);
-    CFD_LAUNCHED();
     // TVD-RK2:  U2 = 1/2 Un + 1/2 (U1 + dt R(U1)),  U1 = Un + dt R(Un)
     // A1 = Ubar_1 = 1/2 Ubar_2 + (dR/dU(U1))^T (1/2 dt Ubar_2)
     hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.5, Ubar_np1, 0.0,
                        (const double*)nullptr, 0.0, (const double*)nullptr, g);
     CFD_LAUNCHED();
-    if ((rc = enqueue_rhs_adjoint(s, s->U1, s->Pb[1], Ubar_np1, 0.5 * dt, s->A1, st))) return rc;
+    if ((rc = enqueue_rhs_adjoint(s, s->Pb[1], Ubar_np1, 0.5 * dt, s->A1, st))) return rc;
     // Ubar_n = 1/2 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
     hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 0.5, Ubar_np1, 1.0,
                        (const double*)s->A1, 0.0, (const double*)nullptr, g);
     CFD_LAUNCHED();
-    return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
+    return enqueue_rhs_adjoint(s, s->Pb[0], s->A1, dt, Ubar_n, st);
   }
   io.Uk = s->U1;
   io.Uout = s->U2;
@@ -895,30 +903,23 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   io.b = 0.25;
   io.Pn = s->Pb[2];
   if ((rc = enqueue_fluxes(s, s->Pb[1], io, true, st))) return rc;
-  // the stage updates store no T~ with the next primitives: the primitive
-  // passes of U1, U2 complete P for the face reverses
-  for (int k = 1; k < 3; ++k) {
-    hipLaunchKernelGGL(k_prim, plane_grid(g), dim3(kBlock), 0, st, (const double*)(k == 1 ? s->U1 : s->U2), s->Pb[k],
-                       g, s->ctl, 0, (const double*)nullptr, s->partial);
-    CFD_LAUNCHED();
-  }
   // reverse:  U3 = 1/3 Un + 2/3 (U2 + dt R(U2)),  U2 = 3/4 Un + 1/4 (U1 + dt R(U1)),
   //           U1 = Un + dt R(Un)
   // A2 = Ubar_2 = 2/3 Ubar_3 + (dR/dU(U2))^T (2/3 dt Ubar_3)
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
                      (const double*)nullptr, 0.0, (const double*)nullptr, g);
   CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->U2, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
+  if ((rc = enqueue_rhs_adjoint(s, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
   // A1 = Ubar_1 = 1/4 Ubar_2 + (dR/dU(U1))^T (1/4 dt Ubar_2)
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
                      (const double*)nullptr, 0.0, (const double*)nullptr, g);
   CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->U1, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
+  if ((rc = enqueue_rhs_adjoint(s, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
   // Ubar_n = 1/3 Ubar_3 + 3/4 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
                      (const double*)s->A2, 1.0, (const double*)s->A1, g);
   CFD_LAUNCHED();
-  return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
+  return enqueue_rhs_adjoint(s, s->Pb[0], s->A1, dt, Ubar_n, st);
 }
 
 cfd_status cfd_set_nn_weights(cfd_solver* s, const double* theta, double* theta_bar) {
@@ -970,15 +971,59 @@ cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const do
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
                      (const double*)nullptr, 0.0, (const double*)nullptr, g);
   CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, U2, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
+  if ((rc = enqueue_rhs_adjoint(s, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
                      (const double*)nullptr, 0.0, (const double*)nullptr, g);
   CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, U1, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
+  if ((rc = enqueue_rhs_adjoint(s, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
   hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
                      (const double*)s->A2, 1.0, (const double*)s->A1, g);
   CFD_LAUNCHED();
-  return enqueue_rhs_adjoint(s, Un, s->Pb[0], s->A1, dt, Ubar_n, st);
+  return enqueue_rhs_adjoint(s, s->Pb[0], s->A1, dt, Ubar_n, st);
+}
+
+cfd_status cfd_rk3_step_prims(cfd_solver* s, double* U, double dt, double* P_out, void* stream) {
+  if (!s || !U || !P_out) return fail(CFD_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
+  if (P_out == U) return fail(CFD_EINVAL, "P_out must not alias U");
+  if (s->g.rk2) return fail(CFD_EUNSUPPORTED, "the stages kept are those of TVD-RK3");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t ps = kPrimComps * (size_t)s->ncell;
+  double* const Pst[3] = {P_out, P_out + ps, P_out + 2 * ps};
+  hipLaunchKernelGGL(k_prim, plane_grid(s->g), dim3(kBlock), 0, st, (const double*)U, Pst[0], s->g, s->ctl,
+                     PRIM_HEALTH, (const double*)nullptr, s->partial);
+  CFD_LAUNCHED();
+  cfd_status rc = enqueue_step(s, U, dt, 0.0, nullptr, nullptr, st, nullptr, nullptr, Pst);
+  if (rc) return rc;
+  return enqueue_fill_halo(s, U, st);
+}
+
+cfd_status cfd_rk3_step_adjoint_prims(cfd_solver* s, const double* P, double dt, const double* Ubar_np1,
+                                      double* Ubar_n, void* stream) {
+  if (!s || !P || !Ubar_np1 || !Ubar_n) return fail(CFD_EINVAL, "NULL argument");
+  if (!adjoint_supported(s)) return fail(CFD_EUNSUPPORTED, CFD_ADJ_SCOPE);
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CFD_EINVAL, "dt must be > 0");
+  if (Ubar_n == Ubar_np1 || Ubar_n == P) return fail(CFD_EINVAL, "Ubar_n must not alias the inputs");
+  if (s->g.rk2) return fail(CFD_EUNSUPPORTED, "the stages kept are those of TVD-RK3");
+  cfd_status rc = ensure_adjoint_scratch(s);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const Geom& g = s->g;
+  const size_t ps = kPrimComps * (size_t)s->ncell;
+  const double* const Pk[3] = {P, P + ps, P + 2 * ps};
+  // the reverse sweep of cfd_rk3_step_adjoint on the kept stage primitives
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
+                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_rhs_adjoint(s, Pk[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
+                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
+  CFD_LAUNCHED();
+  if ((rc = enqueue_rhs_adjoint(s, Pk[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
+  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
+                     (const double*)s->A2, 1.0, (const double*)s->A1, g);
+  CFD_LAUNCHED();
+  return enqueue_rhs_adjoint(s, Pk[0], s->A1, dt, Ubar_n, st);
 }
 
 }  // extern "C"

@@ -17,8 +17,8 @@
 //      added to Wbar at every padded cell;
 //   4. k_adj_halo: the transposed halo fill, every halo cell's Wbar added to
 //      its interior source cell;
-//   5. k_adj_fold: per interior cell, the transposed primitive map at U gives
-//      Ubar.
+//   5. k_adj_fold: per interior cell, the transposed primitive map at the
+//      state (from its primitives) gives Ubar.
 // The atomics make the summation order, and so the last bits, vary between
 // runs; everything else is deterministic.
 #pragma once
@@ -593,22 +593,21 @@ __global__ void __launch_bounds__(kBlock) k_adj_halo(double* Wbar, Geom g) {
 }
 
 // Per interior cell s, after k_adj_halo (and, with viscous fluxes,
-// k_adj_dbar): the transposed primitive map at U[s] applied to Wbar[s];
-// Ubar[s] += result. Halo entries of Ubar are not touched.
-__global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ U, const double* __restrict__ Wbar,
+// k_adj_dbar): the transposed primitive map at the state, given by its
+// primitives P[s] (rho, u, v, w, p), applied to Wbar[s]; Ubar[s] += result.
+// Halo entries of Ubar are not touched.
+__global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ P, const double* __restrict__ Wbar,
                                                      double* __restrict__ Ubar, Geom g) {
   const PlaneIdx p = plane_index(g, true);
   if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
   double wb[6];
 #pragma unroll
   for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + p.c];
-  // transposed primitive map at U[s]
   const long long s = p.c;
-  const double rho = U[s], m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];
-  const double ir = 1.0 / rho;
-  const double u[3] = {m0 * ir, m1 * ir, m2 * ir};
+  const double rho = P[s], pr = P[4 * g.vs + s];
+  const double u[3] = {P[g.vs + s], P[2 * g.vs + s], P[3 * g.vs + s]};
+  const double ir = div_nr(1.0, rho);
   const double gm1 = g.gamma - 1.0;
-  const double pr = gm1 * (E - 0.5 * (m0 * u[0] + m1 * u[1] + m2 * u[2]));
   // T~ = p / rho
   const double pb = wb[4] + wb[5] * ir;
   double rb = wb[0] - wb[5] * pr * ir * ir;

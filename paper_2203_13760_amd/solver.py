@@ -117,6 +117,20 @@ class Solver:
         cfd.cfd_rk3_step_adjoint_stages(self.h, Un, U1, U2, float(dt), Ubar_np1, Ubar_n)
         return Ubar_n
 
+    def empty_stage_prims(self):
+        """Buffer for the primitives of a step's three stage inputs (cfd_rk3_step_prims)."""
+        return torch.empty((3, 6) + self.shape[1:], dtype=torch.float64, device=self.device)
+
+    def step_prims(self, U, dt, P):
+        """One fixed-dt step in place, keeping the primitives of its stage inputs in P."""
+        cfd.cfd_rk3_step_prims(self.h, U, float(dt), P)
+        return U
+
+    def step_adjoint_prims(self, P, dt, Ubar_np1, Ubar_n=None):
+        Ubar_n = self.empty_state() if Ubar_n is None else Ubar_n
+        cfd.cfd_rk3_step_adjoint_prims(self.h, P, float(dt), Ubar_np1, Ubar_n)
+        return Ubar_n
+
     def set_nn_weights(self, theta, theta_bar=None):
         """Rusanov-NN weights (a device float64 tensor of cfd.CFD_NN_PARAMS values,
         read at every launch, so it may be updated in place) and an optional

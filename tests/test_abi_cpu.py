@@ -122,6 +122,8 @@ def test_entry_points_reject_null_arguments():
                        ("cfd_rk3_step_stages", (null, null, ctypes.c_double(1e-3), null, null, null)),
                        ("cfd_rk3_step_adjoint_stages", (null, null, null, null, ctypes.c_double(1e-3), null, null,
                                                         null)),
+                       ("cfd_rk3_step_prims", (null, null, ctypes.c_double(1e-3), null, null)),
+                       ("cfd_rk3_step_adjoint_prims", (null, null, ctypes.c_double(1e-3), null, null, null)),
                        ("cfd_set_nn_weights", (null, null, null)),
                        ("cfd_state_init", (null, null, null, null))]:
         assert getattr(lib, name)(*args) == cfd.CFD_EINVAL, name

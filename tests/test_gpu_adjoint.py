@@ -176,6 +176,41 @@ def test_kept_stages_and_their_step_adjoint_match_oracle(Solver, name):
     assert e <= 1e-10, (name, e)
 
 
+@pytest.mark.parametrize("name", ["tgv_noisy", "shocky3d", "kh", "sod", "viscous_only", "heat_only"])
+def test_kept_stage_primitives_and_their_step_adjoint_match_oracle(Solver, name):
+    """cfd_rk3_step_prims: the step equals the oracle's fixed-dt step and the
+    kept primitives of Un, U1, U2 (every padded cell) equal the primitive map
+    of the oracle's stage states with their halos filled;
+    cfd_rk3_step_adjoint_prims on them matches the oracle tape."""
+    case, W = CASES[name]
+    print(f"kept stage primitives + their step adjoint: {name}", flush=True)
+    s = Solver(case)
+    U = s.init(W)
+    Uo = oracle.state_init(case, W)
+    dt = 0.8 * oracle.cfl_dt(case, Uo)
+    P = s.empty_stage_prims()
+    s.step_prims(U, dt, P)
+    m = _interior_mask(case, Uo.shape) > 0
+    o1 = oracle.fill_halo(case, np.where(m, Uo + dt * oracle.rhs(case, Uo), 0.0))
+    o2 = oracle.fill_halo(case, np.where(m, 0.75 * Uo + 0.25 * (o1 + dt * oracle.rhs(case, o1)), 0.0))
+    Pg = P.cpu().numpy()
+    gamma = case.get("gamma", 1.4)
+    for k, Us in enumerate((Uo, o1, o2)):
+        rho = Us[0]
+        want = np.stack([rho, Us[1] / rho, Us[2] / rho, Us[3] / rho,
+                         (gamma - 1.0) * (Us[4] - 0.5 * (Us[1] ** 2 + Us[2] ** 2 + Us[3] ** 2) / rho)])
+        assert normwise(Pg[k, :5], want) <= 1e-12, (name, k)
+    Uo3, _ = oracle.rk3_step(case, Uo, dt)
+    assert normwise(U.cpu().numpy(), Uo3) <= 1e-12, name
+    rng = np.random.default_rng(9)
+    Ub1 = rng.standard_normal(Uo.shape) * _interior_mask(case, Uo.shape)
+    want = oracle.vjp_rk3_step(case, Uo, dt, Ub1)
+    got = s.step_adjoint_prims(P, dt, torch.from_numpy(Ub1).cuda()).cpu().numpy()
+    s.close()
+    e = normwise(got, want)
+    assert e <= 1e-10, (name, e)
+
+
 def test_rhs_adjoint_dot_product_on_gpu(Solver):
     # <w, J v> by fourth-order central differences of the GPU right-hand side
     # against <J^T w, v> from the GPU adjoint, at a size spanning several tiles
