@@ -75,6 +75,10 @@ struct cfd_solver {
   double* A3 = nullptr;
   double* Wbar = nullptr; // 6 x padded
   double* Dbar = nullptr; // 9 x padded (viscous runs)
+  // a second pair, cleared on the side stream during one right-hand-side
+  // adjoint for the next one of the same step adjoint (the two swap)
+  double* Wbar2 = nullptr;
+  double* Dbar2 = nullptr;
   double* partial = nullptr;  // CFL rate maxima slots (kCflSlots)
   double* nna = nullptr;      // Rusanov-NN alpha per face (3 x padded)
   double* nntape = nullptr;   // Rusanov-NN per-face records of the reverse (adjoint scratch)
@@ -466,8 +470,11 @@ static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   if (s->ncell >= (1LL << 31)) return fail(CFD_EINVAL, "grid too large for the adjoint (2^31 padded cells or more)");
   const size_t st = sizeof(double) * 5 * (size_t)s->ncell;
   bool ok = hipMalloc(&s->A1, st) == hipSuccess && hipMalloc(&s->A2, st) == hipSuccess &&
-            hipMalloc(&s->Wbar, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess;
-  if (ok && s->g.viscous) ok = hipMalloc(&s->Dbar, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
+            hipMalloc(&s->Wbar, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess &&
+            hipMalloc(&s->Wbar2, sizeof(double) * 6 * (size_t)s->ncell) == hipSuccess;
+  if (ok && s->g.viscous)
+    ok = hipMalloc(&s->Dbar, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess &&
+         hipMalloc(&s->Dbar2, sizeof(double) * kGradComps * (size_t)s->ncell) == hipSuccess;
   long long F = 0;
   if (s->g.nn) {
     for (int d = 0; d < 3; ++d)
@@ -477,10 +484,10 @@ static cfd_status ensure_adjoint_scratch(cfd_solver* s) {
   }
   if (!ok) {
     (void)hipGetLastError();
-    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar, s->nntape};
+    double* b[] = {s->A1, s->A2, s->Wbar, s->Dbar, s->Wbar2, s->Dbar2, s->nntape};
     for (double* x : b)
       if (x) (void)hipFree(x);
-    s->A1 = s->A2 = s->Wbar = s->Dbar = s->nntape = nullptr;
+    s->A1 = s->A2 = s->Wbar = s->Dbar = s->Wbar2 = s->Dbar2 = s->nntape = nullptr;
     return fail(CFD_ENOMEM, "adjoint scratch allocation failed");
   }
   if (s->g.nn) {
@@ -525,17 +532,40 @@ static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, 
   }
 }
 
-// Ubar += (dR/dU(U))^T (rscale Rbar), interior cells, with U given by its
-// primitives P (padded, halos included; rho, u, v, w, p are read).
-static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const double* Rbar,
-                                      double rscale, double* Ubar, hipStream_t st) {
-  const Geom& g = s->g;
-  hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * s->ncell)), dim3(kBlock), 0, st, s->Wbar, 6 * s->ncell);
-  CFD_LAUNCHED();
-  if (g.viscous) {
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(kGradComps * s->ncell)), dim3(kBlock), 0, st, s->Dbar,
+// out.out = (the combination in out) + (dR/dU(U))^T (rscale Rbar) at the
+// interior cells, with U given by its primitives P (padded, halos included;
+// rho, u, v, w, p are read).
+// Clear the accumulators Wbar, Dbar (graph-safe fill kernels).
+static void enqueue_clear_adj(cfd_solver* s, double* Wb, double* Db, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * s->ncell)), dim3(kBlock), 0, st, Wb, 6 * s->ncell);
+  if (s->g.viscous)
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(kGradComps * s->ncell)), dim3(kBlock), 0, st, Db,
                        kGradComps * s->ncell);
+}
+
+// cleared: s->Wbar, s->Dbar are already zero (cleared on the side stream by
+// the previous call of the same step adjoint); clear_next: clear the other
+// pair on the side stream, after the face reverses there, for the next call.
+// The pairs swap at the end.
+static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const double* Rbar,
+                                      double rscale, const AdjOut& out, hipStream_t st, bool cleared = false,
+                                      bool clear_next = false) {
+  const Geom& g = s->g;
+  if (!cleared) {
+    enqueue_clear_adj(s, s->Wbar, s->Dbar, st);
     CFD_LAUNCHED();
+  }
+  // the inviscid reverses (FP64-bound) and the dissipative ones (bound by
+  // their stencil loads) add to disjoint or commuting entries of Wbar and
+  // Dbar: they run side by side on two streams, and the side stream then
+  // clears the next pair
+  const bool side_faces = !g.nn && g.inviscid && (g.viscous || g.heat);
+  const bool fork = side_faces || clear_next;
+  hipStream_t sd = st;
+  if (fork) {
+    CFD_HIP(hipEventRecord(s->ev_fork, st));
+    CFD_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
+    if (side_faces) sd = s->side;
   }
   if (g.nn) {
     // Rusanov-NN faces of every axis in one launch, then the weight gradient
@@ -552,24 +582,18 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const doub
       CFD_LAUNCHED();
     }
   } else {
-    // the inviscid reverses (FP64-bound) and the dissipative ones (bound by
-    // their stencil loads) add to disjoint or commuting entries of Wbar and
-    // Dbar: they run side by side on two streams
-    const bool fork = g.inviscid && (g.viscous || g.heat);
-    hipStream_t sd = st;
-    if (fork) {
-      CFD_HIP(hipEventRecord(s->ev_fork, st));
-      CFD_HIP(hipStreamWaitEvent(s->side, s->ev_fork, 0));
-      sd = s->side;
-    }
     if (g.act[0]) launch_face_adj<0>(s, P, Rbar, rscale, st, sd);
     if (g.act[1]) launch_face_adj<1>(s, P, Rbar, rscale, st, sd);
     if (g.act[2]) launch_face_adj<2>(s, P, Rbar, rscale, st, sd);
     CFD_LAUNCHED();
-    if (fork) {
-      CFD_HIP(hipEventRecord(s->ev_join, s->side));
-      CFD_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
+  }
+  if (fork) {
+    if (clear_next) {
+      enqueue_clear_adj(s, s->Wbar2, s->Dbar2, s->side);
+      CFD_LAUNCHED();
     }
+    CFD_HIP(hipEventRecord(s->ev_join, s->side));
+    CFD_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
   }
   if (g.viscous) {
     hipLaunchKernelGGL(k_adj_dbar, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->Dbar, s->Wbar, g);
@@ -577,9 +601,53 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const doub
   }
   hipLaunchKernelGGL(k_adj_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, s->Wbar, g);
   CFD_LAUNCHED();
-  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, P, (const double*)s->Wbar, Ubar, g);
+  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, P, (const double*)s->Wbar, out, g);
   CFD_LAUNCHED();
+  std::swap(s->Wbar, s->Wbar2);
+  std::swap(s->Dbar, s->Dbar2);
   return CFD_OK;
+}
+
+static AdjOut adj_out(double* out, double a, const double* X, double b = 0.0, const double* Y = nullptr,
+                      double c = 0.0, const double* Z = nullptr, bool zero_halo = false) {
+  AdjOut o;
+  o.out = out;
+  o.a = a;
+  o.b = b;
+  o.c = c;
+  o.X = X;
+  o.Y = Y;
+  o.Z = Z;
+  o.zero_halo = zero_halo ? 1 : 0;
+  return o;
+}
+
+// The reverse sweep of a step given the primitives Pk[0..2] of its stage
+// inputs Un, U1 (, U2):
+//   TVD-RK3  U1 = Un + dt R(Un),  U2 = 3/4 Un + 1/4 (U1 + dt R(U1)),
+//            U3 = 1/3 Un + 2/3 (U2 + dt R(U2)):
+//     A2 = 2/3 Ubar_3 + (dR/dU(U2))^T (2/3 dt Ubar_3)
+//     A1 = 1/4 A2 + (dR/dU(U1))^T (1/4 dt A2)
+//     Ubar_n = 1/3 Ubar_3 + 3/4 A2 + A1 + (dR/dU(Un))^T (dt A1)
+//   TVD-RK2  U2 = 1/2 Un + 1/2 (U1 + dt R(U1)):
+//     A1 = 1/2 Ubar_2 + (dR/dU(U1))^T (1/2 dt Ubar_2)
+//     Ubar_n = 1/2 Ubar_2 + A1 + (dR/dU(Un))^T (dt A1)
+// Ubar_n's halo entries are set to zero.
+static cfd_status enqueue_step_reverse(cfd_solver* s, const double* const* Pk, double dt, const double* Ubar_np1,
+                                       double* Ubar_n, hipStream_t st) {
+  cfd_status rc;
+  if (s->g.rk2) {
+    if ((rc = enqueue_rhs_adjoint(s, Pk[1], Ubar_np1, 0.5 * dt, adj_out(s->A1, 0.5, Ubar_np1), st, false, true)))
+      return rc;
+    return enqueue_rhs_adjoint(s, Pk[0], s->A1, dt, adj_out(Ubar_n, 0.5, Ubar_np1, 1.0, s->A1, 0.0, nullptr, true),
+                               st, true, false);
+  }
+  if ((rc = enqueue_rhs_adjoint(s, Pk[2], Ubar_np1, 2.0 / 3.0 * dt, adj_out(s->A2, 2.0 / 3.0, Ubar_np1), st, false,
+                                true)))
+    return rc;
+  if ((rc = enqueue_rhs_adjoint(s, Pk[1], s->A2, 0.25 * dt, adj_out(s->A1, 0.25, s->A2), st, true, true))) return rc;
+  return enqueue_rhs_adjoint(s, Pk[0], s->A1, dt,
+                             adj_out(Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75, s->A2, 1.0, s->A1, true), st, true, false);
 }
 
 // The adjoint covers WENO5-JS with HLLC (any physics), and WENO3-JS with the
@@ -653,7 +721,7 @@ void cfd_destroy(cfd_solver* s) {
   if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
   if (s->ev_join) (void)hipEventDestroy(s->ev_join);
   double* bufs[] = {s->U1, s->U2,   s->Pb[0], s->Pb[1], s->Pb[2], s->Racc,    s->Racc2, s->A1,
-                    s->A2, s->A3,   s->Wbar,  s->Dbar,  s->partial, s->nna, s->nntape};
+                    s->A2, s->A3,   s->Wbar,  s->Dbar,  s->Wbar2, s->Dbar2, s->partial, s->nna, s->nntape};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (s->ctl) (void)hipFree(s->ctl);
@@ -849,7 +917,7 @@ cfd_status cfd_rhs_adjoint(cfd_solver* s, const double* U, const double* Rbar, d
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   if ((rc = enqueue_prim(s, U, 0, nullptr, st))) return rc;
-  return enqueue_rhs_adjoint(s, s->P, Rbar, 1.0, Ubar, st);
+  return enqueue_rhs_adjoint(s, s->P, Rbar, 1.0, adj_out(Ubar, 1.0, Ubar), st);
 }
 
 cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, const double* Ubar_np1,
@@ -885,17 +953,8 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   if ((rc = enqueue_prim(s, Un, 0, dtp, st))) return rc;
   if ((rc = enqueue_fluxes(s, s->Pb[0], io, true, st))) return rc;
   if (g.rk2) {
-    // TVD-RK2:  U2 = 1/2 Un + 1/2 (U1 + dt R(U1)),  U1 = Un + dt R(Un)
-    // A1 = Ubar_1 = 1/2 Ubar_2 + (dR/dU(U1))^T (1/2 dt Ubar_2)
-    hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.5, Ubar_np1, 0.0,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, g);
-    CFD_LAUNCHED();
-    if ((rc = enqueue_rhs_adjoint(s, s->Pb[1], Ubar_np1, 0.5 * dt, s->A1, st))) return rc;
-    // Ubar_n = 1/2 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
-    hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 0.5, Ubar_np1, 1.0,
-                       (const double*)s->A1, 0.0, (const double*)nullptr, g);
-    CFD_LAUNCHED();
-    return enqueue_rhs_adjoint(s, s->Pb[0], s->A1, dt, Ubar_n, st);
+    const double* const Pk[2] = {s->Pb[0], s->Pb[1]};
+    return enqueue_step_reverse(s, Pk, dt, Ubar_np1, Ubar_n, st);
   }
   io.Uk = s->U1;
   io.Uout = s->U2;
@@ -903,23 +962,8 @@ cfd_status cfd_rk3_step_adjoint(cfd_solver* s, const double* Un, double dt, cons
   io.b = 0.25;
   io.Pn = s->Pb[2];
   if ((rc = enqueue_fluxes(s, s->Pb[1], io, true, st))) return rc;
-  // reverse:  U3 = 1/3 Un + 2/3 (U2 + dt R(U2)),  U2 = 3/4 Un + 1/4 (U1 + dt R(U1)),
-  //           U1 = Un + dt R(Un)
-  // A2 = Ubar_2 = 2/3 Ubar_3 + (dR/dU(U2))^T (2/3 dt Ubar_3)
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
-                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
-  CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
-  // A1 = Ubar_1 = 1/4 Ubar_2 + (dR/dU(U1))^T (1/4 dt Ubar_2)
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
-                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
-  CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
-  // Ubar_n = 1/3 Ubar_3 + 3/4 Ubar_2 + Ubar_1 + (dR/dU(Un))^T (dt Ubar_1)
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
-                     (const double*)s->A2, 1.0, (const double*)s->A1, g);
-  CFD_LAUNCHED();
-  return enqueue_rhs_adjoint(s, s->Pb[0], s->A1, dt, Ubar_n, st);
+  const double* const Pk[3] = {s->Pb[0], s->Pb[1], s->Pb[2]};
+  return enqueue_step_reverse(s, Pk, dt, Ubar_np1, Ubar_n, st);
 }
 
 cfd_status cfd_set_nn_weights(cfd_solver* s, const double* theta, double* theta_bar) {
@@ -967,19 +1011,8 @@ cfd_status cfd_rk3_step_adjoint_stages(cfd_solver* s, const double* Un, const do
                        (const double*)nullptr, s->partial);
     CFD_LAUNCHED();
   }
-  // the reverse sweep of cfd_rk3_step_adjoint
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
-                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
-  CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->Pb[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
-                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
-  CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, s->Pb[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
-                     (const double*)s->A2, 1.0, (const double*)s->A1, g);
-  CFD_LAUNCHED();
-  return enqueue_rhs_adjoint(s, s->Pb[0], s->A1, dt, Ubar_n, st);
+  const double* const Pk[3] = {s->Pb[0], s->Pb[1], s->Pb[2]};
+  return enqueue_step_reverse(s, Pk, dt, Ubar_np1, Ubar_n, st);
 }
 
 cfd_status cfd_rk3_step_prims(cfd_solver* s, double* U, double dt, double* P_out, void* stream) {
@@ -1008,22 +1041,9 @@ cfd_status cfd_rk3_step_adjoint_prims(cfd_solver* s, const double* P, double dt,
   cfd_status rc = ensure_adjoint_scratch(s);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  const Geom& g = s->g;
   const size_t ps = kPrimComps * (size_t)s->ncell;
   const double* const Pk[3] = {P, P + ps, P + 2 * ps};
-  // the reverse sweep of cfd_rk3_step_adjoint on the kept stage primitives
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A2, 2.0 / 3.0, Ubar_np1, 0.0,
-                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
-  CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, Pk[2], Ubar_np1, 2.0 / 3.0 * dt, s->A2, st))) return rc;
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, s->A1, 0.25, (const double*)s->A2, 0.0,
-                     (const double*)nullptr, 0.0, (const double*)nullptr, g);
-  CFD_LAUNCHED();
-  if ((rc = enqueue_rhs_adjoint(s, Pk[1], s->A2, 0.25 * dt, s->A1, st))) return rc;
-  hipLaunchKernelGGL(k_lincomb, plane_grid(g), dim3(kBlock), 0, st, Ubar_n, 1.0 / 3.0, Ubar_np1, 0.75,
-                     (const double*)s->A2, 1.0, (const double*)s->A1, g);
-  CFD_LAUNCHED();
-  return enqueue_rhs_adjoint(s, Pk[0], s->A1, dt, Ubar_n, st);
+  return enqueue_step_reverse(s, Pk, dt, Ubar_np1, Ubar_n, st);
 }
 
 }  // extern "C"

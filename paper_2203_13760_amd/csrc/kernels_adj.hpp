@@ -592,18 +592,47 @@ __global__ void __launch_bounds__(kBlock) k_adj_halo(double* Wbar, Geom g) {
   for (int v = 0; v < 6; ++v) atomic_add(Wbar + v * g.vs + s, f[v] * Wbar[v * g.vs + c]);
 }
 
-// Per interior cell s, after k_adj_halo (and, with viscous fluxes,
-// k_adj_dbar): the transposed primitive map at the state, given by its
-// primitives P[s] (rho, u, v, w, p), applied to Wbar[s]; Ubar[s] += result.
-// Halo entries of Ubar are not touched.
+// The destination of a right-hand-side adjoint: out = a X + b Y + c Z + the
+// folded adjoint at the interior cells (null terms are skipped; out may be
+// one of X, Y, Z), and, with zero_halo, zeros at its halo cells (otherwise
+// they are not touched). The linear combinations of the step adjoint's
+// stages are formed here, in the pass that writes out anyway.
+struct AdjOut {
+  double* out;
+  double a, b, c;
+  const double* X;
+  const double* Y;
+  const double* Z;
+  int zero_halo;
+};
+
+// Per cell s, after k_adj_halo (and, with viscous fluxes, k_adj_dbar): the
+// transposed primitive map at the state, given by its primitives P[s]
+// (rho, u, v, w, p), applied to Wbar[s], into the destination o.
 __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ P, const double* __restrict__ Wbar,
-                                                     double* __restrict__ Ubar, Geom g) {
+                                                     AdjOut o, Geom g) {
   const PlaneIdx p = plane_index(g, true);
-  if (!p.in || p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) return;
+  if (!p.in) return;
+  const long long s = p.c;
+  if (p.i < 0 || p.i >= g.n[0] || p.j < 0 || p.j >= g.n[1] || p.k < 0 || p.k >= g.n[2]) {
+    if (o.zero_halo)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) o.out[v * g.vs + s] = 0.0;
+    return;
+  }
+  double base[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long e = v * g.vs + s;
+    double r = 0.0;
+    if (o.X) r += o.a * o.X[e];
+    if (o.Y) r += o.b * o.Y[e];
+    if (o.Z) r += o.c * o.Z[e];
+    base[v] = r;
+  }
   double wb[6];
 #pragma unroll
-  for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + p.c];
-  const long long s = p.c;
+  for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + s];
   const double rho = P[s], pr = P[4 * g.vs + s];
   const double u[3] = {P[g.vs + s], P[2 * g.vs + s], P[3 * g.vs + s]};
   const double ir = div_nr(1.0, rho);
@@ -620,31 +649,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ 
     mb[a] = wb[1 + a] * ir - pb * gm1 * u[a];
     rb -= wb[1 + a] * u[a] * ir;
   }
-  Ubar[s] += rb;
-  Ubar[g.vs + s] += mb[0];
-  Ubar[2 * g.vs + s] += mb[1];
-  Ubar[3 * g.vs + s] += mb[2];
-  Ubar[4 * g.vs + s] += pb * gm1;
-}
-
-// out = a X + b Y + c Z over interior cells (null terms are skipped); the halo
-// of out is set to zero.
-__global__ void __launch_bounds__(kBlock) k_lincomb(double* __restrict__ out, double a, const double* X, double b,
-                                                    const double* Y, double c, const double* Z, Geom g) {
-  const PlaneIdx p = plane_index(g);
-  if (!p.in) return;
-  const bool in = p.i >= 0 && p.i < g.n[0] && p.j >= 0 && p.j < g.n[1] && p.k >= 0 && p.k < g.n[2];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const long long e = v * g.vs + p.c;
-    double r = 0.0;
-    if (in) {
-      if (X) r += a * X[e];
-      if (Y) r += b * Y[e];
-      if (Z) r += c * Z[e];
-    }
-    out[e] = r;
-  }
+  o.out[s] = base[0] + rb;
+  o.out[g.vs + s] = base[1] + mb[0];
+  o.out[2 * g.vs + s] = base[2] + mb[1];
+  o.out[3 * g.vs + s] = base[3] + mb[2];
+  o.out[4 * g.vs + s] = base[4] + pb * gm1;
 }
 
 // Coordinates along one axis (n cells, halo h) whose value in a state with
