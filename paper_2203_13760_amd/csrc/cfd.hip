@@ -535,6 +535,9 @@ static void launch_face_adj(cfd_solver* s, const double* P, const double* Rbar, 
 // out.out = (the combination in out) + (dR/dU(U))^T (rscale Rbar) at the
 // interior cells, with U given by its primitives P (padded, halos included;
 // rho, u, v, w, p are read).
+// Padded cells from which a right-hand-side adjoint uses its second stream.
+constexpr long long kAdjForkMinCells = 1LL << 18;
+
 // Clear the accumulators Wbar, Dbar (graph-safe fill kernels).
 static void enqueue_clear_adj(cfd_solver* s, double* Wb, double* Db, hipStream_t st) {
   hipLaunchKernelGGL(k_zero, dim3(grid_for(6 * s->ncell)), dim3(kBlock), 0, st, Wb, 6 * s->ncell);
@@ -551,6 +554,12 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const doub
                                       double rscale, const AdjOut& out, hipStream_t st, bool cleared = false,
                                       bool clear_next = false) {
   const Geom& g = s->g;
+  // Small grids (a few microseconds per kernel) keep everything on one
+  // stream: there the fork and join cost more than the overlap gains, and
+  // each call clears its own pair.
+  const bool big = s->ncell >= kAdjForkMinCells;
+  cleared = cleared && big;
+  clear_next = clear_next && big;
   if (!cleared) {
     enqueue_clear_adj(s, s->Wbar, s->Dbar, st);
     CFD_LAUNCHED();
@@ -559,7 +568,7 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const doub
   // their stencil loads) add to disjoint or commuting entries of Wbar and
   // Dbar: they run side by side on two streams, and the side stream then
   // clears the next pair
-  const bool side_faces = !g.nn && g.inviscid && (g.viscous || g.heat);
+  const bool side_faces = big && !g.nn && g.inviscid && (g.viscous || g.heat);
   const bool fork = side_faces || clear_next;
   hipStream_t sd = st;
   if (fork) {
