@@ -605,12 +605,14 @@ static cfd_status enqueue_rhs_adjoint(cfd_solver* s, const double* P, const doub
     CFD_HIP(hipStreamWaitEvent(st, s->ev_join, 0));
   }
   if (g.viscous) {
-    hipLaunchKernelGGL(k_adj_dbar, plane_grid(g), dim3(kBlock), 0, st, (const double*)s->Dbar, s->Wbar, g);
+    hipLaunchKernelGGL(k_adj_dbar_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, (const double*)s->Dbar, s->Wbar,
+                       g);
     CFD_LAUNCHED();
   }
   hipLaunchKernelGGL(k_adj_halo, dim3(halo_blocks(g)), dim3(kBlock), 0, st, s->Wbar, g);
   CFD_LAUNCHED();
-  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, P, (const double*)s->Wbar, out, g);
+  hipLaunchKernelGGL(k_adj_fold, plane_grid(g), dim3(kBlock), 0, st, P, (const double*)s->Wbar,
+                     (const double*)(g.viscous ? s->Dbar : nullptr), out, g);
   CFD_LAUNCHED();
   std::swap(s->Wbar, s->Wbar2);
   std::swap(s->Dbar, s->Dbar2);

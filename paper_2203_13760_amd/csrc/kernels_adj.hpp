@@ -13,8 +13,9 @@
 //      (one atomic per cell and variable). y and z faces
 //      (k_march_adj_inv/dis): marching wavefronts, the reverse of the forward
 //      marches. The inviscid and dissipative reverses run on two streams;
-//   3. k_adj_dbar (viscous): the transposed centred differences of Dbar,
-//      added to Wbar at every padded cell;
+//   3. k_adj_dbar_halo (viscous): the transposed centred differences of
+//      Dbar, added to Wbar at the halo cells (k_adj_fold adds the interior
+//      cells' share);
 //   4. k_adj_halo: the transposed halo fill, every halo cell's Wbar added to
 //      its interior source cell;
 //   5. k_adj_fold: per interior cell, the transposed primitive map at the
@@ -559,19 +560,21 @@ __device__ __forceinline__ void fold_dbar(const Geom& g, const double* __restric
   }
 }
 
-// Transposed centred differences of Dbar, for every padded cell c:
-// Wbar(u, v, w)[c] += the adjoint the tangential derivatives give c. Every
-// padded cell is the image of exactly one interior cell, so after this pass
-// the fold only sums Wbar over images. Each thread updates its own cell.
-__global__ void __launch_bounds__(kBlock) k_adj_dbar(const double* __restrict__ Dbar, double* __restrict__ Wbar,
-                                                     Geom g) {
-  const PlaneIdx p = plane_index(g, true);
-  if (!p.in) return;
-  const int q[3] = {p.i, p.j, p.k};
+// Transposed centred differences of Dbar at the halo cells: Wbar(u, v, w)[c]
+// += the adjoint the tangential derivatives give halo cell c, before
+// k_adj_halo adds the halo cells to their interior sources (the interior
+// cells' own share is formed in k_adj_fold). One thread per halo cell, each
+// updating its own cell.
+__global__ void __launch_bounds__(kBlock) k_adj_dbar_halo(const double* __restrict__ Dbar, double* __restrict__ Wbar,
+                                                          Geom g) {
+  int i, j, k;
+  if (!halo_cell(g, (long long)blockIdx.x * kBlock + threadIdx.x, i, j, k)) return;
+  const long long c = cell_at(g, i, j, k);
+  const int q[3] = {i, j, k};
   double wb[4] = {0.0, 0.0, 0.0, 0.0};
-  fold_dbar<true>(g, Dbar, p.c, q, wb);
+  fold_dbar<true>(g, Dbar, c, q, wb);
 #pragma unroll
-  for (int c = 1; c < 4; ++c) Wbar[c * g.vs + p.c] += wb[c];
+  for (int v = 1; v < 4; ++v) Wbar[v * g.vs + c] += wb[v];
 }
 
 // Transposed halo fill of the primitive adjoints: every halo cell adds its
@@ -606,11 +609,12 @@ struct AdjOut {
   int zero_halo;
 };
 
-// Per cell s, after k_adj_halo (and, with viscous fluxes, k_adj_dbar): the
-// transposed primitive map at the state, given by its primitives P[s]
-// (rho, u, v, w, p), applied to Wbar[s], into the destination o.
+// Per cell s, after k_adj_halo (and, with viscous fluxes, k_adj_dbar_halo):
+// Wbar[s] plus (Dbar non-null) the transposed centred differences of Dbar at
+// s, then the transposed primitive map at the state, given by its primitives
+// P[s] (rho, u, v, w, p), into the destination o.
 __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ P, const double* __restrict__ Wbar,
-                                                     AdjOut o, Geom g) {
+                                                     const double* __restrict__ Dbar, AdjOut o, Geom g) {
   const PlaneIdx p = plane_index(g, true);
   if (!p.in) return;
   const long long s = p.c;
@@ -633,6 +637,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_fold(const double* __restrict__ 
   double wb[6];
 #pragma unroll
   for (int v = 0; v < 6; ++v) wb[v] = Wbar[v * g.vs + s];
+  if (Dbar) {
+    // an interior cell's +-2 neighbours lie inside the padded block
+    const int q[3] = {p.i, p.j, p.k};
+    fold_dbar<false>(g, Dbar, s, q, wb);
+  }
   const double rho = P[s], pr = P[4 * g.vs + s];
   const double u[3] = {P[g.vs + s], P[2 * g.vs + s], P[3 * g.vs + s]};
   const double ir = div_nr(1.0, rho);

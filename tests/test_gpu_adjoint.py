@@ -48,6 +48,10 @@ def _cases():
         "sod": wl.sod(40),
         "viscous_only": wl.random_smooth((10, 9, 8), seed=5, mu=0.05, flags=wl.VISCOUS),
         "heat_only": wl.random_smooth((10, 9, 8), seed=6, mu=0.05, flags=wl.HEAT),
+        # x rows longer than a wavefront (the x reverses' slots of one row span
+        # several wavefronts) and y, z columns of several march segments
+        "long_rows": wl.random_smooth((70, 19, 17), seed=21, mu=0.02,
+                                      bc=(P, P, Z, Z, wl.REFLECT, wl.REFLECT)),
     }
 
 
@@ -176,7 +180,7 @@ def test_kept_stages_and_their_step_adjoint_match_oracle(Solver, name):
     assert e <= 1e-10, (name, e)
 
 
-@pytest.mark.parametrize("name", ["tgv_noisy", "shocky3d", "kh", "sod", "viscous_only", "heat_only"])
+@pytest.mark.parametrize("name", ["tgv_noisy", "shocky3d", "kh", "sod", "viscous_only", "heat_only", "long_rows"])
 def test_kept_stage_primitives_and_their_step_adjoint_match_oracle(Solver, name):
     """cfd_rk3_step_prims: the step equals the oracle's fixed-dt step and the
     kept primitives of Un, U1, U2 (every padded cell) equal the primitive map
