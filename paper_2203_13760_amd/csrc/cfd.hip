@@ -174,10 +174,14 @@ static void make_geom(const cfd_config& c, Geom& g) {
   g.heat = ((c.flags & CFD_F_HEAT) && c.mu > 0.0) ? 1 : 0;
 }
 
-// March segment length of a single-grid solver: halved (down to 8 cells)
-// while a y or z march would run fewer than 1024 wavefronts, so that small
-// grids spread their marches over more lanes (each segment recomputes one
-// seed face). The serving batch keeps kSeg: it fills the chip with many grids.
+// March segment length of a single-grid solver: kSegSolo, halved (down to 8
+// cells) while a y or z march would run fewer than 1024 wavefronts, so that
+// small grids spread their marches over more lanes (each segment recomputes
+// its seed face and, in the adjoint, a reconstruction pair). Long segments
+// pay that less often: at 256^3 the marches run 128-cell segments (2048
+// wavefronts, one per wavefront slot at two per SIMD), 2-3 % faster than
+// 32-cell ones; 16-cell ones are 4 % slower. The serving batch keeps kSeg: it
+// fills the chip with many grids.
 static void choose_segment(Geom& g) {
   auto waves = [&](int seg) {
     long long w = -1;
@@ -189,7 +193,7 @@ static void choose_segment(Geom& g) {
     }
     return w;
   };
-  g.seg = kSeg;
+  g.seg = kSegSolo;
   while (g.seg > 8 && waves(g.seg) >= 0 && waves(g.seg) < 1024) g.seg /= 2;
 }
 

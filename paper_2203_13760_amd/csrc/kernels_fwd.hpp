@@ -738,10 +738,12 @@ __host__ __device__ __forceinline__ int sweep_x_blocks(const Geom& g) {
 }
 
 // y / z sweep: one lane per (x, other) column segment of Geom::seg cells
-// along the axis (kSeg by default; fewer on grids too small to fill the chip
-// with segments that long); lanes run along x so every load is coalesced. The
-// segment's first face is computed only to seed the left flux.
+// along the axis (kSegSolo for a single grid, kSeg in the serving batch;
+// fewer on grids too small to fill the chip with segments that long); lanes
+// run along x so every load is coalesced. The segment's first face is
+// computed only to seed the left flux.
 constexpr int kSeg = 32;
+constexpr int kSegSolo = 128;
 
 // y / z sweep body of one lane. Lanes beyond the grid (a partial last block)
 // march a valid column too but store nothing, so that every lane reaches the
