@@ -87,6 +87,48 @@ def test_alone_equals_in_mix_bitwise(cfd):
         assert np.array_equal(alone, together[k]), k
 
 
+def _march_blocks(case, seg):
+    """Workgroups of a grid's y (or z) march at a segment length (the launch
+    shape of sweep_march_blocks: 64 x per block row, four columns per block)."""
+    n = case["n"]
+    return -(-n[0] // 64) * -(-(n[2] * -(-n[1] // seg)) // 4)
+
+
+def test_long_march_segments_of_a_full_batch_equal_each_grid_alone(cfd):
+    """A resident set whose y and z march phases hold a block for every one of
+    the 2048 persistent workgroups with 128-cell segments marches with those;
+    each grid alone keeps 32-cell segments. The results agree bitwise (every
+    face flux is computed the same way whatever the segment length), and the
+    grid alone is the path the oracle parity tests cover."""
+    grids = [wl.taylor_green_noisy(192, sigma=1e-3, seed=40 + k) for k in range(8)]
+    assert sum(_march_blocks(c, 128) for c, _ in grids) >= 2048
+    assert _march_blocks(grids[0][0], 64) < 2048
+    print("long march segments: 8 x TGV 192^3 + noise, 2 steps, mix vs alone", flush=True)
+
+    def run(sel, arena):
+        b = cfd.cfd_batch_create(8, arena)
+        slots = [cfd.cfd_batch_add(b, grids[k][0], torch.from_numpy(np.ascontiguousarray(grids[k][1])).cuda())
+                 for k in sel]
+        assert None not in slots
+        for _ in range(2):
+            cfd.cfd_batch_step(b)
+        from paper_2203_13760_amd.solver import padded_shape
+        out = []
+        for k, sl in zip(sel, slots):
+            cfd.cfd_batch_finish(b, sl)
+            U = torch.empty(padded_shape(grids[k][0]), dtype=torch.float64, device="cuda")
+            cfd.cfd_batch_copy_state(b, sl, U)
+            out.append(U.cpu().numpy())
+        torch.cuda.synchronize()
+        cfd.cfd_batch_destroy(b)
+        return out
+
+    mix = run(list(range(8)), 24 << 30)
+    for k in (0, 5):
+        alone = run([k], 4 << 30)[0]
+        assert np.array_equal(alone, mix[k]), k
+
+
 def test_admission_by_footprint(cfd):
     case, W = wl.taylor_green(32)
     need = cfd.cfd_batch_footprint(case)
