@@ -224,14 +224,15 @@ __device__ __forceinline__ double block_max(double x) {
   return x;
 }
 
-// CFL rate of an interior cell: max(sum_d (|u_d| + c)/dx_d, (mu/rho) visc_rate).
-__device__ __forceinline__ double cfl_rate(const Geom& g, double rho, const double* u, double p) {
-  const double c = sqrt(g.gamma * p / rho);
+// CFL rate of an interior cell from its primitives w = (rho, u, v, w, p, p/rho)
+// and ir = 1/rho: max(sum_d (|u_d| + c)/dx_d, (mu/rho) visc_rate), c^2 = gamma p/rho.
+__device__ __forceinline__ double cfl_rate(const Geom& g, const double* w, double ir) {
+  const double c = sqrt_pos(g.gamma * w[5]);
   double s = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d)
-    if (g.act[d]) s += (fabs(u[d]) + c) * g.idx[d];
-  if (g.viscous || g.heat) s = fmax(s, (g.mu / rho) * g.visc_rate);
+    if (g.act[d]) s += (fabs(w[1 + d]) + c) * g.idx[d];
+  if (g.viscous || g.heat) s = fmax(s, (g.mu * ir) * g.visc_rate);
   return s;
 }
 
@@ -248,16 +249,18 @@ __device__ __forceinline__ void publish_rate(double* slots, int block_index, dou
               (unsigned long long)__double_as_longlong(s));
 }
 
-// Primitive variables w = (rho, u, v, w, p, p/rho) of conservative values q.
-__device__ __forceinline__ void cons_to_prim(const Geom& g, const double* q, double* w) {
+// Primitive variables w = (rho, u, v, w, p, p/rho) of conservative values q;
+// returns 1/rho.
+__device__ __forceinline__ double cons_to_prim(const Geom& g, const double* q, double* w) {
   const double rho = q[0];
   w[0] = rho;
-  const double ir = 1.0 / rho;
+  const double ir = div_nr(1.0, rho);
   w[1] = q[1] * ir;
   w[2] = q[2] * ir;
   w[3] = q[3] * ir;
   w[4] = (g.gamma - 1.0) * (q[4] - 0.5 * (q[1] * w[1] + q[2] * w[2] + q[3] * w[3]));
   w[5] = w[4] * ir;
+  return ir;
 }
 
 // Health bits of a cell: 1 non-finite conservative value, 2 rho <= 0, 4 p <= 0;
@@ -313,11 +316,11 @@ __device__ __forceinline__ void prim_body(const double* __restrict__ U, double* 
     u[1] *= bc_sign(q.i, g.n[0], g.bc[0], g.bc[1]);
     u[2] *= bc_sign(q.j, g.n[1], g.bc[2], g.bc[3]);
     u[3] *= bc_sign(q.k, g.n[2], g.bc[4], g.bc[5]);
-    cons_to_prim(g, u, w);
+    const double ir = cons_to_prim(g, u, w);
 #pragma unroll
     for (int v = 0; v < 6; ++v) P[v * g.vs + c] = w[v];
     if (what && s == c) {
-      if (what & PRIM_CFL) smax = cfl_rate(g, w[0], w + 1, w[4]);
+      if (what & PRIM_CFL) smax = cfl_rate(g, w, ir);
       if (what & PRIM_HEALTH) {
         const int bad = health_bits(u, w[4]);
         if (bad) atomicOr(&ctl->status, bad);
@@ -340,12 +343,11 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const double* __restrict__ U, Ge
   const PlaneIdx q = plane_index(g);
   double smax = 0.0;
   if (q.in && q.i >= 0 && q.i < g.n[0] && q.j >= 0 && q.j < g.n[1] && q.k >= 0 && q.k < g.n[2]) {
-    const long long s = q.c;
-    const double rho = U[s];
-    const double m0 = U[g.vs + s], m1 = U[2 * g.vs + s], m2 = U[3 * g.vs + s], E = U[4 * g.vs + s];
-    const double u[3] = {m0 / rho, m1 / rho, m2 / rho};
-    const double p = (g.gamma - 1.0) * (E - 0.5 * (m0 * u[0] + m1 * u[1] + m2 * u[2]));
-    smax = cfl_rate(g, rho, u, p);
+    double u[5], w[6];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) u[v] = U[v * g.vs + q.c];
+    const double ir = cons_to_prim(g, u, w);
+    smax = cfl_rate(g, w, ir);
   }
   publish_rate(partial, blockIdx.y * gridDim.x + blockIdx.x, smax);
 }
@@ -405,7 +407,7 @@ __device__ __forceinline__ void tangential_at(const Geom& g, const double* __res
   const double* uD = P + (1 + D) * g.vs + c;
   if (g.act[T1]) {
     const long long st = g.s[T1];
-    const double i12 = g.idx[T1] / 12.0;
+    const double i12 = g.idx[T1] * (1.0 / 12.0);
     tg[0] = central4(uD, st, i12);
     tg[1] = central4(P + (1 + T1) * g.vs + c, st, i12);
   } else {
@@ -414,7 +416,7 @@ __device__ __forceinline__ void tangential_at(const Geom& g, const double* __res
   }
   if (g.act[T2]) {
     const long long st = g.s[T2];
-    const double i12 = g.idx[T2] / 12.0;
+    const double i12 = g.idx[T2] * (1.0 / 12.0);
     tg[2] = central4(uD, st, i12);
     tg[3] = central4(P + (1 + T2) * g.vs + c, st, i12);
   } else {
@@ -448,7 +450,7 @@ __device__ __forceinline__ void tangential_load(const Geom& g, const double* __r
 template <int D>
 __device__ __forceinline__ void tangential_combine(const Geom& g, const double (&x)[4][4], double* tg) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
-  const double w1 = g.act[T1] ? g.idx[T1] / 12.0 : 0.0, w2 = g.act[T2] ? g.idx[T2] / 12.0 : 0.0;
+  const double w1 = g.act[T1] ? g.idx[T1] * (1.0 / 12.0) : 0.0, w2 = g.act[T2] ? g.idx[T2] * (1.0 / 12.0) : 0.0;
   const double w[4] = {w1, w1, w2, w2};
 #pragma unroll
   for (int m = 0; m < 4; ++m) tg[m] = (x[m][0] - 8.0 * x[m][1] + 8.0 * x[m][2] - x[m][3]) * w[m];
@@ -505,10 +507,10 @@ __device__ __forceinline__ void emit_put(const StageIO& io, const Geom& g, long 
   }
   if constexpr (PN && mode_rk(MODE)) {
     double w[6];
-    cons_to_prim(g, uo, w);
+    const double ir = cons_to_prim(g, uo, w);
 #pragma unroll
     for (int v = 0; v < (STORE_T ? 6 : 5); ++v) io.Pn[v * g.vs + c] = w[v];
-    if (io.what & PRIM_CFL) smax = fmax(smax, cfl_rate(g, w[0], w + 1, w[4]));
+    if (io.what & PRIM_CFL) smax = fmax(smax, cfl_rate(g, w, ir));
     if (io.what & PRIM_HEALTH) bad |= health_bits(uo, w[4]);
   }
 }

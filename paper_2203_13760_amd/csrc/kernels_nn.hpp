@@ -70,7 +70,7 @@ __device__ __forceinline__ void nn_face_states(const Geom& g, const double* __re
 template <int D>
 __device__ __forceinline__ void nn_features(const Geom& g, const double* WL, const double* WR, double* f) {
   const double uL = WL[1 + D], uR = WR[1 + D];
-  const double cL = sqrt(div_nr(g.gamma * WL[4], WL[0])), cR = sqrt(div_nr(g.gamma * WR[4], WR[0]));
+  const double cL = sqrt_pos(div_nr(g.gamma * WL[4], WL[0])), cR = sqrt_pos(div_nr(g.gamma * WR[4], WR[0]));
   const double sL = (log(WL[4]) - g.gamma * log(WL[0])) * g.gm1i;
   const double sR = (log(WR[4]) - g.gamma * log(WR[0])) * g.gm1i;
   f[0] = fabs(uR - uL);
@@ -238,7 +238,7 @@ __device__ __forceinline__ void nn_features_rev(const Geom& g, const double* WL,
   WRb[1 + D] += fb[0] * sg0 + 0.5 * fb[1];
   WLb[1 + D] += -fb[0] * sg0 + 0.5 * fb[1];
   // c = sqrt(gamma p / rho): dc/dp = c/(2p), dc/drho = -c/(2 rho)
-  const double cL = sqrt(div_nr(g.gamma * WL[4], WL[0])), cR = sqrt(div_nr(g.gamma * WR[4], WR[0]));
+  const double cL = sqrt_pos(div_nr(g.gamma * WL[4], WL[0])), cR = sqrt_pos(div_nr(g.gamma * WR[4], WR[0]));
   const double cb = 0.5 * fb[2];
   WLb[4] += cb * cL / (2.0 * WL[4]);
   WLb[0] -= cb * cL / (2.0 * WL[0]);

@@ -80,6 +80,31 @@ __host__ __device__ __forceinline__ double div_nr(double a, double b) {
 #endif
 }
 
+// sqrt(x) for a finite x >= 2^-767 (densities, pressures, squared sound
+// speeds): the hardware reciprocal square root estimate y ~ 1/sqrt(x)
+// (v_rsq_f64) refined by one Goldschmidt step on the pair g ~ sqrt(x),
+// h ~ 1/(2 sqrt(x)) (r = 1/2 - g h, g += g r, h += h r) and two Newton
+// corrections of the root (g += (x - g^2) h). These are the steps of the
+// compiler's own square root on gfx950 for such x, without its range scaling
+// for tiny arguments and its fixups for 0 and infinity (x = 0 gives NaN, a
+// negative x NaN as sqrt does): about half of its instructions. The host pass
+// takes sqrt.
+__host__ __device__ __forceinline__ double sqrt_pos(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+#else
+  return sqrt(x);
+#endif
+}
+
 // Cell index of interior-relative coordinates (i,j,k) (halo cells negative).
 __device__ __forceinline__ long long cell_at(const Geom& g, int i, int j, int k) {
   return (long long)(k + g.h[2]) * g.s[2] + (long long)(j + g.h[1]) * g.s[1] + (i + g.h[0]);
@@ -229,7 +254,7 @@ __host__ __device__ __forceinline__ void rusanov(double gamma, double gm1i, cons
   const double EL = pL * gm1i + kL, ER = pR * gm1i + kR;
   double alpha = alpha_in;
   if constexpr (!GIVEN) {
-    const double cL = sqrt(div_nr(gamma * pL, rL)), cR = sqrt(div_nr(gamma * pR, rR));
+    const double cL = sqrt_pos(div_nr(gamma * pL, rL)), cR = sqrt_pos(div_nr(gamma * pR, rR));
     alpha = fmax(fmax(fabs(uL - cL), fabs(uL + cL)), fmax(fabs(uR - cR), fabs(uR + cR)));
   }
   const double UL[5] = {rL, rL * WL[1], rL * WL[2], rL * WL[3], EL};
@@ -263,13 +288,13 @@ __host__ __device__ __forceinline__ void hllc(double gamma, double gm1i, const d
   const double EL = pL * gm1i + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
   const double ER = pR * gm1i + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
   const double c2L = div_nr(gamma * pL, rL), c2R = div_nr(gamma * pR, rR);
-  const double cL = sqrt(c2L), cR = sqrt(c2R);
+  const double cL = sqrt_pos(c2L), cR = sqrt_pos(c2R);
   // Einfeldt: Roe-averaged normal velocity and sound-speed bound
-  const double sL = sqrt(rL), sR = sqrt(rR);
+  const double sL = sqrt_pos(rL), sR = sqrt_pos(rR);
   const double isum = div_nr(1.0, sL + sR);
   const double ubar = (sL * uL + sR * uR) * isum;
   const double eta2 = 0.5 * sL * sR * isum * isum;
-  const double dbar = sqrt((sL * c2L + sR * c2R) * isum + eta2 * sq(uR - uL));
+  const double dbar = sqrt_pos((sL * c2L + sR * c2R) * isum + eta2 * sq(uR - uL));
   const double SL = fmin(uL - cL, ubar - dbar);
   const double SR = fmax(uR + cR, ubar + dbar);
   const double mL = rL * (SL - uL), mR = rR * (SR - uR);  // mass fluxes relative to the waves
@@ -346,7 +371,7 @@ __host__ __device__ __forceinline__ void sub_dissipative_q(const Geom& g, const 
                                                            const double* tf, double* F) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   if (g.viscous || g.heat) {
-    const double i24 = g.idx[D] / 24.0;
+    const double i24 = g.idx[D] * (1.0 / 24.0);
     auto dn = [&](double a, double b, double c, double d) { return (a - 27.0 * b + 27.0 * c - d) * i24; };
     double Fd1 = 0.0, Fd2 = 0.0, Fd3 = 0.0, Fd4 = 0.0;  // slots D, T1, T2 momentum; energy
     if (g.viscous) {
@@ -418,7 +443,7 @@ template <int D>
 __host__ __device__ __forceinline__ void roe_flux(const Geom& g, const double (&q)[6][5], double* F) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const double gm1 = g.gamma - 1.0;
-  const double sl = sqrt(q[2][0]), sr = sqrt(q[3][0]);
+  const double sl = sqrt_pos(q[2][0]), sr = sqrt_pos(q[3][0]);
   const double isum = 1.0 / (sl + sr);
   const double al = sl * isum, ar = sr * isum;
   const double uD = al * q[2][1 + D] + ar * q[3][1 + D];
@@ -430,7 +455,7 @@ __host__ __device__ __forceinline__ void roe_flux(const Geom& g, const double (&
   const double H = al * (hp * q[2][4] / q[2][0] + kl) + ar * (hp * q[3][4] / q[3][0] + kr);
   const double q2 = uD * uD + u1 * u1 + u2 * u2;
   const double c2 = gm1 * (H - 0.5 * q2);
-  const double c = sqrt(c2);
+  const double c = sqrt_pos(c2);
   const double ic = 1.0 / c;
   const double b = gm1 * ic * ic;
   const double lam[5] = {fabs(uD - c), fabs(uD), fabs(uD), fabs(uD), fabs(uD + c)};

@@ -129,14 +129,14 @@ __host__ __device__ __forceinline__ void hllc_rev(double gamma, double gm1i, con
   const double EL = pL * gm1i + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
   const double ER = pR * gm1i + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
   const double c2L = div_nr(gamma * pL, rL), c2R = div_nr(gamma * pR, rR);
-  const double cL = sqrt(c2L), cR = sqrt(c2R);
-  const double sL = sqrt(rL), sR = sqrt(rR);
+  const double cL = sqrt_pos(c2L), cR = sqrt_pos(c2R);
+  const double sL = sqrt_pos(rL), sR = sqrt_pos(rR);
   const double isum = div_nr(1.0, sL + sR);
   const double ubar = (sL * uL + sR * uR) * isum;
   const double eta2 = 0.5 * sL * sR * isum * isum;
   const double Hs = sL * c2L + sR * c2R;
   const double du = uR - uL;
-  const double dbar = sqrt(Hs * isum + eta2 * du * du);
+  const double dbar = sqrt_pos(Hs * isum + eta2 * du * du);
   const double candL1 = uL - cL, candL2 = ubar - dbar;
   const double candR1 = uR + cR, candR2 = ubar + dbar;
   const bool firstL = !(candL2 < candL1);  // fmin keeps the first on ties
