@@ -290,10 +290,10 @@ const char* cfd_last_error(void);
  * Serving batch: many independent solves (mixed sizes, 2D and 3D, different
  * physics) resident on the device at once, advanced together. Each TVD-RK3
  * step is one replay of a captured HIP graph whose launches are persistent
- * kernels, one per phase of each stage (primitives, CFL step, z/y/x
+ * kernels, one per phase of each stage (primitives, CFL step, y/z/x
  * sweeps, halo refresh of the next primitives), each covering the work of
- * every resident grid
- * through a device descriptor table. Every grid keeps its own state, scratch
+ * the resident grids of its sub-batch (up to four, run as concurrent
+ * branches) through a device descriptor table. Every grid keeps its own state, scratch
  * and CFL step, so its result does not depend on the other grids in the batch.
  * A batch is used from one stream at a time. */
 typedef struct cfd_batch cfd_batch; /* opaque */
@@ -324,7 +324,12 @@ cfd_status cfd_batch_remove(cfd_batch* b, int32_t slot);
 cfd_status cfd_batch_state(cfd_batch* b, int32_t slot, double** U_out, int64_t* numel);
 
 /* One CFL TVD-RK3 step of every resident grid (uploads the descriptor table
- * first when grids were added or removed since the last step). */
+ * first when grids were added or removed since the last step). The step graph
+ * leaves out the phases a sub-batch has no blocks in and sizes each launch to
+ * its blocks; a pattern of phases and widths not met before is captured on
+ * that step (a few milliseconds of host time) and kept, up to 16 patterns;
+ * with 16 kept the next new pattern first synchronises `stream` and drops
+ * them, so `stream` must not be under graph capture then. */
 cfd_status cfd_batch_step(cfd_batch* b, void* stream);
 
 /* Refresh the halo cells of a resident grid's state (for read-out). */

@@ -129,6 +129,44 @@ def test_long_march_segments_of_a_full_batch_equal_each_grid_alone(cfd):
         assert np.array_equal(alone, mix[k]), k
 
 
+def test_step_graphs_beyond_the_cache_keep_results(cfd):
+    """The step graph is kept per pattern of launched phases (chain count and
+    each sub-batch's phases and launch widths), 16 patterns at most. Cycling
+    one batch through the singles, pairs and triples of the mix's grids (3D,
+    2D, 1D along x, no x axis: different phase sets) meets more patterns than
+    that, so the kept graphs are dropped and captured again; a resident set
+    stepped afterwards gives the same bits as in a fresh batch."""
+    import itertools
+    grids = _mix()
+    Ws = [torch.from_numpy(np.ascontiguousarray(W)).cuda() for _, W in grids]
+    subsets = [c for r in (1, 2, 3) for c in itertools.combinations(range(len(grids)), r)]
+    print(f"step graph cache: {len(subsets)} resident sets, one step each", flush=True)
+    b = cfd.cfd_batch_create(16, 2 << 30)
+    for sub in subsets:
+        slots = [cfd.cfd_batch_add(b, grids[k][0], Ws[k]) for k in sub]
+        assert None not in slots
+        cfd.cfd_batch_step(b)
+        torch.cuda.synchronize()
+        for sl in slots:
+            cfd.cfd_batch_remove(b, sl)
+    final = (0, 1, 5)
+    slots = [cfd.cfd_batch_add(b, grids[k][0], Ws[k]) for k in final]
+    for _ in range(3):
+        cfd.cfd_batch_step(b)
+    from paper_2203_13760_amd.solver import padded_shape
+    got = []
+    for k, sl in zip(final, slots):
+        cfd.cfd_batch_finish(b, sl)
+        U = torch.empty(padded_shape(grids[k][0]), dtype=torch.float64, device="cuda")
+        cfd.cfd_batch_copy_state(b, sl, U)
+        got.append(U.cpu().numpy())
+    torch.cuda.synchronize()
+    cfd.cfd_batch_destroy(b)
+    fresh = _run(cfd, [grids[k] for k in final], 3)
+    for k, U, V in zip(final, got, fresh):
+        assert np.array_equal(U, V), k
+
+
 def test_admission_by_footprint(cfd):
     case, W = wl.taylor_green(32)
     need = cfd.cfd_batch_footprint(case)
