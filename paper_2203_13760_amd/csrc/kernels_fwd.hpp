@@ -180,8 +180,12 @@ __device__ __forceinline__ void prim_halo_body(double* P, const Geom& g, long lo
   const long long c = cell_at(g, i, j, k), s = cell_at(g, si, sj, sk);
   const double sg[3] = {bc_sign(i, g.n[0], g.bc[0], g.bc[1]), bc_sign(j, g.n[1], g.bc[2], g.bc[3]),
                         bc_sign(k, g.n[2], g.bc[4], g.bc[5])};
+  // T~ = p/rho (slot 5) only for the face-by-face schemes, which read it from
+  // P; the cell-centred ones form it from the window and do not store it
+  const bool with_t = g.roe || g.wenoz;
 #pragma unroll
-  for (int v = 0; v < 6; ++v) P[v * g.vs + c] = (v >= 1 && v <= 3 ? sg[v - 1] : 1.0) * P[v * g.vs + s];
+  for (int v = 0; v < 6; ++v)
+    if (v < 5 || with_t) P[v * g.vs + c] = (v >= 1 && v <= 3 ? sg[v - 1] : 1.0) * P[v * g.vs + s];
 }
 
 __global__ void __launch_bounds__(kBlock) k_prim_halo(double* P, Geom g, const double* dtp) {
@@ -474,15 +478,18 @@ struct EmitIn {
   double r[5], un[5], uk[5];
 };
 
+// A stage whose weight a of U^n is zero (TVD-RK3 stage 1, where U^(k) is
+// U^n) does not load U^n.
 template <int MODE>
 __device__ __forceinline__ void emit_fetch(const StageIO& io, long long vs, long long c, EmitIn& in) {
+  const bool with_un = io.a != 0.0;
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     const long long e = v * vs + c;
     if (MODE == MODE_ACC || MODE == MODE_ACC_RK) in.r[v] = io.R[e];
     if (MODE == MODE_ACC2_RK) in.r[v] = io.R[e] + io.R2[e];
     if (mode_rk(MODE)) {
-      in.un[v] = io.Un[e];
+      in.un[v] = with_un ? io.Un[e] : 0.0;
       in.uk[v] = io.Uk[e];
     }
   }
