@@ -180,8 +180,8 @@ static void make_geom(const cfd_config& c, Geom& g) {
 // its seed face and, in the adjoint, a reconstruction pair). Long segments
 // pay that less often: at 256^3 the marches run 128-cell segments (2048
 // wavefronts, one per wavefront slot at two per SIMD), 2-3 % faster than
-// 32-cell ones; 16-cell ones are 4 % slower. The serving batch keeps kSeg: it
-// fills the chip with many grids.
+// 32-cell ones; 16-cell ones are 4 % slower. The serving batch chooses its
+// own (batch_segment): it fills the chip with many grids.
 static void choose_segment(Geom& g) {
   auto waves = [&](int seg) {
     long long w = -1;

@@ -2,11 +2,12 @@
 //
 // Many independent grids (mixed sizes, 2D and 3D, different physics) are
 // resident at once. For every phase of a TVD-RK3 stage (primitives, step size,
-// x/y/z sweeps, primitive halo) one persistent launch of a fixed number of
-// workgroups covers the work of all resident grids: the work of grid k is
-// blocks [prefix[k], prefix[k+1]) of that phase, and each workgroup strides
-// over the concatenated block range, finds its grid by binary search, and runs
-// the same per-block body as the single-grid kernels. Grids never interact:
+// x/y/z sweeps, primitive halo) one persistent launch covers the work of the
+// resident grids of a sub-batch (its width chosen on the host from the
+// phase's blocks): the work of grid k is blocks [prefix[k], prefix[k+1]) of
+// that phase, and each workgroup takes blocks of the concatenated range, finds
+// their grid by binary search, and runs the same per-block body as the
+// single-grid kernels. Grids never interact:
 // each keeps its own state, scratch and CFL step, so a grid's result does not
 // depend on which other grids share the launch.
 //
